@@ -1,0 +1,102 @@
+"""Oracle for the swept-rule hot path (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg use this package. The GPU library never imports, links or calls it, and
+the two share no code; both start from the seeded fields of ``swept_inputs``.
+
+* ``advance_f64`` / ``advance_f32c``: the plain FP64 (and FP32-compensated)
+  step-by-step stepper written in C (``stepper.c``, built with
+  ``-O2 -ffp-contract=off``). This is the definition that the swept rule
+  reproduces exactly: no redundant computation, every point computed from its
+  full 3x3 neighbourhood one level below (abstract; Sec. 4).
+* ``swept_model``: the paper's Algorithms 1-5 (upward pyramid, the two
+  bridges, downward pyramid and the driver) executed literally on small grids
+  in pure Python, used to pin the readings of the algorithms' index ranges.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "stepper.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall"]
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle in place (gcc)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_advance_f64.restype = ctypes.c_int
+        lib.oracle_advance_f64.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+            ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
+        ]
+        lib.oracle_advance_f32c.restype = ctypes.c_int
+        lib.oracle_advance_f32c.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
+        ]
+        _lib = lib
+    return _lib
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def advance_f64(pde: int, state: np.ndarray, params, nsub: int, t0: int = 0, threads: int | None = None) -> np.ndarray:
+    """Return the state after ``nsub`` sub-steps starting at global sub-step t0.
+
+    ``state`` is ``[nvars][ny][nx]`` float64; it is not modified."""
+    lib = _load()
+    s = np.ascontiguousarray(state, dtype=np.float64).copy()
+    nvars, ny, nx = s.shape
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    rc = lib.oracle_advance_f64(int(pde), nx, ny, nvars, p.ctypes.data if p.size else None, int(p.size),
+                                s.ctypes.data, int(t0), int(nsub), int(threads or default_threads()))
+    if rc != 0:
+        raise ValueError(f"oracle_advance_f64 failed with {rc}")
+    return s
+
+
+def advance_f32c(pde: int, u: np.ndarray, c: np.ndarray, params, nsub: int, t0: int = 0,
+                 threads: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """FP32-compensated stepper; ``u`` and ``c`` are ``[nvars][ny][nx]`` float32."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float32).copy()
+    cc = np.ascontiguousarray(c, dtype=np.float32).copy()
+    nvars, ny, nx = uu.shape
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    rc = lib.oracle_advance_f32c(int(pde), nx, ny, nvars, p.ctypes.data, int(p.size),
+                                 uu.ctypes.data, cc.ctypes.data, int(t0), int(nsub),
+                                 int(threads or default_threads()))
+    if rc != 0:
+        raise ValueError(f"oracle_advance_f32c failed with {rc}")
+    return uu, cc
+
+
+def split_f32c(state64: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Initial FP32-compensated state from an FP64 field: u = fl32(x), c = 0."""
+    u = state64.astype(np.float32)
+    return u, np.zeros_like(u)

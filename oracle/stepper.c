@@ -1,0 +1,418 @@
+/*
+ * Oracle for the swept-rule hot path: a plain, slow, obviously correct CPU
+ * stepper.
+ *
+ * TEST INFRASTRUCTURE ONLY. It exists to check the GPU library. Only the
+ * tests, the smoke check and the benchmark's CPU-baseline leg may load it;
+ * the product path never calls it and shares no code with it.
+ *
+ * What it computes. The swept rule of space-time decomposition reaches
+ * exactly the values of plain step-by-step time advancing: every space-time
+ * point is computed once, from its complete 3x3 neighbourhood one level below
+ * (abstract: no redundant computation; Sec. 4, first paragraph). The oracle is
+ * that plain definition written out: on a doubly periodic grid (Sec. 2,
+ * assumption 1), for every global sub-step T, every point receives the
+ * sub-step operation St_{T mod m} applied to its 3x3 neighbourhood at level T
+ * (Sec. 2, assumption 2; the stencil list St of Algorithms 1-5).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math (x86-64 SSE2 arithmetic,
+ * IEEE binary64 / binary32, round to nearest even). The OpenMP loop over rows
+ * does not change any bit: there is no reduction.
+ *
+ * Layout: state[v][j][i] (structure of arrays), i = x fastest, j = 0 is the
+ * north row. Neighbour k = 3*(dj+1) + (di+1): 0 NW, 1 N, 2 NE, 3 W, 4 centre,
+ * 5 E, 6 SW, 7 S, 8 SE.
+ *
+ * The per-point operations below are the canonical expressions of the heat,
+ * wave, Euler and test stencils, evaluated left to right as written. The
+ * paper fixes none of these (its experiments use a wave and an Euler solver
+ * whose code is not part of the text); the expressions are this project's
+ * definitions and are restated, not shared, on the GPU side.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PDE_HEAT5 1
+#define PDE_WAVE_LF 2
+#define PDE_EULER_RUS_RK2 3
+#define PDE_TEST_HASH 100
+#define PDE_TEST_INCR 101
+#define PDE_TEST_PUSH5 102
+
+#define MAXV 8
+
+/* ---------------------------------------------------------------- FP64 */
+
+/* Heat, 5-point forward-time centred-space: u' = u + r * lap(u). */
+static void st_heat(const double nb[9][MAXV], double *out, const double *prm)
+{
+    double r = prm[0];
+    double u = nb[4][0];
+    double t1 = nb[3][0] + nb[5][0];
+    double t2 = nb[1][0] + nb[7][0];
+    double lap = (t1 + t2) - 4.0 * u;
+    out[0] = u + r * lap;
+}
+
+/* Wave, leapfrog with the previous level carried as a second variable:
+ * (u, p) -> ((2u - p) + C2 lap(u), u). */
+static void st_wave(const double nb[9][MAXV], double *out, const double *prm)
+{
+    double c2 = prm[0];
+    double u = nb[4][0];
+    double p = nb[4][1];
+    double t1 = nb[3][0] + nb[5][0];
+    double t2 = nb[1][0] + nb[7][0];
+    double lap = (t1 + t2) - 4.0 * u;
+    out[0] = (2.0 * u - p) + c2 * lap;
+    out[1] = u;
+}
+
+/* Order-sensitive 64-bit mix of the 9 neighbours and the sub-step index.
+ * Values are integers below 2^52 held exactly in doubles. Any neighbour taken
+ * from the wrong place or the wrong level changes the result. */
+static void st_hash(long long T, const double nb[9][MAXV], double *out)
+{
+    uint64_t h = 0x9E3779B97F4A7C15ull ^ (uint64_t)T;
+    for (int k = 0; k < 9; ++k) {
+        h ^= (uint64_t)nb[k][0];
+        h *= 0xFF51AFD7ED558CCDull;
+        h ^= h >> 32;
+    }
+    out[0] = (double)(h >> 12);
+}
+
+/* The paper's worked example (Sec. 3.1): increment by one. A point whose
+ * neighbours are not all at its own level becomes NaN, so a swept schedule
+ * that mixes levels is caught. */
+static void st_incr(const double nb[9][MAXV], double *out)
+{
+    double u = nb[4][0];
+    int same = 1;
+    for (int k = 0; k < 9; ++k)
+        if (nb[k][0] != u) same = 0;
+    out[0] = same ? u + 1.0 : NAN;
+}
+
+/* Sub-step decomposition of Eq. (1) into Eq. (2) (push the four neighbours)
+ * and Eq. (3) (combine the pushed values). 0-based slots: slot 0 holds u,
+ * slots 1..4 hold the pushed west, east, north (j-1) and south (j+1) values. */
+static void st_push5(long long T, const double nb[9][MAXV], double *out)
+{
+    if ((T & 1) == 0) {
+        out[0] = nb[4][0];
+        out[1] = nb[3][0];
+        out[2] = nb[5][0];
+        out[3] = nb[1][0];
+        out[4] = nb[7][0];
+    } else {
+        out[0] = nb[3][1] + nb[5][2] + nb[1][3] + nb[7][4] - 4.0 * nb[4][0];
+        out[1] = 0.0;
+        out[2] = 0.0;
+        out[3] = 0.0;
+        out[4] = 0.0;
+    }
+}
+
+/* Euler: physical flux along direction d (0 = x, 1 = y) of U = (rho, mx, my, E)
+ * and the largest signal speed |u_n| + c. */
+static void euler_phys(const double *U, int d, double gamma, double *F, double *speed)
+{
+    double rho = U[0], mx = U[1], my = U[2], en = U[3];
+    double ke = 0.5 * ((mx * mx + my * my) / rho);
+    double p = (gamma - 1.0) * (en - ke);
+    double c = sqrt((gamma * p) / rho);
+    if (d == 0) {
+        double un = mx / rho;
+        F[0] = mx;
+        F[1] = mx * un + p;
+        F[2] = my * un;
+        F[3] = (en + p) * un;
+        *speed = fabs(un) + c;
+    } else {
+        double un = my / rho;
+        F[0] = my;
+        F[1] = mx * un;
+        F[2] = my * un + p;
+        F[3] = (en + p) * un;
+        *speed = fabs(un) + c;
+    }
+}
+
+/* Rusanov (local Lax-Friedrichs) flux through the face between the left /
+ * lower state L and the right / upper state R. The arguments are always
+ * passed in (left, right) order, so both cells sharing a face see the same
+ * bits and the update telescopes exactly. */
+static void euler_rusanov(const double *L, const double *R, int d, double gamma, double *Fh)
+{
+    double FL[4], FR[4], aL, aR;
+    euler_phys(L, d, gamma, FL, &aL);
+    euler_phys(R, d, gamma, FR, &aR);
+    double a = fmax(aL, aR);
+    for (int k = 0; k < 4; ++k)
+        Fh[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * (a * (R[k] - L[k]));
+}
+
+/* dt * L(U) at the centre, from the slots starting at off of the 5-point
+ * neighbourhood; j increases southward, so the south face is j + 1/2. */
+static void euler_increment(const double nb[9][MAXV], int off, double gamma, double dtoh, double *du)
+{
+    double Fw[4], Fe[4], Gn[4], Gs[4];
+    euler_rusanov(nb[3] + off, nb[4] + off, 0, gamma, Fw);
+    euler_rusanov(nb[4] + off, nb[5] + off, 0, gamma, Fe);
+    euler_rusanov(nb[1] + off, nb[4] + off, 1, gamma, Gn);
+    euler_rusanov(nb[4] + off, nb[7] + off, 1, gamma, Gs);
+    for (int k = 0; k < 4; ++k) {
+        double div = (Fe[k] - Fw[k]) + (Gs[k] - Gn[k]);
+        du[k] = -(dtoh * div);
+    }
+}
+
+/* Two-stage strong-stability-preserving Runge-Kutta (Heun) as two sub-steps.
+ * Slots 0..3 hold U^n, slots 4..7 the stage U*.
+ * sub-step 0: U* = U + dt L(U)                 (slots 0..3 carried along)
+ * sub-step 1: U' = 0.5 U + 0.5 (U* + dt L(U*)) (slots 4..7 := slots 0..3) */
+static void st_euler(long long T, const double nb[9][MAXV], double *out, const double *prm)
+{
+    double gamma = prm[0], dtoh = prm[1];
+    double du[4];
+    const double *C = nb[4];
+    if ((T & 1) == 0) {
+        euler_increment(nb, 0, gamma, dtoh, du);
+        for (int k = 0; k < 4; ++k) {
+            out[k] = C[k];
+            out[4 + k] = C[k] + du[k];
+        }
+    } else {
+        euler_increment(nb, 4, gamma, dtoh, du);
+        for (int k = 0; k < 4; ++k) {
+            double v = 0.5 * C[k] + 0.5 * (C[4 + k] + du[k]);
+            out[k] = v;
+            out[4 + k] = v;
+        }
+    }
+}
+
+static int pde_shape_ok(int pde, int nvars)
+{
+    switch (pde) {
+    case PDE_HEAT5: return nvars == 1;
+    case PDE_WAVE_LF: return nvars == 2;
+    case PDE_EULER_RUS_RK2: return nvars == 8;
+    case PDE_TEST_HASH: return nvars == 1;
+    case PDE_TEST_INCR: return nvars == 1;
+    case PDE_TEST_PUSH5: return nvars == 5;
+    default: return 0;
+    }
+}
+
+static int nparams_needed(int pde)
+{
+    switch (pde) {
+    case PDE_HEAT5: return 1;
+    case PDE_WAVE_LF: return 1;
+    case PDE_EULER_RUS_RK2: return 2;
+    default: return 0;
+    }
+}
+
+/* Advance a doubly periodic FP64 state by nsub sub-steps, starting at global
+ * sub-step index t0. Returns 0, or -1 on invalid arguments, -3 when out of
+ * memory. */
+int oracle_advance_f64(int pde, int nx, int ny, int nvars, const double *params, int nparams,
+                       double *state, long long t0, long long nsub, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nsub < 0 || t0 < 0 || !state || !pde_shape_ok(pde, nvars))
+        return -1;
+    if (nparams < nparams_needed(pde) || (nparams_needed(pde) > 0 && !params))
+        return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t plane = (size_t)nx * (size_t)ny;
+    double *tmp = (double *)malloc(plane * (size_t)nvars * sizeof(double));
+    if (!tmp) return -3;
+    double *cur = state, *nxt = tmp;
+    for (long long s = 0; s < nsub; ++s) {
+        long long T = t0 + s;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int j = 0; j < ny; ++j) {
+            double nb[9][MAXV];
+            double out[MAXV];
+            for (int i = 0; i < nx; ++i) {
+                for (int dj = -1; dj <= 1; ++dj) {
+                    int jj = (j + dj + ny) % ny;
+                    for (int di = -1; di <= 1; ++di) {
+                        int ii = (i + di + nx) % nx;
+                        int k = 3 * (dj + 1) + (di + 1);
+                        for (int v = 0; v < nvars; ++v)
+                            nb[k][v] = cur[(size_t)v * plane + (size_t)jj * nx + ii];
+                    }
+                }
+                switch (pde) {
+                case PDE_HEAT5: st_heat(nb, out, params); break;
+                case PDE_WAVE_LF: st_wave(nb, out, params); break;
+                case PDE_EULER_RUS_RK2: st_euler(T, nb, out, params); break;
+                case PDE_TEST_HASH: st_hash(T, nb, out); break;
+                case PDE_TEST_INCR: st_incr(nb, out); break;
+                case PDE_TEST_PUSH5: st_push5(T, nb, out); break;
+                }
+                for (int v = 0; v < nvars; ++v)
+                    nxt[(size_t)v * plane + (size_t)j * nx + i] = out[v];
+            }
+        }
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != state)
+        memcpy(state, cur, plane * (size_t)nvars * sizeof(double));
+    free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------- FP32, compensated update
+ *
+ * The state is FP32 values u with, per value, an FP32 compensation term c
+ * that is part of the state (it travels with the point).
+ *
+ * Heat and wave use Kahan's summation for the time update u += delta: with
+ * y = delta - c, t = u + y, the new compensation is c = (t - u) - y (the
+ * negative of the part of y that did not make it into t) and u = t.
+ * Differences of neighbours are formed against the centre first, so for a
+ * smooth field they are exact (Sterbenz).
+ *
+ * Euler keeps the flux and pressure arithmetic in FP64: the compensated value
+ * (double)u + (double)c of every input is formed exactly in FP64, the whole
+ * FP64 update is applied, and the FP64 result t is split back into
+ * u = (float)t and c = (float)(t - (double)u). */
+
+static void st_heat_f32c(const float nu[9][MAXV], const float *cc, float *ou, float *oc, const double *prm)
+{
+    float r = (float)prm[0];
+    float u = nu[4][0];
+    float lap = ((nu[3][0] - u) + (nu[5][0] - u)) + ((nu[1][0] - u) + (nu[7][0] - u));
+    float y = r * lap - cc[0];
+    float t = u + y;
+    oc[0] = (t - u) - y;
+    ou[0] = t;
+}
+
+/* Leapfrog as u' = u + v with v = (u - p) + C2 lap; the compensated previous
+ * difference (u - p) - (c_u - c_p) keeps the velocity accurate. */
+static void st_wave_f32c(const float nu[9][MAXV], const float *cc, float *ou, float *oc, const double *prm)
+{
+    float c2 = (float)prm[0];
+    float u = nu[4][0];
+    float p = nu[4][1];
+    float cu = cc[0], cp = cc[1];
+    float lap = ((nu[3][0] - u) + (nu[5][0] - u)) + ((nu[1][0] - u) + (nu[7][0] - u));
+    float v = ((u - p) - (cu - cp)) + c2 * lap;
+    float y = v - cu;
+    float t = u + y;
+    oc[0] = (t - u) - y;
+    ou[0] = t;
+    ou[1] = u;
+    oc[1] = cu;
+}
+
+static void split_f64(double t, float *u, float *c)
+{
+    float hi = (float)t;
+    *u = hi;
+    *c = (float)(t - (double)hi);
+}
+
+static void st_euler_f32c(long long T, const float nu[9][MAXV], const float nc[9][MAXV], float *ou,
+                          float *oc, const double *prm)
+{
+    double gamma = prm[0], dtoh = prm[1];
+    double nb[9][MAXV];
+    for (int k = 0; k < 9; ++k)
+        for (int v = 0; v < 8; ++v)
+            nb[k][v] = (double)nu[k][v] + (double)nc[k][v];
+    double du[4];
+    if ((T & 1) == 0) {
+        euler_increment(nb, 0, gamma, dtoh, du);
+        for (int k = 0; k < 4; ++k) {
+            ou[k] = nu[4][k];
+            oc[k] = nc[4][k];
+            split_f64(nb[4][k] + du[k], &ou[4 + k], &oc[4 + k]);
+        }
+    } else {
+        euler_increment(nb, 4, gamma, dtoh, du);
+        for (int k = 0; k < 4; ++k) {
+            double v = 0.5 * nb[4][k] + 0.5 * (nb[4][4 + k] + du[k]);
+            split_f64(v, &ou[k], &oc[k]);
+            ou[4 + k] = ou[k];
+            oc[4 + k] = oc[k];
+        }
+    }
+}
+
+/* Advance an FP32-compensated state (u and c planes, each [nvars][ny][nx]).
+ * Only heat, wave and Euler have a compensated form. */
+int oracle_advance_f32c(int pde, int nx, int ny, int nvars, const double *params, int nparams,
+                        float *u, float *c, long long t0, long long nsub, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nsub < 0 || t0 < 0 || !u || !c || !pde_shape_ok(pde, nvars))
+        return -1;
+    if (pde != PDE_HEAT5 && pde != PDE_WAVE_LF && pde != PDE_EULER_RUS_RK2)
+        return -1;
+    if (nparams < nparams_needed(pde) || !params)
+        return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t plane = (size_t)nx * (size_t)ny;
+    size_t tot = plane * (size_t)nvars;
+    float *tu = (float *)malloc(tot * sizeof(float));
+    float *tc = (float *)malloc(tot * sizeof(float));
+    if (!tu || !tc) {
+        free(tu);
+        free(tc);
+        return -3;
+    }
+    float *cu = u, *cc = c, *xu = tu, *xc = tc;
+    for (long long s = 0; s < nsub; ++s) {
+        long long T = t0 + s;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int j = 0; j < ny; ++j) {
+            float nu[9][MAXV], ncp[9][MAXV];
+            float ou[MAXV], oc[MAXV];
+            for (int i = 0; i < nx; ++i) {
+                for (int dj = -1; dj <= 1; ++dj) {
+                    int jj = (j + dj + ny) % ny;
+                    for (int di = -1; di <= 1; ++di) {
+                        int ii = (i + di + nx) % nx;
+                        int k = 3 * (dj + 1) + (di + 1);
+                        for (int v = 0; v < nvars; ++v) {
+                            nu[k][v] = cu[(size_t)v * plane + (size_t)jj * nx + ii];
+                            ncp[k][v] = cc[(size_t)v * plane + (size_t)jj * nx + ii];
+                        }
+                    }
+                }
+                switch (pde) {
+                case PDE_HEAT5: st_heat_f32c(nu, ncp[4], ou, oc, params); break;
+                case PDE_WAVE_LF: st_wave_f32c(nu, ncp[4], ou, oc, params); break;
+                case PDE_EULER_RUS_RK2: st_euler_f32c(T, nu, ncp, ou, oc, params); break;
+                }
+                for (int v = 0; v < nvars; ++v) {
+                    xu[(size_t)v * plane + (size_t)j * nx + i] = ou[v];
+                    xc[(size_t)v * plane + (size_t)j * nx + i] = oc[v];
+                }
+            }
+        }
+        float *t = cu;
+        cu = xu;
+        xu = t;
+        t = cc;
+        cc = xc;
+        xc = t;
+    }
+    if (cu != u) {
+        memcpy(u, cu, tot * sizeof(float));
+        memcpy(c, cc, tot * sizeof(float));
+    }
+    free(tu);
+    free(tc);
+    return 0;
+}

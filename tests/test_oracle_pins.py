@@ -1,0 +1,421 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+CPU only. Each test checks the oracle (``oracle/``) against something other
+than itself: closed forms (von Neumann factors, discrete energy), exact
+arithmetic on small inputs, conservation, symmetry, the worked example of the
+paper (``tests/golden/worked_example.json``) and the paper's Algorithms 1-5
+run literally (``oracle.swept_model``).
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import swept_inputs as si
+from oracle import swept_model as sm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# ------------------------------------------------------------------ heat
+
+@pytest.mark.parametrize("nx,ny,kx,ky,steps", [(32, 16, 3, 2, 50), (64, 64, 8, 1, 200), (16, 48, 1, 7, 30)])
+def test_heat_single_mode_von_neumann(nx, ny, kx, ky, steps):
+    """A Fourier mode is an eigenvector of the 5-point FTCS update with factor
+    G = 1 - 4 r (sin^2(pi kx / nx) + sin^2(pi ky / ny)); nx != ny so that an
+    x/y mix-up changes G."""
+    r = si.HEAT_R
+    u0 = si.heat_single_mode(nx, ny, kx, ky)
+    u = oracle.advance_f64(si.HEAT5, u0, [r], steps)
+    G = 1.0 - 4.0 * r * (math.sin(math.pi * kx / nx) ** 2 + math.sin(math.pi * ky / ny) ** 2)
+    assert np.max(np.abs(u - G ** steps * u0)) < 1e-12
+
+
+def test_heat_eight_modes_superposition():
+    """The 64x64 heat workload (8 seeded modes, 1000 steps) equals the sum of
+    the modes times their amplification factors (linearity)."""
+    nx = ny = 64
+    rng = np.random.default_rng(0)
+    kx = rng.integers(1, 9, size=8)
+    ky = rng.integers(1, 9, size=8)
+    amp = rng.uniform(-1.0, 1.0, size=8)
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=8)
+    u0 = si.heat_field(nx, ny, seed=0)
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    steps = 1000
+    exact = np.zeros((ny, nx))
+    for m in range(8):
+        G = 1.0 - 4.0 * si.HEAT_R * (math.sin(math.pi * kx[m] / nx) ** 2 + math.sin(math.pi * ky[m] / ny) ** 2)
+        exact += amp[m] * G ** steps * np.cos(2 * math.pi * (kx[m] * i / nx + ky[m] * j / ny) + phase[m])
+    u = oracle.advance_f64(si.HEAT5, u0, [si.HEAT_R], steps)[0]
+    assert np.max(np.abs(u - exact)) < 1e-11
+
+
+def test_heat_impulse_response():
+    """One step of a unit impulse gives 1-4r at the centre, r on the four
+    edge neighbours (with periodic wrap) and 0 elsewhere."""
+    nx, ny = 7, 5
+    r = 0.125
+    for (ci, cj) in [(0, 0), (6, 4), (3, 2), (0, 4)]:
+        u0 = np.zeros((1, ny, nx))
+        u0[0, cj, ci] = 1.0
+        u = oracle.advance_f64(si.HEAT5, u0, [r], 1)[0]
+        want = np.zeros((ny, nx))
+        want[cj, ci] = 1 - 4 * r
+        for di, dj in [(-1, 0), (1, 0), (0, -1), (0, 1)]:
+            want[(cj + dj) % ny, (ci + di) % nx] = r
+        assert np.array_equal(u, want)
+
+
+def test_heat_mass_conserved():
+    u0 = si.heat_field(64, 32, seed=4)
+    steps = 300
+    u = oracle.advance_f64(si.HEAT5, u0, [si.HEAT_R], steps)
+    drift = abs(float(u.sum()) - float(u0.sum()))
+    bound = steps * 8 * np.finfo(np.float64).eps * float(np.abs(u0).sum())
+    assert drift < bound
+
+
+def test_heat_exact_dyadic_8x8():
+    """With r = 1/8 and integer data in [-8, 8] every FP64 operation of 15 steps
+    is exact (denominators 8^15 = 2^45, magnitudes <= 8), so the oracle must
+    equal exact rational arithmetic."""
+    rng = np.random.default_rng(11)
+    n = 8
+    u0 = rng.integers(-8, 9, size=(1, n, n)).astype(np.float64)
+    got = oracle.advance_f64(si.HEAT5, u0, [0.125], 15)[0]
+    r = Fraction(1, 8)
+    q = [[Fraction(int(u0[0, j, i])) for i in range(n)] for j in range(n)]
+    for _ in range(15):
+        q = [[q[j][i] + r * (q[j][(i - 1) % n] + q[j][(i + 1) % n] + q[(j - 1) % n][i] + q[(j + 1) % n][i]
+                             - 4 * q[j][i]) for i in range(n)] for j in range(n)]
+    exact = np.array([[float(x) for x in row] for row in q])
+    assert np.array_equal(got, exact)
+
+
+def test_heat_r02_within_rounding_bound():
+    """r = 0.2 is not dyadic: compare with exact rational arithmetic on the
+    FP64 value of 0.2 and bound the rounding error (max norm is non-increasing
+    for r <= 1/4, each step adds at most a few ulps)."""
+    rng = np.random.default_rng(12)
+    n = 8
+    steps = 10
+    u0 = rng.integers(-8, 9, size=(1, n, n)).astype(np.float64)
+    got = oracle.advance_f64(si.HEAT5, u0, [0.2], steps)[0]
+    r = Fraction(0.2)
+    q = [[Fraction(int(u0[0, j, i])) for i in range(n)] for j in range(n)]
+    for _ in range(steps):
+        q = [[q[j][i] + r * (q[j][(i - 1) % n] + q[j][(i + 1) % n] + q[(j - 1) % n][i] + q[(j + 1) % n][i]
+                             - 4 * q[j][i]) for i in range(n)] for j in range(n)]
+    exact = np.array([[float(x) for x in row] for row in q])
+    assert np.max(np.abs(got - exact)) < steps * 16 * 8 * np.finfo(np.float64).eps
+
+
+# ------------------------------------------------------------------ wave
+
+def _lap(u):
+    return (np.roll(u, 1, 1) + np.roll(u, -1, 1) + np.roll(u, 1, 0) + np.roll(u, -1, 0)) - 4.0 * u
+
+
+def test_wave_discrete_energy_conserved():
+    """Leapfrog conserves E = |u^{n+1} - u^n|^2 - C2 <u^{n+1}, L u^n> exactly in
+    exact arithmetic (L symmetric); here to rounding."""
+    s = si.wave_field(64, 48, seed=2, sigma=4.0)
+    energies = []
+    for _ in range(40):
+        s = oracle.advance_f64(si.WAVE_LF, s, [si.WAVE_C2], 5)
+        u, p = s[0], s[1]
+        energies.append(float(np.sum((u - p) ** 2) - si.WAVE_C2 * np.sum(u * _lap(p))))
+    e = np.array(energies)
+    assert e[0] > 1e-3
+    assert np.max(np.abs(e - e[0])) / e[0] < 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,kx,ky", [(32, 24, 2, 3), (64, 64, 5, 1)])
+def test_wave_single_mode_closed_form(nx, ny, kx, ky):
+    """With u^{-1} = u^0 a mode evolves as cos(w (n + 1/2)) / cos(w / 2), where
+    cos w = 1 - 2 C2 (sin^2(pi kx / nx) + sin^2(pi ky / ny))."""
+    u0 = si.heat_single_mode(nx, ny, kx, ky)[0]
+    s = np.stack([u0, u0])
+    steps = 300
+    out = oracle.advance_f64(si.WAVE_LF, s, [si.WAVE_C2], steps)
+    w = math.acos(1.0 - 2.0 * si.WAVE_C2 * (math.sin(math.pi * kx / nx) ** 2 + math.sin(math.pi * ky / ny) ** 2))
+    a = math.cos(w * (steps + 0.5)) / math.cos(w / 2)
+    ap = math.cos(w * (steps - 0.5)) / math.cos(w / 2)
+    assert np.max(np.abs(out[0] - a * u0)) < 1e-11
+    assert np.max(np.abs(out[1] - ap * u0)) < 1e-11
+
+
+def test_wave_previous_level_is_carried():
+    s = si.wave_field(32, 32, seed=1, sigma=3.0)
+    one = oracle.advance_f64(si.WAVE_LF, s, [si.WAVE_C2], 1)
+    two = oracle.advance_f64(si.WAVE_LF, s, [si.WAVE_C2], 2)
+    assert np.array_equal(two[1], one[0])
+    assert np.array_equal(one[1], s[0])
+
+
+def test_wave_momentum_conserved():
+    s = si.wave_field(48, 32, seed=3, sigma=4.0)
+    s[1] = s[0] - 0.01 * np.cos(np.arange(48)[None, :] * 2 * math.pi / 48)
+    m0 = float(np.sum(s[0] - s[1]))
+    out = oracle.advance_f64(si.WAVE_LF, s, [si.WAVE_C2], 200)
+    assert abs(float(np.sum(out[0] - out[1])) - m0) < 1e-11
+
+
+# ----------------------------------------------------------------- euler
+
+def test_euler_uniform_state_preserved_bitwise():
+    s = np.zeros((8, 12, 10))
+    vals = [1.3, 0.7, -0.4, 3.1]
+    for k in range(4):
+        s[k] = vals[k]
+        s[4 + k] = vals[k]
+    out = oracle.advance_f64(si.EULER_RUS_RK2, s, [1.4, 0.05], 20)
+    assert np.array_equal(out, s)
+
+
+def test_euler_conservation_and_positivity():
+    s = si.euler_field(48, 48, seed=0)
+    prm = si.default_params(si.EULER_RUS_RK2, s)
+    out = oracle.advance_f64(si.EULER_RUS_RK2, s, prm, 2 * 40)
+    for k in range(4):
+        t0 = float(np.sum(s[k]))
+        t1 = float(np.sum(out[k]))
+        scale = float(np.sum(np.abs(s[k])))
+        assert abs(t1 - t0) <= 1e-13 * scale
+    rho = out[0]
+    p = 0.4 * (out[3] - 0.5 * (out[1] ** 2 + out[2] ** 2) / rho)
+    assert rho.min() > 0 and p.min() > 0
+    assert np.array_equal(out[4:], out[:4])
+
+
+def test_euler_transpose_symmetry_bitwise():
+    """Swapping x and y (and the two momenta) commutes with the update."""
+    s = si.euler_field(32, 32, seed=5)
+    prm = si.default_params(si.EULER_RUS_RK2, s)
+    t = s.transpose(0, 2, 1).copy()
+    t[[1, 2]] = t[[2, 1]]
+    t[[5, 6]] = t[[6, 5]]
+    a = oracle.advance_f64(si.EULER_RUS_RK2, s, prm, 6)
+    b = oracle.advance_f64(si.EULER_RUS_RK2, t, prm, 6)
+    b = b.transpose(0, 2, 1).copy()
+    b[[1, 2]] = b[[2, 1]]
+    b[[5, 6]] = b[[6, 5]]
+    assert np.array_equal(a, b)
+
+
+def test_euler_vortex_advects_with_the_flow():
+    """One isentropic vortex on a (1, 1) stream moves by (t, t): the density
+    minimum after time t sits within a cell of its start shifted by t."""
+    nx = 64
+    s = si.euler_field(nx, nx, seed=0, vortices=1)
+    prm = si.default_params(si.EULER_RUS_RK2, s)
+    h = si.EULER_SIDE / nx
+    dt = prm[1] * h
+    steps = 60
+    out = oracle.advance_f64(si.EULER_RUS_RK2, s, prm, 2 * steps)
+
+    def centre(rho):
+        j, i = np.unravel_index(np.argmin(rho), rho.shape)
+        return (i + 0.5) * h, (j + 0.5) * h
+
+    x0, y0 = centre(s[0])
+    x1, y1 = centre(out[0])
+    dist = steps * dt
+    L = si.EULER_SIDE
+    ex = (x1 - x0 - dist + L / 2) % L - L / 2
+    ey = (y1 - y0 - dist + L / 2) % L - L / 2
+    assert dist > 3 * h
+    assert abs(ex) <= 1.01 * h and abs(ey) <= 1.01 * h
+
+
+# ----------------------------------------------------------- test stencils
+
+def test_push5_two_substeps_equal_wide_stencil():
+    """Eq. (2)-(3) reproduce Eq. (1) bit for bit (same values, same order)."""
+    s = si.push5_field(24, 20, seed=7)
+    s[0] = np.random.default_rng(7).standard_normal((20, 24))
+    out = oracle.advance_f64(si.TEST_PUSH5, s, [], 2)
+    u = s[0]
+    wide = (np.roll(u, 2, 1) + np.roll(u, -2, 1)) + np.roll(u, 2, 0)
+    wide = wide + np.roll(u, -2, 0)
+    wide = wide - 4.0 * u
+    assert np.array_equal(out[0], wide)
+    assert not np.any(out[1:])
+
+
+def test_hash_is_local_and_position_sensitive():
+    """One step of the hash stencil changes exactly the 3x3 neighbourhood of a
+    changed input, and swapping two inputs of a neighbourhood changes the
+    output."""
+    s = si.hash_field(9, 7, seed=1)
+    base = oracle.advance_f64(si.TEST_HASH, s, [], 1, t0=3)
+    t = s.copy()
+    t[0, 0, 0] += 1.0
+    moved = oracle.advance_f64(si.TEST_HASH, t, [], 1, t0=3)
+    diff = moved[0] != base[0]
+    want = np.zeros_like(diff)
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            want[dj % 7, di % 9] = True
+    assert np.array_equal(diff, want)
+    w = s.copy()
+    w[0, 3, 3], w[0, 3, 4] = s[0, 3, 4], s[0, 3, 3]
+    swapped = oracle.advance_f64(si.TEST_HASH, w, [], 1, t0=3)
+    assert swapped[0, 3, 3] != base[0, 3, 3]
+    other_level = oracle.advance_f64(si.TEST_HASH, s, [], 1, t0=4)
+    assert np.all(other_level != base)
+    assert np.all(base < 2.0 ** 52) and np.all(base == np.floor(base))
+
+
+def test_incr_every_value_equals_its_level():
+    s = si.incr_field(12, 10)
+    out = oracle.advance_f64(si.TEST_INCR, s, [], 17)
+    assert np.all(out == 18.0)
+    s[0, 4, 4] = 5.0
+    out = oracle.advance_f64(si.TEST_INCR, s, [], 1)
+    assert np.isnan(out[0, 4, 4]) and np.isnan(out[0, 3, 5]) and out[0, 0, 0] == 2.0
+
+
+# ------------------------------------------------------------------ FP32C
+
+def _norm_rel(a, ref):
+    return max(float(np.max(np.abs(a[v] - ref[v])) / np.max(np.abs(ref[v]))) for v in range(ref.shape[0]))
+
+
+def test_f32c_heat_exact_when_fp32_is_exact():
+    """Integer data, r = 1/8, 6 steps: every FP32 operation is exact, so the
+    compensated stepper equals the FP64 oracle and every compensation is 0."""
+    rng = np.random.default_rng(3)
+    u0 = rng.integers(-8, 9, size=(1, 8, 8)).astype(np.float64)
+    u, c = oracle.split_f32c(u0)
+    u6, c6 = oracle.advance_f32c(si.HEAT5, u, c, [0.125], 6)
+    ref = oracle.advance_f64(si.HEAT5, u0, [0.125], 6)
+    assert np.array_equal(u6.astype(np.float64), ref)
+    assert not np.any(c6)
+
+
+def test_f32c_heat_error_and_benefit():
+    """Compensated FP32 stays within 1e-6 (normwise, per variable) of FP64 and
+    beats plain FP32 (the same stepper with the compensation reset every step).
+    256^2 keeps the field from decaying below the FP32 floor of its initial
+    rounding within 2000 steps."""
+    s = si.heat_field(256, 256, seed=0)
+    steps = 2000
+    ref = oracle.advance_f64(si.HEAT5, s, [si.HEAT_R], steps)
+    u, c = oracle.split_f32c(s)
+    uc, _ = oracle.advance_f32c(si.HEAT5, u, c, [si.HEAT_R], steps)
+    err_c = _norm_rel(uc.astype(np.float64), ref)
+    up = u.copy()
+    for _ in range(steps):
+        up, _ = oracle.advance_f32c(si.HEAT5, up, np.zeros_like(up), [si.HEAT_R], 1, threads=1)
+    err_p = _norm_rel(up.astype(np.float64), ref)
+    assert err_c < 1e-6
+    assert err_c < 0.3 * err_p
+
+
+def test_f32c_wave_error():
+    s = si.wave_field(64, 64, seed=0, sigma=6.0)
+    steps = 500
+    ref = oracle.advance_f64(si.WAVE_LF, s, [si.WAVE_C2], steps)
+    u, c = oracle.split_f32c(s)
+    uc, _ = oracle.advance_f32c(si.WAVE_LF, u, c, [si.WAVE_C2], steps)
+    assert _norm_rel(uc.astype(np.float64), ref) < 1e-6
+
+
+def test_f32c_euler_error():
+    s = si.euler_field(32, 32, seed=1)
+    prm = si.default_params(si.EULER_RUS_RK2, s)
+    steps = 50
+    ref = oracle.advance_f64(si.EULER_RUS_RK2, s, prm, 2 * steps)
+    u, c = oracle.split_f32c(s)
+    uc, cc = oracle.advance_f32c(si.EULER_RUS_RK2, u, c, prm, 2 * steps)
+    got = uc.astype(np.float64) + cc.astype(np.float64)
+    assert _norm_rel(got[:4], ref[:4]) < 1e-6
+
+
+# ------------------------------------------- the paper's algorithms, literally
+
+@pytest.mark.parametrize("nx,ny,n", [(16, 16, 8), (8, 8, 8), (16, 16, 4), (24, 16, 8), (12, 12, 4), (8, 12, 2)])
+def test_algorithms_1_to_5_equal_plain_stepping(nx, ny, n):
+    """Every half cycle of Algorithm 5 (with the readings of the printed index
+    ranges) lands on the plain result; the hash stencil makes any misplaced
+    neighbour or level visible."""
+    g = si.hash_field(nx, ny, seed=3)
+    got = {}
+    sm.swept2d(sm.st_hash, g[0], n, cycles=2, T0=5, after_half=lambda T, grid: got.__setitem__(T, grid))
+    assert sorted(got) == [5 + k * (n // 2) for k in range(1, 5)]
+    for T, grid in got.items():
+        ref = oracle.advance_f64(si.TEST_HASH, g, [], T - 5, t0=5)[0]
+        assert np.array_equal(grid, ref)
+
+
+def test_algorithms_heat_equal_plain_stepping():
+    g = si.heat_field(16, 24, seed=2)
+    out = sm.swept2d(sm.st_heat(si.HEAT_R), g[0], 8, cycles=2)
+    assert np.array_equal(out, oracle.advance_f64(si.HEAT5, g, [si.HEAT_R], 16)[0])
+
+
+@pytest.mark.parametrize("flag", ["LITERAL_BRIDGE_LOOP", "LITERAL_LAT_OUTPUTS"])
+def test_printed_ranges_do_not_reproduce_plain_stepping(flag, monkeypatch):
+    monkeypatch.setattr(sm, flag, True)
+    g = si.hash_field(16, 16, seed=3)
+    out = sm.swept2d(sm.st_hash, g[0], 8, cycles=1)
+    assert not np.array_equal(out, oracle.advance_f64(si.TEST_HASH, g, [], 8)[0])
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+def test_component_sizes(n):
+    """Points computed per tile and half cycle: up n(n-1)(n-2)/6, each bridge
+    (n^3-4n)/12, down n(n+1)(n+2)/6; together n^2 * n/2 (Sec. 5: a half cycle
+    performs n/2 sub-steps on n^2 points)."""
+    nx = ny = 2 * n
+    st = sm.Stats()
+    sm.swept2d(sm.st_hash, si.hash_field(nx, ny)[0], n, cycles=1, stats=st)
+    tiles_halves = (nx // n) * (ny // n) * 2
+    assert st.computed["up"] == tiles_halves * n * (n - 1) * (n - 2) // 6
+    assert st.computed["long"] == tiles_halves * (n ** 3 - 4 * n) // 12
+    assert st.computed["lat"] == tiles_halves * (n ** 3 - 4 * n) // 12
+    assert st.computed["down"] == tiles_halves * n * (n + 1) * (n + 2) // 6
+    assert sum(st.computed.values()) == tiles_halves * n * n * (n // 2)
+
+
+def test_worked_example_values():
+    gold = json.load(open(GOLDEN))
+    n = gold["upward_panel_values_per_level"]["n"]
+    st = sm.Stats()
+    base = np.ones((n, n))
+    N, S, W, E = sm.upward_pyramid(sm.st_incr, base, 0, st)
+    assert [p.size for p in N] == gold["upward_panel_values_per_level"]["values"]
+    assert [p.size for p in S] == [p.size for p in W] == [p.size for p in E] == [p.size for p in N]
+    # Every value equals its level; the last panel level is the 2x2 tip.
+    start = gold["pyramid_tip_level"]["start_level"]
+    base = np.full((n, n), float(start))
+    N, S, W, E = sm.upward_pyramid(sm.st_incr, base, 0)
+    for k, p in enumerate(N):
+        assert np.all(p == start + k)
+    assert N[-1].shape == (2, 2) and N[-1][0, 0] == gold["pyramid_tip_level"]["tip_level"]
+    # A full cycle on 8x8 subdomains advances 8 levels with 4 communications.
+    cyc = gold["cycle"]
+    st = sm.Stats()
+    out = sm.swept2d(sm.st_incr, np.full((2 * n, 2 * n), float(cyc["start_level"])), cyc["n"], cycles=1, stats=st)
+    assert np.all(out == cyc["start_level"] + cyc["levels_advanced"])
+    assert st.exchanges == cyc["communications"]
+    # The downward pyramid computes squares of side 2, 4, ..., n.
+    sq = gold["downward_first_square"]["computed_squares"]
+    assert sum(s * s for s in sq) == n * (n + 1) * (n + 2) // 6
+    half = gold["half_cycle_substeps"]
+    got = {}
+    sm.swept2d(sm.st_incr, np.ones((2 * n, 2 * n)), half["n"], cycles=1,
+               after_half=lambda T, grid: got.__setitem__(T, grid))
+    assert sorted(got)[0] == half["substeps"]
+    assert np.all(got[half["substeps"]] == 1 + half["substeps"])
