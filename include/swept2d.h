@@ -1,0 +1,211 @@
+/*
+ * swept2d.h - C ABI of the MI355X (gfx950) swept-rule stencil library.
+ *
+ * The library advances explicit two-dimensional stencil schemes on a doubly
+ * periodic, logically Cartesian grid (Sec. 2, assumption 1). Every sub-step
+ * computes each point from its 3x3 neighbourhood one level below (Sec. 2,
+ * assumption 2); a scheme may take several sub-steps per time step (Sec. 2,
+ * Eq. (1)-(3)). The library runs such schemes two ways:
+ *
+ *   swept2d_advance        the swept rule of space-time decomposition
+ *                          (Sec. 3-4, Algorithms 1-5): square tiles of side n
+ *                          build upward pyramids, then the latitudinal and
+ *                          longitudinal bridges, then downward pyramids, n/2
+ *                          levels per half cycle, exchanging only the
+ *                          pyramids' and bridges' triangular sides (panels).
+ *                          On one GPU a panel exchange is an HBM round trip
+ *                          between kernels instead of a network message.
+ *   swept2d_plain_advance  the classical per-step method: one kernel launch
+ *                          per sub-step (the "latency barrier" of Sec. 5).
+ *
+ * Both compute exactly the same values: the swept rule does no redundant work
+ * and gives every point its complete 3x3 neighbourhood from the level below
+ * (abstract; Sec. 4).
+ *
+ * Conventions for every call:
+ *   - Return 0 on success or a negative SWEPT2D_E* code. The thread-local
+ *     message of the last failure is available from swept2d_last_error().
+ *   - Calls that launch GPU work are asynchronous on the handle's stream.
+ *     A kernel fault is reported by swept2d_synchronize, swept2d_download or
+ *     the next call that checks the stream.
+ *   - No C++ exception crosses this interface.
+ *   - A handle is not thread safe: one thread at a time per handle.
+ *
+ * State layout (device and host): structure of arrays [nvars][ny][nx], x
+ * fastest, row j = 0 is the north edge. The paper's point (i, j) is
+ * state[v][j][i].
+ */
+#ifndef SWEPT2D_H
+#define SWEPT2D_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define SWEPT2D_OK 0
+#define SWEPT2D_EINVAL (-1)       /* bad argument: sizes, ids, tile, null handle */
+#define SWEPT2D_EHIP (-2)         /* HIP runtime error; message carries hipGetErrorString */
+#define SWEPT2D_ENOMEM (-3)       /* device allocation failed */
+#define SWEPT2D_EUNSUPPORTED (-4) /* valid request this build does not provide */
+
+/* ------------------------------------------------------------- scheme ids
+ * Built-in per-point sub-step operations (the paper's timestep(i, p)
+ * callback of Sec. 6, compiled in). nvars / substeps each must take:
+ *   HEAT5          1 / 1  u' = u + r lap(u), 5-point Laplacian; params {r}
+ *   WAVE_LF        2 / 1  leapfrog, (u, u_prev) -> ((2u - u_prev) + C2 lap(u), u);
+ *                         params {C2}
+ *   EULER_RUS_RK2  8 / 2  compressible Euler, first-order finite volumes with
+ *                         the Rusanov flux, two-stage SSP Runge-Kutta; slots
+ *                         0..3 conserved (rho, rho u, rho v, E), 4..7 the
+ *                         stage; params {gamma, dt/h}
+ *   TEST_HASH      1 / 1  order-sensitive 64-bit mix of the 9 neighbours and
+ *                         the sub-step index (values: integers < 2^52)
+ *   TEST_INCR      1 / 1  u' = u + 1 if all 9 neighbours equal u, else NaN
+ *                         (the worked example of Sec. 3.1)
+ *   TEST_PUSH5     5 / 2  Eq. (2) then Eq. (3): the 2-ring stencil of Eq. (1)
+ *                         decomposed into nearest-neighbour sub-steps */
+#define SWEPT2D_HEAT5 1
+#define SWEPT2D_WAVE_LF 2
+#define SWEPT2D_EULER_RUS_RK2 3
+#define SWEPT2D_TEST_HASH 100
+#define SWEPT2D_TEST_INCR 101
+#define SWEPT2D_TEST_PUSH5 102
+
+/* ------------------------------------------------------------- precisions
+ * FP64:  one double per value.
+ * FP32C: FP32 value u plus an FP32 compensation c per value (the pair stands
+ *        for u - c); the time update is compensated (Kahan), Euler fluxes and
+ *        pressure are evaluated in FP64. Available for HEAT5, WAVE_LF and
+ *        EULER_RUS_RK2. Device layout: nvars u-planes then nvars c-planes,
+ *        each [ny][nx] float. */
+#define SWEPT2D_FP64 0
+#define SWEPT2D_FP32C 1
+
+/* ---------------------------------------------------------- launch modes
+ * DIRECT: every kernel is launched with hipLaunchKernel.
+ * GRAPH:  the launch sequence of an advance is captured once into a HIP
+ *         graph (per distinct step count) and replayed. */
+#define SWEPT2D_LAUNCH_DIRECT 0
+#define SWEPT2D_LAUNCH_GRAPH 1
+
+/* ------------------------------------------------------- panel staging
+ * AUTO: a bridge or downward-pyramid workgroup copies all the panel levels it
+ *       consumes into LDS when it starts, if they fit beside its window.
+ * OFF:  every workgroup fetches each level's panels one level ahead. */
+#define SWEPT2D_STAGING_AUTO 0
+#define SWEPT2D_STAGING_OFF 1
+
+typedef struct swept2d swept2d; /* opaque, owned by the library */
+
+/* Create a handle for an nx by ny periodic grid (Sec. 2) with nvars values
+ * per point and `substeps` sub-steps per time step, for scheme `pde`.
+ * Uses the current HIP device and a stream of its own (created with
+ * hipStreamNonBlocking); allocates and zeroes a library-owned FP64 state.
+ * The tile side starts at the size the built-in tuner picks
+ * (swept2d_set_tile(h, 0)).
+ * Returns NULL on error (bad sizes, nvars/substeps not matching pde, nx or ny
+ * below 2, no device, out of memory); see swept2d_last_error(). */
+swept2d *swept2d_create(int nx, int ny, int nvars, int pde, int substeps);
+
+/* Free all library-owned device memory, graphs and events. A bound state
+ * (swept2d_bind) belongs to the caller and is not freed. Waits for the
+ * handle's stream first. NULL is accepted and ignored. */
+void swept2d_destroy(swept2d *h);
+
+/* Set the scheme's physical parameters (see the scheme list). np must be at
+ * least the number the scheme uses; p is copied. EINVAL otherwise. */
+int swept2d_set_params(swept2d *h, const double *p, int np);
+
+/* Select FP64 or FP32C. Reallocates a library-owned state (zeroed); fails
+ * with EINVAL while a caller buffer is bound, EUNSUPPORTED for schemes
+ * without an FP32C form. */
+int swept2d_set_precision(swept2d *h, int prec);
+
+/* Tile side n of the swept decomposition (Sec. 3: square subdomains of side
+ * n; a half cycle advances n/2 levels). n must be even, at least 2, divide nx
+ * and ny, and fit the tile's working set in one workgroup's LDS. n = 0 lets
+ * the built-in tuner choose (cost model of Sec. 5, Eq. (4)-(5), constrained
+ * by LDS size and compute-unit count). EINVAL if n is not usable. */
+int swept2d_set_tile(swept2d *h, int n);
+
+/* Current tile side. */
+int swept2d_get_tile(const swept2d *h);
+
+/* Use a caller-owned device buffer as the state and a caller stream for all
+ * launches. dev_state must hold swept2d_state_bytes(h) bytes in the layout
+ * of the handle's precision and stay valid until the handle is destroyed or
+ * rebound. hip_stream is a hipStream_t; NULL selects the library's own
+ * stream. Passing dev_state = NULL returns to a library-owned state
+ * (zeroed). */
+int swept2d_bind(swept2d *h, void *dev_state, void *hip_stream);
+
+/* Bytes of the device state: nvars*nx*ny*8 for both precisions (FP32C keeps
+ * 4-byte u and 4-byte c per value). */
+size_t swept2d_state_bytes(const swept2d *h);
+
+/* Copy a host FP64 state [nvars][ny][nx] in (synchronous). FP32C stores
+ * u = (float)x and c = 0. */
+int swept2d_upload(swept2d *h, const double *host);
+
+/* Copy the state out as FP64 [nvars][ny][nx] (synchronous; waits for the
+ * stream). FP32C returns (double)u - (double)c. */
+int swept2d_download(swept2d *h, double *host);
+
+/* Copy the raw device state (swept2d_state_bytes bytes, precision layout)
+ * in or out (synchronous). */
+int swept2d_upload_raw(swept2d *h, const void *host);
+int swept2d_download_raw(swept2d *h, void *host);
+
+/* Advance nsteps full time steps (nsteps * substeps sub-steps) with the
+ * swept rule (Algorithm 5): an initial upward pyramid per tile, then for
+ * every half cycle the bridges and the downward pyramid fused with the next
+ * upward pyramid (an octahedron), the tiling shifting by n/2 in x and y each
+ * half cycle; a remainder shorter than n/2 sub-steps is run as a half cycle
+ * of reduced height. On return (after the stream completes) the state holds
+ * every point at one level, in global coordinates. Results are bitwise equal
+ * to swept2d_plain_advance. nsteps = 0 is a no-op; EINVAL if negative. */
+int swept2d_advance(swept2d *h, long long nsteps);
+
+/* Advance nsteps full time steps with one kernel launch per sub-step, the
+ * classical per-step method (Sec. 5; the comparison baseline of Sec. 7-8). */
+int swept2d_plain_advance(swept2d *h, long long nsteps);
+
+/* Wait for the handle's stream; reports a pending kernel fault as EHIP. */
+int swept2d_synchronize(swept2d *h);
+
+/* Global sub-step counter T: the level of the state, counted in sub-steps
+ * since creation (or since the last swept2d_set_substep_counter). The
+ * scheme applied at level T is sub-step T mod substeps, so checkpoint and
+ * resume save and restore T with the state. set: EINVAL if T < 0 or not a
+ * multiple of substeps. */
+long long swept2d_substep_counter(const swept2d *h);
+int swept2d_set_substep_counter(swept2d *h, long long T);
+
+/* Launch mode (SWEPT2D_LAUNCH_DIRECT or SWEPT2D_LAUNCH_GRAPH). */
+int swept2d_set_launch_mode(swept2d *h, int mode);
+
+/* Panel staging mode (SWEPT2D_STAGING_AUTO or SWEPT2D_STAGING_OFF). Both
+ * modes give identical results. */
+int swept2d_set_staging(swept2d *h, int mode);
+
+/* Per-kernel timing. While on, every kernel the handle launches is bracketed
+ * by HIP events on the handle's stream. get writes up to cap records of
+ * {kind, launches, total_ms, work_points} (4 doubles each, kind: 0 plain,
+ * 1 upward pyramid, 2 bridges, 3 octahedron / downward pyramid) and returns
+ * the number of records; it synchronizes the stream. Turning timing on
+ * clears the records. work_points counts the space-time points the kernels
+ * of that kind computed. */
+int swept2d_set_timing(swept2d *h, int on);
+int swept2d_get_timing(swept2d *h, double *out, int cap);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *swept2d_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEPT2D_H */

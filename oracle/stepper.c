@@ -283,9 +283,11 @@ int oracle_advance_f64(int pde, int nx, int ny, int nvars, const double *params,
  * smooth field they are exact (Sterbenz).
  *
  * Euler keeps the flux and pressure arithmetic in FP64: the compensated value
- * (double)u + (double)c of every input is formed exactly in FP64, the whole
+ * (double)u - (double)c of every input is formed exactly in FP64, the whole
  * FP64 update is applied, and the FP64 result t is split back into
- * u = (float)t and c = (float)(t - (double)u). */
+ * u = (float)t and c = (float)((double)u - t).
+ *
+ * In all three the pair (u, c) stands for the value u - c. */
 
 static void st_heat_f32c(const float nu[9][MAXV], const float *cc, float *ou, float *oc, const double *prm)
 {
@@ -320,7 +322,7 @@ static void split_f64(double t, float *u, float *c)
 {
     float hi = (float)t;
     *u = hi;
-    *c = (float)(t - (double)hi);
+    *c = (float)((double)hi - t);
 }
 
 static void st_euler_f32c(long long T, const float nu[9][MAXV], const float nc[9][MAXV], float *ou,
@@ -330,7 +332,7 @@ static void st_euler_f32c(long long T, const float nu[9][MAXV], const float nc[9
     double nb[9][MAXV];
     for (int k = 0; k < 9; ++k)
         for (int v = 0; v < 8; ++v)
-            nb[k][v] = (double)nu[k][v] + (double)nc[k][v];
+            nb[k][v] = (double)nu[k][v] - (double)nc[k][v];
     double du[4];
     if ((T & 1) == 0) {
         euler_increment(nb, 0, gamma, dtoh, du);

@@ -1,0 +1,334 @@
+"""Python binding of the swept2d HIP library (gfx950).
+
+Argument marshalling only: every step of the stencil path runs in the HIP
+kernels of ``libswept2d.so`` (built in place by ``build.py``). There is no
+CPU fallback: importing works without a GPU, but every call that needs the
+library raises if it is not built, and every call that needs a device fails
+with the library's own error.
+
+The functions carry the names of the C ABI in ``include/swept2d.h``;
+``Swept2D`` wraps a handle for convenience and can bind a torch CUDA tensor as
+the state (torch is used for device memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LIB_PATH = _build.LIB
+
+OK = 0
+EINVAL = -1
+EHIP = -2
+ENOMEM = -3
+EUNSUPPORTED = -4
+
+HEAT5 = 1
+WAVE_LF = 2
+EULER_RUS_RK2 = 3
+TEST_HASH = 100
+TEST_INCR = 101
+TEST_PUSH5 = 102
+
+FP64 = 0
+FP32C = 1
+
+LAUNCH_DIRECT = 0
+LAUNCH_GRAPH = 1
+
+STAGING_AUTO = 0
+STAGING_OFF = 1
+
+KIND_NAMES = {0: "plain", 1: "up", 2: "bridge", 3: "oct"}
+
+EXPORTS = [
+    "swept2d_create", "swept2d_destroy", "swept2d_set_params", "swept2d_set_precision",
+    "swept2d_set_tile", "swept2d_get_tile", "swept2d_bind", "swept2d_state_bytes",
+    "swept2d_upload", "swept2d_download", "swept2d_upload_raw", "swept2d_download_raw",
+    "swept2d_advance", "swept2d_plain_advance", "swept2d_synchronize",
+    "swept2d_substep_counter", "swept2d_set_substep_counter", "swept2d_set_launch_mode",
+    "swept2d_set_staging",
+    "swept2d_set_timing", "swept2d_get_timing", "swept2d_last_error",
+]
+
+_lib = None
+
+
+class Swept2DError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"swept2d error {code}: {msg}")
+        self.code = code
+
+
+def load_library():
+    """Load libswept2d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1602_07558_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, ll, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double
+    sig = {
+        "swept2d_create": (vp, [i, i, i, i, i]),
+        "swept2d_destroy": (None, [vp]),
+        "swept2d_set_params": (i, [vp, ctypes.POINTER(d), i]),
+        "swept2d_set_precision": (i, [vp, i]),
+        "swept2d_set_tile": (i, [vp, i]),
+        "swept2d_get_tile": (i, [vp]),
+        "swept2d_bind": (i, [vp, vp, vp]),
+        "swept2d_state_bytes": (ctypes.c_size_t, [vp]),
+        "swept2d_upload": (i, [vp, vp]),
+        "swept2d_download": (i, [vp, vp]),
+        "swept2d_upload_raw": (i, [vp, vp]),
+        "swept2d_download_raw": (i, [vp, vp]),
+        "swept2d_advance": (i, [vp, ll]),
+        "swept2d_plain_advance": (i, [vp, ll]),
+        "swept2d_synchronize": (i, [vp]),
+        "swept2d_substep_counter": (ll, [vp]),
+        "swept2d_set_substep_counter": (i, [vp, ll]),
+        "swept2d_set_launch_mode": (i, [vp, i]),
+        "swept2d_set_staging": (i, [vp, i]),
+        "swept2d_set_timing": (i, [vp, i]),
+        "swept2d_get_timing": (i, [vp, ctypes.POINTER(d), i]),
+        "swept2d_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def swept2d_last_error() -> str:
+    return load_library().swept2d_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise Swept2DError(rc, swept2d_last_error())
+    return rc
+
+
+def swept2d_create(nx: int, ny: int, nvars: int, pde: int, substeps: int) -> int:
+    h = load_library().swept2d_create(nx, ny, nvars, pde, substeps)
+    if not h:
+        raise Swept2DError(EINVAL, swept2d_last_error())
+    return h
+
+
+def swept2d_destroy(h: int) -> None:
+    load_library().swept2d_destroy(h)
+
+
+def swept2d_set_params(h: int, params) -> int:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    return _check(load_library().swept2d_set_params(
+        h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(p.size)))
+
+
+def swept2d_set_precision(h: int, prec: int) -> int:
+    return _check(load_library().swept2d_set_precision(h, prec))
+
+
+def swept2d_set_tile(h: int, n: int) -> int:
+    return _check(load_library().swept2d_set_tile(h, n))
+
+
+def swept2d_get_tile(h: int) -> int:
+    return _check(load_library().swept2d_get_tile(h))
+
+
+def swept2d_bind(h: int, dev_ptr: int | None, stream: int | None) -> int:
+    return _check(load_library().swept2d_bind(h, dev_ptr or None, stream or None))
+
+
+def swept2d_state_bytes(h: int) -> int:
+    return int(load_library().swept2d_state_bytes(h))
+
+
+def swept2d_upload(h: int, host: np.ndarray) -> int:
+    a = np.ascontiguousarray(host, dtype=np.float64)
+    return _check(load_library().swept2d_upload(h, a.ctypes.data))
+
+
+def swept2d_download(h: int, host: np.ndarray) -> int:
+    assert host.dtype == np.float64 and host.flags.c_contiguous
+    return _check(load_library().swept2d_download(h, host.ctypes.data))
+
+
+def swept2d_upload_raw(h: int, host: np.ndarray) -> int:
+    a = np.ascontiguousarray(host)
+    if a.nbytes != swept2d_state_bytes(h):
+        raise ValueError("raw state has the wrong size")
+    return _check(load_library().swept2d_upload_raw(h, a.ctypes.data))
+
+
+def swept2d_download_raw(h: int, host: np.ndarray) -> int:
+    assert host.flags.c_contiguous and host.nbytes == swept2d_state_bytes(h)
+    return _check(load_library().swept2d_download_raw(h, host.ctypes.data))
+
+
+def swept2d_advance(h: int, nsteps: int) -> int:
+    return _check(load_library().swept2d_advance(h, nsteps))
+
+
+def swept2d_plain_advance(h: int, nsteps: int) -> int:
+    return _check(load_library().swept2d_plain_advance(h, nsteps))
+
+
+def swept2d_synchronize(h: int) -> int:
+    return _check(load_library().swept2d_synchronize(h))
+
+
+def swept2d_substep_counter(h: int) -> int:
+    return _check(load_library().swept2d_substep_counter(h))
+
+
+def swept2d_set_substep_counter(h: int, T: int) -> int:
+    return _check(load_library().swept2d_set_substep_counter(h, T))
+
+
+def swept2d_set_launch_mode(h: int, mode: int) -> int:
+    return _check(load_library().swept2d_set_launch_mode(h, mode))
+
+
+def swept2d_set_staging(h: int, mode: int) -> int:
+    return _check(load_library().swept2d_set_staging(h, mode))
+
+
+def swept2d_set_timing(h: int, on: bool) -> int:
+    return _check(load_library().swept2d_set_timing(h, 1 if on else 0))
+
+
+def swept2d_get_timing(h: int) -> list[dict]:
+    buf = (ctypes.c_double * 16)()
+    k = _check(load_library().swept2d_get_timing(h, buf, 4))
+    out = []
+    for r in range(k):
+        kind = int(buf[4 * r])
+        out.append({"kind": KIND_NAMES.get(kind, str(kind)), "launches": int(buf[4 * r + 1]),
+                    "ms": float(buf[4 * r + 2]), "points": float(buf[4 * r + 3])})
+    return out
+
+
+PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), TEST_HASH: (1, 1),
+             TEST_INCR: (1, 1), TEST_PUSH5: (5, 2)}
+
+
+class Swept2D:
+    """Owner of one swept2d handle."""
+
+    def __init__(self, nx: int, ny: int, pde: int, params=None, prec: int = FP64, tile: int = 0):
+        nvars, sub = PDE_SHAPE[pde]
+        self.nx, self.ny, self.pde, self.nvars, self.substeps = nx, ny, pde, nvars, sub
+        self.h = swept2d_create(nx, ny, nvars, pde, sub)
+        try:
+            if params is not None and len(params):
+                swept2d_set_params(self.h, params)
+            if prec != FP64:
+                swept2d_set_precision(self.h, prec)
+            if tile:
+                swept2d_set_tile(self.h, tile)
+        except Exception:
+            self.close()
+            raise
+        self.prec = prec
+
+    def close(self):
+        if getattr(self, "h", None):
+            swept2d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def tile(self) -> int:
+        return swept2d_get_tile(self.h)
+
+    @tile.setter
+    def tile(self, n: int):
+        swept2d_set_tile(self.h, n)
+
+    def upload(self, state: np.ndarray):
+        assert state.shape == (self.nvars, self.ny, self.nx)
+        swept2d_upload(self.h, state)
+
+    def download(self) -> np.ndarray:
+        out = np.empty((self.nvars, self.ny, self.nx), dtype=np.float64)
+        swept2d_download(self.h, out)
+        return out
+
+    def raw_shape(self):
+        if self.prec == FP64:
+            return (self.nvars, self.ny, self.nx), np.float64
+        return (2 * self.nvars, self.ny, self.nx), np.float32
+
+    def upload_raw(self, a: np.ndarray):
+        swept2d_upload_raw(self.h, a)
+
+    def download_raw(self) -> np.ndarray:
+        shape, dt = self.raw_shape()
+        out = np.empty(shape, dtype=dt)
+        swept2d_download_raw(self.h, out)
+        return out
+
+    def bind_tensor(self, t, stream=None):
+        """Use a torch CUDA tensor as the state (and torch's current stream)."""
+        import torch
+        shape, dt = self.raw_shape()
+        tdt = torch.float64 if dt == np.float64 else torch.float32
+        if tuple(t.shape) != shape or t.dtype != tdt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"state tensor must be a contiguous CUDA {tdt} tensor of shape {shape}")
+        s = stream if stream is not None else torch.cuda.current_stream(t.device)
+        swept2d_bind(self.h, t.data_ptr(), s.cuda_stream)
+        self._bound = t
+
+    def unbind(self):
+        swept2d_bind(self.h, None, None)
+        self._bound = None
+
+    def advance(self, nsteps: int):
+        swept2d_advance(self.h, nsteps)
+
+    def plain_advance(self, nsteps: int):
+        swept2d_plain_advance(self.h, nsteps)
+
+    def synchronize(self):
+        swept2d_synchronize(self.h)
+
+    @property
+    def T(self) -> int:
+        return swept2d_substep_counter(self.h)
+
+    @T.setter
+    def T(self, v: int):
+        swept2d_set_substep_counter(self.h, v)
+
+    def set_launch_mode(self, mode: int):
+        swept2d_set_launch_mode(self.h, mode)
+
+    def set_staging(self, mode: int):
+        swept2d_set_staging(self.h, mode)
+
+    def set_timing(self, on: bool):
+        swept2d_set_timing(self.h, on)
+
+    def timing(self) -> list[dict]:
+        return swept2d_get_timing(self.h)

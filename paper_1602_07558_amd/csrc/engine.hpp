@@ -1,0 +1,148 @@
+// Launch descriptors shared by the kernels (swept2d_kernels.hip) and the
+// host planner (swept2d_api.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "schemes.hpp"
+
+namespace swept {
+
+constexpr int kThreads = 512;  // threads per workgroup of every stage kernel (8 waves)
+constexpr int kWaves = kThreads / 64;
+
+// Geometry of one half cycle of the swept decomposition.
+//
+// Tiles are n x n squares, n = 2h, whose north-west points sit at
+// (off + a n, off + b n) modulo (nx, ny), a < ntx = nx/n, b < nty = ny/n; off is
+// 0 or h and alternates between half cycles (Sec. 4: each half cycle shifts
+// the arrangement by half a tile). Level l of the half cycle is global
+// sub-step level T0 + l.
+//
+// Within a half cycle of height H (H = h for a full one, H < h only for the
+// last, reduced one), with dx, dy the distance of a point to the nearest
+// tile edge in x and y (0 on the outermost ring of the tile), level l in
+// 1..H of the point is computed by
+//   the upward pyramid          if dx >= l and dy >= l,
+//   the bridge across an x-edge if dx <  l and dy >= l  (x-bridge),
+//   the bridge across a y-edge  if dx >= l and dy <  l  (y-bridge),
+//   the downward pyramid        if dx <  l and dy <  l.
+// For H = h this is the paper's decomposition (Sec. 3): the upward pyramid
+// of Alg. 1 holds levels 0..h-1, the bridges of Alg. 2-3 levels 1..h-1, the
+// downward pyramid of Alg. 4 levels 1..h and ends as the full tile centred on
+// the corner. The x-bridge is Alg. 3's latitudinal bridge (it joins a tile to
+// its east neighbour), the y-bridge Alg. 2's longitudinal bridge.
+struct Geo {
+  int nx, ny;      // grid
+  int n, h;        // tile side, h = n/2
+  int ntx, nty;    // tiles in x and y
+  int off;         // tiling offset (x and y)
+  int W;           // LDS window side n + 2
+  long long T0;    // level at the start of the half cycle, relative to *tbase
+  const long long* tbase;  // device-resident level base (graph replay), or null
+};
+
+// Panels exchanged through HBM (the triangular sides of Sec. 3).
+// Every panel is stored compactly, level after level, each level as
+// [value v][k][t] with k = 0 the row or column nearer the edge the panel
+// faces and t running along that edge over the level's valid range only:
+//  up: upward-pyramid strip of one side (ends N, S, W, E) of a tile: the two
+//      outermost rows / columns of the level-l square, t = 0 .. n-2l-1 for
+//      tile-local positions l .. n-1-l.
+//  xb: x-bridge over the east edge of tile (a, b), ends N, S: two rows of the
+//      bridge's level-l band plus the 2x2 pyramid corners beside it,
+//      2l+4 long, t = 0 at x = edge - l - 2.
+//  yb: y-bridge over the south edge of tile (a, b), ends W, E: two columns of
+//      the band, 2l long, t = 0 at y = edge - l.
+// The downward pyramid at the south-east corner of tile (a, b) reads the
+// S end of xb(a, b), the N end of xb(a, b+1), the E end of yb(a, b) and the
+// W end of yb(a+1, b): the ring two wide around its level-l square, corners
+// included (they arrive with the x-bridges).
+struct PanelPtrs {
+  void* up;
+  void* xb;
+  void* yb;
+};
+
+// Values of one end of a panel over levels 0..L-1, per value slot and k
+// (multiply by 2 * nv for values).
+__host__ __device__ inline int up_levels_len(int n, int L) { return L * (n - L + 1); }
+__host__ __device__ inline int xb_levels_len(int L) { return L * (L + 3); }
+__host__ __device__ inline int yb_levels_len(int L) { return L * (L - 1); }
+
+inline size_t up_panel_values(int ntiles, int n, int nv) {
+  return (size_t)ntiles * 4 * 2 * nv * up_levels_len(n, n / 2);
+}
+inline size_t xb_panel_values(int ntiles, int n, int nv) { return (size_t)ntiles * 2 * 2 * nv * xb_levels_len(n / 2); }
+inline size_t yb_panel_values(int ntiles, int n, int nv) { return (size_t)ntiles * 2 * 2 * nv * yb_levels_len(n / 2); }
+
+enum Scheme : int {
+  kHeat64 = 0,
+  kWave64,
+  kEuler64,
+  kHash64,
+  kIncr64,
+  kPush5,
+  kHeat32C,
+  kWave32C,
+  kEuler32C,
+  kNumSchemes
+};
+
+// Launch entry points (defined in swept2d_kernels.hip). Each returns the
+// hipError_t of the launch.
+//   up:     upward pyramid of every tile from the state (height H; emits
+//           panels of levels 0..H-1; if H < h writes its level-H region to
+//           the state).
+//   bridge: x- and y-bridges of every edge (height H; same conventions).
+//   oct:    downward pyramid of height Hd at every tile corner; if Hd == h
+//           and Hu > 0 it continues in LDS as the upward pyramid of the
+//           shifted tile (an octahedron) of height Hu; the last stage of an
+//           advance writes its region at the final level to the state.
+//   plain:  one sub-step of every point, in -> out.
+// `staged`: the kernel copies all panel inputs of the component into LDS at
+// its start (one memory latency); otherwise it fetches each level's inputs
+// one level ahead into registers.
+hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp,
+                     hipStream_t s);
+hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, void* state, PanelPtrs p,
+                         const SchemeParams& sp, hipStream_t s);
+hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p,
+                      const SchemeParams& sp, hipStream_t s);
+hipError_t launch_plain(int scheme, int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
+                        const SchemeParams& sp, hipStream_t s);
+// Device-side helpers that are safe inside a captured graph: copy `bytes`
+// (a multiple of 8) and set the level base.
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_set_base(long long* tbase, long long value, hipStream_t s);
+
+// Static facts about a scheme.
+struct SchemeInfo {
+  int nv;          // values per point
+  int nvar;        // the scheme's nvars
+  int sub;         // sub-steps per step
+  int vbytes;      // bytes per value
+};
+SchemeInfo scheme_info(int scheme);
+
+// LDS bytes of the stage kernels for tile side n: a double-buffered
+// (n+2)^2 window per value slot, plus the staged panel inputs.
+inline size_t window_lds_bytes(const SchemeInfo& si, int n) {
+  return (size_t)2 * (size_t)(n + 2) * (size_t)(n + 2) * (size_t)si.nv * (size_t)si.vbytes;
+}
+inline size_t oct_stage_bytes(const SchemeInfo& si, int n) {
+  const int h = n / 2;
+  return (size_t)2 * 2 * si.nv * (size_t)(xb_levels_len(h) + yb_levels_len(h)) * si.vbytes;
+}
+inline size_t bridge_stage_bytes(const SchemeInfo& si, int n) {
+  return (size_t)2 * 2 * si.nv * (size_t)up_levels_len(n, n / 2) * si.vbytes;
+}
+// Largest panel run per level is n + 2 values; the per-level fetch path holds
+// two per lane.
+inline bool tile_fits_fetch(int n) { return n + 2 <= 128; }
+
+// Raise the dynamic LDS limit of every stage kernel to `bytes` (once).
+hipError_t configure_lds(size_t bytes);
+
+}  // namespace swept

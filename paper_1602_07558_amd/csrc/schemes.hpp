@@ -1,0 +1,313 @@
+// Per-point sub-step operations (the paper's timestep(i, p) callback of
+// Sec. 6, compiled in) for the built-in schemes, on gfx950.
+//
+// Each scheme is a struct with
+//   V        value type stored in the state, LDS and panels
+//   NV       values per grid point (FP32C schemes: nvars u's then nvars c's)
+//   NVAR     the scheme's nvars, SUB its sub-steps per time step
+//   step(T, nb, out, prm)
+//            computes the point at level T+1 from its 3x3 neighbourhood at
+//            level T (Sec. 2, assumption 2); nb(di, dj, v) returns value v of
+//            the neighbour at offset (di, dj), dj = -1 being north. T is the
+//            global sub-step index, so St_{T mod SUB} is applied.
+//
+// Every expression is evaluated exactly as written (the library is compiled
+// with -ffp-contract=off): sums are left to right, no fused multiply-add.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace swept {
+
+struct SchemeParams {
+  double p[4];
+};
+
+// ------------------------------------------------------------------ FP64
+
+// Heat, forward time centred space: u' = u + r lap(u), 5-point Laplacian
+// lap = ((uW + uE) + (uN + uS)) - 4u.
+struct Heat64 {
+  using V = double;
+  static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
+    const double r = sp.p[0];
+    const double u = nb(0, 0, 0);
+    const double t1 = nb(-1, 0, 0) + nb(1, 0, 0);
+    const double t2 = nb(0, -1, 0) + nb(0, 1, 0);
+    const double lap = (t1 + t2) - 4.0 * u;
+    out[0] = u + r * lap;
+  }
+};
+
+// Wave equation, leapfrog with the previous level as a second variable:
+// (u, q) -> ((2u - q) + C2 lap(u), u).
+struct Wave64 {
+  using V = double;
+  static constexpr int NV = 2, NVAR = 2, SUB = 1;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
+    const double c2 = sp.p[0];
+    const double u = nb(0, 0, 0);
+    const double q = nb(0, 0, 1);
+    const double t1 = nb(-1, 0, 0) + nb(1, 0, 0);
+    const double t2 = nb(0, -1, 0) + nb(0, 1, 0);
+    const double lap = (t1 + t2) - 4.0 * u;
+    out[0] = (2.0 * u - q) + c2 * lap;
+    out[1] = u;
+  }
+};
+
+// Test stencil: 64-bit mix, in row-major neighbour order (north-west first),
+// of the nine neighbour values (integers < 2^52 held in doubles) seeded with
+// the sub-step index; the top 52 bits are the new value.
+struct Hash64 {
+  using V = double;
+  static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
+    uint64_t m = 0x9E3779B97F4A7C15ull ^ (uint64_t)T;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        m ^= (uint64_t)nb(di, dj, 0);
+        m *= 0xFF51AFD7ED558CCDull;
+        m ^= m >> 32;
+      }
+    out[0] = (double)(m >> 12);
+  }
+};
+
+// Test stencil from the worked example of Sec. 3.1: increment by one; NaN
+// when the nine neighbours are not all at the centre's value (level).
+struct Incr64 {
+  using V = double;
+  static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams&) {
+    const double u = nb(0, 0, 0);
+    bool same = true;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) same = same && (nb(di, dj, 0) == u);
+    out[0] = same ? u + 1.0 : __builtin_nan("");
+  }
+};
+
+// Eq. (2)-(3): sub-step 0 pushes (u, u_W, u_E, u_N, u_S) into slots 0..4;
+// sub-step 1 forms W.slot1 + E.slot2 + N.slot3 + S.slot4 - 4 C.slot0, which is
+// the 2-ring stencil of Eq. (1), and clears slots 1..4.
+struct Push5 {
+  using V = double;
+  static constexpr int NV = 5, NVAR = 5, SUB = 2;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
+    if ((T & 1) == 0) {
+      out[0] = nb(0, 0, 0);
+      out[1] = nb(-1, 0, 0);
+      out[2] = nb(1, 0, 0);
+      out[3] = nb(0, -1, 0);
+      out[4] = nb(0, 1, 0);
+    } else {
+      const double s = nb(-1, 0, 1) + nb(1, 0, 2) + nb(0, -1, 3) + nb(0, 1, 4);
+      out[0] = s - 4.0 * nb(0, 0, 0);
+      out[1] = 0.0;
+      out[2] = 0.0;
+      out[3] = 0.0;
+      out[4] = 0.0;
+    }
+  }
+};
+
+// Compressible Euler, first-order finite volumes, Rusanov flux.
+// State U = (rho, mx, my, E); p = (gamma-1)(E - 0.5 (mx^2 + my^2)/rho),
+// c = sqrt(gamma p / rho). Physical flux along x: (mx, mx u + p, my u, (E+p) u)
+// with u = mx/rho; along y: (my, mx v, my v + p, (E+p) v) with v = my/rho.
+// Face flux 0.5 (F(L) + F(R)) - 0.5 (a (R - L)), a = max(|u_L|+c_L, |u_R|+c_R),
+// always taken with (left/north, right/south) argument order so neighbouring
+// cells see identical bits.
+namespace euler {
+
+__device__ __forceinline__ void phys(const double* U, int d, double gamma, double* F, double& speed) {
+  const double rho = U[0], mx = U[1], my = U[2], en = U[3];
+  const double ke = 0.5 * ((mx * mx + my * my) / rho);
+  const double p = (gamma - 1.0) * (en - ke);
+  const double c = sqrt((gamma * p) / rho);
+  if (d == 0) {
+    const double un = mx / rho;
+    F[0] = mx;
+    F[1] = mx * un + p;
+    F[2] = my * un;
+    F[3] = (en + p) * un;
+    speed = fabs(un) + c;
+  } else {
+    const double un = my / rho;
+    F[0] = my;
+    F[1] = mx * un;
+    F[2] = my * un + p;
+    F[3] = (en + p) * un;
+    speed = fabs(un) + c;
+  }
+}
+
+__device__ __forceinline__ void rusanov(const double* L, const double* R, int d, double gamma, double* Fh) {
+  double FL[4], FR[4], aL, aR;
+  phys(L, d, gamma, FL, aL);
+  phys(R, d, gamma, FR, aR);
+  const double a = fmax(aL, aR);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Fh[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * (a * (R[k] - L[k]));
+}
+
+// dt L(U) at the centre from the 5-point states W, E, N, S, C (4 values each).
+__device__ __forceinline__ void increment(const double* W, const double* E, const double* N, const double* S,
+                                          const double* C, double gamma, double dtoh, double* du) {
+  double Fw[4], Fe[4], Gn[4], Gs[4];
+  rusanov(W, C, 0, gamma, Fw);
+  rusanov(C, E, 0, gamma, Fe);
+  rusanov(N, C, 1, gamma, Gn);
+  rusanov(C, S, 1, gamma, Gs);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double div = (Fe[k] - Fw[k]) + (Gs[k] - Gn[k]);
+    du[k] = -(dtoh * div);
+  }
+}
+
+}  // namespace euler
+
+// Two-stage SSP Runge-Kutta as two sub-steps; slots 0..3 = U^n, 4..7 = U*.
+// sub-step 0: U* = U + dt L(U), U^n carried. sub-step 1:
+// U' = 0.5 U + 0.5 (U* + dt L(U*)), written to both halves.
+struct Euler64 {
+  using V = double;
+  static constexpr int NV = 8, NVAR = 8, SUB = 2;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
+    const double gamma = sp.p[0], dtoh = sp.p[1];
+    const int o = (T & 1) ? 4 : 0;
+    double W[4], E[4], N[4], S[4], C[4], du[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      W[k] = nb(-1, 0, o + k);
+      E[k] = nb(1, 0, o + k);
+      N[k] = nb(0, -1, o + k);
+      S[k] = nb(0, 1, o + k);
+      C[k] = nb(0, 0, o + k);
+    }
+    euler::increment(W, E, N, S, C, gamma, dtoh, du);
+    if ((T & 1) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        out[k] = C[k];
+        out[4 + k] = C[k] + du[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = 0.5 * nb(0, 0, k) + 0.5 * (C[k] + du[k]);
+        out[k] = v;
+        out[4 + k] = v;
+      }
+    }
+  }
+};
+
+// ------------------------------------------- FP32 with compensated update
+// Values u and compensations c; the pair stands for u - c. Heat and wave use
+// Kahan's update for u += delta: y = delta - c, t = u + y, c' = (t - u) - y,
+// u' = t; neighbour differences are taken against the centre first.
+
+struct Heat32C {
+  using V = float;
+  static constexpr int NV = 2, NVAR = 1, SUB = 1;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
+    const float r = (float)sp.p[0];
+    const float u = nb(0, 0, 0);
+    const float c = nb(0, 0, 1);
+    const float lap = ((nb(-1, 0, 0) - u) + (nb(1, 0, 0) - u)) + ((nb(0, -1, 0) - u) + (nb(0, 1, 0) - u));
+    const float y = r * lap - c;
+    const float t = u + y;
+    out[1] = (t - u) - y;
+    out[0] = t;
+  }
+};
+
+// Leapfrog as u' = u + v, v = ((u - q) - (c_u - c_q)) + C2 lap(u) with Kahan
+// on u; q' = u and c_q' = c_u. Slots: u, q, c_u, c_q.
+struct Wave32C {
+  using V = float;
+  static constexpr int NV = 4, NVAR = 2, SUB = 1;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
+    const float c2 = (float)sp.p[0];
+    const float u = nb(0, 0, 0);
+    const float q = nb(0, 0, 1);
+    const float cu = nb(0, 0, 2);
+    const float cq = nb(0, 0, 3);
+    const float lap = ((nb(-1, 0, 0) - u) + (nb(1, 0, 0) - u)) + ((nb(0, -1, 0) - u) + (nb(0, 1, 0) - u));
+    const float v = ((u - q) - (cu - cq)) + c2 * lap;
+    const float y = v - cu;
+    const float t = u + y;
+    out[2] = (t - u) - y;
+    out[0] = t;
+    out[1] = u;
+    out[3] = cu;
+  }
+};
+
+// Euler with FP32 state: every input is widened to the FP64 value u - c,
+// the FP64 update above is applied, and the FP64 result t is split into
+// u = fl32(t), c = fl32(u - t). Slots 0..7 values, 8..15 compensations.
+struct Euler32C {
+  using V = float;
+  static constexpr int NV = 16, NVAR = 8, SUB = 2;
+  template <class NB>
+  __device__ __forceinline__ static double wide(const NB& nb, int di, int dj, int v) {
+    return (double)nb(di, dj, v) - (double)nb(di, dj, 8 + v);
+  }
+  __device__ __forceinline__ static void split(double t, float& u, float& c) {
+    const float hi = (float)t;
+    u = hi;
+    c = (float)((double)hi - t);
+  }
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
+    const double gamma = sp.p[0], dtoh = sp.p[1];
+    const int o = (T & 1) ? 4 : 0;
+    double W[4], E[4], N[4], S[4], C[4], du[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      W[k] = wide(nb, -1, 0, o + k);
+      E[k] = wide(nb, 1, 0, o + k);
+      N[k] = wide(nb, 0, -1, o + k);
+      S[k] = wide(nb, 0, 1, o + k);
+      C[k] = wide(nb, 0, 0, o + k);
+    }
+    euler::increment(W, E, N, S, C, gamma, dtoh, du);
+    if ((T & 1) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        out[k] = nb(0, 0, k);
+        out[8 + k] = nb(0, 0, 8 + k);
+        split(C[k] + du[k], out[4 + k], out[12 + k]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = 0.5 * wide(nb, 0, 0, k) + 0.5 * (C[k] + du[k]);
+        split(v, out[k], out[8 + k]);
+        out[4 + k] = out[k];
+        out[12 + k] = out[8 + k];
+      }
+    }
+  }
+};
+
+}  // namespace swept

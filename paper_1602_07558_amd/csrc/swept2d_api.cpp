@@ -1,0 +1,701 @@
+// Host side of the swept2d C ABI: validation, device memory, the half-cycle
+// schedule of the swept rule (Algorithm 5), the per-step baseline, HIP graph
+// replay, per-kernel timing and the tile-size tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/swept2d.h"
+#include "engine.hpp"
+
+using namespace swept;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hipfail(hipError_t e, const char* what) {
+  return fail(SWEPT2D_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                      \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hipfail(e_, what); \
+  } while (0)
+
+enum Kind { kKindPlain = 0, kKindUp = 1, kKindBridge = 2, kKindOct = 3, kNumKinds = 4 };
+
+struct TimedLaunch {
+  int kind;
+  double work;
+  hipEvent_t a, b;
+};
+
+int pde_nvars(int pde) {
+  switch (pde) {
+    case SWEPT2D_HEAT5: return 1;
+    case SWEPT2D_WAVE_LF: return 2;
+    case SWEPT2D_EULER_RUS_RK2: return 8;
+    case SWEPT2D_TEST_HASH: return 1;
+    case SWEPT2D_TEST_INCR: return 1;
+    case SWEPT2D_TEST_PUSH5: return 5;
+    default: return -1;
+  }
+}
+
+int pde_substeps(int pde) {
+  switch (pde) {
+    case SWEPT2D_EULER_RUS_RK2:
+    case SWEPT2D_TEST_PUSH5: return 2;
+    default: return pde_nvars(pde) > 0 ? 1 : -1;
+  }
+}
+
+int pde_nparams(int pde) {
+  switch (pde) {
+    case SWEPT2D_HEAT5: return 1;
+    case SWEPT2D_WAVE_LF: return 1;
+    case SWEPT2D_EULER_RUS_RK2: return 2;
+    default: return 0;
+  }
+}
+
+int scheme_of(int pde, int prec) {
+  if (prec == SWEPT2D_FP64) {
+    switch (pde) {
+      case SWEPT2D_HEAT5: return kHeat64;
+      case SWEPT2D_WAVE_LF: return kWave64;
+      case SWEPT2D_EULER_RUS_RK2: return kEuler64;
+      case SWEPT2D_TEST_HASH: return kHash64;
+      case SWEPT2D_TEST_INCR: return kIncr64;
+      case SWEPT2D_TEST_PUSH5: return kPush5;
+    }
+  } else if (prec == SWEPT2D_FP32C) {
+    switch (pde) {
+      case SWEPT2D_HEAT5: return kHeat32C;
+      case SWEPT2D_WAVE_LF: return kWave32C;
+      case SWEPT2D_EULER_RUS_RK2: return kEuler32C;
+    }
+  }
+  return -1;
+}
+
+bool g_lds_configured = false;
+size_t g_lds_limit = 0;
+
+int ensure_device_setup(int* device_out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (!g_lds_configured) {
+    int lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    g_lds_limit = (size_t)lds;
+    HIP_TRY(configure_lds(g_lds_limit), "hipFuncSetAttribute");
+    g_lds_configured = true;
+  }
+  *device_out = dev;
+  return 0;
+}
+
+}  // namespace
+
+struct swept2d {
+  int nx = 0, ny = 0, nvars = 0, pde = 0, substeps = 0, prec = SWEPT2D_FP64;
+  int scheme = 0;
+  SchemeInfo si{};
+  SchemeParams sp{};
+  int device = 0;
+  int cu_count = 0;
+  int n = 0;  // tile side
+  void* state = nullptr;
+  bool owns_state = true;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  void* scratch = nullptr;  // second state buffer of the per-step method
+  void* up = nullptr;
+  void* xb = nullptr;
+  void* yb = nullptr;
+  size_t panel_tile = 0;    // tile side the panels are sized for
+  long long T = 0;          // global sub-step counter
+  long long* d_tbase = nullptr;  // device copy of the level base for graph replay
+  int launch_mode = SWEPT2D_LAUNCH_DIRECT;
+  int staging = SWEPT2D_STAGING_AUTO;
+  std::map<std::pair<int, long long>, hipGraphExec_t> graphs;  // (method, substeps) -> replayable graph
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_next = 0;
+};
+
+namespace {
+
+size_t state_bytes_of(const swept2d* h) {
+  return (size_t)h->nx * h->ny * h->si.nv * h->si.vbytes;
+}
+
+void drop_graphs(swept2d* h) {
+  for (auto& kv : h->graphs) hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+}
+
+int alloc_state(swept2d* h) {
+  if (h->owns_state && h->state) hipFree(h->state);
+  h->state = nullptr;
+  h->owns_state = true;
+  const size_t bytes = state_bytes_of(h);
+  if (hipMalloc(&h->state, bytes) != hipSuccess) {
+    hipGetLastError();
+    h->state = nullptr;
+    return fail(SWEPT2D_ENOMEM, "cannot allocate %zu bytes of state", bytes);
+  }
+  HIP_TRY(hipMemsetAsync(h->state, 0, bytes, h->stream), "hipMemsetAsync");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (h->scratch) hipFree(h->scratch);
+  h->scratch = nullptr;
+  drop_graphs(h);
+  return 0;
+}
+
+int ensure_scratch(swept2d* h) {
+  if (h->scratch) return 0;
+  const size_t bytes = state_bytes_of(h);
+  if (hipMalloc(&h->scratch, bytes) != hipSuccess) {
+    hipGetLastError();
+    h->scratch = nullptr;
+    return fail(SWEPT2D_ENOMEM, "cannot allocate %zu bytes of per-step scratch", bytes);
+  }
+  return 0;
+}
+
+void free_panels(swept2d* h) {
+  if (h->up) hipFree(h->up);
+  if (h->xb) hipFree(h->xb);
+  if (h->yb) hipFree(h->yb);
+  h->up = h->xb = h->yb = nullptr;
+  h->panel_tile = 0;
+}
+
+int ensure_panels(swept2d* h) {
+  if (h->panel_tile == (size_t)h->n && h->up) return 0;
+  free_panels(h);
+  const int ntiles = (h->nx / h->n) * (h->ny / h->n);
+  const size_t vb = h->si.vbytes;
+  const size_t ub = std::max<size_t>(8, up_panel_values(ntiles, h->n, h->si.nv) * vb);
+  const size_t xbb = std::max<size_t>(8, xb_panel_values(ntiles, h->n, h->si.nv) * vb);
+  const size_t ybb = std::max<size_t>(8, yb_panel_values(ntiles, h->n, h->si.nv) * vb);
+  if (hipMalloc(&h->up, ub) != hipSuccess || hipMalloc(&h->xb, xbb) != hipSuccess ||
+      hipMalloc(&h->yb, ybb) != hipSuccess) {
+    hipGetLastError();
+    free_panels(h);
+    return fail(SWEPT2D_ENOMEM, "cannot allocate panels (%zu + %zu + %zu bytes)", ub, xbb, ybb);
+  }
+  h->panel_tile = (size_t)h->n;
+  drop_graphs(h);
+  return 0;
+}
+
+// Why a tile side is not usable, or nullptr.
+const char* tile_problem(const swept2d* h, int n) {
+  if (n < 2 || (n & 1)) return "tile side must be even and at least 2";
+  if (h->nx % n || h->ny % n) return "tile side must divide nx and ny";
+  if (window_lds_bytes(h->si, n) > g_lds_limit) return "tile working set exceeds the workgroup LDS";
+  if (!tile_fits_fetch(n)) return "tile side above 126";
+  return nullptr;
+}
+
+bool oct_staged(const swept2d* h) {
+  return h->staging == SWEPT2D_STAGING_AUTO &&
+         window_lds_bytes(h->si, h->n) + oct_stage_bytes(h->si, h->n) <= g_lds_limit;
+}
+
+bool bridge_staged(const swept2d* h) {
+  return h->staging == SWEPT2D_STAGING_AUTO &&
+         window_lds_bytes(h->si, h->n) + bridge_stage_bytes(h->si, h->n) <= g_lds_limit;
+}
+
+// Relative cost of one point sub-step of a scheme (heat FP64 = 1), for the
+// tuner's cost model.
+double scheme_cost(int scheme) {
+  switch (scheme) {
+    case kWave64: return 1.4;
+    case kEuler64: return 30.0;
+    case kHash64: return 3.0;
+    case kPush5: return 2.5;
+    case kHeat32C: return 1.5;
+    case kWave32C: return 2.2;
+    case kEuler32C: return 36.0;
+    default: return 1.0;
+  }
+}
+
+// Tile-size choice from the swept rule's cost model (Sec. 5, Eq. (4)): the
+// time per sub-step is [2 tau + (half-cycle work) + (n/2) beta] / (n/2), where
+// tau is the cost of one exchange (on one GPU, a kernel boundary), the work
+// of a half cycle is n^2 * n/2 point updates per tile spread over the compute
+// units (ceil(tiles / CUs) tiles in sequence per CU), and beta is the cost of
+// one level's workgroup barrier, paid once per resident wave of tiles. The
+// constants are rough gfx950 figures; the model only ranks tile sides.
+int model_tile(const swept2d* h) {
+  const double tau = 3.0e-6;
+  const double s_cu = 0.17e-9 * scheme_cost(h->scheme);
+  const double beta = 0.1e-6;
+  int best = 0;
+  double best_cost = 1e300;
+  for (int n = 2; n <= std::min(h->nx, h->ny); n += 2) {
+    if (tile_problem(h, n)) continue;
+    const double tiles = (double)(h->nx / n) * (h->ny / n);
+    const double per_cu = std::max(1.0, std::floor((double)g_lds_limit / (double)window_lds_bytes(h->si, n)));
+    const double seq = std::ceil(tiles / h->cu_count);
+    const double resident = std::ceil(tiles / (h->cu_count * std::min(per_cu, 8.0)));
+    const double half = 2.0 * tau + seq * n * (double)n * (n / 2) * s_cu + resident * (n / 2) * beta;
+    const double cost = half / (n / 2);
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best = n;
+    }
+  }
+  return best;
+}
+
+hipEvent_t next_event(swept2d* h) {
+  if (h->event_next == h->event_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->event_pool.push_back(e);
+  }
+  return h->event_pool[h->event_next++];
+}
+
+// Points each kernel kind computes (the space-time volume of its component).
+double up_points(int n, int H) {
+  double s = 0;
+  for (int l = 1; l <= std::min(H, n / 2 - 1); ++l) s += (double)(n - 2 * l) * (n - 2 * l);
+  return s;
+}
+double bridge_points(int n, int H) {
+  double s = 0;
+  for (int l = 1; l <= std::min(H, n / 2 - 1); ++l) s += 2.0 * l * (n - 2 * l);
+  return 2.0 * s;  // x- and y-bridge per tile
+}
+double down_points(int Hd) {
+  double s = 0;
+  for (int l = 1; l <= Hd; ++l) s += 4.0 * l * l;
+  return s;
+}
+
+struct Launcher {
+  swept2d* h;
+  bool timed;
+  template <class F>
+  int run(int kind, double work, F&& f) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timed) {
+      a = next_event(h);
+      b = next_event(h);
+      if (!a || !b) return fail(SWEPT2D_EHIP, "cannot create timing events");
+      HIP_TRY(hipEventRecord(a, h->stream), "hipEventRecord");
+    }
+    hipError_t e = f();
+    if (e != hipSuccess) return hipfail(e, "kernel launch");
+    if (timed) {
+      HIP_TRY(hipEventRecord(b, h->stream), "hipEventRecord");
+      h->timed.push_back(TimedLaunch{kind, work, a, b});
+    }
+    return 0;
+  }
+};
+
+// Enqueue the swept schedule for S sub-steps starting at level T.
+int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, bool timed) {
+  const int n = h->n, hh = n / 2;
+  Geo g{};
+  g.nx = h->nx;
+  g.ny = h->ny;
+  g.n = n;
+  g.h = hh;
+  g.ntx = h->nx / n;
+  g.nty = h->ny / n;
+  g.off = 0;
+  g.W = n + 2;
+  g.T0 = T;
+  g.tbase = tbase;
+  const double ntiles = (double)g.ntx * g.nty;
+  PanelPtrs pp{h->up, h->xb, h->yb};
+  Launcher L{h, timed};
+  const int sc = h->scheme;
+  const bool so = oct_staged(h), sb = bridge_staged(h);
+  const long long q = S / hh;
+  const int r = (int)(S % hh);
+  int rc;
+  if (q == 0) {
+    // A single reduced half cycle of height r.
+    rc = L.run(kKindUp, ntiles * up_points(n, r), [&] { return launch_up(sc, g, r, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    rc = L.run(kKindBridge, ntiles * bridge_points(n, r),
+               [&] { return launch_bridge(sc, g, r, sb, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    return L.run(kKindOct, ntiles * down_points(r),
+                 [&] { return launch_oct(sc, g, r, 0, so, h->state, pp, h->sp, h->stream); });
+  }
+  rc = L.run(kKindUp, ntiles * up_points(n, hh), [&] { return launch_up(sc, g, hh, h->state, pp, h->sp, h->stream); });
+  if (rc) return rc;
+  for (long long c = 0; c < q; ++c) {
+    rc = L.run(kKindBridge, ntiles * bridge_points(n, hh),
+               [&] { return launch_bridge(sc, g, hh, sb, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    const bool last = (c == q - 1);
+    const int Hu = last ? r : hh;
+    rc = L.run(kKindOct, ntiles * (down_points(hh) + up_points(n, Hu)),
+               [&] { return launch_oct(sc, g, hh, Hu, so, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    g.off = (g.off == 0) ? hh : 0;
+    g.T0 += hh;
+  }
+  if (r > 0) {
+    rc = L.run(kKindBridge, ntiles * bridge_points(n, r),
+               [&] { return launch_bridge(sc, g, r, sb, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    rc = L.run(kKindOct, ntiles * down_points(r), [&] { return launch_oct(sc, g, r, 0, so, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// Enqueue S per-step launches starting at level T; the last one writes the
+// state buffer.
+int enqueue_plain(swept2d* h, long long S, long long T, const long long* tbase, bool timed) {
+  Launcher L{h, timed};
+  const double pts = (double)h->nx * h->ny;
+  void* bufs[2] = {h->state, h->scratch};
+  int src;
+  if (S & 1) {
+    // odd count: start from a copy so the final write lands in the state
+    HIP_TRY(launch_copy(h->scratch, h->state, state_bytes_of(h), h->stream), "copy kernel");
+    src = 1;
+  } else {
+    src = 0;
+  }
+  for (long long s = 0; s < S; ++s) {
+    const void* in = bufs[src];
+    void* out = bufs[src ^ 1];
+    const long long Ts = T + s;
+    int rc = L.run(kKindPlain, pts,
+                   [&] { return launch_plain(h->scheme, h->nx, h->ny, Ts, tbase, in, out, h->sp, h->stream); });
+    if (rc) return rc;
+    src ^= 1;
+  }
+  return 0;
+}
+
+int run_method(swept2d* h, int method, long long nsteps) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (nsteps < 0) return fail(SWEPT2D_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return 0;
+  if (nsteps > (1LL << 40)) return fail(SWEPT2D_EINVAL, "nsteps too large");
+  const long long S = nsteps * h->substeps;
+  int rc;
+  if (method == 0) {
+    if (const char* why = tile_problem(h, h->n)) return fail(SWEPT2D_EINVAL, "tile %d: %s", h->n, why);
+    if ((rc = ensure_panels(h))) return rc;
+  } else {
+    if ((rc = ensure_scratch(h))) return rc;
+  }
+  const bool use_graph = (h->launch_mode == SWEPT2D_LAUNCH_GRAPH) && !h->timing;
+  if (!use_graph) {
+    rc = method == 0 ? enqueue_swept(h, S, h->T, nullptr, h->timing) : enqueue_plain(h, S, h->T, nullptr, h->timing);
+    if (rc) return rc;
+    h->T += S;
+    return 0;
+  }
+  // Graph mode: kernels take their level relative to a device-resident base,
+  // so one captured graph per (method, sub-step count) replays at any level.
+  if (!h->d_tbase) {
+    if (hipMalloc(&h->d_tbase, sizeof(long long)) != hipSuccess) {
+      hipGetLastError();
+      h->d_tbase = nullptr;
+      return fail(SWEPT2D_ENOMEM, "cannot allocate the level base");
+    }
+  }
+  hipGraphExec_t exec = nullptr;
+  auto it = h->graphs.find({method, S});
+  if (it != h->graphs.end()) exec = it->second;
+  if (!exec) {
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    rc = method == 0 ? enqueue_swept(h, S, 0, h->d_tbase, false) : enqueue_plain(h, S, 0, h->d_tbase, false);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hipfail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hipfail(e, "hipGraphInstantiate");
+    h->graphs[{method, S}] = exec;
+  }
+  HIP_TRY(launch_set_base(h->d_tbase, h->T, h->stream), "level base kernel");
+  HIP_TRY(hipGraphLaunch(exec, h->stream), "hipGraphLaunch");
+  h->T += S;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* swept2d_last_error(void) { return g_err.c_str(); }
+
+swept2d* swept2d_create(int nx, int ny, int nvars, int pde, int substeps) {
+  g_err.clear();
+  if (pde_nvars(pde) < 0) {
+    fail(SWEPT2D_EINVAL, "unknown pde id %d", pde);
+    return nullptr;
+  }
+  if (nvars != pde_nvars(pde) || substeps != pde_substeps(pde)) {
+    fail(SWEPT2D_EINVAL, "pde %d takes nvars=%d substeps=%d (got %d, %d)", pde, pde_nvars(pde), pde_substeps(pde),
+         nvars, substeps);
+    return nullptr;
+  }
+  if (nx < 2 || ny < 2 || nx > (1 << 16) || ny > (1 << 16)) {
+    fail(SWEPT2D_EINVAL, "grid %d x %d out of range (2..65536 per side)", nx, ny);
+    return nullptr;
+  }
+  int dev = 0;
+  if (ensure_device_setup(&dev)) return nullptr;
+  swept2d* h = new (std::nothrow) swept2d();
+  if (!h) {
+    fail(SWEPT2D_ENOMEM, "out of host memory");
+    return nullptr;
+  }
+  h->nx = nx;
+  h->ny = ny;
+  h->nvars = nvars;
+  h->pde = pde;
+  h->substeps = substeps;
+  h->prec = SWEPT2D_FP64;
+  h->scheme = scheme_of(pde, SWEPT2D_FP64);
+  h->si = scheme_info(h->scheme);
+  h->device = dev;
+  hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+  if (h->cu_count <= 0) h->cu_count = 256;
+  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    hipGetLastError();
+    fail(SWEPT2D_EHIP, "cannot create a stream");
+    delete h;
+    return nullptr;
+  }
+  h->stream = h->own_stream;
+  if (alloc_state(h)) {
+    hipStreamDestroy(h->own_stream);
+    delete h;
+    return nullptr;
+  }
+  h->n = model_tile(h);
+  return h;
+}
+
+void swept2d_destroy(swept2d* h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  drop_graphs(h);
+  free_panels(h);
+  if (h->scratch) hipFree(h->scratch);
+  if (h->owns_state && h->state) hipFree(h->state);
+  if (h->d_tbase) hipFree(h->d_tbase);
+  for (hipEvent_t e : h->event_pool) hipEventDestroy(e);
+  if (h->own_stream) hipStreamDestroy(h->own_stream);
+  delete h;
+}
+
+int swept2d_set_params(swept2d* h, const double* p, int np) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  const int need = pde_nparams(h->pde);
+  if (np < need || np > 4 || (need > 0 && !p)) return fail(SWEPT2D_EINVAL, "pde %d takes %d parameters", h->pde, need);
+  for (int i = 0; i < 4; ++i) h->sp.p[i] = (i < np) ? p[i] : 0.0;
+  drop_graphs(h);
+  return 0;
+}
+
+int swept2d_set_precision(swept2d* h, int prec) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (prec != SWEPT2D_FP64 && prec != SWEPT2D_FP32C) return fail(SWEPT2D_EINVAL, "unknown precision %d", prec);
+  const int sc = scheme_of(h->pde, prec);
+  if (sc < 0) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no FP32-compensated form", h->pde);
+  if (!h->owns_state) return fail(SWEPT2D_EINVAL, "unbind the caller buffer before changing precision");
+  if (prec == h->prec) return 0;
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->prec = prec;
+  h->scheme = sc;
+  h->si = scheme_info(sc);
+  free_panels(h);
+  int rc = alloc_state(h);
+  if (rc) return rc;
+  if (tile_problem(h, h->n)) h->n = model_tile(h);
+  return 0;
+}
+
+int swept2d_set_tile(swept2d* h, int n) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (n == 0) {
+    n = model_tile(h);
+    if (n == 0) return fail(SWEPT2D_EINVAL, "no usable tile side for %d x %d", h->nx, h->ny);
+  }
+  if (const char* why = tile_problem(h, n)) return fail(SWEPT2D_EINVAL, "tile %d: %s", n, why);
+  if (n != h->n) {
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    free_panels(h);
+    drop_graphs(h);
+  }
+  h->n = n;
+  return 0;
+}
+
+int swept2d_get_tile(const swept2d* h) { return h ? h->n : SWEPT2D_EINVAL; }
+
+int swept2d_bind(swept2d* h, void* dev_state, void* hip_stream) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  drop_graphs(h);
+  h->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->own_stream;
+  if (dev_state) {
+    if (h->owns_state && h->state) hipFree(h->state);
+    h->state = dev_state;
+    h->owns_state = false;
+    if (h->scratch) {
+      hipFree(h->scratch);
+      h->scratch = nullptr;
+    }
+    return 0;
+  }
+  if (!h->owns_state) {
+    h->state = nullptr;
+    return alloc_state(h);
+  }
+  return 0;
+}
+
+size_t swept2d_state_bytes(const swept2d* h) { return h ? state_bytes_of(h) : 0; }
+
+int swept2d_upload_raw(swept2d* h, const void* host) {
+  if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(h->state, host, state_bytes_of(h), hipMemcpyHostToDevice), "hipMemcpy");
+  return 0;
+}
+
+int swept2d_download_raw(swept2d* h, void* host) {
+  if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(host, h->state, state_bytes_of(h), hipMemcpyDeviceToHost), "hipMemcpy");
+  return 0;
+}
+
+int swept2d_upload(swept2d* h, const double* host) {
+  if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
+  if (h->prec == SWEPT2D_FP64) return swept2d_upload_raw(h, host);
+  const size_t cnt = (size_t)h->nx * h->ny * h->nvars;
+  std::vector<float> buf(2 * cnt, 0.0f);
+  for (size_t i = 0; i < cnt; ++i) buf[i] = (float)host[i];
+  return swept2d_upload_raw(h, buf.data());
+}
+
+int swept2d_download(swept2d* h, double* host) {
+  if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
+  if (h->prec == SWEPT2D_FP64) return swept2d_download_raw(h, host);
+  const size_t cnt = (size_t)h->nx * h->ny * h->nvars;
+  std::vector<float> buf(2 * cnt);
+  int rc = swept2d_download_raw(h, buf.data());
+  if (rc) return rc;
+  for (size_t i = 0; i < cnt; ++i) host[i] = (double)buf[i] - (double)buf[cnt + i];
+  return 0;
+}
+
+int swept2d_advance(swept2d* h, long long nsteps) { return run_method(h, 0, nsteps); }
+
+int swept2d_plain_advance(swept2d* h, long long nsteps) { return run_method(h, 1, nsteps); }
+
+int swept2d_synchronize(swept2d* h) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  HIP_TRY(hipStreamSynchronize(h->stream), "kernel execution");
+  return 0;
+}
+
+long long swept2d_substep_counter(const swept2d* h) { return h ? h->T : (long long)SWEPT2D_EINVAL; }
+
+int swept2d_set_substep_counter(swept2d* h, long long T) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (T < 0 || T % h->substeps) return fail(SWEPT2D_EINVAL, "counter must be >= 0 and a multiple of substeps");
+  h->T = T;
+  return 0;
+}
+
+int swept2d_set_launch_mode(swept2d* h, int mode) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (mode != SWEPT2D_LAUNCH_DIRECT && mode != SWEPT2D_LAUNCH_GRAPH) return fail(SWEPT2D_EINVAL, "unknown mode");
+  h->launch_mode = mode;
+  return 0;
+}
+
+int swept2d_set_staging(swept2d* h, int mode) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (mode != SWEPT2D_STAGING_AUTO && mode != SWEPT2D_STAGING_OFF) return fail(SWEPT2D_EINVAL, "unknown staging mode");
+  if (mode != h->staging) drop_graphs(h);
+  h->staging = mode;
+  return 0;
+}
+
+int swept2d_set_timing(swept2d* h, int on) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->timing = on != 0;
+  h->timed.clear();
+  h->event_next = 0;
+  return 0;
+}
+
+int swept2d_get_timing(swept2d* h, double* out, int cap) {
+  if (!h || (cap > 0 && !out)) return fail(SWEPT2D_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  double launches[kNumKinds] = {0}, ms[kNumKinds] = {0}, work[kNumKinds] = {0};
+  for (const TimedLaunch& t : h->timed) {
+    float e = 0;
+    HIP_TRY(hipEventElapsedTime(&e, t.a, t.b), "hipEventElapsedTime");
+    launches[t.kind] += 1;
+    ms[t.kind] += e;
+    work[t.kind] += t.work;
+  }
+  int k = 0;
+  for (int kind = 0; kind < kNumKinds; ++kind) {
+    if (launches[kind] == 0) continue;
+    if (k < cap) {
+      out[4 * k + 0] = kind;
+      out[4 * k + 1] = launches[kind];
+      out[4 * k + 2] = ms[kind];
+      out[4 * k + 3] = work[kind];
+    }
+    ++k;
+  }
+  return std::min(k, std::max(cap, 0));
+}
+
+}  // extern "C"

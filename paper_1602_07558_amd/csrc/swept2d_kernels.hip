@@ -1,0 +1,761 @@
+// HIP kernels of the swept rule for gfx950 (CDNA4).
+//
+// Stage kernels: one workgroup of kThreads threads (8 waves) per tile
+// (upward pyramid, octahedron) or per tile edge (bridges). A workgroup keeps
+// its whole space-time component in LDS: a window of (n+2) x (n+2) points per
+// value slot, double buffered by level parity (the internal arrays U and D of
+// Algorithms 1-4). A level is one pass over that level's rectangle, threads
+// mapped densely onto the rectangle two points at a time, then one workgroup
+// barrier.
+//
+// Panels (Sec. 3) travel through HBM between kernel launches. A consumer
+// either copies all its panel levels into LDS at its start, with every load
+// in flight at once (staged), or fetches level l+1 into registers before it
+// computes level l. Panel rows are read and written with lanes along the
+// panel, one (side, value, k) run per wave.
+//
+// The plain kernel advances every point by one sub-step, reading its 3x3
+// neighbourhood from HBM (rows kept in registers as a thread walks down a
+// column strip).
+#include <algorithm>
+
+#include "engine.hpp"
+
+#pragma clang fp contract(off)
+
+namespace swept {
+
+namespace {
+
+template <class V>
+struct WinNb {
+  const V* c;
+  int pitch;
+  int plane;
+  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return c[v * plane + dj * pitch + di]; }
+};
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+__device__ __forceinline__ int wrap(int x, int m) {
+  if (x < 0) x += m;
+  if (x >= m) x -= m;
+  if (x >= m) x -= m;
+  return x;
+}
+
+__device__ __forceinline__ long long level_base(const Geo& g) { return g.T0 + (g.tbase ? *g.tbase : 0LL); }
+
+// q = a d + b for 0 <= q < 2^21: (q + 1/2) / d is at least 1/(2d) away from
+// an integer, far more than the error of the float product below.
+__device__ __forceinline__ void fdivmod(int q, int d, float invd, int& a, int& b) {
+  a = (int)(((float)q + 0.5f) * invd);
+  b = q - a * d;
+}
+
+// Start of one end of a tile's panel (values).
+__device__ __forceinline__ size_t up_end(const Geo& g, int nv, int tile, int end) {
+  return ((size_t)tile * 4 + end) * (size_t)(2 * nv * up_levels_len(g.n, g.h));
+}
+__device__ __forceinline__ size_t xb_end(const Geo& g, int nv, int tile, int end) {
+  return ((size_t)tile * 2 + end) * (size_t)(2 * nv * xb_levels_len(g.h));
+}
+__device__ __forceinline__ size_t yb_end(const Geo& g, int nv, int tile, int end) {
+  return ((size_t)tile * 2 + end) * (size_t)(2 * nv * yb_levels_len(g.h));
+}
+
+// Gather `total` values into LDS with up to kBatch loads in flight per thread.
+constexpr int kBatch = 16;
+template <class V, class Src, class Dst>
+__device__ __forceinline__ void gather(int total, Src src, Dst dst) {
+  for (int base = 0; base < total; base += kBatch * kThreads) {
+    V r[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int q = base + (int)threadIdx.x + i * kThreads;
+      if (q < total) r[i] = src(q);
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int q = base + (int)threadIdx.x + i * kThreads;
+      if (q < total) dst(q, r[i]);
+    }
+  }
+}
+
+// Copy up to four contiguous global runs, back to back, into LDS.
+template <class V>
+__device__ __forceinline__ void stage_runs(V* __restrict__ lds, const V* s0, int n0, const V* s1, int n1, const V* s2,
+                                           int n2, const V* s3, int n3) {
+  const int e1 = n0, e2 = n0 + n1, e3 = n0 + n1 + n2, total = e3 + n3;
+  gather<V>(
+      total,
+      [&](int q) -> V {
+        const V* p = s0 + q;
+        if (q >= e1) p = s1 + (q - e1);
+        if (q >= e2) p = s2 + (q - e2);
+        if (q >= e3) p = s3 + (q - e3);
+        return *p;
+      },
+      [&](int q, V v) { lds[q] = v; });
+}
+
+template <class S>
+__device__ __forceinline__ void point(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int idx,
+                                      int W, int plane, long long T, const SchemeParams& sp) {
+  using V = typename S::V;
+  const WinNb<V> nb{in + idx, W, plane};
+  V o[S::NV];
+  S::step(T, nb, o, sp);
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) out[v * plane + idx] = o[v];
+}
+
+// One level: every point of the window rectangle [x0, x0+w) x [y0, y0+hg)
+// gets the sub-step T applied to its neighbourhood in `in`, into `out`.
+// Thread t takes points t, t + kThreads, ... of the rectangle in row-major
+// order, two per iteration; the window index advances incrementally.
+template <class S>
+__device__ __forceinline__ void compute_rect(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                             int W, int x0, int y0, int w, int hg, long long T,
+                                             const SchemeParams& sp) {
+  const int npts = w * hg;
+  if (npts <= 0) return;
+  const int plane = W * W;
+  const float invw = 1.0f / (float)w;
+  int dy, dx, y, x;
+  fdivmod(kThreads, w, invw, dy, dx);
+  fdivmod((int)threadIdx.x, w, invw, y, x);
+  int idx = (y0 + y) * W + x0 + x;
+  const int didx = dy * W + dx, carry = W - w;
+  int p = (int)threadIdx.x;
+  for (; p + kThreads < npts; p += 2 * kThreads) {
+    int x1 = x + dx, i1 = idx + didx;
+    if (x1 >= w) {
+      x1 -= w;
+      i1 += carry;
+    }
+    point<S>(in, out, idx, W, plane, T, sp);
+    point<S>(in, out, i1, W, plane, T, sp);
+    x = x1 + dx;
+    idx = i1 + didx;
+    if (x >= w) {
+      x -= w;
+      idx += carry;
+    }
+  }
+  if (p < npts) point<S>(in, out, idx, W, plane, T, sp);
+}
+
+// Window -> state for the rectangle [wx0, wx0+w) x [wy0, wy0+hg); the window
+// origin is global (xw0, yw0).
+template <class S>
+__device__ void write_rect(const typename S::V* __restrict__ win, typename S::V* __restrict__ state, const Geo& g,
+                           int xw0, int yw0, int wx0, int wy0, int w, int hg) {
+  const int npts = w * hg;
+  if (npts <= 0) return;
+  const int plane = g.W * g.W;
+  const size_t gplane = (size_t)g.nx * g.ny;
+  const float invw = 1.0f / (float)w;
+  for (int p = threadIdx.x; p < npts; p += kThreads) {
+    int y, x;
+    fdivmod(p, w, invw, y, x);
+    const int wx = wx0 + x, wy = wy0 + y;
+    const int gx = wrap(xw0 + wx, g.nx), gy = wrap(yw0 + wy, g.ny);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) state[v * gplane + (size_t)gy * g.nx + gx] = win[v * plane + wy * g.W + wx];
+  }
+}
+
+// Upward-pyramid panels of level l (Alg. 1): the two outermost rows/columns
+// of the level-l square [l+1, n-l+1)^2 of the window, one strip per side.
+template <class S>
+__device__ void emit_up(const typename S::V* __restrict__ win, typename S::V* __restrict__ up, const Geo& g,
+                        int tile, int l) {
+  constexpr int NV = S::NV;
+  const int n = g.n, W = g.W, plane = W * W, len = n - 2 * l;
+  const size_t lev = (size_t)2 * NV * up_levels_len(n, l);
+  for (int u = wave_id(); u < 8 * NV; u += kWaves) {
+    const int end = u / (2 * NV), rem = u - end * 2 * NV;  // rem = 2 v + k
+    const int v = rem >> 1, k = rem & 1;
+    typename S::V* dst = up + up_end(g, NV, tile, end) + lev + (size_t)rem * len;
+    for (int t = lane_id(); t < len; t += 64) {
+      int wx, wy;
+      if (end == 0) {
+        wy = l + 1 + k;
+        wx = l + 1 + t;
+      } else if (end == 1) {
+        wy = n - l - k;
+        wx = l + 1 + t;
+      } else if (end == 2) {
+        wx = l + 1 + k;
+        wy = l + 1 + t;
+      } else {
+        wx = n - l - k;
+        wy = l + 1 + t;
+      }
+      dst[t] = win[v * plane + wy * W + wx];
+    }
+  }
+}
+
+// Levels 1..H of the upward pyramid of `tile` whose level 0 (the whole tile,
+// window interior) is in buffer b0. Emits the panels of levels 0..H-1; when
+// H < h (reduced last half cycle) writes the level-H square to the state.
+template <class S>
+__device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, const Geo& g, int tile, int x0, int y0,
+                          long long T0, int H, typename S::V* state, typename S::V* up, const SchemeParams& sp) {
+  const int n = g.n, h = g.h;
+  for (int l = 0; l <= H; ++l) {
+    typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
+    if (l >= 1 && l <= h - 1) {
+      const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
+      compute_rect<S>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
+      __syncthreads();
+    }
+    if (l < H) emit_up<S>(cur, up, g, tile, l);
+  }
+  if (H < h) {
+    const typename S::V* fin = ((b0 + H) & 1) ? buf1 : buf0;
+    write_rect<S>(fin, state, g, x0 - 1, y0 - 1, H + 1, H + 1, n - 2 * H, n - 2 * H);
+  }
+}
+
+// Per-level panel inputs held in registers (fetch path): unit u = wave +
+// j * kWaves (j < NV covers 8 NV units for rings, 4 NV for bridges), lanes
+// along the run, two positions per lane (runs are at most n + 2 <= 128).
+template <class S>
+struct Fetch {
+  typename S::V val[S::NV][2];
+  int dst[S::NV][2];
+};
+
+// Window position of element t of ring band `band` (0 top, 1 bottom, 2 left,
+// 3 right) at level l, row/column k; the downward pyramid's square at level
+// l is [h+1-l, h+1+l)^2.
+__device__ __forceinline__ void ring_pos(int h, int l, int band, int k, int t, int& wx, int& wy) {
+  if (band == 0) {
+    wx = h - l - 1 + t;
+    wy = h - l - k;
+  } else if (band == 1) {
+    wx = h - l - 1 + t;
+    wy = h + 1 + l + k;
+  } else if (band == 2) {
+    wx = h - l - k;
+    wy = h + 1 - l + t;
+  } else {
+    wx = h + 1 + l + k;
+    wy = h + 1 - l + t;
+  }
+}
+
+// Window position of element t of bridge input strip `side` (0: tile A's
+// facing strip, 1: tile B's) at level l, row/column k.
+__device__ __forceinline__ void strip_pos(bool isx, int h, int l, int side, int k, int t, int& wx, int& wy) {
+  const int across = side ? (h + 1 + l + k) : (h - l - k);
+  if (isx) {
+    wx = across;
+    wy = l + 1 + t;
+  } else {
+    wy = across;
+    wx = l + 1 + t;
+  }
+}
+
+// Ring of level l into the window from the staged LDS runs
+// [top | bottom | left | right], each of LxH or LyH values.
+template <class S>
+__device__ __forceinline__ void place_ring_staged(const typename S::V* __restrict__ stg, typename S::V* __restrict__ win,
+                                                  const Geo& g, int l, int LxH, int LyH) {
+  constexpr int NV = S::NV;
+  const int h = g.h, W = g.W, plane = W * W;
+  for (int u = wave_id(); u < 8 * NV; u += kWaves) {
+    const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
+    const bool horiz = band < 2;
+    const int len = horiz ? 2 * l + 4 : 2 * l;
+    const int base =
+        horiz ? band * LxH + 2 * NV * xb_levels_len(l) : 2 * LxH + (band - 2) * LyH + 2 * NV * yb_levels_len(l);
+    const typename S::V* src = stg + base + rem * len;
+    for (int t = lane_id(); t < len; t += 64) {
+      int wx, wy;
+      ring_pos(h, l, band, k, t, wx, wy);
+      win[v * plane + wy * W + wx] = src[t];
+    }
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void fetch_ring(Fetch<S>& f, const Geo& g, int l, const typename S::V* __restrict__ xb,
+                                           const typename S::V* __restrict__ yb, int eTop, int eBot, int eLeft,
+                                           int eRight) {
+  constexpr int NV = S::NV;
+  const int h = g.h, W = g.W, plane = W * W;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int u = wave_id() + j * kWaves;  // < 8 NV
+    const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
+    const bool horiz = band < 2;
+    const int len = horiz ? 2 * l + 4 : 2 * l;
+    const typename S::V* src;
+    if (band == 0)
+      src = xb + xb_end(g, NV, eTop, 1) + 2 * NV * xb_levels_len(l);
+    else if (band == 1)
+      src = xb + xb_end(g, NV, eBot, 0) + 2 * NV * xb_levels_len(l);
+    else if (band == 2)
+      src = yb + yb_end(g, NV, eLeft, 1) + 2 * NV * yb_levels_len(l);
+    else
+      src = yb + yb_end(g, NV, eRight, 0) + 2 * NV * yb_levels_len(l);
+    src += rem * len;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int t = lane_id() + 64 * i;
+      f.dst[j][i] = -1;
+      if (t < len) {
+        int wx, wy;
+        ring_pos(h, l, band, k, t, wx, wy);
+        f.val[j][i] = src[t];
+        f.dst[j][i] = v * plane + wy * W + wx;
+      }
+    }
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void place_fetched(const Fetch<S>& f, typename S::V* __restrict__ win) {
+#pragma unroll
+  for (int j = 0; j < S::NV; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (f.dst[j][i] >= 0) win[f.dst[j][i]] = f.val[j][i];
+}
+
+template <class S>
+__device__ __forceinline__ void place_strips_staged(const typename S::V* __restrict__ stg,
+                                                    typename S::V* __restrict__ win, bool isx, const Geo& g, int l,
+                                                    int LH) {
+  constexpr int NV = S::NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
+  for (int u = wave_id(); u < 4 * NV; u += kWaves) {
+    const int side = u / (2 * NV), rem = u - side * 2 * NV, v = rem >> 1, k = rem & 1;
+    const typename S::V* src = stg + side * LH + 2 * NV * up_levels_len(n, l) + rem * len;
+    for (int t = lane_id(); t < len; t += 64) {
+      int wx, wy;
+      strip_pos(isx, h, l, side, k, t, wx, wy);
+      win[v * plane + wy * W + wx] = src[t];
+    }
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void fetch_strips(Fetch<S>& f, bool isx, const Geo& g, int l,
+                                             const typename S::V* __restrict__ up, int tA, int tB) {
+  constexpr int NV = S::NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int u = wave_id() + j * kWaves;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    if (u >= 4 * NV) continue;
+    const int side = u / (2 * NV), rem = u - side * 2 * NV, v = rem >> 1, k = rem & 1;
+    const int end = isx ? (side ? 2 : 3) : (side ? 0 : 1);
+    const typename S::V* src = up + up_end(g, NV, side ? tB : tA, end) + 2 * NV * up_levels_len(n, l) + rem * len;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int t = lane_id() + 64 * i;
+      if (t < len) {
+        int wx, wy;
+        strip_pos(isx, h, l, side, k, t, wx, wy);
+        f.val[j][i] = src[t];
+        f.dst[j][i] = v * plane + wy * W + wx;
+      }
+    }
+  }
+}
+
+// Bridge panels of level l: the two end bands of the bridge's level-l
+// rectangle. x-bridge: window rows l+1+k (N end) and n-l-k (S end), columns
+// h-l-1 .. h+l+2 (the band plus the pyramid corners placed beside it).
+// y-bridge: columns l+1+k (W end) and n-l-k (E end), rows h+1-l .. h+l.
+template <class S>
+__device__ void emit_bridge(const typename S::V* __restrict__ win, typename S::V* __restrict__ out, bool isx,
+                            const Geo& g, int e, int l) {
+  constexpr int NV = S::NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W;
+  const int len = isx ? 2 * l + 4 : 2 * l;
+  if (len == 0) return;
+  for (int u = wave_id(); u < 4 * NV; u += kWaves) {
+    const int end = u / (2 * NV), rem = u - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    typename S::V* dst = out +
+                         (isx ? xb_end(g, NV, e, end) + 2 * NV * xb_levels_len(l)
+                              : yb_end(g, NV, e, end) + 2 * NV * yb_levels_len(l)) +
+                         (size_t)rem * len;
+    const int across = end ? (n - l - k) : (l + 1 + k);
+    for (int t = lane_id(); t < len; t += 64) {
+      const int wx = isx ? (h - l - 1 + t) : across;
+      const int wy = isx ? across : (h + 1 - l + t);
+      dst[t] = win[v * plane + wy * W + wx];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- kernels
+
+// Upward pyramid of every tile, from the state (Alg. 1).
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
+                                                 SchemeParams sp) {
+  using V = typename S::V;
+  extern __shared__ double smem_d[];
+  V* buf0 = reinterpret_cast<V*>(smem_d);
+  V* buf1 = buf0 + S::NV * g.W * g.W;
+  const int tile = blockIdx.x;
+  const int a = tile % g.ntx, b = tile / g.ntx;
+  const int x0 = g.off + a * g.n, y0 = g.off + b * g.n;
+  const int n = g.n, W = g.W, plane = W * W;
+  const size_t gplane = (size_t)g.nx * g.ny;
+  const float invn = 1.0f / (float)n;
+  gather<V>(
+      S::NV * n * n,
+      [&](int q) -> V {
+        int vr, c, v, r;
+        fdivmod(q, n, invn, vr, c);
+        fdivmod(vr, n, invn, v, r);
+        return state[v * gplane + (size_t)wrap(y0 + r, g.ny) * g.nx + wrap(x0 + c, g.nx)];
+      },
+      [&](int q, V val) {
+        int vr, c, v, r;
+        fdivmod(q, n, invn, vr, c);
+        fdivmod(vr, n, invn, v, r);
+        buf0[v * plane + (r + 1) * W + (c + 1)] = val;
+      });
+  __syncthreads();
+  up_levels<S>(buf0, buf1, 0, g, tile, x0, y0, level_base(g), H, state, static_cast<V*>(pp.up), sp);
+}
+
+// x-bridges (blocks 0 .. ntiles-1, over the east edge of each tile) and
+// y-bridges (blocks ntiles .. 2 ntiles-1, over the south edge), Alg. 2-3.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, typename S::V* __restrict__ state,
+                                                     PanelPtrs pp, SchemeParams sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  extern __shared__ double smem_d[];
+  V* buf0 = reinterpret_cast<V*>(smem_d);
+  V* buf1 = buf0 + NV * g.W * g.W;
+  V* stg = buf1 + NV * g.W * g.W;
+  const int ntiles = g.ntx * g.nty;
+  const bool isx = (int)blockIdx.x < ntiles;
+  const int e = isx ? (int)blockIdx.x : (int)blockIdx.x - ntiles;
+  const int a = e % g.ntx, b = e / g.ntx;
+  const int n = g.n, h = g.h;
+  int xw0, yw0, tB;
+  if (isx) {
+    xw0 = g.off + (a + 1) * n - h - 1;
+    yw0 = g.off + b * n - 1;
+    tB = b * g.ntx + (a + 1 == g.ntx ? 0 : a + 1);
+  } else {
+    xw0 = g.off + a * n - 1;
+    yw0 = g.off + (b + 1) * n - h - 1;
+    tB = (b + 1 == g.nty ? 0 : b + 1) * g.ntx + a;
+  }
+  const V* up = static_cast<const V*>(pp.up);
+  V* out = static_cast<V*>(isx ? pp.xb : pp.yb);
+  const long long T0 = level_base(g);
+  const int LH = 2 * NV * up_levels_len(n, H);
+  if (staged) {
+    const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
+    const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
+    stage_runs<V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
+    __syncthreads();
+  }
+  Fetch<S> f;
+  for (int l = 0; l <= H; ++l) {
+    V* cur = (l & 1) ? buf1 : buf0;
+    const V* prv = (l & 1) ? buf0 : buf1;
+    if (!staged && l < H) fetch_strips<S>(f, isx, g, l, up, e, tB);
+    if (l >= 1 && l <= h - 1) {
+      if (isx)
+        compute_rect<S>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
+      else
+        compute_rect<S>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+    }
+    if (l < H) {
+      if (staged)
+        place_strips_staged<S>(stg, cur, isx, g, l, LH);
+      else
+        place_fetched<S>(f, cur);
+    }
+    __syncthreads();
+    if (l < H) emit_bridge<S>(cur, out, isx, g, e, l);
+  }
+  if (H < h) {
+    const V* fin = (H & 1) ? buf1 : buf0;
+    if (isx)
+      write_rect<S>(fin, state, g, xw0, yw0, h + 1 - H, H + 1, 2 * H, n - 2 * H);
+    else
+      write_rect<S>(fin, state, g, xw0, yw0, H + 1, h + 1 - H, n - 2 * H, 2 * H);
+  }
+}
+
+// Downward pyramid at the south-east corner of every tile (Alg. 4), fused
+// with the next half cycle's upward pyramid of the tile centred on that
+// corner (an octahedron): the level-h tile never leaves LDS.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int staged,
+                                                  typename S::V* __restrict__ state, PanelPtrs pp, SchemeParams sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  extern __shared__ double smem_d[];
+  V* buf0 = reinterpret_cast<V*>(smem_d);
+  V* buf1 = buf0 + NV * g.W * g.W;
+  V* stg = buf1 + NV * g.W * g.W;
+  const int c = blockIdx.x;
+  const int a = c % g.ntx, b = c / g.ntx;
+  const int n = g.n, h = g.h;
+  const int a1 = (a + 1 == g.ntx) ? 0 : a + 1, b1 = (b + 1 == g.nty) ? 0 : b + 1;
+  const int eTop = c, eBot = b1 * g.ntx + a, eLeft = c, eRight = b * g.ntx + a1;
+  const int xw0 = g.off + (a + 1) * n - h - 1, yw0 = g.off + (b + 1) * n - h - 1;
+  const V* xb = static_cast<const V*>(pp.xb);
+  const V* yb = static_cast<const V*>(pp.yb);
+  const long long T0 = level_base(g);
+  const int LxH = 2 * NV * xb_levels_len(Hd), LyH = 2 * NV * yb_levels_len(Hd);
+  if (staged) {
+    stage_runs<V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
+                  yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
+    __syncthreads();
+  }
+  Fetch<S> f;
+  for (int l = 0; l <= Hd; ++l) {
+    V* cur = (l & 1) ? buf1 : buf0;
+    const V* prv = (l & 1) ? buf0 : buf1;
+    if (!staged && l < Hd) fetch_ring<S>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
+    if (l >= 1) compute_rect<S>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+    if (l < Hd) {
+      if (staged)
+        place_ring_staged<S>(stg, cur, g, l, LxH, LyH);
+      else
+        place_fetched<S>(f, cur);
+    }
+    __syncthreads();
+  }
+  const V* top = (Hd & 1) ? buf1 : buf0;
+  if (Hd < h) {
+    write_rect<S>(top, state, g, xw0, yw0, h + 1 - Hd, h + 1 - Hd, 2 * Hd, 2 * Hd);
+    return;
+  }
+  if (Hu == 0) {
+    write_rect<S>(top, state, g, xw0, yw0, 1, 1, n, n);
+    return;
+  }
+  // The tile centred on this corner is tile (a, b) of the tiling shifted by h
+  // (tile (a+1, b+1) of the unshifted one when the shift wraps to 0).
+  Geo g2 = g;
+  g2.off = g.off + h;
+  int a2 = a, b2 = b;
+  if (g2.off == n) {
+    g2.off = 0;
+    a2 = a1;
+    b2 = b1;
+  }
+  up_levels<S>(buf0, buf1, h & 1, g2, b2 * g.ntx + a2, xw0 + 1, yw0 + 1, T0 + h, Hu, state,
+               static_cast<V*>(pp.up), sp);
+}
+
+template <class V, int NV>
+struct RegNb {
+  const V (*rw)[3][NV];
+  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return rw[dj + 1][di + 1][v]; }
+};
+
+template <class S>
+constexpr int plain_rows() {
+  return S::NV >= 8 ? 2 : 8;
+}
+
+// One sub-step of every point (the classical per-step update). Block 64 x 4;
+// each thread walks plain_rows rows of one column, keeping three rows of its
+// 3-wide neighbourhood in registers.
+template <class S>
+__global__ __launch_bounds__(256) void k_plain(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                               int nx, int ny, long long Trel, const long long* tbase,
+                                               SchemeParams sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  constexpr int R = plain_rows<S>();
+  const long long T = Trel + (tbase ? *tbase : 0LL);
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int ys = (blockIdx.y * 4 + threadIdx.y) * R;
+  if (x >= nx || ys >= ny) return;
+  const int xw = (x == 0) ? nx - 1 : x - 1;
+  const int xe = (x == nx - 1) ? 0 : x + 1;
+  const size_t plane = (size_t)nx * ny;
+  V rw[3][3][NV];
+  auto load = [&](V(&row)[3][NV], int y) {
+    if (y < 0) y += ny;
+    if (y >= ny) y -= ny;
+    const V* base = in + (size_t)y * nx;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      row[0][v] = base[v * plane + xw];
+      row[1][v] = base[v * plane + x];
+      row[2][v] = base[v * plane + xe];
+    }
+  };
+  load(rw[0], ys - 1);
+  load(rw[1], ys);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = ys + r;
+    if (y >= ny) break;
+    load(rw[2], y + 1);
+    const RegNb<V, NV> nb{rw};
+    V o[NV];
+    S::step(T, nb, o, sp);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * plane + (size_t)y * nx + x] = o[v];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        rw[0][i][v] = rw[1][i][v];
+        rw[1][i][v] = rw[2][i][v];
+      }
+  }
+}
+
+__global__ void k_copy8(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_set_base(long long* tbase, long long value) {
+  if (threadIdx.x == 0) *tbase = value;
+}
+
+// ------------------------------------------------------------ launchers
+
+template <class S>
+SchemeInfo info_of() {
+  return SchemeInfo{S::NV, S::NVAR, S::SUB, (int)sizeof(typename S::V)};
+}
+
+template <class S>
+hipError_t up_t(const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp, hipStream_t s) {
+  const size_t lds = window_lds_bytes(info_of<S>(), g.n);
+  hipLaunchKernelGGL(k_up<S>, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, H,
+                     static_cast<typename S::V*>(state), p, sp);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t bridge_t(const Geo& g, int H, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
+                    hipStream_t s) {
+  const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? bridge_stage_bytes(info_of<S>(), g.n) : 0);
+  hipLaunchKernelGGL(k_bridge<S>, dim3(2 * g.ntx * g.nty), dim3(kThreads), lds, s, g, H, staged ? 1 : 0,
+                     static_cast<typename S::V*>(state), p, sp);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t oct_t(const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
+                 hipStream_t s) {
+  const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? oct_stage_bytes(info_of<S>(), g.n) : 0);
+  hipLaunchKernelGGL(k_oct<S>, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, Hd, Hu, staged ? 1 : 0,
+                     static_cast<typename S::V*>(state), p, sp);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t plain_t(int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
+                   const SchemeParams& sp, hipStream_t s) {
+  constexpr int R = plain_rows<S>();
+  const dim3 grid((nx + 63) / 64, (ny + 4 * R - 1) / (4 * R));
+  hipLaunchKernelGGL(k_plain<S>, grid, dim3(64, 4), 0, s, static_cast<const typename S::V*>(in),
+                     static_cast<typename S::V*>(out), nx, ny, T, tbase, sp);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t lds_t(size_t bytes) {
+  const int b = (int)bytes;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_up<S>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge<S>), hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_oct<S>), hipFuncAttributeMaxDynamicSharedMemorySize, b);
+}
+
+#define SWEPT_DISPATCH(FN, ...)                       \
+  switch (scheme) {                                   \
+    case kHeat64: return FN<Heat64>(__VA_ARGS__);     \
+    case kWave64: return FN<Wave64>(__VA_ARGS__);     \
+    case kEuler64: return FN<Euler64>(__VA_ARGS__);   \
+    case kHash64: return FN<Hash64>(__VA_ARGS__);     \
+    case kIncr64: return FN<Incr64>(__VA_ARGS__);     \
+    case kPush5: return FN<Push5>(__VA_ARGS__);       \
+    case kHeat32C: return FN<Heat32C>(__VA_ARGS__);   \
+    case kWave32C: return FN<Wave32C>(__VA_ARGS__);   \
+    case kEuler32C: return FN<Euler32C>(__VA_ARGS__); \
+    default: break;                                   \
+  }
+
+}  // namespace
+
+SchemeInfo scheme_info(int scheme) {
+  SWEPT_DISPATCH(info_of)
+  return SchemeInfo{0, 0, 0, 0};
+}
+
+hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp,
+                     hipStream_t s) {
+  SWEPT_DISPATCH(up_t, g, H, state, p, sp, s)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, void* state, PanelPtrs p,
+                         const SchemeParams& sp, hipStream_t s) {
+  SWEPT_DISPATCH(bridge_t, g, H, staged, state, p, sp, s)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p,
+                      const SchemeParams& sp, hipStream_t s) {
+  SWEPT_DISPATCH(oct_t, g, Hd, Hu, staged, state, p, sp, s)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_plain(int scheme, int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
+                        const SchemeParams& sp, hipStream_t s) {
+  SWEPT_DISPATCH(plain_t, nx, ny, T, tbase, in, out, sp, s)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 8;
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_copy8, dim3(blocks), dim3(256), 0, s, static_cast<uint64_t*>(dst),
+                     static_cast<const uint64_t*>(src), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_base(long long* tbase, long long value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, tbase, value);
+  return hipGetLastError();
+}
+
+hipError_t configure_lds(size_t bytes) {
+  for (int scheme = 0; scheme < kNumSchemes; ++scheme) {
+    hipError_t e = [&]() -> hipError_t {
+      SWEPT_DISPATCH(lds_t, bytes)
+      return hipErrorInvalidValue;
+    }();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace swept

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (CPU only: no kernel is launched).
+
+The library must load and export every function include/swept2d.h declares;
+the Python binding must carry the same names; without a GPU, creating a handle
+fails with an error message instead of falling back to anything.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1602_07558_amd as sw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swept2d.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swept2d_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if sw._build.stale():
+        sw._build.build()
+    return sw.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("swept2d_create", "swept2d_advance", "swept2d_plain_advance"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", sw.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (swept2d_[a-z_]+)\b", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_binding_names_match_header():
+    assert sorted(sw.EXPORTS) == declared_functions()
+    for n in declared_functions():
+        assert callable(getattr(sw, n))
+
+
+def test_library_built_for_gfx950_without_contraction():
+    flags = sw._build.FLAGS
+    assert "--offload-arch=gfx950" in flags
+    assert "-ffp-contract=off" in flags
+    assert "-packed-fp32-ops" in flags
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device error path")
+def test_create_without_device_fails_loudly(lib):
+    h = lib.swept2d_create(64, 64, 1, sw.HEAT5, 1)
+    assert not h
+    assert sw.swept2d_last_error()
+
+
+def test_invalid_pde_shapes_rejected_before_device(lib):
+    assert not lib.swept2d_create(64, 64, 2, sw.HEAT5, 1)
+    assert "nvars" in sw.swept2d_last_error()
+    assert not lib.swept2d_create(64, 64, 1, 999, 1)
+    assert "unknown pde" in sw.swept2d_last_error()
+    assert not lib.swept2d_create(1, 64, 1, sw.HEAT5, 1)
+    assert not lib.swept2d_create(64, 64, 8, sw.EULER_RUS_RK2, 1)
+
+
+def test_null_handle_calls_return_einval(lib):
+    assert lib.swept2d_advance(None, 1) == sw.EINVAL
+    assert lib.swept2d_plain_advance(None, 1) == sw.EINVAL
+    assert lib.swept2d_set_tile(None, 8) == sw.EINVAL
+    assert lib.swept2d_synchronize(None) == sw.EINVAL
+    assert lib.swept2d_state_bytes(None) == 0
+    lib.swept2d_destroy(None)
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    monkeypatch.setattr(sw, "_lib", None)
+    monkeypatch.setattr(sw, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError):
+        sw.load_library()

@@ -339,7 +339,7 @@ def test_f32c_euler_error():
     ref = oracle.advance_f64(si.EULER_RUS_RK2, s, prm, 2 * steps)
     u, c = oracle.split_f32c(s)
     uc, cc = oracle.advance_f32c(si.EULER_RUS_RK2, u, c, prm, 2 * steps)
-    got = uc.astype(np.float64) + cc.astype(np.float64)
+    got = uc.astype(np.float64) - cc.astype(np.float64)
     assert _norm_rel(got[:4], ref[:4]) < 1e-6
 
 
