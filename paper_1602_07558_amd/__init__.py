@@ -72,6 +72,14 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1602_07558_amd/build.py "
                            "(or __graft_entry__.build())")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same
+    # soname as the system one); loading torch first makes the dynamic loader
+    # bind this library to torch's copy, so torch streams and allocations
+    # handed to the library belong to the runtime that executes its kernels.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, ll, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double
     sig = {

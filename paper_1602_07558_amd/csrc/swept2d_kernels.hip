@@ -65,16 +65,19 @@ __device__ __forceinline__ size_t yb_end(const Geo& g, int nv, int tile, int end
   return ((size_t)tile * 2 + end) * (size_t)(2 * nv * yb_levels_len(g.h));
 }
 
-// Gather `total` values into LDS with up to kBatch loads in flight per thread.
+// Gather `total` values into LDS with kBatch loads in flight per thread. The
+// loads are unconditional (indices clamped into range) so the compiler issues
+// them back to back; only the LDS stores are guarded.
 constexpr int kBatch = 16;
 template <class V, class Src, class Dst>
 __device__ __forceinline__ void gather(int total, Src src, Dst dst) {
+  if (total <= 0) return;
   for (int base = 0; base < total; base += kBatch * kThreads) {
     V r[kBatch];
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
       const int q = base + (int)threadIdx.x + i * kThreads;
-      if (q < total) r[i] = src(q);
+      r[i] = src(q < total ? q : total - 1);
     }
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
@@ -311,11 +314,13 @@ __device__ __forceinline__ void fetch_ring(Fetch<S>& f, const Geo& g, int l, con
     for (int i = 0; i < 2; ++i) {
       const int t = lane_id() + 64 * i;
       f.dst[j][i] = -1;
-      if (t < len) {
-        int wx, wy;
-        ring_pos(h, l, band, k, t, wx, wy);
-        f.val[j][i] = src[t];
-        f.dst[j][i] = v * plane + wy * W + wx;
+      if (len > 0) {
+        f.val[j][i] = src[t < len ? t : len - 1];
+        if (t < len) {
+          int wx, wy;
+          ring_pos(h, l, band, k, t, wx, wy);
+          f.dst[j][i] = v * plane + wy * W + wx;
+        }
       }
     }
   }
@@ -364,10 +369,10 @@ __device__ __forceinline__ void fetch_strips(Fetch<S>& f, bool isx, const Geo& g
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int t = lane_id() + 64 * i;
+      f.val[j][i] = src[t < len ? t : len - 1];
       if (t < len) {
         int wx, wy;
         strip_pos(isx, h, l, side, k, t, wx, wy);
-        f.val[j][i] = src[t];
         f.dst[j][i] = v * plane + wy * W + wx;
       }
     }

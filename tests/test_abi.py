@@ -95,3 +95,11 @@ def test_missing_library_raises(monkeypatch, tmp_path):
     monkeypatch.setattr(sw, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError):
         sw.load_library()
+
+
+def test_single_hip_runtime_in_process(lib):
+    """torch and the library must share one HIP runtime (torch's), so torch
+    streams and tensors passed to the library are valid in its runtime."""
+    maps = open("/proc/self/maps").read()
+    hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(hip) == 1, hip
