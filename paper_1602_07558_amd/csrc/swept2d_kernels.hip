@@ -3,16 +3,23 @@
 // Stage kernels: one workgroup of kThreads threads (8 waves) per tile
 // (upward pyramid, octahedron) or per tile edge (bridges). A workgroup keeps
 // its whole space-time component in LDS: a window of (n+2) x (n+2) points per
-// value slot, double buffered by level parity (the internal arrays U and D of
-// Algorithms 1-4). A level is one pass over that level's rectangle, threads
-// mapped densely onto the rectangle two points at a time, then one workgroup
-// barrier.
+// value slot (the internal arrays U and D of Algorithms 1-4). A level is one
+// pass over that level's rectangle, followed by a workgroup barrier.
 //
-// Panels (Sec. 3) travel through HBM between kernel launches. A consumer
-// either copies all its panel levels into LDS at its start, with every load
-// in flight at once (staged), or fetches level l+1 into registers before it
-// computes level l. Panel rows are read and written with lanes along the
-// panel, one (side, value, k) run per wave.
+// Every rectangle a component computes has even width and height, so a level
+// is tiled exactly by 2x2 quads: a thread computes a quad at a time, the four
+// points sharing their neighbourhood loads from one LDS base address. For the
+// two tile sides used at scale (32 and 64) the window pitch is a compile-time
+// constant and every neighbour offset is an immediate.
+//
+// Panels (Sec. 3) travel through HBM between kernel launches. A level's
+// panel strip is the two-wide boundary band of its rectangle; with double
+// buffering, the band of level l stays untouched in buffer l mod 2 for the
+// rest of the component (later levels of that parity lie strictly inside it),
+// so each kernel writes all its panel levels in one coalesced burst at its
+// end instead of once per level. A consumer either copies all its panel
+// levels into LDS at its start, with every load in flight at once (staged),
+// or fetches level l+1 into registers before it computes level l.
 //
 // The plain kernel advances every point by one sub-step, reading its 3x3
 // neighbourhood from HBM (rows kept in registers as a thread walks down a
@@ -36,7 +43,9 @@ struct WinNb {
 };
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+// Wave index as a wave-uniform (scalar) value, so per-wave loops branch on
+// scalars instead of masking lanes.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 __device__ __forceinline__ int wrap(int x, int m) {
   if (x < 0) x += m;
@@ -65,9 +74,11 @@ __device__ __forceinline__ size_t yb_end(const Geo& g, int nv, int tile, int end
   return ((size_t)tile * 2 + end) * (size_t)(2 * nv * yb_levels_len(g.h));
 }
 
-// Gather `total` values into LDS with kBatch loads in flight per thread. The
-// loads are unconditional (indices clamped into range) so the compiler issues
-// them back to back; only the LDS stores are guarded.
+// Gather `total` values into LDS with up to kBatch loads in flight per
+// thread. Within a batch the loads are unconditional (indices clamped into
+// range) so they issue back to back; the batch stops at the first row of
+// kThreads that lies wholly past the end (a uniform test), and only the LDS
+// stores are guarded.
 constexpr int kBatch = 16;
 template <class V, class Src, class Dst>
 __device__ __forceinline__ void gather(int total, Src src, Dst dst) {
@@ -76,11 +87,13 @@ __device__ __forceinline__ void gather(int total, Src src, Dst dst) {
     V r[kBatch];
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
+      if (base + i * kThreads >= total) break;
       const int q = base + (int)threadIdx.x + i * kThreads;
       r[i] = src(q < total ? q : total - 1);
     }
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
+      if (base + i * kThreads >= total) break;
       const int q = base + (int)threadIdx.x + i * kThreads;
       if (q < total) dst(q, r[i]);
     }
@@ -104,51 +117,56 @@ __device__ __forceinline__ void stage_runs(V* __restrict__ lds, const V* s0, int
       [&](int q, V v) { lds[q] = v; });
 }
 
+// ------------------------------------------------------------------ quads
+
+// The four points of a quad: o[0] = (x, y), o[1] = (x+1, y), o[2] = (x, y+1),
+// o[3] = (x+1, y+1).
 template <class S>
-__device__ __forceinline__ void point(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int idx,
-                                      int W, int plane, long long T, const SchemeParams& sp) {
-  using V = typename S::V;
-  const WinNb<V> nb{in + idx, W, plane};
-  V o[S::NV];
-  S::step(T, nb, o, sp);
-#pragma unroll
-  for (int v = 0; v < S::NV; ++v) out[v * plane + idx] = o[v];
+struct Quad {
+  typename S::V o[4][S::NV];
+};
+
+template <class S, int WC>
+__device__ __forceinline__ void quad_step(const typename S::V* __restrict__ in, int idx, int Wrt, long long T,
+                                          const SchemeParams& sp, Quad<S>& q) {
+  const int W = WC ? WC : Wrt, plane = W * W;
+  S::step(T, WinNb<typename S::V>{in + idx, W, plane}, q.o[0], sp);
+  S::step(T, WinNb<typename S::V>{in + idx + 1, W, plane}, q.o[1], sp);
+  S::step(T, WinNb<typename S::V>{in + idx + W, W, plane}, q.o[2], sp);
+  S::step(T, WinNb<typename S::V>{in + idx + W + 1, W, plane}, q.o[3], sp);
 }
 
-// One level: every point of the window rectangle [x0, x0+w) x [y0, y0+hg)
-// gets the sub-step T applied to its neighbourhood in `in`, into `out`.
-// Thread t takes points t, t + kThreads, ... of the rectangle in row-major
-// order, two per iteration; the window index advances incrementally.
-template <class S>
-__device__ __forceinline__ void compute_rect(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
-                                             int W, int x0, int y0, int w, int hg, long long T,
-                                             const SchemeParams& sp) {
-  const int npts = w * hg;
-  if (npts <= 0) return;
-  const int plane = W * W;
-  const float invw = 1.0f / (float)w;
-  int dy, dx, y, x;
-  fdivmod(kThreads, w, invw, dy, dx);
-  fdivmod((int)threadIdx.x, w, invw, y, x);
-  int idx = (y0 + y) * W + x0 + x;
-  const int didx = dy * W + dx, carry = W - w;
-  int p = (int)threadIdx.x;
-  for (; p + kThreads < npts; p += 2 * kThreads) {
-    int x1 = x + dx, i1 = idx + didx;
-    if (x1 >= w) {
-      x1 -= w;
-      i1 += carry;
-    }
-    point<S>(in, out, idx, W, plane, T, sp);
-    point<S>(in, out, i1, W, plane, T, sp);
-    x = x1 + dx;
-    idx = i1 + didx;
-    if (x >= w) {
-      x -= w;
-      idx += carry;
-    }
+template <class S, int WC>
+__device__ __forceinline__ void quad_store(typename S::V* __restrict__ out, int idx, int Wrt, const Quad<S>& q) {
+  const int W = WC ? WC : Wrt, plane = W * W;
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) {
+    out[v * plane + idx] = q.o[0][v];
+    out[v * plane + idx + 1] = q.o[1][v];
+    out[v * plane + idx + W] = q.o[2][v];
+    out[v * plane + idx + W + 1] = q.o[3][v];
   }
-  if (p < npts) point<S>(in, out, idx, W, plane, T, sp);
+}
+
+// One level, double buffered: every quad of the window rectangle
+// [x0, x0+w) x [y0, y0+hg) gets sub-step T from `in` into `out`; thread t
+// takes quads t, t + kThreads, ... in row-major quad order.
+template <class S, int WC>
+__device__ __forceinline__ void compute_quads(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                              int Wrt, int x0, int y0, int w, int hg, long long T,
+                                              const SchemeParams& sp) {
+  const int W = WC ? WC : Wrt;
+  const int bw = w >> 1, nq = bw * (hg >> 1);
+  if (nq <= 0) return;
+  const float inv = 1.0f / (float)bw;
+  for (int q = threadIdx.x; q < nq; q += kThreads) {
+    int by, bx;
+    fdivmod(q, bw, inv, by, bx);
+    const int idx = (y0 + 2 * by) * W + x0 + 2 * bx;
+    Quad<S> r;
+    quad_step<S, WC>(in, idx, W, T, sp, r);
+    quad_store<S, WC>(out, idx, W, r);
+  }
 }
 
 // Window -> state for the rectangle [wx0, wx0+w) x [wy0, wy0+hg); the window
@@ -171,54 +189,56 @@ __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V*
   }
 }
 
-// Upward-pyramid panels of level l (Alg. 1): the two outermost rows/columns
-// of the level-l square [l+1, n-l+1)^2 of the window, one strip per side.
+// All upward-pyramid panels of levels 0..H-1 (Alg. 1), written at the end
+// of the pyramid: strip k of side `end` at level l is the row / column at
+// distance l + k from the tile edge, read from buffer (b0 + l) mod 2 where
+// the level's band survives. Unit u = (l, end, v, k) per wave, lanes along
+// the strip.
 template <class S>
-__device__ void emit_up(const typename S::V* __restrict__ win, typename S::V* __restrict__ up, const Geo& g,
-                        int tile, int l) {
+__device__ void emit_up_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1, int b0,
+                            typename S::V* __restrict__ up, const Geo& g, int tile, int H) {
   constexpr int NV = S::NV;
-  const int n = g.n, W = g.W, plane = W * W, len = n - 2 * l;
-  const size_t lev = (size_t)2 * NV * up_levels_len(n, l);
-  for (int u = wave_id(); u < 8 * NV; u += kWaves) {
-    const int end = u / (2 * NV), rem = u - end * 2 * NV;  // rem = 2 v + k
+  const int n = g.n, W = g.W, plane = W * W;
+  const int per = 8 * NV;
+  for (int u = wave_id(); u < per * H; u += kWaves) {
+    const int l = u / per, r8 = u - l * per;
+    const int end = r8 / (2 * NV), rem = r8 - end * 2 * NV;  // rem = 2 v + k
     const int v = rem >> 1, k = rem & 1;
-    typename S::V* dst = up + up_end(g, NV, tile, end) + lev + (size_t)rem * len;
-    for (int t = lane_id(); t < len; t += 64) {
-      int wx, wy;
-      if (end == 0) {
-        wy = l + 1 + k;
-        wx = l + 1 + t;
-      } else if (end == 1) {
-        wy = n - l - k;
-        wx = l + 1 + t;
-      } else if (end == 2) {
-        wx = l + 1 + k;
-        wy = l + 1 + t;
-      } else {
-        wx = n - l - k;
-        wy = l + 1 + t;
-      }
-      dst[t] = win[v * plane + wy * W + wx];
+    const int len = n - 2 * l;
+    const typename S::V* win = ((b0 + l) & 1) ? buf1 : buf0;
+    typename S::V* dst = up + up_end(g, NV, tile, end) + (size_t)2 * NV * up_levels_len(n, l) + (size_t)rem * len;
+    int wx0, wy0, dx, dy;  // window position of t = 0 and step along the strip
+    if (end == 0) {
+      wx0 = l + 1, wy0 = l + 1 + k, dx = 1, dy = 0;
+    } else if (end == 1) {
+      wx0 = l + 1, wy0 = n - l - k, dx = 1, dy = 0;
+    } else if (end == 2) {
+      wx0 = l + 1 + k, wy0 = l + 1, dx = 0, dy = 1;
+    } else {
+      wx0 = n - l - k, wy0 = l + 1, dx = 0, dy = 1;
     }
+    const typename S::V* src = win + v * plane + wy0 * W + wx0;
+    const int stride = dy * W + dx;
+    for (int t = lane_id(); t < len; t += 64) dst[t] = src[t * stride];
   }
 }
 
 // Levels 1..H of the upward pyramid of `tile` whose level 0 (the whole tile,
-// window interior) is in buffer b0. Emits the panels of levels 0..H-1; when
-// H < h (reduced last half cycle) writes the level-H square to the state.
-template <class S>
+// window interior) is in buffer b0, then its panels of levels 0..H-1; when
+// H < h (reduced last half cycle) it also writes the level-H square to the
+// state.
+template <class S, int WC>
 __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, const Geo& g, int tile, int x0, int y0,
                           long long T0, int H, typename S::V* state, typename S::V* up, const SchemeParams& sp) {
   const int n = g.n, h = g.h;
-  for (int l = 0; l <= H; ++l) {
+  const int top = H < h - 1 ? H : h - 1;
+  for (int l = 1; l <= top; ++l) {
     typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
-    if (l >= 1 && l <= h - 1) {
-      const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
-      compute_rect<S>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
-      __syncthreads();
-    }
-    if (l < H) emit_up<S>(cur, up, g, tile, l);
+    const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
+    compute_quads<S, WC>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
+    __syncthreads();
   }
+  emit_up_all<S>(buf0, buf1, b0, up, g, tile, H);
   if (H < h) {
     const typename S::V* fin = ((b0 + H) & 1) ? buf1 : buf0;
     write_rect<S>(fin, state, g, x0 - 1, y0 - 1, H + 1, H + 1, n - 2 * H, n - 2 * H);
@@ -379,36 +399,38 @@ __device__ __forceinline__ void fetch_strips(Fetch<S>& f, bool isx, const Geo& g
   }
 }
 
-// Bridge panels of level l: the two end bands of the bridge's level-l
-// rectangle. x-bridge: window rows l+1+k (N end) and n-l-k (S end), columns
-// h-l-1 .. h+l+2 (the band plus the pyramid corners placed beside it).
-// y-bridge: columns l+1+k (W end) and n-l-k (E end), rows h+1-l .. h+l.
+// All bridge panels of levels 0..H-1 (Alg. 2-3), written at the end of the
+// bridge from the buffers where each level's bands survive. x-bridge: window
+// rows l+1+k (N end) and n-l-k (S end), columns h-l-1 .. h+l+2 (the band and
+// the pyramid corners placed beside it). y-bridge: columns l+1+k (W end) and
+// n-l-k (E end), rows h+1-l .. h+l.
 template <class S>
-__device__ void emit_bridge(const typename S::V* __restrict__ win, typename S::V* __restrict__ out, bool isx,
-                            const Geo& g, int e, int l) {
+__device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1,
+                                typename S::V* __restrict__ out, bool isx, const Geo& g, int e, int H) {
   constexpr int NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W;
-  const int len = isx ? 2 * l + 4 : 2 * l;
-  if (len == 0) return;
-  for (int u = wave_id(); u < 4 * NV; u += kWaves) {
-    const int end = u / (2 * NV), rem = u - end * 2 * NV, v = rem >> 1, k = rem & 1;
+  const int per = 4 * NV;
+  for (int u = wave_id(); u < per * H; u += kWaves) {
+    const int l = u / per, r4 = u - l * per;
+    const int end = r4 / (2 * NV), rem = r4 - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    const int len = isx ? 2 * l + 4 : 2 * l;
+    const typename S::V* win = (l & 1) ? buf1 : buf0;
     typename S::V* dst = out +
                          (isx ? xb_end(g, NV, e, end) + 2 * NV * xb_levels_len(l)
                               : yb_end(g, NV, e, end) + 2 * NV * yb_levels_len(l)) +
                          (size_t)rem * len;
     const int across = end ? (n - l - k) : (l + 1 + k);
-    for (int t = lane_id(); t < len; t += 64) {
-      const int wx = isx ? (h - l - 1 + t) : across;
-      const int wy = isx ? across : (h + 1 - l + t);
-      dst[t] = win[v * plane + wy * W + wx];
-    }
+    const typename S::V* src =
+        win + v * plane + (isx ? (across * W + (h - l - 1)) : ((h + 1 - l) * W + across));
+    const int stride = isx ? 1 : W;
+    for (int t = lane_id(); t < len; t += 64) dst[t] = src[t * stride];
   }
 }
 
 // ----------------------------------------------------------------- kernels
 
 // Upward pyramid of every tile, from the state (Alg. 1).
-template <class S>
+template <class S, int WC>
 __global__ __launch_bounds__(kThreads) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
                                                  SchemeParams sp) {
   using V = typename S::V;
@@ -436,12 +458,12 @@ __global__ __launch_bounds__(kThreads) void k_up(Geo g, int H, typename S::V* __
         buf0[v * plane + (r + 1) * W + (c + 1)] = val;
       });
   __syncthreads();
-  up_levels<S>(buf0, buf1, 0, g, tile, x0, y0, level_base(g), H, state, static_cast<V*>(pp.up), sp);
+  up_levels<S, WC>(buf0, buf1, 0, g, tile, x0, y0, level_base(g), H, state, static_cast<V*>(pp.up), sp);
 }
 
 // x-bridges (blocks 0 .. ntiles-1, over the east edge of each tile) and
 // y-bridges (blocks ntiles .. 2 ntiles-1, over the south edge), Alg. 2-3.
-template <class S>
+template <class S, int WC>
 __global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, typename S::V* __restrict__ state,
                                                      PanelPtrs pp, SchemeParams sp) {
   using V = typename S::V;
@@ -482,9 +504,9 @@ __global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, t
     if (!staged && l < H) fetch_strips<S>(f, isx, g, l, up, e, tB);
     if (l >= 1 && l <= h - 1) {
       if (isx)
-        compute_rect<S>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
+        compute_quads<S, WC>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
       else
-        compute_rect<S>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+        compute_quads<S, WC>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
     }
     if (l < H) {
       if (staged)
@@ -493,8 +515,8 @@ __global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, t
         place_fetched<S>(f, cur);
     }
     __syncthreads();
-    if (l < H) emit_bridge<S>(cur, out, isx, g, e, l);
   }
+  emit_bridge_all<S>(buf0, buf1, out, isx, g, e, H);
   if (H < h) {
     const V* fin = (H & 1) ? buf1 : buf0;
     if (isx)
@@ -507,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, t
 // Downward pyramid at the south-east corner of every tile (Alg. 4), fused
 // with the next half cycle's upward pyramid of the tile centred on that
 // corner (an octahedron): the level-h tile never leaves LDS.
-template <class S>
+template <class S, int WC>
 __global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int staged,
                                                   typename S::V* __restrict__ state, PanelPtrs pp, SchemeParams sp) {
   using V = typename S::V;
@@ -524,8 +546,20 @@ __global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int sta
   const int xw0 = g.off + (a + 1) * n - h - 1, yw0 = g.off + (b + 1) * n - h - 1;
   const V* xb = static_cast<const V*>(pp.xb);
   const V* yb = static_cast<const V*>(pp.yb);
+  V* up = static_cast<V*>(pp.up);
   const long long T0 = level_base(g);
   const int LxH = 2 * NV * xb_levels_len(Hd), LyH = 2 * NV * yb_levels_len(Hd);
+  // The tile centred on this corner is tile (a, b) of the tiling shifted by h
+  // (tile (a+1, b+1) of the unshifted one when the shift wraps to 0).
+  Geo g2 = g;
+  g2.off = g.off + h;
+  int a2 = a, b2 = b;
+  if (g2.off == n) {
+    g2.off = 0;
+    a2 = a1;
+    b2 = b1;
+  }
+  const int tile2 = b2 * g.ntx + a2;
   if (staged) {
     stage_runs<V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
                   yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
@@ -536,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int sta
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
     if (!staged && l < Hd) fetch_ring<S>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
-    if (l >= 1) compute_rect<S>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+    if (l >= 1) compute_quads<S, WC>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
     if (l < Hd) {
       if (staged)
         place_ring_staged<S>(stg, cur, g, l, LxH, LyH);
@@ -554,18 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int sta
     write_rect<S>(top, state, g, xw0, yw0, 1, 1, n, n);
     return;
   }
-  // The tile centred on this corner is tile (a, b) of the tiling shifted by h
-  // (tile (a+1, b+1) of the unshifted one when the shift wraps to 0).
-  Geo g2 = g;
-  g2.off = g.off + h;
-  int a2 = a, b2 = b;
-  if (g2.off == n) {
-    g2.off = 0;
-    a2 = a1;
-    b2 = b1;
-  }
-  up_levels<S>(buf0, buf1, h & 1, g2, b2 * g.ntx + a2, xw0 + 1, yw0 + 1, T0 + h, Hu, state,
-               static_cast<V*>(pp.up), sp);
+  up_levels<S, WC>(buf0, buf1, h & 1, g2, tile2, xw0 + 1, yw0 + 1, T0 + h, Hu, state, up, sp);
 }
 
 template <class V, int NV>
@@ -646,11 +669,22 @@ SchemeInfo info_of() {
   return SchemeInfo{S::NV, S::NVAR, S::SUB, (int)sizeof(typename S::V)};
 }
 
+// Window pitch as a compile-time constant for tile sides 32 and 64.
+#define SWEPT_BY_PITCH(KERNEL, S, n, ...)               \
+  do {                                                  \
+    if ((n) == 64)                                      \
+      hipLaunchKernelGGL((KERNEL<S, 66>), __VA_ARGS__); \
+    else if ((n) == 32)                                 \
+      hipLaunchKernelGGL((KERNEL<S, 34>), __VA_ARGS__); \
+    else                                                \
+      hipLaunchKernelGGL((KERNEL<S, 0>), __VA_ARGS__);  \
+  } while (0)
+
 template <class S>
 hipError_t up_t(const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp, hipStream_t s) {
   const size_t lds = window_lds_bytes(info_of<S>(), g.n);
-  hipLaunchKernelGGL(k_up<S>, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, H,
-                     static_cast<typename S::V*>(state), p, sp);
+  SWEPT_BY_PITCH(k_up, S, g.n, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, H, static_cast<typename S::V*>(state),
+                 p, sp);
   return hipGetLastError();
 }
 
@@ -658,8 +692,8 @@ template <class S>
 hipError_t bridge_t(const Geo& g, int H, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
                     hipStream_t s) {
   const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? bridge_stage_bytes(info_of<S>(), g.n) : 0);
-  hipLaunchKernelGGL(k_bridge<S>, dim3(2 * g.ntx * g.nty), dim3(kThreads), lds, s, g, H, staged ? 1 : 0,
-                     static_cast<typename S::V*>(state), p, sp);
+  SWEPT_BY_PITCH(k_bridge, S, g.n, dim3(2 * g.ntx * g.nty), dim3(kThreads), lds, s, g, H, staged ? 1 : 0,
+                 static_cast<typename S::V*>(state), p, sp);
   return hipGetLastError();
 }
 
@@ -667,8 +701,8 @@ template <class S>
 hipError_t oct_t(const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
                  hipStream_t s) {
   const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? oct_stage_bytes(info_of<S>(), g.n) : 0);
-  hipLaunchKernelGGL(k_oct<S>, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, Hd, Hu, staged ? 1 : 0,
-                     static_cast<typename S::V*>(state), p, sp);
+  SWEPT_BY_PITCH(k_oct, S, g.n, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, Hd, Hu, staged ? 1 : 0,
+                 static_cast<typename S::V*>(state), p, sp);
   return hipGetLastError();
 }
 
@@ -682,15 +716,26 @@ hipError_t plain_t(int nx, int ny, long long T, const long long* tbase, const vo
   return hipGetLastError();
 }
 
+template <class S, int WC>
+hipError_t lds_one(int b) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_up<S, WC>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge<S, WC>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          b);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_oct<S, WC>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             b);
+}
+
 template <class S>
 hipError_t lds_t(size_t bytes) {
   const int b = (int)bytes;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_up<S>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  hipError_t e = lds_one<S, 0>(b);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge<S>), hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  e = lds_one<S, 34>(b);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_oct<S>), hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  return lds_one<S, 66>(b);
 }
 
 #define SWEPT_DISPATCH(FN, ...)                       \
