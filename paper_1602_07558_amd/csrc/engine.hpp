@@ -9,8 +9,23 @@
 
 namespace swept {
 
-constexpr int kThreads = 512;  // threads per workgroup of every stage kernel (8 waves)
-constexpr int kWaves = kThreads / 64;
+// Thread layout of a stage kernel instantiation (WC: compile-time window
+// pitch, 66 for tile side 64, 34 for 32, 0 for any other side).
+//  - Schemes with at most 16 bytes of state per point ("light") run 16 waves
+//    (4 for tile side 32); the Euler schemes 8 waves.
+//  - Light schemes at a fixed pitch use column ownership: thread t owns
+//    window column 1 + t mod N and the R rows from 1 + R (t div N) at every
+//    level, N = WC - 2, R = N^2 / NT. Otherwise a level is split into 2x2
+//    quads handed out round robin.
+template <class S, int WC>
+struct Lay {
+  static constexpr bool light = S::NV * (int)sizeof(typename S::V) <= 16;
+  static constexpr int N = WC ? WC - 2 : 0;
+  static constexpr int NT = !light ? 512 : (WC == 34 ? 256 : 1024);
+  static constexpr int NW = NT / 64;
+  static constexpr bool cols = light && WC != 0;
+  static constexpr int R = cols ? N * N / NT : 0;
+};
 
 // Geometry of one half cycle of the swept decomposition.
 //

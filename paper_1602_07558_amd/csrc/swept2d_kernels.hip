@@ -1,6 +1,6 @@
 // HIP kernels of the swept rule for gfx950 (CDNA4).
 //
-// Stage kernels: one workgroup of kThreads threads (8 waves) per tile
+// Stage kernels: one workgroup of 16 waves (8 for the Euler schemes) per tile
 // (upward pyramid, octahedron) or per tile edge (bridges). A workgroup keeps
 // its whole space-time component in LDS: a window of (n+2) x (n+2) points per
 // value slot (the internal arrays U and D of Algorithms 1-4). A level is one
@@ -80,7 +80,7 @@ __device__ __forceinline__ size_t yb_end(const Geo& g, int nv, int tile, int end
 // kThreads that lies wholly past the end (a uniform test), and only the LDS
 // stores are guarded.
 constexpr int kBatch = 16;
-template <class V, class Src, class Dst>
+template <int kThreads, class V, class Src, class Dst>
 __device__ __forceinline__ void gather(int total, Src src, Dst dst) {
   if (total <= 0) return;
   for (int base = 0; base < total; base += kBatch * kThreads) {
@@ -101,11 +101,11 @@ __device__ __forceinline__ void gather(int total, Src src, Dst dst) {
 }
 
 // Copy up to four contiguous global runs, back to back, into LDS.
-template <class V>
+template <int kThreads, class V>
 __device__ __forceinline__ void stage_runs(V* __restrict__ lds, const V* s0, int n0, const V* s1, int n1, const V* s2,
                                            int n2, const V* s3, int n3) {
   const int e1 = n0, e2 = n0 + n1, e3 = n0 + n1 + n2, total = e3 + n3;
-  gather<V>(
+  gather<kThreads, V>(
       total,
       [&](int q) -> V {
         const V* p = s0 + q;
@@ -151,10 +151,11 @@ __device__ __forceinline__ void quad_store(typename S::V* __restrict__ out, int 
 // One level, double buffered: every quad of the window rectangle
 // [x0, x0+w) x [y0, y0+hg) gets sub-step T from `in` into `out`; thread t
 // takes quads t, t + kThreads, ... in row-major quad order.
-template <class S, int WC>
+template <class S, int WC, int kThreads>
 __device__ __forceinline__ void compute_quads(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
+  constexpr int kWaves = kThreads / 64;
   const int W = WC ? WC : Wrt;
   const int bw = w >> 1, nq = bw * (hg >> 1);
   if (nq <= 0) return;
@@ -169,11 +170,65 @@ __device__ __forceinline__ void compute_quads(const typename S::V* __restrict__ 
   }
 }
 
+template <class V, int NV>
+struct RegNb {
+  const V (*rw)[3][NV];
+  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return rw[dj + 1][di + 1][v]; }
+};
+
+// One level with column ownership: the rows of the thread's column that lie
+// in the rectangle [x0, x0+w) x [y0, y0+hg) get sub-step T from `in` into
+// `out`. The (R+2) x 3 neighbourhood is read into registers with fixed
+// offsets; rows outside the rectangle are computed from whatever the window
+// holds there and not stored. Lanes are consecutive columns, so every LDS
+// access of a wave is one contiguous run.
+template <class S, int WC>
+__device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                             int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC>::N, R = Lay<S, WC>::R;
+  const int t = (int)threadIdx.x;
+  const int c = 1 + t % N, r0 = 1 + R * (t / N);
+  if ((unsigned)(c - x0) >= (unsigned)w) return;
+  if (r0 + R <= y0 || r0 >= y0 + hg) return;
+  const V* src = in + (r0 - 1) * W + c - 1;
+  V nb[R + 2][3][NV];
+#pragma unroll
+  for (int i = 0; i < R + 2; ++i)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) nb[i][d][v] = src[v * plane + i * W + d];
+  V* dst = out + r0 * W + c;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    V o[NV];
+    S::step(T, RegNb<V, NV>{&nb[i]}, o, sp);
+    if ((unsigned)(r0 + i - y0) < (unsigned)hg) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+    }
+  }
+}
+
+// One level of a stage kernel: column ownership where the layout has it,
+// 2x2 quads otherwise.
+template <class S, int WC>
+__device__ __forceinline__ void compute_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                              int Wrt, int x0, int y0, int w, int hg, long long T,
+                                              const SchemeParams& sp) {
+  if constexpr (Lay<S, WC>::cols)
+    compute_cols<S, WC>(in, out, x0, y0, w, hg, T, sp);
+  else
+    compute_quads<S, WC, Lay<S, WC>::NT>(in, out, Wrt, x0, y0, w, hg, T, sp);
+}
+
 // Window -> state for the rectangle [wx0, wx0+w) x [wy0, wy0+hg); the window
 // origin is global (xw0, yw0).
-template <class S>
+template <class S, int kThreads>
 __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V* __restrict__ state, const Geo& g,
                            int xw0, int yw0, int wx0, int wy0, int w, int hg) {
+  constexpr int kWaves = kThreads / 64;
   const int npts = w * hg;
   if (npts <= 0) return;
   const int plane = g.W * g.W;
@@ -194,9 +249,10 @@ __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V*
 // distance l + k from the tile edge, read from buffer (b0 + l) mod 2 where
 // the level's band survives. Unit u = (l, end, v, k) per wave, lanes along
 // the strip.
-template <class S>
+template <class S, int kThreads>
 __device__ void emit_up_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1, int b0,
                             typename S::V* __restrict__ up, const Geo& g, int tile, int H) {
+  constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int n = g.n, W = g.W, plane = W * W;
   const int per = 8 * NV;
@@ -230,28 +286,31 @@ __device__ void emit_up_all(const typename S::V* __restrict__ buf0, const typena
 template <class S, int WC>
 __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, const Geo& g, int tile, int x0, int y0,
                           long long T0, int H, typename S::V* state, typename S::V* up, const SchemeParams& sp) {
+  constexpr int NT = Lay<S, WC>::NT;
   const int n = g.n, h = g.h;
   const int top = H < h - 1 ? H : h - 1;
   for (int l = 1; l <= top; ++l) {
     typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
     const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
-    compute_quads<S, WC>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
+    compute_level<S, WC>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
     __syncthreads();
   }
-  emit_up_all<S>(buf0, buf1, b0, up, g, tile, H);
+  emit_up_all<S, NT>(buf0, buf1, b0, up, g, tile, H);
   if (H < h) {
     const typename S::V* fin = ((b0 + H) & 1) ? buf1 : buf0;
-    write_rect<S>(fin, state, g, x0 - 1, y0 - 1, H + 1, H + 1, n - 2 * H, n - 2 * H);
+    write_rect<S, NT>(fin, state, g, x0 - 1, y0 - 1, H + 1, H + 1, n - 2 * H, n - 2 * H);
   }
 }
 
 // Per-level panel inputs held in registers (fetch path): unit u = wave +
-// j * kWaves (j < NV covers 8 NV units for rings, 4 NV for bridges), lanes
-// along the run, two positions per lane (runs are at most n + 2 <= 128).
-template <class S>
+// j * kWaves, j < J (enough for the 8 NV units of a ring and the 4 NV of a
+// bridge), lanes along the run, two positions per lane (runs are at most
+// n + 2 <= 128).
+template <class S, int kThreads>
 struct Fetch {
-  typename S::V val[S::NV][2];
-  int dst[S::NV][2];
+  static constexpr int J = (8 * S::NV + kThreads / 64 - 1) / (kThreads / 64);
+  typename S::V val[J][2];
+  int dst[J][2];
 };
 
 // Window position of element t of ring band `band` (0 top, 1 bottom, 2 left,
@@ -288,9 +347,10 @@ __device__ __forceinline__ void strip_pos(bool isx, int h, int l, int side, int 
 
 // Ring of level l into the window from the staged LDS runs
 // [top | bottom | left | right], each of LxH or LyH values.
-template <class S>
+template <class S, int kThreads>
 __device__ __forceinline__ void place_ring_staged(const typename S::V* __restrict__ stg, typename S::V* __restrict__ win,
                                                   const Geo& g, int l, int LxH, int LyH) {
+  constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int h = g.h, W = g.W, plane = W * W;
   for (int u = wave_id(); u < 8 * NV; u += kWaves) {
@@ -308,15 +368,19 @@ __device__ __forceinline__ void place_ring_staged(const typename S::V* __restric
   }
 }
 
-template <class S>
-__device__ __forceinline__ void fetch_ring(Fetch<S>& f, const Geo& g, int l, const typename S::V* __restrict__ xb,
+template <class S, int kThreads>
+__device__ __forceinline__ void fetch_ring(Fetch<S, kThreads>& f, const Geo& g, int l, const typename S::V* __restrict__ xb,
                                            const typename S::V* __restrict__ yb, int eTop, int eBot, int eLeft,
                                            int eRight) {
+  constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int h = g.h, W = g.W, plane = W * W;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    const int u = wave_id() + j * kWaves;  // < 8 NV
+  for (int j = 0; j < Fetch<S, kThreads>::J; ++j) {
+    const int u = wave_id() + j * kWaves;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    if (u >= 8 * NV) continue;
     const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
     const bool horiz = band < 2;
     const int len = horiz ? 2 * l + 4 : 2 * l;
@@ -346,19 +410,20 @@ __device__ __forceinline__ void fetch_ring(Fetch<S>& f, const Geo& g, int l, con
   }
 }
 
-template <class S>
-__device__ __forceinline__ void place_fetched(const Fetch<S>& f, typename S::V* __restrict__ win) {
+template <class S, int kThreads>
+__device__ __forceinline__ void place_fetched(const Fetch<S, kThreads>& f, typename S::V* __restrict__ win) {
 #pragma unroll
-  for (int j = 0; j < S::NV; ++j)
+  for (int j = 0; j < Fetch<S, kThreads>::J; ++j)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
       if (f.dst[j][i] >= 0) win[f.dst[j][i]] = f.val[j][i];
 }
 
-template <class S>
+template <class S, int kThreads>
 __device__ __forceinline__ void place_strips_staged(const typename S::V* __restrict__ stg,
                                                     typename S::V* __restrict__ win, bool isx, const Geo& g, int l,
                                                     int LH) {
+  constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
   for (int u = wave_id(); u < 4 * NV; u += kWaves) {
@@ -372,13 +437,14 @@ __device__ __forceinline__ void place_strips_staged(const typename S::V* __restr
   }
 }
 
-template <class S>
-__device__ __forceinline__ void fetch_strips(Fetch<S>& f, bool isx, const Geo& g, int l,
+template <class S, int kThreads>
+__device__ __forceinline__ void fetch_strips(Fetch<S, kThreads>& f, bool isx, const Geo& g, int l,
                                              const typename S::V* __restrict__ up, int tA, int tB) {
+  constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) {
+  for (int j = 0; j < Fetch<S, kThreads>::J; ++j) {
     const int u = wave_id() + j * kWaves;
 #pragma unroll
     for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
@@ -404,9 +470,10 @@ __device__ __forceinline__ void fetch_strips(Fetch<S>& f, bool isx, const Geo& g
 // rows l+1+k (N end) and n-l-k (S end), columns h-l-1 .. h+l+2 (the band and
 // the pyramid corners placed beside it). y-bridge: columns l+1+k (W end) and
 // n-l-k (E end), rows h+1-l .. h+l.
-template <class S>
+template <class S, int kThreads>
 __device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1,
                                 typename S::V* __restrict__ out, bool isx, const Geo& g, int e, int H) {
+  constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W;
   const int per = 4 * NV;
@@ -431,8 +498,9 @@ __device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const ty
 
 // Upward pyramid of every tile, from the state (Alg. 1).
 template <class S, int WC>
-__global__ __launch_bounds__(kThreads) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
+__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
                                                  SchemeParams sp) {
+  constexpr int NT = Lay<S, WC>::NT;
   using V = typename S::V;
   extern __shared__ double smem_d[];
   V* buf0 = reinterpret_cast<V*>(smem_d);
@@ -443,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_up(Geo g, int H, typename S::V* __
   const int n = g.n, W = g.W, plane = W * W;
   const size_t gplane = (size_t)g.nx * g.ny;
   const float invn = 1.0f / (float)n;
-  gather<V>(
+  gather<NT, V>(
       S::NV * n * n,
       [&](int q) -> V {
         int vr, c, v, r;
@@ -464,8 +532,9 @@ __global__ __launch_bounds__(kThreads) void k_up(Geo g, int H, typename S::V* __
 // x-bridges (blocks 0 .. ntiles-1, over the east edge of each tile) and
 // y-bridges (blocks ntiles .. 2 ntiles-1, over the south edge), Alg. 2-3.
 template <class S, int WC>
-__global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, typename S::V* __restrict__ state,
+__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_bridge(Geo g, int H, int staged, typename S::V* __restrict__ state,
                                                      PanelPtrs pp, SchemeParams sp) {
+  constexpr int NT = Lay<S, WC>::NT;
   using V = typename S::V;
   constexpr int NV = S::NV;
   extern __shared__ double smem_d[];
@@ -494,35 +563,35 @@ __global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, t
   if (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
-    stage_runs<V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
+    stage_runs<NT, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
     __syncthreads();
   }
-  Fetch<S> f;
+  Fetch<S, NT> f;
   for (int l = 0; l <= H; ++l) {
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
-    if (!staged && l < H) fetch_strips<S>(f, isx, g, l, up, e, tB);
+    if (!staged && l < H) fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
     if (l >= 1 && l <= h - 1) {
       if (isx)
-        compute_quads<S, WC>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
+        compute_level<S, WC>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
       else
-        compute_quads<S, WC>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+        compute_level<S, WC>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
     }
     if (l < H) {
       if (staged)
-        place_strips_staged<S>(stg, cur, isx, g, l, LH);
+        place_strips_staged<S, NT>(stg, cur, isx, g, l, LH);
       else
-        place_fetched<S>(f, cur);
+        place_fetched<S, NT>(f, cur);
     }
     __syncthreads();
   }
-  emit_bridge_all<S>(buf0, buf1, out, isx, g, e, H);
+  emit_bridge_all<S, NT>(buf0, buf1, out, isx, g, e, H);
   if (H < h) {
     const V* fin = (H & 1) ? buf1 : buf0;
     if (isx)
-      write_rect<S>(fin, state, g, xw0, yw0, h + 1 - H, H + 1, 2 * H, n - 2 * H);
+      write_rect<S, NT>(fin, state, g, xw0, yw0, h + 1 - H, H + 1, 2 * H, n - 2 * H);
     else
-      write_rect<S>(fin, state, g, xw0, yw0, H + 1, h + 1 - H, n - 2 * H, 2 * H);
+      write_rect<S, NT>(fin, state, g, xw0, yw0, H + 1, h + 1 - H, n - 2 * H, 2 * H);
   }
 }
 
@@ -530,8 +599,9 @@ __global__ __launch_bounds__(kThreads) void k_bridge(Geo g, int H, int staged, t
 // with the next half cycle's upward pyramid of the tile centred on that
 // corner (an octahedron): the level-h tile never leaves LDS.
 template <class S, int WC>
-__global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int staged,
+__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_oct(Geo g, int Hd, int Hu, int staged,
                                                   typename S::V* __restrict__ state, PanelPtrs pp, SchemeParams sp) {
+  constexpr int NT = Lay<S, WC>::NT;
   using V = typename S::V;
   constexpr int NV = S::NV;
   extern __shared__ double smem_d[];
@@ -561,41 +631,35 @@ __global__ __launch_bounds__(kThreads) void k_oct(Geo g, int Hd, int Hu, int sta
   }
   const int tile2 = b2 * g.ntx + a2;
   if (staged) {
-    stage_runs<V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
+    stage_runs<NT, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
                   yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
     __syncthreads();
   }
-  Fetch<S> f;
+  Fetch<S, NT> f;
   for (int l = 0; l <= Hd; ++l) {
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
-    if (!staged && l < Hd) fetch_ring<S>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
-    if (l >= 1) compute_quads<S, WC>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+    if (!staged && l < Hd) fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
+    if (l >= 1) compute_level<S, WC>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
     if (l < Hd) {
       if (staged)
-        place_ring_staged<S>(stg, cur, g, l, LxH, LyH);
+        place_ring_staged<S, NT>(stg, cur, g, l, LxH, LyH);
       else
-        place_fetched<S>(f, cur);
+        place_fetched<S, NT>(f, cur);
     }
     __syncthreads();
   }
   const V* top = (Hd & 1) ? buf1 : buf0;
   if (Hd < h) {
-    write_rect<S>(top, state, g, xw0, yw0, h + 1 - Hd, h + 1 - Hd, 2 * Hd, 2 * Hd);
+    write_rect<S, NT>(top, state, g, xw0, yw0, h + 1 - Hd, h + 1 - Hd, 2 * Hd, 2 * Hd);
     return;
   }
   if (Hu == 0) {
-    write_rect<S>(top, state, g, xw0, yw0, 1, 1, n, n);
+    write_rect<S, NT>(top, state, g, xw0, yw0, 1, 1, n, n);
     return;
   }
   up_levels<S, WC>(buf0, buf1, h & 1, g2, tile2, xw0 + 1, yw0 + 1, T0 + h, Hu, state, up, sp);
 }
-
-template <class V, int NV>
-struct RegNb {
-  const V (*rw)[3][NV];
-  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return rw[dj + 1][di + 1][v]; }
-};
 
 template <class S>
 constexpr int plain_rows() {
@@ -669,21 +733,22 @@ SchemeInfo info_of() {
   return SchemeInfo{S::NV, S::NVAR, S::SUB, (int)sizeof(typename S::V)};
 }
 
-// Window pitch as a compile-time constant for tile sides 32 and 64.
-#define SWEPT_BY_PITCH(KERNEL, S, n, ...)               \
-  do {                                                  \
-    if ((n) == 64)                                      \
-      hipLaunchKernelGGL((KERNEL<S, 66>), __VA_ARGS__); \
-    else if ((n) == 32)                                 \
-      hipLaunchKernelGGL((KERNEL<S, 34>), __VA_ARGS__); \
-    else                                                \
-      hipLaunchKernelGGL((KERNEL<S, 0>), __VA_ARGS__);  \
+// Window pitch as a compile-time constant for tile sides 32 and 64; the
+// workgroup size follows the instantiation's layout.
+#define SWEPT_BY_PITCH(KERNEL, S, n, GRID, LDS, STREAM, ...)                                              \
+  do {                                                                                                    \
+    if ((n) == 64)                                                                                        \
+      hipLaunchKernelGGL((KERNEL<S, 66>), GRID, dim3(Lay<S, 66>::NT), LDS, STREAM, __VA_ARGS__);          \
+    else if ((n) == 32)                                                                                   \
+      hipLaunchKernelGGL((KERNEL<S, 34>), GRID, dim3(Lay<S, 34>::NT), LDS, STREAM, __VA_ARGS__);          \
+    else                                                                                                  \
+      hipLaunchKernelGGL((KERNEL<S, 0>), GRID, dim3(Lay<S, 0>::NT), LDS, STREAM, __VA_ARGS__);            \
   } while (0)
 
 template <class S>
 hipError_t up_t(const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp, hipStream_t s) {
   const size_t lds = window_lds_bytes(info_of<S>(), g.n);
-  SWEPT_BY_PITCH(k_up, S, g.n, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, H, static_cast<typename S::V*>(state),
+  SWEPT_BY_PITCH(k_up, S, g.n, dim3(g.ntx * g.nty), lds, s, g, H, static_cast<typename S::V*>(state),
                  p, sp);
   return hipGetLastError();
 }
@@ -692,7 +757,7 @@ template <class S>
 hipError_t bridge_t(const Geo& g, int H, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
                     hipStream_t s) {
   const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? bridge_stage_bytes(info_of<S>(), g.n) : 0);
-  SWEPT_BY_PITCH(k_bridge, S, g.n, dim3(2 * g.ntx * g.nty), dim3(kThreads), lds, s, g, H, staged ? 1 : 0,
+  SWEPT_BY_PITCH(k_bridge, S, g.n, dim3(2 * g.ntx * g.nty), lds, s, g, H, staged ? 1 : 0,
                  static_cast<typename S::V*>(state), p, sp);
   return hipGetLastError();
 }
@@ -701,7 +766,7 @@ template <class S>
 hipError_t oct_t(const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
                  hipStream_t s) {
   const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? oct_stage_bytes(info_of<S>(), g.n) : 0);
-  SWEPT_BY_PITCH(k_oct, S, g.n, dim3(g.ntx * g.nty), dim3(kThreads), lds, s, g, Hd, Hu, staged ? 1 : 0,
+  SWEPT_BY_PITCH(k_oct, S, g.n, dim3(g.ntx * g.nty), lds, s, g, Hd, Hu, staged ? 1 : 0,
                  static_cast<typename S::V*>(state), p, sp);
   return hipGetLastError();
 }
