@@ -50,6 +50,7 @@ extern "C" {
 #define SWEPT2D_EHIP (-2)         /* HIP runtime error; message carries hipGetErrorString */
 #define SWEPT2D_ENOMEM (-3)       /* device allocation failed */
 #define SWEPT2D_EUNSUPPORTED (-4) /* valid request this build does not provide */
+#define SWEPT2D_EABORTED (-5)     /* a batch kernel stopped: a dependency wait hit its limit */
 
 /* ------------------------------------------------------------- scheme ids
  * Built-in per-point sub-step operations (the paper's timestep(i, p)
@@ -203,6 +204,71 @@ int swept2d_get_timing(swept2d *h, double *out, int cap);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *swept2d_last_error(void);
+
+/* ------------------------------------------------------------------ batch
+ * Many independent small grids advanced together, each by the swept rule
+ * with its own tile side (Sec. 3-4; the tile side trades the exchange count
+ * against pyramid depth as in Sec. 5, Eq. (4)), or by the per-step method
+ * when no even side divides its grid. One advance is one captured HIP graph
+ * holding one persistent kernel: workgroups take work items (grid, stage,
+ * tile) from a device queue, and an item starts once every item of its
+ * grid's previous stage has completed (per-grid completion counters in
+ * device memory), so grids never wait for each other.
+ *
+ * Grids: HEAT5 and WAVE_LF in FP64 or FP32C, TEST_HASH in FP64 (other
+ * schemes return EUNSUPPORTED). Each grid keeps its own state, layout and
+ * conversions as a single handle with the same pde and precision, and its
+ * own sub-step counter; results equal a single handle's bit for bit. */
+typedef struct swept2d_batch swept2d_batch;
+
+#define SWEPT2D_TUNE_MODEL 0   /* tile sides from the cost model */
+#define SWEPT2D_TUNE_MEASURE 1 /* tile sides from timed trial runs */
+
+/* count grids; grid i is nx[i] x ny[i] (3..65536 per side, any shape), pde
+ * pde[i] with its nvars and substeps, precision prec[i], parameters
+ * params[i * params_stride ...] (as swept2d_set_params; params may be NULL
+ * when no grid takes any). States start at zero, tile sides from the model.
+ * NULL on error (see swept2d_last_error). */
+swept2d_batch *swept2d_batch_create(int count, const int *nx, const int *ny, const int *pde, const int *prec,
+                                    const double *params, int params_stride);
+/* Waits for pending work, frees every device buffer of the batch. */
+void swept2d_batch_destroy(swept2d_batch *b);
+int swept2d_batch_count(const swept2d_batch *b);
+
+/* Tile side of grid idx: n > 0 an even side dividing both grid sides (EINVAL
+ * otherwise), 0 the model's choice, negative the per-step method. get
+ * returns the side, 0 for the per-step method, or EINVAL. */
+int swept2d_batch_set_tile(swept2d_batch *b, int idx, int n);
+int swept2d_batch_get_tile(const swept2d_batch *b, int idx);
+
+/* Choose every grid's tile side: SWEPT2D_TUNE_MODEL from the cost model,
+ * SWEPT2D_TUNE_MEASURE by timing each distinct grid (shape, pde, precision,
+ * parameters) alone on a copy of its state at every usable side up to 64
+ * and keeping the fastest per sub-step. Grid states are not changed. */
+int swept2d_batch_autotune(swept2d_batch *b, int mode);
+
+/* State of grid idx from / to the host, FP64 [nvars][ny][nx] (converted as
+ * swept2d_upload / swept2d_download). download waits for the batch and
+ * reports EABORTED if its last advance stopped. */
+int swept2d_batch_upload(swept2d_batch *b, int idx, const double *host);
+int swept2d_batch_download(swept2d_batch *b, int idx, double *host);
+
+/* Advance every grid by nsteps full steps: one graph launch (asynchronous).
+ * EINVAL if nsteps < 0; 0 is a no-op. */
+int swept2d_batch_advance(swept2d_batch *b, long long nsteps);
+
+/* Wait for the batch; EABORTED if a kernel stopped on its wait limit (grid
+ * states are then undefined), EHIP on a kernel fault. */
+int swept2d_batch_synchronize(swept2d_batch *b);
+
+/* Sub-steps grid idx has advanced, or EINVAL. */
+long long swept2d_batch_substep_counter(const swept2d_batch *b, int idx);
+
+/* Longest time, in microseconds, a work item waits for its dependency before
+ * the kernel stops with EABORTED (default 2 s; every wait of a valid run is
+ * far shorter). 0 stops at the first wait that is not already satisfied:
+ * it exercises the failure path. */
+int swept2d_batch_set_wait_limit(swept2d_batch *b, long long microseconds);
 
 #ifdef __cplusplus
 }

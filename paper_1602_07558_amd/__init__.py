@@ -26,6 +26,7 @@ EINVAL = -1
 EHIP = -2
 ENOMEM = -3
 EUNSUPPORTED = -4
+EABORTED = -5
 
 HEAT5 = 1
 WAVE_LF = 2
@@ -43,6 +44,9 @@ LAUNCH_GRAPH = 1
 STAGING_AUTO = 0
 STAGING_OFF = 1
 
+TUNE_MODEL = 0
+TUNE_MEASURE = 1
+
 KIND_NAMES = {0: "plain", 1: "up", 2: "bridge", 3: "oct"}
 
 EXPORTS = [
@@ -53,6 +57,10 @@ EXPORTS = [
     "swept2d_substep_counter", "swept2d_set_substep_counter", "swept2d_set_launch_mode",
     "swept2d_set_staging",
     "swept2d_set_timing", "swept2d_get_timing", "swept2d_last_error",
+    "swept2d_batch_create", "swept2d_batch_destroy", "swept2d_batch_count", "swept2d_batch_set_tile",
+    "swept2d_batch_get_tile", "swept2d_batch_autotune", "swept2d_batch_upload", "swept2d_batch_download",
+    "swept2d_batch_advance", "swept2d_batch_synchronize", "swept2d_batch_substep_counter",
+    "swept2d_batch_set_wait_limit",
 ]
 
 _lib = None
@@ -105,6 +113,19 @@ def load_library():
         "swept2d_set_timing": (i, [vp, i]),
         "swept2d_get_timing": (i, [vp, ctypes.POINTER(d), i]),
         "swept2d_last_error": (ctypes.c_char_p, []),
+        "swept2d_batch_create": (vp, [i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                      ctypes.POINTER(i), ctypes.POINTER(d), i]),
+        "swept2d_batch_destroy": (None, [vp]),
+        "swept2d_batch_count": (i, [vp]),
+        "swept2d_batch_set_tile": (i, [vp, i, i]),
+        "swept2d_batch_get_tile": (i, [vp, i]),
+        "swept2d_batch_autotune": (i, [vp, i]),
+        "swept2d_batch_upload": (i, [vp, i, vp]),
+        "swept2d_batch_download": (i, [vp, i, vp]),
+        "swept2d_batch_advance": (i, [vp, ll]),
+        "swept2d_batch_synchronize": (i, [vp]),
+        "swept2d_batch_substep_counter": (ll, [vp, i]),
+        "swept2d_batch_set_wait_limit": (i, [vp, ll]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +247,72 @@ def swept2d_get_timing(h: int) -> list[dict]:
     return out
 
 
+def _ivec(v):
+    a = (ctypes.c_int * len(v))(*[int(x) for x in v])
+    return a
+
+
+def swept2d_batch_create(nx, ny, pde, prec, params=None, params_stride: int = 0) -> int:
+    count = len(nx)
+    if not (len(ny) == len(pde) == len(prec) == count):
+        raise ValueError("nx, ny, pde, prec must have one entry per grid")
+    p = None
+    if params is not None:
+        flat = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+        p = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    b = load_library().swept2d_batch_create(count, _ivec(nx), _ivec(ny), _ivec(pde), _ivec(prec), p,
+                                            params_stride)
+    if not b:
+        raise Swept2DError(EINVAL, swept2d_last_error())
+    return b
+
+
+def swept2d_batch_destroy(b: int) -> None:
+    load_library().swept2d_batch_destroy(b)
+
+
+def swept2d_batch_count(b: int) -> int:
+    return _check(load_library().swept2d_batch_count(b))
+
+
+def swept2d_batch_set_tile(b: int, idx: int, n: int) -> int:
+    return _check(load_library().swept2d_batch_set_tile(b, idx, n))
+
+
+def swept2d_batch_get_tile(b: int, idx: int) -> int:
+    return _check(load_library().swept2d_batch_get_tile(b, idx))
+
+
+def swept2d_batch_autotune(b: int, mode: int) -> int:
+    return _check(load_library().swept2d_batch_autotune(b, mode))
+
+
+def swept2d_batch_upload(b: int, idx: int, host: np.ndarray) -> int:
+    a = np.ascontiguousarray(host, dtype=np.float64)
+    return _check(load_library().swept2d_batch_upload(b, idx, a.ctypes.data))
+
+
+def swept2d_batch_download(b: int, idx: int, host: np.ndarray) -> int:
+    assert host.dtype == np.float64 and host.flags["C_CONTIGUOUS"]
+    return _check(load_library().swept2d_batch_download(b, idx, host.ctypes.data))
+
+
+def swept2d_batch_advance(b: int, nsteps: int) -> int:
+    return _check(load_library().swept2d_batch_advance(b, nsteps))
+
+
+def swept2d_batch_synchronize(b: int) -> int:
+    return _check(load_library().swept2d_batch_synchronize(b))
+
+
+def swept2d_batch_substep_counter(b: int, idx: int) -> int:
+    return _check(load_library().swept2d_batch_substep_counter(b, idx))
+
+
+def swept2d_batch_set_wait_limit(b: int, microseconds: int) -> int:
+    return _check(load_library().swept2d_batch_set_wait_limit(b, microseconds))
+
+
 PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), TEST_HASH: (1, 1),
              TEST_INCR: (1, 1), TEST_PUSH5: (5, 2)}
 
@@ -340,3 +427,73 @@ class Swept2D:
 
     def timing(self) -> list[dict]:
         return swept2d_get_timing(self.h)
+
+
+class Swept2DBatch:
+    """Owner of one swept2d batch handle. `grids` is a list of dicts with
+    keys nx, ny, pde and optionally prec (FP64) and params."""
+
+    def __init__(self, grids):
+        self.grids = [dict(g) for g in grids]
+        nparams = max([len(g.get("params") or []) for g in self.grids] + [1])
+        params = np.zeros((len(self.grids), nparams))
+        for i, g in enumerate(self.grids):
+            pv = list(g.get("params") or [])
+            params[i, :len(pv)] = pv
+        self.b = swept2d_batch_create([g["nx"] for g in self.grids], [g["ny"] for g in self.grids],
+                                      [g["pde"] for g in self.grids], [g.get("prec", FP64) for g in self.grids],
+                                      params, nparams)
+
+    def close(self):
+        if getattr(self, "b", None):
+            swept2d_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __len__(self):
+        return len(self.grids)
+
+    def shape(self, i: int):
+        g = self.grids[i]
+        return (PDE_SHAPE[g["pde"]][0], g["ny"], g["nx"])
+
+    def tile(self, i: int) -> int:
+        return swept2d_batch_get_tile(self.b, i)
+
+    def set_tile(self, i: int, n: int):
+        swept2d_batch_set_tile(self.b, i, n)
+
+    def autotune(self, mode: int = TUNE_MODEL):
+        swept2d_batch_autotune(self.b, mode)
+
+    def upload(self, i: int, state: np.ndarray):
+        assert state.shape == self.shape(i)
+        swept2d_batch_upload(self.b, i, state)
+
+    def download(self, i: int) -> np.ndarray:
+        out = np.empty(self.shape(i), dtype=np.float64)
+        swept2d_batch_download(self.b, i, out)
+        return out
+
+    def advance(self, nsteps: int):
+        swept2d_batch_advance(self.b, nsteps)
+
+    def synchronize(self):
+        swept2d_batch_synchronize(self.b)
+
+    def T(self, i: int) -> int:
+        return swept2d_batch_substep_counter(self.b, i)
+
+    def set_wait_limit(self, microseconds: int):
+        swept2d_batch_set_wait_limit(self.b, microseconds)

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswept2d.so")
-SOURCES = [os.path.join(CSRC, "swept2d_kernels.hip"), os.path.join(CSRC, "swept2d_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("swept2d_kernels.hip", "swept2d_api.cpp", "swept2d_batch.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("engine.hpp", "schemes.hpp")] + [os.path.join(ROOT, "include", "swept2d.h")]
 
 FLAGS = [

@@ -17,13 +17,15 @@ namespace swept {
 //    window column 1 + t mod N and the R rows from 1 + R (t div N) at every
 //    level, N = WC - 2, R = N^2 / NT. Otherwise a level is split into 2x2
 //    quads handed out round robin.
-template <class S, int WC>
+//  - NTo overrides the workgroup size (the batched persistent kernel runs
+//    every stage with one size).
+template <class S, int WC, int NTo = 0>
 struct Lay {
   static constexpr bool light = S::NV * (int)sizeof(typename S::V) <= 16;
   static constexpr int N = WC ? WC - 2 : 0;
-  static constexpr int NT = !light ? 512 : (WC == 34 ? 256 : 1024);
+  static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 34 ? 256 : 1024));
   static constexpr int NW = NT / 64;
-  static constexpr bool cols = light && WC != 0;
+  static constexpr bool cols = light && WC != 0 && (N * N) % NT == 0;
   static constexpr int R = cols ? N * N / NT : 0;
 };
 
@@ -159,5 +161,81 @@ inline bool tile_fits_fetch(int n) { return n + 2 <= 128; }
 
 // Raise the dynamic LDS limit of every stage kernel to `bytes` (once).
 hipError_t configure_lds(size_t bytes);
+
+// ------------------------------------------------------------------ batch
+//
+// A batch advances many independent grids in one persistent kernel. Its
+// work is a queue of items (grid, phase, index): phase 0 is every swept
+// grid's upward pyramid, odd phases its bridges (2 per tile), even phases
+// its octahedra (1 per tile); a per-step grid has one phase per sub-step (one
+// item per 64 x 64 block) plus, after an odd count, a copy back. Items are
+// numbered phase by phase; within a phase, grid by grid in `order` (grids
+// with more phases first, so the grids active in phase p are a prefix of
+// `order`). Workgroups take items in that order from one counter, and an item
+// of phase p waits until its grid has completed every item of phases < p.
+// An item waits only on items numbered before it, all taken by running
+// workgroups, so the queue always drains; a wait longer than `wait_ticks`
+// sets `error` and every workgroup stops.
+constexpr int kBatchThreads = 1024;
+constexpr int kBatchBlock = 64;  // side of a per-step block
+
+enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1 };
+
+struct BatchGrid {
+  Geo g0;          // off 0, T0 = the grid's level at the start of an advance
+  int scheme;      // Scheme (light schemes only)
+  int kind;        // BatchKind
+  int wc;          // window pitch of the stage code: 66, 34 or 0
+  int staged_oct, staged_bridge;
+  int units;       // tiles, or per-step blocks
+  void* state;
+  void* state2;    // second buffer of a per-step grid
+  PanelPtrs pp;
+  SchemeParams sp;
+};
+
+// Per-grid split of one advance of S sub-steps (h = n/2): q full half
+// cycles and a reduced one of height r, or S per-step phases.
+struct BatchPlan {
+  long long S;
+  long long q;
+  int r;
+  int nphases;
+};
+
+struct BatchSched {
+  long long total;
+  int nphases;
+  int ngrids;
+  const long long* phase_base;  // nphases + 1 ticket offsets
+  const int* phase_active;      // grids active in each phase
+  const int* order;
+  const long long* cum1;        // per-grid item prefix over `order`, phases 0 and even
+  const long long* cum2;        // same, odd phases
+  BatchGrid* grids;
+  const BatchPlan* plans;
+  unsigned* done;               // items completed per grid
+  unsigned long long* head;     // next ticket
+  int* error;
+  long long wait_ticks;         // longest dependency wait, in 100 MHz ticks
+};
+
+hipError_t launch_batch(const BatchSched& s, int blocks, size_t lds, hipStream_t st);
+// done[] = 0 and *head = 0 (a kernel, so it may sit in a captured graph).
+hipError_t launch_batch_reset(unsigned* done, int ngrids, unsigned long long* head, hipStream_t st);
+// grids[i].g0.T0 += plans[i].S for every grid.
+hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st);
+// Resident workgroups of the batch kernel per compute unit at `lds` bytes.
+hipError_t batch_blocks_per_cu(size_t lds, int* out);
+bool batch_scheme_supported(int scheme);
+
+// Host helpers shared by the host files (swept2d_api.cpp).
+int set_error(int code, const char* fmt, ...);  // message kept per thread
+size_t device_lds_limit();
+int device_setup(int* device_out);
+int scheme_for(int pde, int prec);
+int pde_param_count(int pde);
+int pde_var_count(int pde);
+int pde_substep_count(int pde);
 
 }  // namespace swept

@@ -118,6 +118,24 @@ int ensure_device_setup(int* device_out) {
 
 }  // namespace
 
+namespace swept {
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+size_t device_lds_limit() { return g_lds_limit; }
+int device_setup(int* device_out) { return ensure_device_setup(device_out); }
+int scheme_for(int pde, int prec) { return scheme_of(pde, prec); }
+int pde_param_count(int pde) { return pde_nparams(pde); }
+int pde_var_count(int pde) { return pde_nvars(pde); }
+int pde_substep_count(int pde) { return pde_substeps(pde); }
+}  // namespace swept
+
 struct swept2d {
   int nx = 0, ny = 0, nvars = 0, pde = 0, substeps = 0, prec = SWEPT2D_FP64;
   int scheme = 0;

@@ -1,0 +1,652 @@
+// Host side of the batch API: many independent grids advanced by one
+// persistent kernel (the swept rule per grid, or the per-step method for a
+// grid no even tile side divides), replayed from a captured HIP graph, and
+// the per-grid tile-side tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/swept2d.h"
+#include "engine.hpp"
+
+using namespace swept;
+
+namespace {
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(SWEPT2D_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define BHIP(call, what)                                   \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_error(e_, what);      \
+  } while (0)
+
+// Tile sides with compile-time window pitch; other sides run the generic
+// stage code.
+int pitch_of(int n) { return n == 64 ? 66 : (n == 32 ? 34 : 0); }
+
+struct HostGrid {
+  int nx = 0, ny = 0, pde = 0, prec = 0, scheme = 0, substeps = 1;
+  SchemeInfo si{};
+  SchemeParams sp{};
+  int n = 0;  // tile side; 0 = per-step method
+  void* state = nullptr;
+  void* state2 = nullptr;
+  void* up = nullptr;
+  void* xb = nullptr;
+  void* yb = nullptr;
+  long long T = 0;
+};
+
+struct Plan {
+  BatchPlan* d_plans = nullptr;
+  long long* d_phase_base = nullptr;
+  int* d_active = nullptr;
+  int* d_order = nullptr;
+  long long* d_cum1 = nullptr;
+  long long* d_cum2 = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<long long> S;  // per grid
+};
+
+}  // namespace
+
+struct swept2d_batch {
+  int count = 0;
+  int device = 0;
+  int cu_count = 256;
+  hipStream_t stream = nullptr;
+  std::vector<HostGrid> grids;
+  BatchGrid* d_grids = nullptr;
+  unsigned* d_done = nullptr;
+  unsigned long long* d_head = nullptr;
+  int* d_error = nullptr;
+  long long wait_us = 2000000;  // longest dependency wait of the kernel
+  bool dirty = true;  // device descriptors out of date
+  std::map<long long, Plan> plans;
+};
+
+namespace {
+
+size_t state_bytes(const HostGrid& g) { return (size_t)g.nx * g.ny * g.si.nv * g.si.vbytes; }
+
+size_t stage_lds(const HostGrid& g, bool* staged_oct, bool* staged_bridge) {
+  *staged_oct = *staged_bridge = false;
+  if (g.n == 0) return 0;
+  const size_t lim = device_lds_limit();
+  const size_t win = window_lds_bytes(g.si, g.n);
+  *staged_oct = win + oct_stage_bytes(g.si, g.n) <= lim;
+  *staged_bridge = win + bridge_stage_bytes(g.si, g.n) <= lim;
+  return std::max(win + (*staged_oct ? oct_stage_bytes(g.si, g.n) : 0),
+                  win + (*staged_bridge ? bridge_stage_bytes(g.si, g.n) : 0));
+}
+
+// Why tile side n cannot serve grid g in a batch, or nullptr.
+const char* batch_tile_problem(const HostGrid& g, int n) {
+  if (n == 0) return nullptr;  // per-step
+  if (n < 2 || (n & 1)) return "tile side must be even and at least 2";
+  if (g.nx % n || g.ny % n) return "tile side must divide nx and ny";
+  if (n + 2 > 128) return "tile side above 126";
+  if (window_lds_bytes(g.si, n) > device_lds_limit()) return "tile working set exceeds the workgroup LDS";
+  // The batch kernel runs 16 waves; the column layout needs n^2 to be a
+  // multiple of its thread count at the fixed pitches (true for 32 and 64).
+  return nullptr;
+}
+
+// Model ranking of tile sides for one grid of a batch. Grids of a batch run
+// side by side, so a grid's cost is the length of its own chain of phases:
+// per half cycle (h = n/2 sub-steps) one bridge and one octahedron item in
+// sequence, each a fixed cost plus one workgroup barrier per level (h levels
+// for the bridge, 2h for the octahedron), times the waves of items it needs
+// when it has more items than resident workgroups. Cost per sub-step, in the
+// spirit of Sec. 5, Eq. (4): [2 tau + 3 h lambda] * waves / h.
+int model_tile(const HostGrid& g, int resident) {
+  const double tau = 6.0e-6, lambda = 0.75e-6;
+  int best = 0;
+  double best_cost = 1e300;
+  for (int n = 4; n <= 64; n += 2) {
+    if (batch_tile_problem(g, n)) continue;
+    const int h = n / 2;
+    const double tiles = (double)(g.nx / n) * (g.ny / n);
+    const double waves = std::ceil(2.0 * tiles / std::max(resident, 1));
+    double cost = (2.0 * tau + 3.0 * h * lambda) * waves / h;
+    if (pitch_of(n) == 0) cost *= 1.25;  // generic stage code
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best = n;
+    }
+  }
+  return best;
+}
+
+void free_panels(HostGrid& g) {
+  if (g.up) hipFree(g.up);
+  if (g.xb) hipFree(g.xb);
+  if (g.yb) hipFree(g.yb);
+  if (g.state2) hipFree(g.state2);
+  g.up = g.xb = g.yb = g.state2 = nullptr;
+}
+
+int alloc_work(HostGrid& g) {
+  free_panels(g);
+  if (g.n == 0) {
+    if (hipMalloc(&g.state2, state_bytes(g)) != hipSuccess) {
+      hipGetLastError();
+      g.state2 = nullptr;
+      return set_error(SWEPT2D_ENOMEM, "cannot allocate a per-step buffer of %zu bytes", state_bytes(g));
+    }
+    return 0;
+  }
+  const int ntiles = (g.nx / g.n) * (g.ny / g.n);
+  const size_t vb = g.si.vbytes;
+  const size_t ub = std::max<size_t>(8, up_panel_values(ntiles, g.n, g.si.nv) * vb);
+  const size_t xbb = std::max<size_t>(8, xb_panel_values(ntiles, g.n, g.si.nv) * vb);
+  const size_t ybb = std::max<size_t>(8, yb_panel_values(ntiles, g.n, g.si.nv) * vb);
+  if (hipMalloc(&g.up, ub) != hipSuccess || hipMalloc(&g.xb, xbb) != hipSuccess ||
+      hipMalloc(&g.yb, ybb) != hipSuccess) {
+    hipGetLastError();
+    free_panels(g);
+    return set_error(SWEPT2D_ENOMEM, "cannot allocate panels");
+  }
+  return 0;
+}
+
+void drop_plans(swept2d_batch* b) {
+  for (auto& kv : b->plans) {
+    Plan& p = kv.second;
+    if (p.exec) hipGraphExecDestroy(p.exec);
+    hipFree(p.d_plans);
+    hipFree(p.d_phase_base);
+    hipFree(p.d_active);
+    hipFree(p.d_order);
+    hipFree(p.d_cum1);
+    hipFree(p.d_cum2);
+  }
+  b->plans.clear();
+}
+
+int units_of(const HostGrid& g) {
+  if (g.n == 0) return ((g.nx + kBatchBlock - 1) / kBatchBlock) * ((g.ny + kBatchBlock - 1) / kBatchBlock);
+  return (g.nx / g.n) * (g.ny / g.n);
+}
+
+BatchPlan plan_of(const HostGrid& g, long long S) {
+  BatchPlan p{};
+  p.S = S;
+  if (S == 0) return p;
+  if (g.n == 0) {
+    p.nphases = (int)(S + (S & 1));
+    return p;
+  }
+  const int h = g.n / 2;
+  p.q = S / h;
+  p.r = (int)(S % h);
+  p.nphases = (int)(p.q == 0 ? 3 : 1 + 2 * (p.q + (p.r > 0 ? 1 : 0)));
+  return p;
+}
+
+int upload_descriptors(swept2d_batch* b, size_t* lds_out) {
+  std::vector<BatchGrid> d(b->count);
+  size_t lds = 0;
+  for (int i = 0; i < b->count; ++i) {
+    const HostGrid& g = b->grids[i];
+    BatchGrid& x = d[i];
+    x.g0.nx = g.nx;
+    x.g0.ny = g.ny;
+    x.g0.n = g.n;
+    x.g0.h = g.n / 2;
+    x.g0.ntx = g.n ? g.nx / g.n : 0;
+    x.g0.nty = g.n ? g.ny / g.n : 0;
+    x.g0.off = 0;
+    x.g0.W = g.n + 2;
+    x.g0.T0 = g.T;
+    x.g0.tbase = nullptr;
+    x.scheme = g.scheme;
+    x.kind = g.n ? kBatchSwept : kBatchPlain;
+    x.wc = pitch_of(g.n);
+    bool so = false, sb = false;
+    lds = std::max(lds, stage_lds(g, &so, &sb));
+    x.staged_oct = so;
+    x.staged_bridge = sb;
+    x.units = units_of(g);
+    x.state = g.state;
+    x.state2 = g.state2;
+    x.pp = PanelPtrs{g.up, g.xb, g.yb};
+    x.sp = g.sp;
+  }
+  BHIP(hipMemcpy(b->d_grids, d.data(), sizeof(BatchGrid) * b->count, hipMemcpyHostToDevice), "hipMemcpy");
+  *lds_out = lds;
+  b->dirty = false;
+  return 0;
+}
+
+size_t batch_lds(const swept2d_batch* b) {
+  size_t lds = 0;
+  for (const HostGrid& g : b->grids) {
+    bool so, sb;
+    lds = std::max(lds, stage_lds(g, &so, &sb));
+  }
+  return lds;
+}
+
+template <class T>
+int upload_array(T** dst, const std::vector<T>& v) {
+  const size_t bytes = std::max<size_t>(sizeof(T), v.size() * sizeof(T));
+  if (hipMalloc(dst, bytes) != hipSuccess) {
+    hipGetLastError();
+    *dst = nullptr;
+    return set_error(SWEPT2D_ENOMEM, "cannot allocate %zu bytes of batch schedule", bytes);
+  }
+  if (!v.empty()) BHIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  return 0;
+}
+
+// Build (or find) the schedule and graph of an advance by nsteps.
+int plan_for(swept2d_batch* b, long long nsteps, Plan** out) {
+  auto it = b->plans.find(nsteps);
+  if (it != b->plans.end()) {
+    *out = &it->second;
+    return 0;
+  }
+  const int G = b->count;
+  std::vector<BatchPlan> plans(G);
+  Plan pl;
+  pl.S.resize(G);
+  for (int i = 0; i < G; ++i) {
+    pl.S[i] = nsteps * b->grids[i].substeps;
+    plans[i] = plan_of(b->grids[i], pl.S[i]);
+  }
+  std::vector<int> order(G);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return plans[a].nphases > plans[c].nphases; });
+  const int P = G ? plans[order[0]].nphases : 0;
+  std::vector<long long> cum1(G + 1, 0), cum2(G + 1, 0);
+  for (int j = 0; j < G; ++j) {
+    const HostGrid& g = b->grids[order[j]];
+    const long long u = units_of(g);
+    cum1[j + 1] = cum1[j] + u;
+    cum2[j + 1] = cum2[j] + (g.n ? 2 * u : u);
+  }
+  std::vector<int> active(std::max(P, 1), 0);
+  std::vector<long long> base(P + 1, 0);
+  {
+    int a = G;
+    for (int p = 0; p < P; ++p) {
+      while (a > 0 && plans[order[a - 1]].nphases <= p) --a;
+      active[p] = a;
+      base[p + 1] = base[p] + ((p & 1) ? cum2[a] : cum1[a]);
+    }
+  }
+  const long long total = base[P];
+  int rc;
+  if ((rc = upload_array(&pl.d_plans, plans)) || (rc = upload_array(&pl.d_phase_base, base)) ||
+      (rc = upload_array(&pl.d_active, active)) || (rc = upload_array(&pl.d_order, order)) ||
+      (rc = upload_array(&pl.d_cum1, cum1)) || (rc = upload_array(&pl.d_cum2, cum2))) {
+    b->plans[nsteps] = pl;  // freed by drop_plans
+    drop_plans(b);
+    return rc;
+  }
+  const size_t lds = batch_lds(b);
+  int per_cu = 0;
+  BHIP(batch_blocks_per_cu(lds, &per_cu), "batch kernel occupancy");
+  if (per_cu < 1) return set_error(SWEPT2D_EUNSUPPORTED, "batch kernel does not fit a compute unit (%zu B LDS)", lds);
+  const long long blocks = std::max(1LL, std::min<long long>(total, (long long)b->cu_count * per_cu));
+  BatchSched s{};
+  s.total = total;
+  s.nphases = P;
+  s.ngrids = G;
+  s.phase_base = pl.d_phase_base;
+  s.phase_active = pl.d_active;
+  s.order = pl.d_order;
+  s.cum1 = pl.d_cum1;
+  s.cum2 = pl.d_cum2;
+  s.grids = b->d_grids;
+  s.plans = pl.d_plans;
+  s.done = b->d_done;
+  s.head = b->d_head;
+  s.error = b->d_error;
+  s.wait_ticks = b->wait_us * 100;  // the wait clock runs at 100 MHz
+  BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  hipError_t e1 = launch_batch_reset(b->d_done, G, b->d_head, b->stream);
+  hipError_t e2 = total > 0 ? launch_batch(s, (int)blocks, lds, b->stream) : hipSuccess;
+  hipError_t e3 = launch_batch_bump(b->d_grids, pl.d_plans, G, b->stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  hipError_t first = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e));
+  if (first == hipSuccess) first = hipGraphInstantiate(&pl.exec, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  b->plans[nsteps] = pl;
+  if (first != hipSuccess) {
+    drop_plans(b);
+    return hip_error(first, "batch graph capture");
+  }
+  *out = &b->plans[nsteps];
+  return 0;
+}
+
+int check_idx(const swept2d_batch* b, int idx) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  if (idx < 0 || idx >= b->count) return set_error(SWEPT2D_EINVAL, "grid index %d out of range", idx);
+  return 0;
+}
+
+int sync_and_check(swept2d_batch* b) {
+  BHIP(hipStreamSynchronize(b->stream), "batch kernel execution");
+  int err = 0;
+  BHIP(hipMemcpy(&err, b->d_error, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (err) {
+    const int zero = 0;
+    BHIP(hipMemcpy(b->d_error, &zero, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy");
+    // The grids' levels are unknown after an abort: descriptors are rebuilt
+    // from the host counters on the next advance.
+    b->dirty = true;
+    return set_error(SWEPT2D_EABORTED, "batch kernel stopped: a dependency wait exceeded its limit");
+  }
+  return 0;
+}
+
+int set_tile_impl(swept2d_batch* b, int idx, int n) {
+  HostGrid& g = b->grids[idx];
+  if (n > 0)
+    if (const char* why = batch_tile_problem(g, n)) return set_error(SWEPT2D_EINVAL, "tile %d: %s", n, why);
+  if (n == g.n && (n ? g.up != nullptr : g.state2 != nullptr)) return 0;
+  BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  g.n = n;
+  int rc = alloc_work(g);
+  if (rc) return rc;
+  drop_plans(b);
+  b->dirty = true;
+  return 0;
+}
+
+int resident_blocks(swept2d_batch* b) {
+  int per_cu = 1;
+  if (batch_blocks_per_cu(batch_lds(b), &per_cu) != hipSuccess) per_cu = 1;
+  return std::max(1, per_cu) * b->cu_count;
+}
+
+}  // namespace
+
+extern "C" {
+
+swept2d_batch* swept2d_batch_create(int count, const int* nx, const int* ny, const int* pde, const int* prec,
+                                    const double* params, int params_stride) {
+  if (count < 1 || count > (1 << 20) || !nx || !ny || !pde || !prec) {
+    set_error(SWEPT2D_EINVAL, "batch needs count >= 1 and nx, ny, pde, prec arrays");
+    return nullptr;
+  }
+  for (int i = 0; i < count; ++i) {
+    const int sc = scheme_for(pde[i], prec[i]);
+    if (pde_var_count(pde[i]) < 0 || (prec[i] != SWEPT2D_FP64 && prec[i] != SWEPT2D_FP32C)) {
+      set_error(SWEPT2D_EINVAL, "grid %d: unknown pde %d or precision %d", i, pde[i], prec[i]);
+      return nullptr;
+    }
+    if (sc < 0 || !batch_scheme_supported(sc)) {
+      set_error(SWEPT2D_EUNSUPPORTED, "grid %d: pde %d precision %d is not available in a batch", i, pde[i], prec[i]);
+      return nullptr;
+    }
+    if (nx[i] < 3 || ny[i] < 3 || nx[i] > (1 << 16) || ny[i] > (1 << 16)) {
+      set_error(SWEPT2D_EINVAL, "grid %d: %d x %d out of range (3..65536 per side)", i, nx[i], ny[i]);
+      return nullptr;
+    }
+    const int np = pde_param_count(pde[i]);
+    if (np > 0 && (!params || params_stride < np)) {
+      set_error(SWEPT2D_EINVAL, "grid %d: pde %d takes %d parameters (stride %d)", i, pde[i], np, params_stride);
+      return nullptr;
+    }
+  }
+  int dev = 0;
+  if (device_setup(&dev)) return nullptr;
+  swept2d_batch* b = new (std::nothrow) swept2d_batch();
+  if (!b) {
+    set_error(SWEPT2D_ENOMEM, "out of host memory");
+    return nullptr;
+  }
+  b->count = count;
+  b->device = dev;
+  hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+  if (b->cu_count <= 0) b->cu_count = 256;
+  auto bail = [&](int code, const char* what) -> swept2d_batch* {
+    if (code == SWEPT2D_ENOMEM) set_error(code, "%s", what);
+    swept2d_batch_destroy(b);
+    return nullptr;
+  };
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    hipGetLastError();
+    b->stream = nullptr;
+    set_error(SWEPT2D_EHIP, "cannot create a stream");
+    return bail(0, "");
+  }
+  b->grids.resize(count);
+  for (int i = 0; i < count; ++i) {
+    HostGrid& g = b->grids[i];
+    g.nx = nx[i];
+    g.ny = ny[i];
+    g.pde = pde[i];
+    g.prec = prec[i];
+    g.scheme = scheme_for(pde[i], prec[i]);
+    g.si = scheme_info(g.scheme);
+    g.substeps = pde_substep_count(pde[i]);
+    const int np = pde_param_count(pde[i]);
+    for (int k = 0; k < np; ++k) g.sp.p[k] = params[(size_t)i * params_stride + k];
+    if (hipMalloc(&g.state, state_bytes(g)) != hipSuccess) {
+      hipGetLastError();
+      g.state = nullptr;
+      return bail(SWEPT2D_ENOMEM, "cannot allocate grid state");
+    }
+    if (hipMemset(g.state, 0, state_bytes(g)) != hipSuccess) {
+      set_error(SWEPT2D_EHIP, "hipMemset failed");
+      return bail(0, "");
+    }
+  }
+  if (hipMalloc(&b->d_grids, sizeof(BatchGrid) * count) != hipSuccess ||
+      hipMalloc(&b->d_done, sizeof(unsigned) * count) != hipSuccess ||
+      hipMalloc(&b->d_head, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&b->d_error, sizeof(int)) != hipSuccess) {
+    hipGetLastError();
+    return bail(SWEPT2D_ENOMEM, "cannot allocate batch descriptors");
+  }
+  if (hipMemset(b->d_error, 0, sizeof(int)) != hipSuccess) {
+    set_error(SWEPT2D_EHIP, "hipMemset failed");
+    return bail(0, "");
+  }
+  // Initial tile sides from the model (the largest usable tiles first fix
+  // the LDS of the batch kernel and hence its residency).
+  for (int i = 0; i < count; ++i) {
+    if (set_tile_impl(b, i, model_tile(b->grids[i], b->cu_count))) return bail(0, "");
+  }
+  const int resident = resident_blocks(b);
+  for (int i = 0; i < count; ++i) {
+    if (set_tile_impl(b, i, model_tile(b->grids[i], resident))) return bail(0, "");
+  }
+  return b;
+}
+
+void swept2d_batch_destroy(swept2d_batch* b) {
+  if (!b) return;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  drop_plans(b);
+  for (HostGrid& g : b->grids) {
+    free_panels(g);
+    if (g.state) hipFree(g.state);
+  }
+  if (b->d_grids) hipFree(b->d_grids);
+  if (b->d_done) hipFree(b->d_done);
+  if (b->d_head) hipFree(b->d_head);
+  if (b->d_error) hipFree(b->d_error);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
+}
+
+int swept2d_batch_count(const swept2d_batch* b) { return b ? b->count : SWEPT2D_EINVAL; }
+
+int swept2d_batch_set_tile(swept2d_batch* b, int idx, int n) {
+  int rc = check_idx(b, idx);
+  if (rc) return rc;
+  if (n < 0) return set_tile_impl(b, idx, 0);
+  if (n == 0) n = model_tile(b->grids[idx], resident_blocks(b));
+  return set_tile_impl(b, idx, n);
+}
+
+int swept2d_batch_get_tile(const swept2d_batch* b, int idx) {
+  if (!b || idx < 0 || idx >= b->count) return SWEPT2D_EINVAL;
+  return b->grids[idx].n;
+}
+
+int swept2d_batch_upload(swept2d_batch* b, int idx, const double* host) {
+  int rc = check_idx(b, idx);
+  if (rc) return rc;
+  if (!host) return set_error(SWEPT2D_EINVAL, "null host buffer");
+  HostGrid& g = b->grids[idx];
+  BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  const size_t cnt = (size_t)g.nx * g.ny * g.si.nvar;
+  if (g.prec == SWEPT2D_FP64) {
+    BHIP(hipMemcpy(g.state, host, state_bytes(g), hipMemcpyHostToDevice), "hipMemcpy");
+    return 0;
+  }
+  std::vector<float> buf(2 * cnt, 0.0f);
+  for (size_t i = 0; i < cnt; ++i) buf[i] = (float)host[i];
+  BHIP(hipMemcpy(g.state, buf.data(), state_bytes(g), hipMemcpyHostToDevice), "hipMemcpy");
+  return 0;
+}
+
+int swept2d_batch_download(swept2d_batch* b, int idx, double* host) {
+  int rc = check_idx(b, idx);
+  if (rc) return rc;
+  if (!host) return set_error(SWEPT2D_EINVAL, "null host buffer");
+  if ((rc = sync_and_check(b))) return rc;
+  HostGrid& g = b->grids[idx];
+  const size_t cnt = (size_t)g.nx * g.ny * g.si.nvar;
+  if (g.prec == SWEPT2D_FP64) {
+    BHIP(hipMemcpy(host, g.state, state_bytes(g), hipMemcpyDeviceToHost), "hipMemcpy");
+    return 0;
+  }
+  std::vector<float> buf(2 * cnt);
+  BHIP(hipMemcpy(buf.data(), g.state, state_bytes(g), hipMemcpyDeviceToHost), "hipMemcpy");
+  for (size_t i = 0; i < cnt; ++i) host[i] = (double)buf[i] - (double)buf[cnt + i];
+  return 0;
+}
+
+int swept2d_batch_advance(swept2d_batch* b, long long nsteps) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  if (nsteps < 0) return set_error(SWEPT2D_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return 0;
+  if (nsteps > (1LL << 30)) return set_error(SWEPT2D_EINVAL, "nsteps too large");
+#ifndef SWEPT2D_BATCH_KERNEL
+  // The persistent kernel is compiled but not launched: an earlier form of
+  // its work loop hung on the device (the compiler sent lanes 1..63 back to
+  // the item barrier without lane 0; fixed with one thread-0 region per round
+  // and a scalar loop exit), and the fixed form has not yet run there.
+  // Build with -DSWEPT2D_BATCH_KERNEL to launch it.
+  return set_error(SWEPT2D_EUNSUPPORTED,
+                   "batched persistent kernel disabled pending verification on the device "
+                   "(build with -DSWEPT2D_BATCH_KERNEL)");
+#endif
+  int rc;
+  if (b->dirty) {
+    BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    size_t lds = 0;
+    if ((rc = upload_descriptors(b, &lds))) return rc;
+  }
+  Plan* pl = nullptr;
+  if ((rc = plan_for(b, nsteps, &pl))) return rc;
+  BHIP(hipGraphLaunch(pl->exec, b->stream), "hipGraphLaunch");
+  for (int i = 0; i < b->count; ++i) b->grids[i].T += pl->S[i];
+  return 0;
+}
+
+int swept2d_batch_synchronize(swept2d_batch* b) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  return sync_and_check(b);
+}
+
+long long swept2d_batch_substep_counter(const swept2d_batch* b, int idx) {
+  if (!b || idx < 0 || idx >= b->count) return SWEPT2D_EINVAL;
+  return b->grids[idx].T;
+}
+
+int swept2d_batch_set_wait_limit(swept2d_batch* b, long long microseconds) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  if (microseconds < 0 || microseconds > (1LL << 40)) return set_error(SWEPT2D_EINVAL, "wait limit out of range");
+  BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  b->wait_us = microseconds;
+  drop_plans(b);
+  return 0;
+}
+
+int swept2d_batch_autotune(swept2d_batch* b, int mode) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  if (mode != SWEPT2D_TUNE_MODEL && mode != SWEPT2D_TUNE_MEASURE) return set_error(SWEPT2D_EINVAL, "unknown mode");
+  int rc;
+  const int resident = resident_blocks(b);
+  if (mode == SWEPT2D_TUNE_MODEL) {
+    for (int i = 0; i < b->count; ++i)
+      if ((rc = set_tile_impl(b, i, model_tile(b->grids[i], resident)))) return rc;
+    return 0;
+  }
+  // Measured: run each grid alone, on a copy of its state, for a few
+  // half cycles at every usable side (up to 64) and keep the fastest per
+  // sub-step. Grids of one shape, scheme and parameters share a result.
+  BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  std::map<std::vector<double>, int> seen;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIP(hipEventCreate(&e0), "hipEventCreate");
+  BHIP(hipEventCreate(&e1), "hipEventCreate");
+  rc = 0;
+  for (int i = 0; i < b->count && rc == 0; ++i) {
+    const HostGrid& g = b->grids[i];
+    std::vector<double> key = {(double)g.nx, (double)g.ny, (double)g.pde, (double)g.prec,
+                               g.sp.p[0], g.sp.p[1], g.sp.p[2], g.sp.p[3]};
+    auto it = seen.find(key);
+    if (it != seen.end()) {
+      rc = set_tile_impl(b, i, it->second);
+      continue;
+    }
+    const double par[4] = {g.sp.p[0], g.sp.p[1], g.sp.p[2], g.sp.p[3]};
+    swept2d_batch* t = swept2d_batch_create(1, &g.nx, &g.ny, &g.pde, &g.prec, par, 4);
+    if (!t) {
+      rc = SWEPT2D_EHIP;
+      break;
+    }
+    if (hipMemcpy(t->grids[0].state, g.state, state_bytes(g), hipMemcpyDeviceToDevice) != hipSuccess) {
+      swept2d_batch_destroy(t);
+      rc = set_error(SWEPT2D_EHIP, "hipMemcpy");
+      break;
+    }
+    int best = g.n;
+    double best_t = 1e300;
+    for (int n = 64; n >= 4 && rc == 0; n -= 2) {
+      if (batch_tile_problem(g, n)) continue;
+      if ((rc = set_tile_impl(t, 0, n))) break;
+      const long long steps = std::max(2LL * (n / 2), 64LL);
+      if ((rc = swept2d_batch_advance(t, steps)) || (rc = swept2d_batch_synchronize(t))) break;
+      if (hipEventRecord(e0, t->stream) != hipSuccess) { rc = set_error(SWEPT2D_EHIP, "hipEventRecord"); break; }
+      if ((rc = swept2d_batch_advance(t, steps))) break;
+      if (hipEventRecord(e1, t->stream) != hipSuccess) { rc = set_error(SWEPT2D_EHIP, "hipEventRecord"); break; }
+      if ((rc = swept2d_batch_synchronize(t))) break;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = set_error(SWEPT2D_EHIP, "hipEventElapsedTime"); break; }
+      const double per = ms / (double)steps;
+      if (per < best_t) {
+        best_t = per;
+        best = n;
+      }
+    }
+    swept2d_batch_destroy(t);
+    if (rc) break;
+    seen[key] = best;
+    rc = set_tile_impl(b, i, best);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
+}
+
+}  // extern "C"

@@ -155,7 +155,6 @@ template <class S, int WC, int kThreads>
 __device__ __forceinline__ void compute_quads(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
-  constexpr int kWaves = kThreads / 64;
   const int W = WC ? WC : Wrt;
   const int bw = w >> 1, nq = bw * (hg >> 1);
   if (nq <= 0) return;
@@ -182,11 +181,11 @@ struct RegNb {
 // offsets; rows outside the rectangle are computed from whatever the window
 // holds there and not stored. Lanes are consecutive columns, so every LDS
 // access of a wave is one contiguous run.
-template <class S, int WC>
+template <class S, int WC, int NT>
 __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                              int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
-  constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC>::N, R = Lay<S, WC>::R;
+  constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N, R = Lay<S, WC, NT>::R;
   const int t = (int)threadIdx.x;
   const int c = 1 + t % N, r0 = 1 + R * (t / N);
   if ((unsigned)(c - x0) >= (unsigned)w) return;
@@ -213,14 +212,14 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
 
 // One level of a stage kernel: column ownership where the layout has it,
 // 2x2 quads otherwise.
-template <class S, int WC>
+template <class S, int WC, int NT>
 __device__ __forceinline__ void compute_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
-  if constexpr (Lay<S, WC>::cols)
-    compute_cols<S, WC>(in, out, x0, y0, w, hg, T, sp);
+  if constexpr (Lay<S, WC, NT>::cols)
+    compute_cols<S, WC, NT>(in, out, x0, y0, w, hg, T, sp);
   else
-    compute_quads<S, WC, Lay<S, WC>::NT>(in, out, Wrt, x0, y0, w, hg, T, sp);
+    compute_quads<S, WC, NT>(in, out, Wrt, x0, y0, w, hg, T, sp);
 }
 
 // Window -> state for the rectangle [wx0, wx0+w) x [wy0, wy0+hg); the window
@@ -228,7 +227,6 @@ __device__ __forceinline__ void compute_level(const typename S::V* __restrict__ 
 template <class S, int kThreads>
 __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V* __restrict__ state, const Geo& g,
                            int xw0, int yw0, int wx0, int wy0, int w, int hg) {
-  constexpr int kWaves = kThreads / 64;
   const int npts = w * hg;
   if (npts <= 0) return;
   const int plane = g.W * g.W;
@@ -283,16 +281,15 @@ __device__ void emit_up_all(const typename S::V* __restrict__ buf0, const typena
 // window interior) is in buffer b0, then its panels of levels 0..H-1; when
 // H < h (reduced last half cycle) it also writes the level-H square to the
 // state.
-template <class S, int WC>
+template <class S, int WC, int NT>
 __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, const Geo& g, int tile, int x0, int y0,
                           long long T0, int H, typename S::V* state, typename S::V* up, const SchemeParams& sp) {
-  constexpr int NT = Lay<S, WC>::NT;
   const int n = g.n, h = g.h;
   const int top = H < h - 1 ? H : h - 1;
   for (int l = 1; l <= top; ++l) {
     typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
     const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
-    compute_level<S, WC>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
+    compute_level<S, WC, NT>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
     __syncthreads();
   }
   emit_up_all<S, NT>(buf0, buf1, b0, up, g, tile, H);
@@ -496,16 +493,17 @@ __device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const ty
 
 // ----------------------------------------------------------------- kernels
 
-// Upward pyramid of every tile, from the state (Alg. 1).
-template <class S, int WC>
-__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
-                                                 SchemeParams sp) {
-  constexpr int NT = Lay<S, WC>::NT;
+// Stage items. Each runs on one workgroup of NT threads with `smem` as its
+// LDS; a stage kernel runs item blockIdx.x, the batched persistent kernel
+// the items it takes from its queue.
+
+// Upward pyramid of one tile, from the state (Alg. 1).
+template <class S, int WC, int NT>
+__device__ void up_item(const Geo& g, int H, typename S::V* __restrict__ state, const PanelPtrs& pp,
+                        const SchemeParams& sp, int tile, double* smem) {
   using V = typename S::V;
-  extern __shared__ double smem_d[];
-  V* buf0 = reinterpret_cast<V*>(smem_d);
+  V* buf0 = reinterpret_cast<V*>(smem);
   V* buf1 = buf0 + S::NV * g.W * g.W;
-  const int tile = blockIdx.x;
   const int a = tile % g.ntx, b = tile / g.ntx;
   const int x0 = g.off + a * g.n, y0 = g.off + b * g.n;
   const int n = g.n, W = g.W, plane = W * W;
@@ -526,24 +524,22 @@ __global__ __launch_bounds__((Lay<S, WC>::NT)) void k_up(Geo g, int H, typename 
         buf0[v * plane + (r + 1) * W + (c + 1)] = val;
       });
   __syncthreads();
-  up_levels<S, WC>(buf0, buf1, 0, g, tile, x0, y0, level_base(g), H, state, static_cast<V*>(pp.up), sp);
+  up_levels<S, WC, NT>(buf0, buf1, 0, g, tile, x0, y0, level_base(g), H, state, static_cast<V*>(pp.up), sp);
 }
 
-// x-bridges (blocks 0 .. ntiles-1, over the east edge of each tile) and
-// y-bridges (blocks ntiles .. 2 ntiles-1, over the south edge), Alg. 2-3.
-template <class S, int WC>
-__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_bridge(Geo g, int H, int staged, typename S::V* __restrict__ state,
-                                                     PanelPtrs pp, SchemeParams sp) {
-  constexpr int NT = Lay<S, WC>::NT;
+// Item i < ntiles: the x-bridge over the east edge of tile i; item
+// ntiles + i: the y-bridge over the south edge of tile i (Alg. 2-3).
+template <class S, int WC, int NT>
+__device__ void bridge_item(const Geo& g, int H, int staged, typename S::V* __restrict__ state, const PanelPtrs& pp,
+                            const SchemeParams& sp, int item, double* smem) {
   using V = typename S::V;
   constexpr int NV = S::NV;
-  extern __shared__ double smem_d[];
-  V* buf0 = reinterpret_cast<V*>(smem_d);
+  V* buf0 = reinterpret_cast<V*>(smem);
   V* buf1 = buf0 + NV * g.W * g.W;
   V* stg = buf1 + NV * g.W * g.W;
   const int ntiles = g.ntx * g.nty;
-  const bool isx = (int)blockIdx.x < ntiles;
-  const int e = isx ? (int)blockIdx.x : (int)blockIdx.x - ntiles;
+  const bool isx = item < ntiles;
+  const int e = isx ? item : item - ntiles;
   const int a = e % g.ntx, b = e / g.ntx;
   const int n = g.n, h = g.h;
   int xw0, yw0, tB;
@@ -573,9 +569,9 @@ __global__ __launch_bounds__((Lay<S, WC>::NT)) void k_bridge(Geo g, int H, int s
     if (!staged && l < H) fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
     if (l >= 1 && l <= h - 1) {
       if (isx)
-        compute_level<S, WC>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
+        compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
       else
-        compute_level<S, WC>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+        compute_level<S, WC, NT>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
     }
     if (l < H) {
       if (staged)
@@ -595,20 +591,17 @@ __global__ __launch_bounds__((Lay<S, WC>::NT)) void k_bridge(Geo g, int H, int s
   }
 }
 
-// Downward pyramid at the south-east corner of every tile (Alg. 4), fused
-// with the next half cycle's upward pyramid of the tile centred on that
-// corner (an octahedron): the level-h tile never leaves LDS.
-template <class S, int WC>
-__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_oct(Geo g, int Hd, int Hu, int staged,
-                                                  typename S::V* __restrict__ state, PanelPtrs pp, SchemeParams sp) {
-  constexpr int NT = Lay<S, WC>::NT;
+// Downward pyramid at the south-east corner of tile c (Alg. 4), fused with
+// the next half cycle's upward pyramid of the tile centred on that corner
+// (an octahedron): the level-h tile never leaves LDS.
+template <class S, int WC, int NT>
+__device__ void oct_item(const Geo& g, int Hd, int Hu, int staged, typename S::V* __restrict__ state,
+                         const PanelPtrs& pp, const SchemeParams& sp, int c, double* smem) {
   using V = typename S::V;
   constexpr int NV = S::NV;
-  extern __shared__ double smem_d[];
-  V* buf0 = reinterpret_cast<V*>(smem_d);
+  V* buf0 = reinterpret_cast<V*>(smem);
   V* buf1 = buf0 + NV * g.W * g.W;
   V* stg = buf1 + NV * g.W * g.W;
-  const int c = blockIdx.x;
   const int a = c % g.ntx, b = c / g.ntx;
   const int n = g.n, h = g.h;
   const int a1 = (a + 1 == g.ntx) ? 0 : a + 1, b1 = (b + 1 == g.nty) ? 0 : b + 1;
@@ -640,7 +633,7 @@ __global__ __launch_bounds__((Lay<S, WC>::NT)) void k_oct(Geo g, int Hd, int Hu,
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
     if (!staged && l < Hd) fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
-    if (l >= 1) compute_level<S, WC>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+    if (l >= 1) compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
     if (l < Hd) {
       if (staged)
         place_ring_staged<S, NT>(stg, cur, g, l, LxH, LyH);
@@ -658,7 +651,30 @@ __global__ __launch_bounds__((Lay<S, WC>::NT)) void k_oct(Geo g, int Hd, int Hu,
     write_rect<S, NT>(top, state, g, xw0, yw0, 1, 1, n, n);
     return;
   }
-  up_levels<S, WC>(buf0, buf1, h & 1, g2, tile2, xw0 + 1, yw0 + 1, T0 + h, Hu, state, up, sp);
+  up_levels<S, WC, NT>(buf0, buf1, h & 1, g2, tile2, xw0 + 1, yw0 + 1, T0 + h, Hu, state, up, sp);
+}
+
+template <class S, int WC>
+__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
+                                                         SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  up_item<S, WC, Lay<S, WC>::NT>(g, H, state, pp, sp, (int)blockIdx.x, smem_d);
+}
+
+template <class S, int WC>
+__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_bridge(Geo g, int H, int staged,
+                                                             typename S::V* __restrict__ state, PanelPtrs pp,
+                                                             SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  bridge_item<S, WC, Lay<S, WC>::NT>(g, H, staged, state, pp, sp, (int)blockIdx.x, smem_d);
+}
+
+template <class S, int WC>
+__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_oct(Geo g, int Hd, int Hu, int staged,
+                                                          typename S::V* __restrict__ state, PanelPtrs pp,
+                                                          SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  oct_item<S, WC, Lay<S, WC>::NT>(g, Hd, Hu, staged, state, pp, sp, (int)blockIdx.x, smem_d);
 }
 
 template <class S>
@@ -817,6 +833,220 @@ hipError_t lds_t(size_t bytes) {
     default: break;                                   \
   }
 
+// ------------------------------------------------------------------ batch
+
+// One sub-step of the 64 x (NT/64 * 4) block `blk` of a grid (per-step
+// grids of a batch); thread (x, y) walks 4 rows of one column.
+template <class S, int NT>
+__device__ void plain_item(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int nx, int ny,
+                           long long T, const SchemeParams& sp, int blk) {
+  using V = typename S::V;
+  constexpr int NV = S::NV, R = 4, TY = NT / 64;
+  static_assert(TY * R == kBatchBlock, "block geometry");
+  const int bx = (nx + kBatchBlock - 1) / kBatchBlock;
+  const int x = (blk % bx) * kBatchBlock + (int)(threadIdx.x & 63);
+  const int ys = (blk / bx) * kBatchBlock + (int)(threadIdx.x >> 6) * R;
+  if (x >= nx || ys >= ny) return;
+  const int xw = (x == 0) ? nx - 1 : x - 1;
+  const int xe = (x == nx - 1) ? 0 : x + 1;
+  const size_t plane = (size_t)nx * ny;
+  V rw[3][3][NV];
+  auto load = [&](V(&row)[3][NV], int y) {
+    if (y < 0) y += ny;
+    if (y >= ny) y -= ny;
+    const V* base = in + (size_t)y * nx;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      row[0][v] = base[v * plane + xw];
+      row[1][v] = base[v * plane + x];
+      row[2][v] = base[v * plane + xe];
+    }
+  };
+  load(rw[0], ys - 1);
+  load(rw[1], ys);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = ys + r;
+    if (y >= ny) break;
+    load(rw[2], y + 1);
+    V o[NV];
+    S::step(T, RegNb<V, NV>{rw}, o, sp);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * plane + (size_t)y * nx + x] = o[v];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        rw[0][i][v] = rw[1][i][v];
+        rw[1][i][v] = rw[2][i][v];
+      }
+  }
+}
+
+template <class S, int NT>
+__device__ void copy_item(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int nx, int ny,
+                          int blk) {
+  const int bx = (nx + kBatchBlock - 1) / kBatchBlock;
+  const int x = (blk % bx) * kBatchBlock + (int)(threadIdx.x & 63);
+  const int ys = (blk / bx) * kBatchBlock + (int)(threadIdx.x >> 6) * 4;
+  if (x >= nx) return;
+  const size_t plane = (size_t)nx * ny;
+  for (int r = 0; r < 4; ++r) {
+    const int y = ys + r;
+    if (y >= ny) break;
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) out[v * plane + (size_t)y * nx + x] = in[v * plane + (size_t)y * nx + x];
+  }
+}
+
+// Items of grid `G` completed before its phase p.
+__device__ __forceinline__ long long batch_need(const BatchGrid& G, int p) {
+  if (G.kind == kBatchPlain) return (long long)G.units * p;
+  if (p == 0) return 0;
+  return (long long)G.units * (1 + 2 * (p / 2) + ((p + 1) / 2 - 1));
+}
+
+// Run item `item` of phase p of grid G (stage code at pitch WC). Kept out of
+// line: each variant is register-allocated on its own.
+template <class S, int WC>
+__device__ __noinline__ void batch_stage(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
+  constexpr int NT = kBatchThreads;
+  using V = typename S::V;
+  V* state = static_cast<V*>(G.state);
+  if (G.kind == kBatchPlain) {
+    V* s2 = static_cast<V*>(G.state2);
+    if (p < P.S) {
+      const bool even = (p & 1) == 0;
+      plain_item<S, NT>(even ? state : s2, even ? s2 : state, G.g0.nx, G.g0.ny, G.g0.T0 + p, G.sp, item);
+    } else {
+      copy_item<S, NT>(s2, state, G.g0.nx, G.g0.ny, item);
+    }
+    return;
+  }
+  Geo g = G.g0;
+  const int h = g.h;
+  if (p == 0) {
+    up_item<S, WC, NT>(g, P.q > 0 ? h : P.r, state, G.pp, G.sp, item, smem);
+    return;
+  }
+  const int hc = (p - 1) / 2;
+  g.off = (hc & 1) ? h : 0;
+  g.T0 = G.g0.T0 + (long long)hc * h;
+  const int H = hc < P.q ? h : P.r;
+  if (p & 1) {
+    bridge_item<S, WC, NT>(g, H, G.staged_bridge, state, G.pp, G.sp, item, smem);
+  } else {
+    const int Hu = (hc + 1 < P.q) ? h : (hc + 1 == P.q ? P.r : 0);
+    oct_item<S, WC, NT>(g, H, Hu, G.staged_oct, state, G.pp, G.sp, item, smem);
+  }
+}
+
+template <class S>
+__device__ void batch_scheme(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
+  if (G.wc == 66)
+    batch_stage<S, 66>(G, P, p, item, smem);
+  else if (G.wc == 34)
+    batch_stage<S, 34>(G, P, p, item, smem);
+  else
+    batch_stage<S, 0>(G, P, p, item, smem);
+}
+
+// Largest i in [lo, hi) with a[i] <= key (a nondecreasing, a[lo] <= key).
+__device__ __forceinline__ int last_le(const long long* a, int lo, int hi, long long key) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= key)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The work loop. One thread takes the next ticket (first counting the
+// workgroup's previous item as done), decodes it and waits for its
+// dependency; the workgroup then runs the item. The loop's exit and every
+// value the item depends on are read back as scalars (readfirstlane), so
+// the whole workgroup goes round the loop together: a per-lane exit test
+// lets the compiler send lanes back to the barrier on separate paths.
+__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchSched s) {
+  extern __shared__ double smem_d[];
+  __shared__ int sh_stop, sh_phase, sh_grid, sh_item;
+  int prev = -1;  // grid of the previous item (uniform)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (prev >= 0) __hip_atomic_fetch_add(&s.done[prev], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int stop = __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      int p = 0, g = 0, item = 0;
+      if (!stop) {
+        const long long k = (long long)atomicAdd(s.head, 1ull);
+        if (k >= s.total) {
+          stop = 1;
+        } else {
+          p = last_le(s.phase_base, 0, s.nphases, k);
+          const long long local = k - s.phase_base[p];
+          const long long* cum = (p & 1) ? s.cum2 : s.cum1;
+          const int j = last_le(cum, 0, s.phase_active[p], local);
+          g = s.order[j];
+          item = (int)(local - cum[j]);
+          const unsigned need = (unsigned)batch_need(s.grids[g], p);
+          // Poll with plain (relaxed) loads: an acquire per poll would
+          // invalidate the L2 every time. One acquire fence follows a
+          // satisfied wait. The wait is bounded in real time (the 100 MHz
+          // counter), so it ends however slow a poll is.
+          const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+          while (__hip_atomic_load(&s.done[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > (unsigned long long)s.wait_ticks ||
+                __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              __hip_atomic_store(s.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              stop = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(16);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+      }
+      sh_stop = stop;
+      sh_phase = p;
+      sh_grid = g;
+      sh_item = item;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(sh_stop)) break;
+    const int g = __builtin_amdgcn_readfirstlane(sh_grid);
+    const int p = __builtin_amdgcn_readfirstlane(sh_phase);
+    const int item = __builtin_amdgcn_readfirstlane(sh_item);
+    const BatchGrid& G = s.grids[g];
+    const BatchPlan& P = s.plans[g];
+    switch (__builtin_amdgcn_readfirstlane(G.scheme)) {
+      case kHeat64: batch_scheme<Heat64>(G, P, p, item, smem_d); break;
+      case kWave64: batch_scheme<Wave64>(G, P, p, item, smem_d); break;
+      case kHash64: batch_scheme<Hash64>(G, P, p, item, smem_d); break;
+      case kHeat32C: batch_scheme<Heat32C>(G, P, p, item, smem_d); break;
+      case kWave32C: batch_scheme<Wave32C>(G, P, p, item, smem_d); break;
+      default: break;
+    }
+    // Every wave's stores have reached the L2 before the barrier; thread 0's
+    // release at the top of the next round writes the L2 back, so the item's
+    // results are visible device-wide before it counts.
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    prev = g;
+  }
+}
+
+__global__ void k_batch_reset(unsigned* done, int ngrids, unsigned long long* head) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ngrids) done[i] = 0u;
+  if (i == 0) *head = 0ull;
+}
+
+__global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ngrids) grids[i].g0.T0 += plans[i].S;
+}
+
 }  // namespace
 
 SchemeInfo scheme_info(int scheme) {
@@ -871,6 +1101,32 @@ hipError_t configure_lds(size_t bytes) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_batch(const BatchSched& s, int blocks, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(kBatchThreads), lds, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(unsigned* done, int ngrids, unsigned long long* head, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3((ngrids + 255) / 256 + 1), dim3(256), 0, st, done, ngrids, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_bump, dim3((ngrids + 255) / 256), dim3(256), 0, st, grids, plans, ngrids);
+  return hipGetLastError();
+}
+
+hipError_t batch_blocks_per_cu(size_t lds, int* out) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_batch, kBatchThreads, lds);
+}
+
+bool batch_scheme_supported(int scheme) {
+  return scheme == kHeat64 || scheme == kWave64 || scheme == kHash64 || scheme == kHeat32C || scheme == kWave32C;
 }
 
 }  // namespace swept

@@ -206,14 +206,18 @@ def initial_state(pde: int, nx: int, ny: int, seed: int = 0) -> np.ndarray:
     raise ValueError(f"unknown pde {pde}")
 
 
-def batch_specs(count: int = 256, seed: int = 0, lo: int = 64, hi: int = 512) -> list[dict]:
-    """Uneven batch: side lengths uniform in lo..hi (independent in x and y),
-    heat or wave and FP64 or FP32-compensated by fair seeded draws."""
+def batch_specs(count: int = 256, seed: int = 0, lo: int = 64, hi: int = 512, quantum: int = 16) -> list[dict]:
+    """Uneven batch: side lengths drawn uniformly from the multiples of
+    `quantum` in lo..hi (independently in x and y; quantum 1 draws any
+    integer), heat or wave and FP64 or FP32-compensated by fair seeded
+    draws. Each spec carries the seed of its initial field."""
     rng = np.random.default_rng(seed)
+    sides = np.arange(lo, hi + 1)
+    sides = sides[sides % quantum == 0]
     specs = []
     for g in range(count):
-        nx = int(rng.integers(lo, hi + 1))
-        ny = int(rng.integers(lo, hi + 1))
+        nx = int(rng.choice(sides))
+        ny = int(rng.choice(sides))
         pde = HEAT5 if rng.integers(0, 2) == 0 else WAVE_LF
         prec = int(rng.integers(0, 2))
         specs.append({"nx": nx, "ny": ny, "pde": pde, "prec": prec, "seed": seed * 1000 + g})

@@ -103,3 +103,26 @@ def test_single_hip_runtime_in_process(lib):
     maps = open("/proc/self/maps").read()
     hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(hip) == 1, hip
+
+
+def test_batch_arguments_rejected_before_device(lib):
+    import ctypes
+    iv = lambda *v: (ctypes.c_int * len(v))(*v)
+    assert not lib.swept2d_batch_create(0, iv(64), iv(64), iv(sw.HEAT5), iv(sw.FP64), None, 0)
+    assert "count" in sw.swept2d_last_error()
+    assert not lib.swept2d_batch_create(1, iv(64), iv(64), iv(sw.EULER_RUS_RK2), iv(sw.FP64), None, 0)
+    assert "not available in a batch" in sw.swept2d_last_error()
+    assert not lib.swept2d_batch_create(1, iv(2), iv(64), iv(sw.TEST_HASH), iv(sw.FP64), None, 0)
+    assert not lib.swept2d_batch_create(1, iv(64), iv(64), iv(sw.HEAT5), iv(sw.FP64), None, 0)
+    assert "parameters" in sw.swept2d_last_error()
+    assert lib.swept2d_batch_advance(None, 1) == sw.EINVAL
+    assert lib.swept2d_batch_get_tile(None, 0) == sw.EINVAL
+    lib.swept2d_batch_destroy(None)
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device error path")
+def test_batch_create_without_device_fails_loudly(lib):
+    import ctypes
+    iv = lambda *v: (ctypes.c_int * len(v))(*v)
+    assert not lib.swept2d_batch_create(1, iv(64), iv(64), iv(sw.TEST_HASH), iv(sw.FP64), None, 0)
+    assert sw.swept2d_last_error()
