@@ -151,11 +151,15 @@ def main():
     g.upload(s0)
     for _ in range(args.warmup):
         g.advance(TIMESTEPS)
-    g.set_timing(True)
     t_swept = timed_runs(g, g.advance, TIMESTEPS, args.steps)
+    swept_out = g.download()
+    # Per-kernel durations from HIP events on the library's stream, in a pass
+    # of its own (the events would add gaps to the timed region).
+    g.set_timing(True)
+    g.advance(TIMESTEPS)
+    g.synchronize()
     kern = {r["kind"]: r for r in g.timing()}
     g.set_timing(False)
-    swept_out = g.download()
     g.close()
 
     # ---- plain per-step FP64 on the same workload (direct launches)

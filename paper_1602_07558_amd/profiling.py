@@ -32,9 +32,9 @@ def kernel_stats(directory: str):
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"(k_[a-z0-9]+)<swept::(\w+)>", name)
+    m = re.search(r"(k_[a-z0-9]+)<swept::(\w+)(?:, (\d+))?>", name)
     if m:
-        return f"{m.group(1)}<{m.group(2)}>"
+        return f"{m.group(1)}<{m.group(2)}>" if not m.group(3) else f"{m.group(1)}<{m.group(2)},{m.group(3)}>"
     m = re.search(r"(k_[a-z0-9]+)INS_(\d+)(\w+)", name)
     if m:
         return f"{m.group(1)}<{m.group(3)[:int(m.group(2))]}>"
