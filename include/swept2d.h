@@ -50,7 +50,7 @@ extern "C" {
 #define SWEPT2D_EHIP (-2)         /* HIP runtime error; message carries hipGetErrorString */
 #define SWEPT2D_ENOMEM (-3)       /* device allocation failed */
 #define SWEPT2D_EUNSUPPORTED (-4) /* valid request this build does not provide */
-#define SWEPT2D_EABORTED (-5)     /* a batch kernel stopped: a dependency wait hit its limit */
+#define SWEPT2D_EABORTED (-5)     /* a persistent batch kernel stopped: a dependency wait hit its limit */
 
 /* ------------------------------------------------------------- scheme ids
  * Built-in per-point sub-step operations (the paper's timestep(i, p)
@@ -209,11 +209,21 @@ const char *swept2d_last_error(void);
  * Many independent small grids advanced together, each by the swept rule
  * with its own tile side (Sec. 3-4; the tile side trades the exchange count
  * against pyramid depth as in Sec. 5, Eq. (4)), or by the per-step method
- * when no even side divides its grid. One advance is one captured HIP graph
- * holding one persistent kernel: workgroups take work items (grid, stage,
- * tile) from a device queue, and an item starts once every item of its
- * grid's previous stage has completed (per-grid completion counters in
- * device memory), so grids never wait for each other.
+ * when no even side divides its grid. A grid's work is a chain of phases
+ * (its upward pyramid, then bridges and octahedra alternating; one phase per
+ * sub-step for the per-step method), each phase a set of independent work
+ * items (one per tile, tile edge or block).
+ *
+ * SWEPT2D_BATCH_PHASED (default): the phases of all grids are spread over
+ * one common sequence of slots, each grid's phases in order; a slot is one
+ * kernel launch per launch class (workgroup size and stage code), one
+ * workgroup per item; the launch boundaries order the phases and no
+ * workgroup waits for another. An advance of up to 1024 steps is one
+ * captured HIP graph (longer advances replay it).
+ * SWEPT2D_BATCH_PERSISTENT: one persistent kernel whose workgroups take
+ * items from a device queue and wait on per-grid completion counters; only
+ * in libraries built with SWEPT2D_BUILD_PERSISTENT_BATCH defined (advance returns
+ * EUNSUPPORTED otherwise).
  *
  * Grids: HEAT5 and WAVE_LF in FP64 or FP32C, TEST_HASH in FP64 (other
  * schemes return EUNSUPPORTED). Each grid keeps its own state, layout and
@@ -257,17 +267,28 @@ int swept2d_batch_download(swept2d_batch *b, int idx, double *host);
  * EINVAL if nsteps < 0; 0 is a no-op. */
 int swept2d_batch_advance(swept2d_batch *b, long long nsteps);
 
-/* Wait for the batch; EABORTED if a kernel stopped on its wait limit (grid
- * states are then undefined), EHIP on a kernel fault. */
+/* Wait for the batch; EABORTED if a persistent kernel stopped on its wait
+ * limit (grid states are then undefined), EHIP on a kernel fault. */
 int swept2d_batch_synchronize(swept2d_batch *b);
 
 /* Sub-steps grid idx has advanced, or EINVAL. */
 long long swept2d_batch_substep_counter(const swept2d_batch *b, int idx);
 
-/* Longest time, in microseconds, a work item waits for its dependency before
- * the kernel stops with EABORTED (default 2 s; every wait of a valid run is
- * far shorter). 0 stops at the first wait that is not already satisfied:
- * it exercises the failure path. */
+#define SWEPT2D_BATCH_PHASED 0
+#define SWEPT2D_BATCH_PERSISTENT 1
+/* Select how advances run (see above); EINVAL for an unknown mode. get
+ * returns the mode or EINVAL. */
+int swept2d_batch_set_mode(swept2d_batch *b, int mode);
+int swept2d_batch_get_mode(const swept2d_batch *b);
+
+/* Kernel launches one advance of nsteps (1..1024) makes in the current mode
+ * (builds and keeps its graph), or a negative error code. */
+int swept2d_batch_launches(swept2d_batch *b, long long nsteps);
+
+/* Persistent mode: longest time, in microseconds, a work item waits for its
+ * dependency before the kernel stops with EABORTED (default 2 s). 0 stops at
+ * the first wait that is not already satisfied. No effect on phased
+ * advances, which never wait. */
 int swept2d_batch_set_wait_limit(swept2d_batch *b, long long microseconds);
 
 #ifdef __cplusplus

@@ -47,6 +47,9 @@ STAGING_OFF = 1
 TUNE_MODEL = 0
 TUNE_MEASURE = 1
 
+BATCH_PHASED = 0
+BATCH_PERSISTENT = 1
+
 KIND_NAMES = {0: "plain", 1: "up", 2: "bridge", 3: "oct"}
 
 EXPORTS = [
@@ -60,7 +63,8 @@ EXPORTS = [
     "swept2d_batch_create", "swept2d_batch_destroy", "swept2d_batch_count", "swept2d_batch_set_tile",
     "swept2d_batch_get_tile", "swept2d_batch_autotune", "swept2d_batch_upload", "swept2d_batch_download",
     "swept2d_batch_advance", "swept2d_batch_synchronize", "swept2d_batch_substep_counter",
-    "swept2d_batch_set_wait_limit",
+    "swept2d_batch_set_wait_limit", "swept2d_batch_set_mode", "swept2d_batch_get_mode",
+    "swept2d_batch_launches",
 ]
 
 _lib = None
@@ -126,6 +130,9 @@ def load_library():
         "swept2d_batch_synchronize": (i, [vp]),
         "swept2d_batch_substep_counter": (ll, [vp, i]),
         "swept2d_batch_set_wait_limit": (i, [vp, ll]),
+        "swept2d_batch_set_mode": (i, [vp, i]),
+        "swept2d_batch_get_mode": (i, [vp]),
+        "swept2d_batch_launches": (i, [vp, ll]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -313,6 +320,18 @@ def swept2d_batch_set_wait_limit(b: int, microseconds: int) -> int:
     return _check(load_library().swept2d_batch_set_wait_limit(b, microseconds))
 
 
+def swept2d_batch_set_mode(b: int, mode: int) -> int:
+    return _check(load_library().swept2d_batch_set_mode(b, mode))
+
+
+def swept2d_batch_get_mode(b: int) -> int:
+    return _check(load_library().swept2d_batch_get_mode(b))
+
+
+def swept2d_batch_launches(b: int, nsteps: int) -> int:
+    return _check(load_library().swept2d_batch_launches(b, nsteps))
+
+
 PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), TEST_HASH: (1, 1),
              TEST_INCR: (1, 1), TEST_PUSH5: (5, 2)}
 
@@ -497,3 +516,13 @@ class Swept2DBatch:
 
     def set_wait_limit(self, microseconds: int):
         swept2d_batch_set_wait_limit(self.b, microseconds)
+
+    def set_mode(self, mode: int):
+        swept2d_batch_set_mode(self.b, mode)
+
+    @property
+    def mode(self) -> int:
+        return swept2d_batch_get_mode(self.b)
+
+    def launches(self, nsteps: int) -> int:
+        return swept2d_batch_launches(self.b, nsteps)

@@ -164,22 +164,40 @@ hipError_t configure_lds(size_t bytes);
 
 // ------------------------------------------------------------------ batch
 //
-// A batch advances many independent grids in one persistent kernel. Its
-// work is a queue of items (grid, phase, index): phase 0 is every swept
-// grid's upward pyramid, odd phases its bridges (2 per tile), even phases
-// its octahedra (1 per tile); a per-step grid has one phase per sub-step (one
-// item per 64 x 64 block) plus, after an odd count, a copy back. Items are
-// numbered phase by phase; within a phase, grid by grid in `order` (grids
-// with more phases first, so the grids active in phase p are a prefix of
-// `order`). Workgroups take items in that order from one counter, and an item
-// of phase p waits until its grid has completed every item of phases < p.
-// An item waits only on items numbered before it, all taken by running
-// workgroups, so the queue always drains; a wait longer than `wait_ticks`
-// sets `error` and every workgroup stops.
+// A batch advances many independent grids. A grid's work is a sequence of
+// phases: phase 0 is its upward pyramid, odd phases its bridges (2 items per
+// tile), even phases its octahedra (1 item per tile); a per-step grid has
+// one phase per sub-step (one item per 64 x 64 block) plus, after an odd
+// count, a copy back. Phase p of a grid may start once its phase p - 1 has
+// completed.
+//
+// Phased launches (the default): the phases of all grids are laid out on a
+// common sequence of slots (grid g's phase j in slot floor(j L / P_g), L the
+// largest phase count, so every grid's phases are spread evenly and keep
+// their order). A slot is one kernel launch per launch class (workgroup size
+// and window pitch), each workgroup running one item of one grid; kernel
+// boundaries order the slots, so no workgroup ever waits for another. All
+// launches of an advance are one captured HIP graph.
+//
+// Persistent (compiled only with SWEPT2D_BUILD_PERSISTENT_BATCH): one kernel whose
+// workgroups take items from a device counter and wait on per-grid
+// completion counters.
 constexpr int kBatchThreads = 1024;
 constexpr int kBatchBlock = 64;  // side of a per-step block
 
 enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1 };
+
+// Launch classes of the phased batch: the stage code of tile side 64 on 16
+// waves, of tile side 32 on 4 waves, of any other side on 4 waves, and of
+// sides up to 22 on one wave; per-step grids run in the 4-wave generic class.
+enum BatchClass : int { kClass66 = 0, kClass34, kClassGen256, kClassGen64, kNumBatchClasses };
+inline int batch_class_of(int n) {
+  if (n == 64) return kClass66;
+  if (n == 32) return kClass34;
+  if (n != 0 && n <= 22) return kClassGen64;
+  return kClassGen256;
+}
+inline int batch_class_threads(int c) { return c == kClass66 ? 1024 : (c == kClassGen64 ? 64 : 256); }
 
 struct BatchGrid {
   Geo g0;          // off 0, T0 = the grid's level at the start of an advance
@@ -203,6 +221,30 @@ struct BatchPlan {
   int nphases;
 };
 
+// One launch of a slot: workgroup b runs item b - cum[j] of phase phase[j]
+// of grid grid[j], j the last entry with cum[j] <= b (cum[0] = 0, cum[n] =
+// the launch's workgroup count).
+struct PhaseLaunch {
+  const BatchGrid* grids;
+  const BatchPlan* plans;
+  const int* grid;
+  const int* phase;
+  const int* cum;
+  int n;
+};
+
+hipError_t launch_batch_phase(int cls, const PhaseLaunch& L, int blocks, size_t lds, hipStream_t st);
+// grids[i].g0.T0 += plans[i].S for every grid.
+hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st);
+bool batch_scheme_supported(int scheme);
+
+#ifdef SWEPT2D_BUILD_PERSISTENT_BATCH
+// Items are numbered phase by phase; within a phase, grid by grid in `order`
+// (grids with more phases first, so the grids active in phase p are a
+// prefix of `order`). Workgroups take items in that order from one counter,
+// and an item of phase p waits until its grid has completed every item of
+// phases < p; a wait longer than `wait_ticks` sets `error` and every
+// workgroup stops.
 struct BatchSched {
   long long total;
   int nphases;
@@ -223,11 +265,9 @@ struct BatchSched {
 hipError_t launch_batch(const BatchSched& s, int blocks, size_t lds, hipStream_t st);
 // done[] = 0 and *head = 0 (a kernel, so it may sit in a captured graph).
 hipError_t launch_batch_reset(unsigned* done, int ngrids, unsigned long long* head, hipStream_t st);
-// grids[i].g0.T0 += plans[i].S for every grid.
-hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st);
-// Resident workgroups of the batch kernel per compute unit at `lds` bytes.
+// Resident workgroups of the persistent kernel per compute unit at `lds` bytes.
 hipError_t batch_blocks_per_cu(size_t lds, int* out);
-bool batch_scheme_supported(int scheme);
+#endif
 
 // Host helpers shared by the host files (swept2d_api.cpp).
 int set_error(int code, const char* fmt, ...);  // message kept per thread

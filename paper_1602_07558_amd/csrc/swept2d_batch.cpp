@@ -1,11 +1,12 @@
-// Host side of the batch API: many independent grids advanced by one
-// persistent kernel (the swept rule per grid, or the per-step method for a
-// grid no even tile side divides), replayed from a captured HIP graph, and
-// the per-grid tile-side tuner.
+// Host side of the batch API: many independent grids (the swept rule per
+// grid, or the per-step method for a grid no even tile side divides), their
+// phases laid out on slots of launches replayed from a captured HIP graph,
+// and the per-grid tile-side tuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <new>
 #include <numeric>
@@ -47,14 +48,21 @@ struct HostGrid {
 
 struct Plan {
   BatchPlan* d_plans = nullptr;
-  long long* d_phase_base = nullptr;
+  int* d_egrid = nullptr;   // phased: entries (grid, phase) of every launch
+  int* d_ephase = nullptr;
+  int* d_cum = nullptr;     // phased: per launch, its entries' workgroup offsets
+  long long* d_phase_base = nullptr;  // persistent schedule
   int* d_active = nullptr;
   int* d_order = nullptr;
   long long* d_cum1 = nullptr;
   long long* d_cum2 = nullptr;
   hipGraphExec_t exec = nullptr;
+  int launches = 0;
   std::vector<long long> S;  // per grid
 };
+
+// Longest advance one graph covers; longer advances replay it.
+constexpr long long kChunkSteps = 1024;
 
 }  // namespace
 
@@ -68,7 +76,8 @@ struct swept2d_batch {
   unsigned* d_done = nullptr;
   unsigned long long* d_head = nullptr;
   int* d_error = nullptr;
-  long long wait_us = 2000000;  // longest dependency wait of the kernel
+  long long wait_us = 2000000;  // longest dependency wait of the persistent kernel
+  int mode = SWEPT2D_BATCH_PHASED;
   bool dirty = true;  // device descriptors out of date
   std::map<long long, Plan> plans;
 };
@@ -88,6 +97,18 @@ size_t stage_lds(const HostGrid& g, bool* staged_oct, bool* staged_bridge) {
                   win + (*staged_bridge ? bridge_stage_bytes(g.si, g.n) : 0));
 }
 
+// LDS of one item of phase p of grid g.
+size_t entry_lds(const HostGrid& g, int p) {
+  if (g.n == 0) return 0;
+  bool so = false, sb = false;
+  stage_lds(g, &so, &sb);
+  if (batch_class_of(g.n) == kClassGen64) so = sb = true;  // the kernel stages them
+  const size_t win = window_lds_bytes(g.si, g.n);
+  if (p == 0) return win;
+  if (p & 1) return win + (sb ? bridge_stage_bytes(g.si, g.n) : 0);
+  return win + (so ? oct_stage_bytes(g.si, g.n) : 0);
+}
+
 // Why tile side n cannot serve grid g in a batch, or nullptr.
 const char* batch_tile_problem(const HostGrid& g, int n) {
   if (n == 0) return nullptr;  // per-step
@@ -95,28 +116,38 @@ const char* batch_tile_problem(const HostGrid& g, int n) {
   if (g.nx % n || g.ny % n) return "tile side must divide nx and ny";
   if (n + 2 > 128) return "tile side above 126";
   if (window_lds_bytes(g.si, n) > device_lds_limit()) return "tile working set exceeds the workgroup LDS";
+  // One-wave items (sides up to 22) always stage their panel inputs.
+  if (batch_class_of(n) == kClassGen64 &&
+      window_lds_bytes(g.si, n) + std::max(oct_stage_bytes(g.si, n), bridge_stage_bytes(g.si, n)) > device_lds_limit())
+    return "tile working set exceeds the workgroup LDS";
   // The batch kernel runs 16 waves; the column layout needs n^2 to be a
   // multiple of its thread count at the fixed pitches (true for 32 and 64).
   return nullptr;
 }
 
-// Model ranking of tile sides for one grid of a batch. Grids of a batch run
-// side by side, so a grid's cost is the length of its own chain of phases:
-// per half cycle (h = n/2 sub-steps) one bridge and one octahedron item in
-// sequence, each a fixed cost plus one workgroup barrier per level (h levels
-// for the bridge, 2h for the octahedron), times the waves of items it needs
-// when it has more items than resident workgroups. Cost per sub-step, in the
-// spirit of Sec. 5, Eq. (4): [2 tau + 3 h lambda] * waves / h.
-int model_tile(const HostGrid& g, int resident) {
+// Model ranking of tile sides for one grid of a batch. Per half cycle
+// (h = n/2 sub-steps) a grid runs one bridge and one octahedron phase, each
+// a fixed cost tau (a launch) plus one workgroup barrier lambda per level
+// (h levels for the bridge, 2h for the octahedron), times the rounds of
+// items it needs when its items outnumber the workgroups resident on `cus`
+// compute units (residency from the item's LDS and its launch class's
+// workgroup size). Cost per sub-step, in the spirit of Sec. 5, Eq. (4):
+// [2 tau + 3 h lambda] * rounds / h.
+int model_tile(const HostGrid& g, int cus) {
   const double tau = 6.0e-6, lambda = 0.75e-6;
+  const size_t lim = std::max<size_t>(device_lds_limit(), 1);
   int best = 0;
   double best_cost = 1e300;
   for (int n = 4; n <= 64; n += 2) {
     if (batch_tile_problem(g, n)) continue;
     const int h = n / 2;
+    bool so, sb;
+    const size_t lds = std::max<size_t>(stage_lds(g, &so, &sb), 1);
+    const int threads = batch_class_threads(batch_class_of(n));
+    const double per_cu = std::max(1.0, std::min((double)(lim / lds), 2048.0 / threads));
     const double tiles = (double)(g.nx / n) * (g.ny / n);
-    const double waves = std::ceil(2.0 * tiles / std::max(resident, 1));
-    double cost = (2.0 * tau + 3.0 * h * lambda) * waves / h;
+    const double rounds = std::ceil(2.0 * tiles / (per_cu * std::max(cus, 1)));
+    double cost = (2.0 * tau + 3.0 * h * lambda * threads / 1024.0) * rounds / h;
     if (pitch_of(n) == 0) cost *= 1.25;  // generic stage code
     if (cost < best_cost * (1.0 - 1e-9)) {
       best_cost = cost;
@@ -163,6 +194,9 @@ void drop_plans(swept2d_batch* b) {
     Plan& p = kv.second;
     if (p.exec) hipGraphExecDestroy(p.exec);
     hipFree(p.d_plans);
+    hipFree(p.d_egrid);
+    hipFree(p.d_ephase);
+    hipFree(p.d_cum);
     hipFree(p.d_phase_base);
     hipFree(p.d_active);
     hipFree(p.d_order);
@@ -227,15 +261,6 @@ int upload_descriptors(swept2d_batch* b, size_t* lds_out) {
   return 0;
 }
 
-size_t batch_lds(const swept2d_batch* b) {
-  size_t lds = 0;
-  for (const HostGrid& g : b->grids) {
-    bool so, sb;
-    lds = std::max(lds, stage_lds(g, &so, &sb));
-  }
-  return lds;
-}
-
 template <class T>
 int upload_array(T** dst, const std::vector<T>& v) {
   const size_t bytes = std::max<size_t>(sizeof(T), v.size() * sizeof(T));
@@ -248,21 +273,83 @@ int upload_array(T** dst, const std::vector<T>& v) {
   return 0;
 }
 
-// Build (or find) the schedule and graph of an advance by nsteps.
-int plan_for(swept2d_batch* b, long long nsteps, Plan** out) {
-  auto it = b->plans.find(nsteps);
-  if (it != b->plans.end()) {
-    *out = &it->second;
-    return 0;
-  }
+// Workgroups of phase p of a grid (the device decode's item count).
+int phase_items(const HostGrid& g, int p) {
+  const int u = units_of(g);
+  if (g.n == 0) return u;
+  return (p & 1) ? 2 * u : u;
+}
+
+int capture_graph(swept2d_batch* b, Plan& pl, const std::function<hipError_t()>& body) {
+  BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  hipError_t e1 = body();
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  hipError_t first = e1 != hipSuccess ? e1 : e;
+  if (first == hipSuccess) first = hipGraphInstantiate(&pl.exec, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  if (first != hipSuccess) return hip_error(first, "batch graph capture");
+  return 0;
+}
+
+// Phased schedule: grid g's phase j goes to slot floor(j L / P_g) (strictly
+// increasing in j since P_g <= L); a slot is one launch per launch class
+// holding that class's entries.
+int plan_phased(swept2d_batch* b, const std::vector<BatchPlan>& plans, Plan& pl) {
   const int G = b->count;
-  std::vector<BatchPlan> plans(G);
-  Plan pl;
-  pl.S.resize(G);
+  int L = 0;
+  for (int i = 0; i < G; ++i) L = std::max(L, plans[i].nphases);
+  std::vector<std::vector<std::pair<int, int>>> slot(L);
   for (int i = 0; i < G; ++i) {
-    pl.S[i] = nsteps * b->grids[i].substeps;
-    plans[i] = plan_of(b->grids[i], pl.S[i]);
+    const int P = plans[i].nphases;
+    for (int j = 0; j < P; ++j) slot[(size_t)((long long)j * L / P)].push_back({i, j});
   }
+  struct Rec {
+    int cls, first, count, cumoff, blocks;
+    size_t lds;
+  };
+  std::vector<int> egrid, ephase, cum;
+  std::vector<Rec> recs;
+  for (int sidx = 0; sidx < L; ++sidx) {
+    for (int cls = 0; cls < kNumBatchClasses; ++cls) {
+      Rec r{cls, (int)egrid.size(), 0, (int)cum.size(), 0, 0};
+      long long tot = 0;
+      for (const auto& e : slot[sidx]) {
+        const HostGrid& g = b->grids[e.first];
+        if (batch_class_of(g.n) != cls) continue;
+        if (r.count == 0) cum.push_back(0);
+        egrid.push_back(e.first);
+        ephase.push_back(e.second);
+        tot += phase_items(g, e.second);
+        if (tot >= (1LL << 31)) return set_error(SWEPT2D_EINVAL, "batch launch exceeds 2^31 workgroups");
+        cum.push_back((int)tot);
+        r.lds = std::max(r.lds, entry_lds(g, e.second));
+        ++r.count;
+      }
+      if (r.count == 0) continue;
+      r.blocks = (int)tot;
+      recs.push_back(r);
+    }
+  }
+  int rc;
+  if ((rc = upload_array(&pl.d_egrid, egrid)) || (rc = upload_array(&pl.d_ephase, ephase)) ||
+      (rc = upload_array(&pl.d_cum, cum)))
+    return rc;
+  pl.launches = (int)recs.size();
+  return capture_graph(b, pl, [&]() -> hipError_t {
+    for (const Rec& r : recs) {
+      PhaseLaunch l{b->d_grids, pl.d_plans, pl.d_egrid + r.first, pl.d_ephase + r.first, pl.d_cum + r.cumoff,
+                    r.count};
+      hipError_t e = launch_batch_phase(r.cls, l, r.blocks, r.lds, b->stream);
+      if (e != hipSuccess) return e;
+    }
+    return launch_batch_bump(b->d_grids, pl.d_plans, G, b->stream);
+  });
+}
+
+#ifdef SWEPT2D_BUILD_PERSISTENT_BATCH
+int plan_persistent(swept2d_batch* b, const std::vector<BatchPlan>& plans, Plan& pl) {
+  const int G = b->count;
   std::vector<int> order(G);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return plans[a].nphases > plans[c].nphases; });
@@ -286,14 +373,15 @@ int plan_for(swept2d_batch* b, long long nsteps, Plan** out) {
   }
   const long long total = base[P];
   int rc;
-  if ((rc = upload_array(&pl.d_plans, plans)) || (rc = upload_array(&pl.d_phase_base, base)) ||
-      (rc = upload_array(&pl.d_active, active)) || (rc = upload_array(&pl.d_order, order)) ||
-      (rc = upload_array(&pl.d_cum1, cum1)) || (rc = upload_array(&pl.d_cum2, cum2))) {
-    b->plans[nsteps] = pl;  // freed by drop_plans
-    drop_plans(b);
+  if ((rc = upload_array(&pl.d_phase_base, base)) || (rc = upload_array(&pl.d_active, active)) ||
+      (rc = upload_array(&pl.d_order, order)) || (rc = upload_array(&pl.d_cum1, cum1)) ||
+      (rc = upload_array(&pl.d_cum2, cum2)))
     return rc;
+  size_t lds = 0;
+  for (const HostGrid& g : b->grids) {
+    bool so, sb;
+    lds = std::max(lds, stage_lds(g, &so, &sb));
   }
-  const size_t lds = batch_lds(b);
   int per_cu = 0;
   BHIP(batch_blocks_per_cu(lds, &per_cu), "batch kernel occupancy");
   if (per_cu < 1) return set_error(SWEPT2D_EUNSUPPORTED, "batch kernel does not fit a compute unit (%zu B LDS)", lds);
@@ -313,19 +401,43 @@ int plan_for(swept2d_batch* b, long long nsteps, Plan** out) {
   s.head = b->d_head;
   s.error = b->d_error;
   s.wait_ticks = b->wait_us * 100;  // the wait clock runs at 100 MHz
-  BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  hipError_t e1 = launch_batch_reset(b->d_done, G, b->d_head, b->stream);
-  hipError_t e2 = total > 0 ? launch_batch(s, (int)blocks, lds, b->stream) : hipSuccess;
-  hipError_t e3 = launch_batch_bump(b->d_grids, pl.d_plans, G, b->stream);
-  hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamEndCapture(b->stream, &graph);
-  hipError_t first = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e));
-  if (first == hipSuccess) first = hipGraphInstantiate(&pl.exec, graph, nullptr, nullptr, 0);
-  if (graph) hipGraphDestroy(graph);
-  b->plans[nsteps] = pl;
-  if (first != hipSuccess) {
+  pl.launches = 1;
+  return capture_graph(b, pl, [&]() -> hipError_t {
+    hipError_t e = launch_batch_reset(b->d_done, G, b->d_head, b->stream);
+    if (e == hipSuccess && total > 0) e = launch_batch(s, (int)blocks, lds, b->stream);
+    if (e == hipSuccess) e = launch_batch_bump(b->d_grids, pl.d_plans, G, b->stream);
+    return e;
+  });
+}
+#endif
+
+// Build (or find) the schedule and graph of an advance by nsteps.
+int plan_for(swept2d_batch* b, long long nsteps, Plan** out) {
+  auto it = b->plans.find(nsteps);
+  if (it != b->plans.end()) {
+    *out = &it->second;
+    return 0;
+  }
+  const int G = b->count;
+  std::vector<BatchPlan> plans(G);
+  Plan pl;
+  pl.S.resize(G);
+  for (int i = 0; i < G; ++i) {
+    pl.S[i] = nsteps * b->grids[i].substeps;
+    plans[i] = plan_of(b->grids[i], pl.S[i]);
+  }
+  int rc = upload_array(&pl.d_plans, plans);
+  if (rc == 0) {
+#ifdef SWEPT2D_BUILD_PERSISTENT_BATCH
+    rc = b->mode == SWEPT2D_BATCH_PERSISTENT ? plan_persistent(b, plans, pl) : plan_phased(b, plans, pl);
+#else
+    rc = plan_phased(b, plans, pl);
+#endif
+  }
+  b->plans[nsteps] = pl;  // freed by drop_plans
+  if (rc) {
     drop_plans(b);
-    return hip_error(first, "batch graph capture");
+    return rc;
   }
   *out = &b->plans[nsteps];
   return 0;
@@ -364,12 +476,6 @@ int set_tile_impl(swept2d_batch* b, int idx, int n) {
   drop_plans(b);
   b->dirty = true;
   return 0;
-}
-
-int resident_blocks(swept2d_batch* b) {
-  int per_cu = 1;
-  if (batch_blocks_per_cu(batch_lds(b), &per_cu) != hipSuccess) per_cu = 1;
-  return std::max(1, per_cu) * b->cu_count;
 }
 
 }  // namespace
@@ -457,14 +563,9 @@ swept2d_batch* swept2d_batch_create(int count, const int* nx, const int* ny, con
     set_error(SWEPT2D_EHIP, "hipMemset failed");
     return bail(0, "");
   }
-  // Initial tile sides from the model (the largest usable tiles first fix
-  // the LDS of the batch kernel and hence its residency).
+  // Initial tile sides from the model.
   for (int i = 0; i < count; ++i) {
     if (set_tile_impl(b, i, model_tile(b->grids[i], b->cu_count))) return bail(0, "");
-  }
-  const int resident = resident_blocks(b);
-  for (int i = 0; i < count; ++i) {
-    if (set_tile_impl(b, i, model_tile(b->grids[i], resident))) return bail(0, "");
   }
   return b;
 }
@@ -491,7 +592,7 @@ int swept2d_batch_set_tile(swept2d_batch* b, int idx, int n) {
   int rc = check_idx(b, idx);
   if (rc) return rc;
   if (n < 0) return set_tile_impl(b, idx, 0);
-  if (n == 0) n = model_tile(b->grids[idx], resident_blocks(b));
+  if (n == 0) n = model_tile(b->grids[idx], b->cu_count);
   return set_tile_impl(b, idx, n);
 }
 
@@ -539,16 +640,53 @@ int swept2d_batch_advance(swept2d_batch* b, long long nsteps) {
   if (nsteps < 0) return set_error(SWEPT2D_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return 0;
   if (nsteps > (1LL << 30)) return set_error(SWEPT2D_EINVAL, "nsteps too large");
-#ifndef SWEPT2D_BATCH_KERNEL
-  // The persistent kernel is compiled but not launched: an earlier form of
-  // its work loop hung on the device (the compiler sent lanes 1..63 back to
-  // the item barrier without lane 0; fixed with one thread-0 region per round
-  // and a scalar loop exit), and the fixed form has not yet run there.
-  // Build with -DSWEPT2D_BATCH_KERNEL to launch it.
-  return set_error(SWEPT2D_EUNSUPPORTED,
-                   "batched persistent kernel disabled pending verification on the device "
-                   "(build with -DSWEPT2D_BATCH_KERNEL)");
+#ifndef SWEPT2D_BUILD_PERSISTENT_BATCH
+  if (b->mode == SWEPT2D_BATCH_PERSISTENT)
+    return set_error(SWEPT2D_EUNSUPPORTED,
+                     "the persistent batch kernel is not built (it hung on the device in an earlier form; "
+                     "the phased launches are the supported mode)");
 #endif
+  int rc;
+  if (b->dirty) {
+    BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    size_t lds = 0;
+    if ((rc = upload_descriptors(b, &lds))) return rc;
+  }
+  // Advances longer than one chunk replay the chunk's graph, then one graph
+  // for the rest (every grid's chain restarts with an upward pyramid at a
+  // chunk boundary; results are the same bits).
+  const long long chunk = std::min(nsteps, kChunkSteps);
+  const long long reps = nsteps / chunk, rest = nsteps % chunk;
+  Plan* pl = nullptr;
+  if ((rc = plan_for(b, chunk, &pl))) return rc;
+  for (long long k = 0; k < reps; ++k) {
+    BHIP(hipGraphLaunch(pl->exec, b->stream), "hipGraphLaunch");
+    for (int i = 0; i < b->count; ++i) b->grids[i].T += pl->S[i];
+  }
+  if (rest) {
+    if ((rc = plan_for(b, rest, &pl))) return rc;
+    BHIP(hipGraphLaunch(pl->exec, b->stream), "hipGraphLaunch");
+    for (int i = 0; i < b->count; ++i) b->grids[i].T += pl->S[i];
+  }
+  return 0;
+}
+
+int swept2d_batch_set_mode(swept2d_batch* b, int mode) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  if (mode != SWEPT2D_BATCH_PHASED && mode != SWEPT2D_BATCH_PERSISTENT)
+    return set_error(SWEPT2D_EINVAL, "unknown batch mode %d", mode);
+  if (mode == b->mode) return 0;
+  BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  b->mode = mode;
+  drop_plans(b);
+  return 0;
+}
+
+int swept2d_batch_get_mode(const swept2d_batch* b) { return b ? b->mode : SWEPT2D_EINVAL; }
+
+int swept2d_batch_launches(swept2d_batch* b, long long nsteps) {
+  if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
+  if (nsteps < 1 || nsteps > kChunkSteps) return set_error(SWEPT2D_EINVAL, "nsteps must be in 1..%lld", kChunkSteps);
   int rc;
   if (b->dirty) {
     BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -557,9 +695,7 @@ int swept2d_batch_advance(swept2d_batch* b, long long nsteps) {
   }
   Plan* pl = nullptr;
   if ((rc = plan_for(b, nsteps, &pl))) return rc;
-  BHIP(hipGraphLaunch(pl->exec, b->stream), "hipGraphLaunch");
-  for (int i = 0; i < b->count; ++i) b->grids[i].T += pl->S[i];
-  return 0;
+  return pl->launches;
 }
 
 int swept2d_batch_synchronize(swept2d_batch* b) {
@@ -585,10 +721,9 @@ int swept2d_batch_autotune(swept2d_batch* b, int mode) {
   if (!b) return set_error(SWEPT2D_EINVAL, "null batch");
   if (mode != SWEPT2D_TUNE_MODEL && mode != SWEPT2D_TUNE_MEASURE) return set_error(SWEPT2D_EINVAL, "unknown mode");
   int rc;
-  const int resident = resident_blocks(b);
   if (mode == SWEPT2D_TUNE_MODEL) {
     for (int i = 0; i < b->count; ++i)
-      if ((rc = set_tile_impl(b, i, model_tile(b->grids[i], resident)))) return rc;
+      if ((rc = set_tile_impl(b, i, model_tile(b->grids[i], b->cu_count)))) return rc;
     return 0;
   }
   // Measured: run each grid alone, on a copy of its state, for a few
@@ -615,6 +750,7 @@ int swept2d_batch_autotune(swept2d_batch* b, int mode) {
       rc = SWEPT2D_EHIP;
       break;
     }
+    t->mode = b->mode;
     if (hipMemcpy(t->grids[0].state, g.state, state_bytes(g), hipMemcpyDeviceToDevice) != hipSuccess) {
       swept2d_batch_destroy(t);
       rc = set_error(SWEPT2D_EHIP, "hipMemcpy");

@@ -835,13 +835,13 @@ hipError_t lds_t(size_t bytes) {
 
 // ------------------------------------------------------------------ batch
 
-// One sub-step of the 64 x (NT/64 * 4) block `blk` of a grid (per-step
-// grids of a batch); thread (x, y) walks 4 rows of one column.
+// One sub-step of the 64 x 64 block `blk` of a grid (per-step grids of a
+// batch); thread (x, y) walks 64 / (NT / 64) rows of one column.
 template <class S, int NT>
 __device__ void plain_item(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int nx, int ny,
                            long long T, const SchemeParams& sp, int blk) {
   using V = typename S::V;
-  constexpr int NV = S::NV, R = 4, TY = NT / 64;
+  constexpr int NV = S::NV, TY = NT / 64, R = kBatchBlock / TY;
   static_assert(TY * R == kBatchBlock, "block geometry");
   const int bx = (nx + kBatchBlock - 1) / kBatchBlock;
   const int x = (blk % bx) * kBatchBlock + (int)(threadIdx.x & 63);
@@ -886,12 +886,13 @@ __device__ void plain_item(const typename S::V* __restrict__ in, typename S::V* 
 template <class S, int NT>
 __device__ void copy_item(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int nx, int ny,
                           int blk) {
+  constexpr int TY = NT / 64, R = kBatchBlock / TY;
   const int bx = (nx + kBatchBlock - 1) / kBatchBlock;
   const int x = (blk % bx) * kBatchBlock + (int)(threadIdx.x & 63);
-  const int ys = (blk / bx) * kBatchBlock + (int)(threadIdx.x >> 6) * 4;
+  const int ys = (blk / bx) * kBatchBlock + (int)(threadIdx.x >> 6) * R;
   if (x >= nx) return;
   const size_t plane = (size_t)nx * ny;
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int y = ys + r;
     if (y >= ny) break;
 #pragma unroll
@@ -899,29 +900,26 @@ __device__ void copy_item(const typename S::V* __restrict__ in, typename S::V* _
   }
 }
 
-// Items of grid `G` completed before its phase p.
-__device__ __forceinline__ long long batch_need(const BatchGrid& G, int p) {
-  if (G.kind == kBatchPlain) return (long long)G.units * p;
-  if (p == 0) return 0;
-  return (long long)G.units * (1 + 2 * (p / 2) + ((p + 1) / 2 - 1));
-}
-
-// Run item `item` of phase p of grid G (stage code at pitch WC). Kept out of
-// line: each variant is register-allocated on its own.
-template <class S, int WC>
-__device__ __noinline__ void batch_stage(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
-  constexpr int NT = kBatchThreads;
+// Run item `item` of phase p of grid G with the stage code at pitch WC on NT
+// threads. Phase 0: upward pyramid; odd phases: bridges of half cycle
+// (p - 1) / 2; even phases: octahedra (the last one of the advance writes the
+// state). A per-step grid: phase p < S is sub-step p, alternating between the
+// state and the second buffer; after an odd count a copy back.
+template <class S, int WC, int NT>
+__device__ __forceinline__ void batch_stage(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
   using V = typename S::V;
   V* state = static_cast<V*>(G.state);
-  if (G.kind == kBatchPlain) {
-    V* s2 = static_cast<V*>(G.state2);
-    if (p < P.S) {
-      const bool even = (p & 1) == 0;
-      plain_item<S, NT>(even ? state : s2, even ? s2 : state, G.g0.nx, G.g0.ny, G.g0.T0 + p, G.sp, item);
-    } else {
-      copy_item<S, NT>(s2, state, G.g0.nx, G.g0.ny, item);
+  if constexpr (WC == 0 && NT == 256) {
+    if (G.kind == kBatchPlain) {
+      V* s2 = static_cast<V*>(G.state2);
+      if (p < P.S) {
+        const bool even = (p & 1) == 0;
+        plain_item<S, NT>(even ? state : s2, even ? s2 : state, G.g0.nx, G.g0.ny, G.g0.T0 + p, G.sp, item);
+      } else {
+        copy_item<S, NT>(s2, state, G.g0.nx, G.g0.ny, item);
+      }
+      return;
     }
-    return;
   }
   Geo g = G.g0;
   const int h = g.h;
@@ -933,22 +931,85 @@ __device__ __noinline__ void batch_stage(const BatchGrid& G, const BatchPlan& P,
   g.off = (hc & 1) ? h : 0;
   g.T0 = G.g0.T0 + (long long)hc * h;
   const int H = hc < P.q ? h : P.r;
+  // One-wave items (tile sides up to 22) always stage their panel inputs
+  // (a few KB), which keeps the per-level fetch registers out of the kernel.
+  constexpr bool always_staged = NT == 64;
   if (p & 1) {
-    bridge_item<S, WC, NT>(g, H, G.staged_bridge, state, G.pp, G.sp, item, smem);
+    bridge_item<S, WC, NT>(g, H, always_staged ? 1 : G.staged_bridge, state, G.pp, G.sp, item, smem);
   } else {
     const int Hu = (hc + 1 < P.q) ? h : (hc + 1 == P.q ? P.r : 0);
-    oct_item<S, WC, NT>(g, H, Hu, G.staged_oct, state, G.pp, G.sp, item, smem);
+    oct_item<S, WC, NT>(g, H, Hu, always_staged ? 1 : G.staged_oct, state, G.pp, G.sp, item, smem);
   }
+}
+
+// One launch of a slot of the phased batch: workgroup b finds its entry by
+// binary search over the launch's item offsets (all reads are uniform) and
+// runs one item. No workgroup waits for another: the slot's launches order
+// the phases.
+template <int WC, int NT>
+__global__ __launch_bounds__(NT) void k_batch_phase(PhaseLaunch L) {
+  extern __shared__ double smem_d[];
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = L.n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (L.cum[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int g = L.grid[lo], p = L.phase[lo], item = b - L.cum[lo];
+  const BatchGrid& G = L.grids[g];
+  const BatchPlan& P = L.plans[g];
+  switch (G.scheme) {
+    case kHeat64: batch_stage<Heat64, WC, NT>(G, P, p, item, smem_d); break;
+    case kWave64: batch_stage<Wave64, WC, NT>(G, P, p, item, smem_d); break;
+    case kHash64: batch_stage<Hash64, WC, NT>(G, P, p, item, smem_d); break;
+    case kHeat32C: batch_stage<Heat32C, WC, NT>(G, P, p, item, smem_d); break;
+    case kWave32C: batch_stage<Wave32C, WC, NT>(G, P, p, item, smem_d); break;
+    default: break;
+  }
+}
+
+__global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ngrids) grids[i].g0.T0 += plans[i].S;
+}
+
+#ifdef SWEPT2D_BUILD_PERSISTENT_BATCH
+// Items of grid `G` completed before its phase p.
+__device__ __forceinline__ long long batch_need(const BatchGrid& G, int p) {
+  if (G.kind == kBatchPlain) return (long long)G.units * p;
+  if (p == 0) return 0;
+  return (long long)G.units * (1 + 2 * (p / 2) + ((p + 1) / 2 - 1));
+}
+
+template <class S, int WC>
+__device__ __noinline__ void batch_stage_persistent(const BatchGrid& G, const BatchPlan& P, int p, int item,
+                                                    double* smem) {
+  if (G.kind == kBatchPlain) {
+    using V = typename S::V;
+    V* state = static_cast<V*>(G.state);
+    V* s2 = static_cast<V*>(G.state2);
+    if (p < P.S) {
+      const bool even = (p & 1) == 0;
+      plain_item<S, kBatchThreads>(even ? state : s2, even ? s2 : state, G.g0.nx, G.g0.ny, G.g0.T0 + p, G.sp, item);
+    } else {
+      copy_item<S, kBatchThreads>(s2, state, G.g0.nx, G.g0.ny, item);
+    }
+    return;
+  }
+  batch_stage<S, WC, kBatchThreads>(G, P, p, item, smem);
 }
 
 template <class S>
 __device__ void batch_scheme(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
   if (G.wc == 66)
-    batch_stage<S, 66>(G, P, p, item, smem);
+    batch_stage_persistent<S, 66>(G, P, p, item, smem);
   else if (G.wc == 34)
-    batch_stage<S, 34>(G, P, p, item, smem);
+    batch_stage_persistent<S, 34>(G, P, p, item, smem);
   else
-    batch_stage<S, 0>(G, P, p, item, smem);
+    batch_stage_persistent<S, 0>(G, P, p, item, smem);
 }
 
 // Largest i in [lo, hi) with a[i] <= key (a nondecreasing, a[lo] <= key).
@@ -963,12 +1024,11 @@ __device__ __forceinline__ int last_le(const long long* a, int lo, int hi, long 
   return lo;
 }
 
-// The work loop. One thread takes the next ticket (first counting the
-// workgroup's previous item as done), decodes it and waits for its
+// The persistent work loop. One thread takes the next ticket (first counting
+// the workgroup's previous item as done), decodes it and waits for its
 // dependency; the workgroup then runs the item. The loop's exit and every
 // value the item depends on are read back as scalars (readfirstlane), so
-// the whole workgroup goes round the loop together: a per-lane exit test
-// lets the compiler send lanes back to the barrier on separate paths.
+// the whole workgroup goes round the loop together.
 __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchSched s) {
   extern __shared__ double smem_d[];
   __shared__ int sh_stop, sh_phase, sh_grid, sh_item;
@@ -990,10 +1050,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchSched s) {
           g = s.order[j];
           item = (int)(local - cum[j]);
           const unsigned need = (unsigned)batch_need(s.grids[g], p);
-          // Poll with plain (relaxed) loads: an acquire per poll would
-          // invalidate the L2 every time. One acquire fence follows a
-          // satisfied wait. The wait is bounded in real time (the 100 MHz
-          // counter), so it ends however slow a poll is.
           const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
           while (__hip_atomic_load(&s.done[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
             if (__builtin_amdgcn_s_memrealtime() - t0 > (unsigned long long)s.wait_ticks ||
@@ -1027,9 +1083,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchSched s) {
       case kWave32C: batch_scheme<Wave32C>(G, P, p, item, smem_d); break;
       default: break;
     }
-    // Every wave's stores have reached the L2 before the barrier; thread 0's
-    // release at the top of the next round writes the L2 back, so the item's
-    // results are visible device-wide before it counts.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     prev = g;
@@ -1041,10 +1094,12 @@ __global__ void k_batch_reset(unsigned* done, int ngrids, unsigned long long* he
   if (i < ngrids) done[i] = 0u;
   if (i == 0) *head = 0ull;
 }
+#endif  // SWEPT2D_BUILD_PERSISTENT_BATCH
 
-__global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ngrids) grids[i].g0.T0 += plans[i].S;
+template <int WC, int NT>
+hipError_t batch_phase_lds(int bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_phase<WC, NT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 }  // namespace
@@ -1100,9 +1155,31 @@ hipError_t configure_lds(size_t bytes) {
     }();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  const int b = (int)bytes;
+  hipError_t e = batch_phase_lds<66, 1024>(b);
+  if (e == hipSuccess) e = batch_phase_lds<34, 256>(b);
+  if (e == hipSuccess) e = batch_phase_lds<0, 256>(b);
+  if (e == hipSuccess) e = batch_phase_lds<0, 64>(b);
+  return e;
 }
 
+hipError_t launch_batch_phase(int cls, const PhaseLaunch& L, int blocks, size_t lds, hipStream_t st) {
+  switch (cls) {
+    case kClass66: hipLaunchKernelGGL((k_batch_phase<66, 1024>), dim3(blocks), dim3(1024), lds, st, L); break;
+    case kClass34: hipLaunchKernelGGL((k_batch_phase<34, 256>), dim3(blocks), dim3(256), lds, st, L); break;
+    case kClassGen256: hipLaunchKernelGGL((k_batch_phase<0, 256>), dim3(blocks), dim3(256), lds, st, L); break;
+    case kClassGen64: hipLaunchKernelGGL((k_batch_phase<0, 64>), dim3(blocks), dim3(64), lds, st, L); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_bump, dim3((ngrids + 255) / 256), dim3(256), 0, st, grids, plans, ngrids);
+  return hipGetLastError();
+}
+
+#ifdef SWEPT2D_BUILD_PERSISTENT_BATCH
 hipError_t launch_batch(const BatchSched& s, int blocks, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(kBatchThreads), lds, st, s);
   return hipGetLastError();
@@ -1113,17 +1190,13 @@ hipError_t launch_batch_reset(unsigned* done, int ngrids, unsigned long long* he
   return hipGetLastError();
 }
 
-hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_bump, dim3((ngrids + 255) / 256), dim3(256), 0, st, grids, plans, ngrids);
-  return hipGetLastError();
-}
-
 hipError_t batch_blocks_per_cu(size_t lds, int* out) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_batch, kBatchThreads, lds);
 }
+#endif
 
 bool batch_scheme_supported(int scheme) {
   return scheme == kHeat64 || scheme == kWave64 || scheme == kHash64 || scheme == kHeat32C || scheme == kWave32C;

@@ -1,11 +1,15 @@
-"""Batch API on the GPU: many grids in one persistent, graph-captured kernel.
+"""Batch API on the GPU: many grids advanced together from one captured graph.
 
 Each grid of a batch must give exactly what the oracle gives for that grid
 alone (bitwise: hash, heat, wave in FP64; FP32C against the FP32C oracle),
-whatever tile side each grid runs with, per-step grids included, across
-split advances and graph replays. The failure path (a dependency wait that
-hits its limit) is forced from the host with a zero wait limit.
+whatever tile side (and hence launch class) each grid runs with, per-step
+grids included, across split advances, graph replays and advances longer
+than one graph. Every case runs in the phased mode (slots of launches, no
+workgroup waits for another); the same cases in the persistent mode are
+kept, skipped (see PERSISTENT_OFF).
 """
+import sys
+
 import numpy as np
 import pytest
 
@@ -15,15 +19,19 @@ import swept_inputs as si
 
 pytestmark = pytest.mark.gpu
 
-# The batched persistent kernel's first device runs hung: its work loop, as
-# compiled, sent lanes 1..63 of every wave back to the item barrier without
-# lane 0 (the ticket taker), so a workgroup repeated one item forever. The
-# loop now has one thread-0 region per round and a scalar exit (checked in
-# the generated code), but the fixed kernel has not run on a device yet and
-# the library refuses to launch it (EUNSUPPORTED). These tests run it; they
-# stay skipped until it is verified.
-KERNEL_PENDING = pytest.mark.skip(reason="batched persistent kernel disabled pending device verification "
-                                         "after a hang in its work loop (fixed, not yet run)")
+# The persistent batch kernel hung on the device twice (its work loop, as
+# compiled, sent lanes 1..63 of a wave back to the item barrier without lane
+# 0, the ticket taker; a first fix did not cure it). It is not built into the
+# library (advance returns EUNSUPPORTED in that mode); its cases stay here,
+# skipped.
+PERSISTENT_OFF = pytest.mark.skip(reason="persistent batch kernel hung on the device twice; not built, "
+                                         "its mode returns EUNSUPPORTED")
+MODES = [pytest.param(sw.BATCH_PHASED, id="phased"),
+         pytest.param(sw.BATCH_PERSISTENT, id="persistent", marks=PERSISTENT_OFF)]
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
 
 
 def _params(pde):
@@ -41,10 +49,12 @@ def _oracle(spec, state, steps, t0=0):
     return u.astype(np.float64) - c.astype(np.float64)
 
 
-def _make(specs):
+def _make(specs, mode=sw.BATCH_PHASED):
     grids = [dict(nx=s["nx"], ny=s["ny"], pde=s["pde"], prec=s.get("prec", sw.FP64), params=_params(s["pde"]))
              for s in specs]
-    return sw.Swept2DBatch(grids)
+    b = sw.Swept2DBatch(grids)
+    b.set_mode(mode)
+    return b
 
 
 def _inits(specs):
@@ -64,11 +74,12 @@ MIXED = [
 ]
 
 
-@KERNEL_PENDING
-def test_mixed_batch_matches_oracle_per_grid():
+@pytest.mark.parametrize("mode", MODES)
+def test_mixed_batch_matches_oracle_per_grid(mode):
     specs = MIXED
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("mixed batch", len(specs), "grids, 70 steps, mode", mode)
+    with _make(specs, mode) as b:
         assert b.tile(2) == 0  # 67 x 45: per-step
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
@@ -82,16 +93,17 @@ def test_mixed_batch_matches_oracle_per_grid():
             assert b.T(i) == steps
 
 
-@KERNEL_PENDING
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("tiles", [
     [64, 48, -1, 4, 32, 16, 32, 16, 32],
     [32, 16, -1, 2, 64, 8, 16, 8, 16],
     [-1, -1, -1, -1, -1, -1, -1, -1, -1],
 ])
-def test_explicit_tiles_and_per_step(tiles):
+def test_explicit_tiles_and_per_step(tiles, mode):
     specs = MIXED
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("explicit tiles", tiles, "mode", mode)
+    with _make(specs, mode) as b:
         for i, n in enumerate(tiles):
             b.set_tile(i, n)
             assert b.tile(i) == (0 if n < 0 else n)
@@ -102,11 +114,12 @@ def test_explicit_tiles_and_per_step(tiles):
             assert np.array_equal(b.download(i), _oracle(spec, s0, 37)), (i, tiles[i])
 
 
-@KERNEL_PENDING
-def test_split_advances_and_graph_replay():
+@pytest.mark.parametrize("mode", MODES)
+def test_split_advances_and_graph_replay(mode):
     specs = MIXED[:6]
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("split advances 13,13,13,40,1 mode", mode)
+    with _make(specs, mode) as b:
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
         for k in (13, 13, 13, 40, 1):  # the 13-step graph replays three times
@@ -117,14 +130,15 @@ def test_split_advances_and_graph_replay():
             assert b.T(i) == total
 
 
-@KERNEL_PENDING
-def test_batch_equals_single_handles():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_equals_single_handles(mode):
     """Each grid of a batch gives the bits of a single handle with the same
     tile side."""
     specs = [dict(nx=128, ny=128, pde=si.HEAT5), dict(nx=96, ny=64, pde=si.WAVE_LF, prec=sw.FP32C),
              dict(nx=64, ny=64, pde=si.HEAT5, prec=sw.FP32C)]
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("batch vs single handles, mode", mode)
+    with _make(specs, mode) as b:
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
         b.advance(100)
@@ -137,11 +151,12 @@ def test_batch_equals_single_handles():
             g.close()
 
 
-@KERNEL_PENDING
-def test_measured_autotune_keeps_results():
+@pytest.mark.parametrize("mode", MODES)
+def test_measured_autotune_keeps_results(mode):
     specs = MIXED[:5]
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("measured autotune, mode", mode)
+    with _make(specs, mode) as b:
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
         b.autotune(sw.TUNE_MEASURE)
@@ -156,14 +171,15 @@ def test_measured_autotune_keeps_results():
             assert np.array_equal(b.download(i), _oracle(spec, s0, 45)), i
 
 
-@KERNEL_PENDING
-def test_uneven_batch_sampled_against_oracle():
+@pytest.mark.parametrize("mode", MODES)
+def test_uneven_batch_sampled_against_oracle(mode):
     """The uneven 256-grid workload (sides multiples of 16 in 64..512, heat or
     wave, FP64 or FP32C) for a few half cycles, sampled grids against the
     oracle."""
     specs = si.batch_specs(256, seed=0)
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("uneven 256-grid batch, 48 steps, mode", mode)
+    with _make(specs, mode) as b:
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
         steps = 48
@@ -175,13 +191,14 @@ def test_uneven_batch_sampled_against_oracle():
             assert np.array_equal(b.download(int(i)), ref), (int(i), specs[i], b.tile(int(i)))
 
 
-@KERNEL_PENDING
-def test_any_sides_batch():
+@pytest.mark.parametrize("mode", MODES)
+def test_any_sides_batch(mode):
     """Sides drawn from every integer: most grids fall back to the per-step
     method, the rest run swept; all exact."""
     specs = si.batch_specs(12, seed=3, lo=20, hi=90, quantum=1)
     inits = _inits(specs)
-    with _make(specs) as b:
+    _say("any-sides batch, mode", mode)
+    with _make(specs, mode) as b:
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
         b.advance(21)
@@ -189,11 +206,11 @@ def test_any_sides_batch():
             assert np.array_equal(b.download(i), _oracle(spec, s0, 21)), (i, spec, b.tile(i))
 
 
-@KERNEL_PENDING
+@PERSISTENT_OFF
 def test_wait_limit_abort_is_reported_and_recoverable():
     specs = [dict(nx=256, ny=256, pde=si.TEST_HASH)]
     inits = _inits(specs)
-    with _make(specs) as b:
+    with _make(specs, sw.BATCH_PERSISTENT) as b:
         b.set_tile(0, 16)
         b.upload(0, inits[0])
         b.set_wait_limit(0)
@@ -218,8 +235,50 @@ def test_batch_argument_errors():
             b.set_tile(0, 32)  # does not divide 48
         with pytest.raises(sw.Swept2DError):
             b.advance(-1)
-        with pytest.raises(sw.Swept2DError) as ei:
-            b.advance(1)  # the persistent kernel is not launched
-        assert ei.value.code == sw.EUNSUPPORTED
         with pytest.raises(sw.Swept2DError):
             b.set_tile(5, 16)
+        with pytest.raises(sw.Swept2DError):
+            b.set_mode(7)
+        b.set_mode(sw.BATCH_PERSISTENT)
+        assert b.mode == sw.BATCH_PERSISTENT
+        with pytest.raises(sw.Swept2DError) as ei:
+            b.advance(1)  # the persistent kernel is not built
+        assert ei.value.code == sw.EUNSUPPORTED
+        b.set_mode(sw.BATCH_PHASED)
+        with pytest.raises(sw.Swept2DError):
+            b.launches(0)
+        with pytest.raises(sw.Swept2DError):
+            b.launches(1025)
+
+
+def test_long_advance_replays_chunks():
+    """An advance longer than one graph (1024 steps) replays the chunk graph
+    and then a graph for the rest; one grid per launch class."""
+    specs = [dict(nx=128, ny=64, pde=si.HEAT5), dict(nx=64, ny=32, pde=si.TEST_HASH),
+             dict(nx=48, ny=48, pde=si.WAVE_LF), dict(nx=32, ny=32, pde=si.HEAT5, prec=sw.FP32C),
+             dict(nx=27, ny=20, pde=si.TEST_HASH)]
+    tiles = [64, 32, 24, 16, -1]
+    inits = _inits(specs)
+    _say("long advance 2100 steps, tiles", tiles)
+    with _make(specs) as b:
+        for i, n in enumerate(tiles):
+            b.set_tile(i, n)
+        for i, s0 in enumerate(inits):
+            b.upload(i, s0)
+        b.advance(2100)
+        for i, (spec, s0) in enumerate(zip(specs, inits)):
+            assert np.array_equal(b.download(i), _oracle(spec, s0, 2100)), (i, tiles[i])
+            assert b.T(i) == 2100 * (2 if spec["pde"] == si.TEST_PUSH5 else 1)
+
+
+def test_slot_layout_launch_count():
+    """Phased schedule: the grid with the most phases sets the slot count; a
+    slot holds one launch per launch class present in it."""
+    specs = [dict(nx=128, ny=128, pde=si.HEAT5), dict(nx=64, ny=64, pde=si.HEAT5)]
+    with _make(specs) as b:
+        b.set_tile(0, 64)   # 16 steps: 1 + 2 * 1 phases (h = 32, one reduced half cycle)
+        b.set_tile(1, 16)   # h = 8: 1 + 2 * 2 = 5 phases
+        # 5 slots; grid 0's 3 phases sit in slots 0, 1, 3 next to grid 1's.
+        assert b.launches(16) == 5 + 3
+        b.set_tile(0, 16)   # both in the one-wave class: one launch per slot
+        assert b.launches(16) == 5
