@@ -98,6 +98,7 @@ extern "C" {
  * OFF:  every workgroup fetches each level's panels one level ahead. */
 #define SWEPT2D_STAGING_AUTO 0
 #define SWEPT2D_STAGING_OFF 1
+#define SWEPT2D_STAGING_SINGLE_BRIDGES 2
 
 typedef struct swept2d swept2d; /* opaque, owned by the library */
 
@@ -188,8 +189,13 @@ int swept2d_set_substep_counter(swept2d *h, long long T);
 /* Launch mode (SWEPT2D_LAUNCH_DIRECT or SWEPT2D_LAUNCH_GRAPH). */
 int swept2d_set_launch_mode(swept2d *h, int mode);
 
-/* Panel staging mode (SWEPT2D_STAGING_AUTO or SWEPT2D_STAGING_OFF). Both
- * modes give identical results. */
+/* Panel staging mode. SWEPT2D_STAGING_AUTO copies a component's panel
+ * inputs into LDS at its start where they fit, and at tile sides 32 and 64
+ * runs a tile's two bridges in one workgroup where both fit its LDS;
+ * SWEPT2D_STAGING_OFF fetches each level's inputs from HBM one level ahead
+ * (bridges still paired; tile sides up to 22 of the one-wave light schemes
+ * always stage); SWEPT2D_STAGING_SINGLE_BRIDGES is AUTO with one workgroup
+ * per bridge. All modes give identical results. */
 int swept2d_set_staging(swept2d *h, int mode);
 
 /* Per-kernel timing. While on, every kernel the handle launches is bracketed

@@ -43,6 +43,7 @@ LAUNCH_GRAPH = 1
 
 STAGING_AUTO = 0
 STAGING_OFF = 1
+STAGING_SINGLE_BRIDGES = 2
 
 TUNE_MODEL = 0
 TUNE_MEASURE = 1

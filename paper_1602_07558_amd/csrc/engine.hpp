@@ -12,7 +12,11 @@ namespace swept {
 // Thread layout of a stage kernel instantiation (WC: compile-time window
 // pitch, 66 for tile side 64, 34 for 32, 0 for any other side).
 //  - Schemes with at most 16 bytes of state per point ("light") run 16 waves
-//    (4 for tile side 32); the Euler schemes 8 waves.
+//    at tile side 64, one wave for sides up to 22 (set by the launcher), 4
+//    waves otherwise; the Euler schemes 8 waves. A level is a short chain of
+//    dependent LDS and arithmetic latencies ended by a barrier, so many waves
+//    with few rows each hide it best (4 waves with 16 rows each measured
+//    twice as slow at tile side 64).
 //  - Light schemes at a fixed pitch use column ownership: thread t owns
 //    window column 1 + t mod N and the R rows from 1 + R (t div N) at every
 //    level, N = WC - 2, R = N^2 / NT. Otherwise a level is split into 2x2
@@ -23,7 +27,7 @@ template <class S, int WC, int NTo = 0>
 struct Lay {
   static constexpr bool light = S::NV * (int)sizeof(typename S::V) <= 16;
   static constexpr int N = WC ? WC - 2 : 0;
-  static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 34 ? 256 : 1024));
+  static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 66 ? 1024 : 256));
   static constexpr int NW = NT / 64;
   static constexpr bool cols = light && WC != 0 && (N * N) % NT == 0;
   static constexpr int R = cols ? N * N / NT : 0;
@@ -112,7 +116,9 @@ enum Scheme : int {
 //   up:     upward pyramid of every tile from the state (height H; emits
 //           panels of levels 0..H-1; if H < h writes its level-H region to
 //           the state).
-//   bridge: x- and y-bridges of every edge (height H; same conventions).
+//   bridge: x- and y-bridges of every edge (height H; same conventions);
+//           with pair_ok, tile sides 32 and 64 run both bridges of a tile
+//           in one workgroup where two fit its LDS.
 //   oct:    downward pyramid of height Hd at every tile corner; if Hd == h
 //           and Hu > 0 it continues in LDS as the upward pyramid of the
 //           shifted tile (an octahedron) of height Hu; the last stage of an
@@ -123,7 +129,7 @@ enum Scheme : int {
 // one level ahead into registers.
 hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp,
                      hipStream_t s);
-hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, void* state, PanelPtrs p,
+hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, bool pair_ok, void* state, PanelPtrs p,
                          const SchemeParams& sp, hipStream_t s);
 hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p,
                       const SchemeParams& sp, hipStream_t s);
@@ -190,6 +196,7 @@ enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1 };
 // Launch classes of the phased batch: the stage code of tile side 64 on 16
 // waves, of tile side 32 on 4 waves, of any other side on 4 waves, and of
 // sides up to 22 on one wave; per-step grids run in the 4-wave generic class.
+// One-wave items always stage their panel inputs.
 enum BatchClass : int { kClass66 = 0, kClass34, kClassGen256, kClassGen64, kNumBatchClasses };
 inline int batch_class_of(int n) {
   if (n == 64) return kClass66;

@@ -5,6 +5,10 @@
 //   V        value type stored in the state, LDS and panels
 //   NV       values per grid point (FP32C schemes: nvars u's then nvars c's)
 //   NVAR     the scheme's nvars, SUB its sub-steps per time step
+//   XY_SYM   step gives the same bits when x and y are exchanged (every
+//            neighbour (di, dj) read as (dj, di)): true where the x terms
+//            and the y terms enter only through one commutative sum, e.g.
+//            (uW + uE) + (uN + uS)
 //   step(T, nb, out, prm)
 //            computes the point at level T+1 from its 3x3 neighbourhood at
 //            level T (Sec. 2, assumption 2); nb(di, dj, v) returns value v of
@@ -32,6 +36,7 @@ struct SchemeParams {
 struct Heat64 {
   using V = double;
   static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
     const double r = sp.p[0];
@@ -48,6 +53,7 @@ struct Heat64 {
 struct Wave64 {
   using V = double;
   static constexpr int NV = 2, NVAR = 2, SUB = 1;
+  static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
     const double c2 = sp.p[0];
@@ -67,6 +73,7 @@ struct Wave64 {
 struct Hash64 {
   using V = double;
   static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
     uint64_t m = 0x9E3779B97F4A7C15ull ^ (uint64_t)T;
@@ -87,6 +94,7 @@ struct Hash64 {
 struct Incr64 {
   using V = double;
   static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams&) {
     const double u = nb(0, 0, 0);
@@ -105,6 +113,7 @@ struct Incr64 {
 struct Push5 {
   using V = double;
   static constexpr int NV = 5, NVAR = 5, SUB = 2;
+  static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
     if ((T & 1) == 0) {
@@ -187,6 +196,7 @@ __device__ __forceinline__ void increment(const double* W, const double* E, cons
 struct Euler64 {
   using V = double;
   static constexpr int NV = 8, NVAR = 8, SUB = 2;
+  static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
     const double gamma = sp.p[0], dtoh = sp.p[1];
@@ -226,6 +236,7 @@ struct Euler64 {
 struct Heat32C {
   using V = float;
   static constexpr int NV = 2, NVAR = 1, SUB = 1;
+  static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
     const float r = (float)sp.p[0];
@@ -244,6 +255,7 @@ struct Heat32C {
 struct Wave32C {
   using V = float;
   static constexpr int NV = 4, NVAR = 2, SUB = 1;
+  static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
     const float c2 = (float)sp.p[0];
@@ -268,6 +280,7 @@ struct Wave32C {
 struct Euler32C {
   using V = float;
   static constexpr int NV = 16, NVAR = 8, SUB = 2;
+  static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static double wide(const NB& nb, int di, int dj, int v) {
     return (double)nb(di, dj, v) - (double)nb(di, dj, 8 + v);

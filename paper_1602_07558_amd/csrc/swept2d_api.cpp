@@ -241,12 +241,12 @@ const char* tile_problem(const swept2d* h, int n) {
 }
 
 bool oct_staged(const swept2d* h) {
-  return h->staging == SWEPT2D_STAGING_AUTO &&
+  return h->staging != SWEPT2D_STAGING_OFF &&
          window_lds_bytes(h->si, h->n) + oct_stage_bytes(h->si, h->n) <= g_lds_limit;
 }
 
 bool bridge_staged(const swept2d* h) {
-  return h->staging == SWEPT2D_STAGING_AUTO &&
+  return h->staging != SWEPT2D_STAGING_OFF &&
          window_lds_bytes(h->si, h->n) + bridge_stage_bytes(h->si, h->n) <= g_lds_limit;
 }
 
@@ -361,6 +361,7 @@ int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, 
   Launcher L{h, timed};
   const int sc = h->scheme;
   const bool so = oct_staged(h), sb = bridge_staged(h);
+  const bool pairs = h->staging != SWEPT2D_STAGING_SINGLE_BRIDGES;
   const long long q = S / hh;
   const int r = (int)(S % hh);
   int rc;
@@ -369,7 +370,7 @@ int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, 
     rc = L.run(kKindUp, ntiles * up_points(n, r), [&] { return launch_up(sc, g, r, h->state, pp, h->sp, h->stream); });
     if (rc) return rc;
     rc = L.run(kKindBridge, ntiles * bridge_points(n, r),
-               [&] { return launch_bridge(sc, g, r, sb, h->state, pp, h->sp, h->stream); });
+               [&] { return launch_bridge(sc, g, r, sb, pairs, h->state, pp, h->sp, h->stream); });
     if (rc) return rc;
     return L.run(kKindOct, ntiles * down_points(r),
                  [&] { return launch_oct(sc, g, r, 0, so, h->state, pp, h->sp, h->stream); });
@@ -378,7 +379,7 @@ int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, 
   if (rc) return rc;
   for (long long c = 0; c < q; ++c) {
     rc = L.run(kKindBridge, ntiles * bridge_points(n, hh),
-               [&] { return launch_bridge(sc, g, hh, sb, h->state, pp, h->sp, h->stream); });
+               [&] { return launch_bridge(sc, g, hh, sb, pairs, h->state, pp, h->sp, h->stream); });
     if (rc) return rc;
     const bool last = (c == q - 1);
     const int Hu = last ? r : hh;
@@ -390,7 +391,7 @@ int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, 
   }
   if (r > 0) {
     rc = L.run(kKindBridge, ntiles * bridge_points(n, r),
-               [&] { return launch_bridge(sc, g, r, sb, h->state, pp, h->sp, h->stream); });
+               [&] { return launch_bridge(sc, g, r, sb, pairs, h->state, pp, h->sp, h->stream); });
     if (rc) return rc;
     rc = L.run(kKindOct, ntiles * down_points(r), [&] { return launch_oct(sc, g, r, 0, so, h->state, pp, h->sp, h->stream); });
     if (rc) return rc;
@@ -676,7 +677,8 @@ int swept2d_set_launch_mode(swept2d* h, int mode) {
 
 int swept2d_set_staging(swept2d* h, int mode) {
   if (!h) return fail(SWEPT2D_EINVAL, "null handle");
-  if (mode != SWEPT2D_STAGING_AUTO && mode != SWEPT2D_STAGING_OFF) return fail(SWEPT2D_EINVAL, "unknown staging mode");
+  if (mode != SWEPT2D_STAGING_AUTO && mode != SWEPT2D_STAGING_OFF && mode != SWEPT2D_STAGING_SINGLE_BRIDGES)
+    return fail(SWEPT2D_EINVAL, "unknown staging mode");
   if (mode != h->staging) drop_graphs(h);
   h->staging = mode;
   return 0;

@@ -102,7 +102,7 @@ size_t entry_lds(const HostGrid& g, int p) {
   if (g.n == 0) return 0;
   bool so = false, sb = false;
   stage_lds(g, &so, &sb);
-  if (batch_class_of(g.n) == kClassGen64) so = sb = true;  // the kernel stages them
+  if (batch_class_threads(batch_class_of(g.n)) == 64) so = sb = true;  // the kernel stages them
   const size_t win = window_lds_bytes(g.si, g.n);
   if (p == 0) return win;
   if (p & 1) return win + (sb ? bridge_stage_bytes(g.si, g.n) : 0);
@@ -117,11 +117,9 @@ const char* batch_tile_problem(const HostGrid& g, int n) {
   if (n + 2 > 128) return "tile side above 126";
   if (window_lds_bytes(g.si, n) > device_lds_limit()) return "tile working set exceeds the workgroup LDS";
   // One-wave items (sides up to 22) always stage their panel inputs.
-  if (batch_class_of(n) == kClassGen64 &&
+  if (batch_class_threads(batch_class_of(n)) == 64 &&
       window_lds_bytes(g.si, n) + std::max(oct_stage_bytes(g.si, n), bridge_stage_bytes(g.si, n)) > device_lds_limit())
     return "tile working set exceeds the workgroup LDS";
-  // The batch kernel runs 16 waves; the column layout needs n^2 to be a
-  // multiple of its thread count at the fixed pitches (true for 32 and 64).
   return nullptr;
 }
 

@@ -34,18 +34,34 @@ namespace swept {
 
 namespace {
 
-template <class V>
+// Neighbour access in an LDS window. TR: the window holds the point at
+// (x, y) in row x, column y (transposed), so the same stencil code reads
+// (di, dj) from row di, column dj.
+template <class V, bool TR = false>
 struct WinNb {
   const V* c;
   int pitch;
   int plane;
-  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return c[v * plane + dj * pitch + di]; }
+  __device__ __forceinline__ V operator()(int di, int dj, int v) const {
+    return TR ? c[v * plane + di * pitch + dj] : c[v * plane + dj * pitch + di];
+  }
 };
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-// Wave index as a wave-uniform (scalar) value, so per-wave loops branch on
-// scalars instead of masking lanes.
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+// Thread and wave index within a group of kThreads threads (a power of
+// two): the whole workgroup, or one half of a workgroup that runs two
+// components side by side. The wave index is read back as a wave-uniform
+// (scalar) value, so per-wave loops branch on scalars instead of masking
+// lanes.
+template <int kThreads>
+__device__ __forceinline__ int ltid() {
+  static_assert((kThreads & (kThreads - 1)) == 0, "group size must be a power of two");
+  return (int)(threadIdx.x & (kThreads - 1));
+}
+template <int kThreads>
+__device__ __forceinline__ int lwave() {
+  return __builtin_amdgcn_readfirstlane((int)((threadIdx.x & (kThreads - 1)) >> 6));
+}
 
 __device__ __forceinline__ int wrap(int x, int m) {
   if (x < 0) x += m;
@@ -88,13 +104,13 @@ __device__ __forceinline__ void gather(int total, Src src, Dst dst) {
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
       if (base + i * kThreads >= total) break;
-      const int q = base + (int)threadIdx.x + i * kThreads;
+      const int q = base + ltid<kThreads>() + i * kThreads;
       r[i] = src(q < total ? q : total - 1);
     }
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
       if (base + i * kThreads >= total) break;
-      const int q = base + (int)threadIdx.x + i * kThreads;
+      const int q = base + ltid<kThreads>() + i * kThreads;
       if (q < total) dst(q, r[i]);
     }
   }
@@ -126,14 +142,15 @@ struct Quad {
   typename S::V o[4][S::NV];
 };
 
-template <class S, int WC>
+template <class S, int WC, bool TR>
 __device__ __forceinline__ void quad_step(const typename S::V* __restrict__ in, int idx, int Wrt, long long T,
                                           const SchemeParams& sp, Quad<S>& q) {
   const int W = WC ? WC : Wrt, plane = W * W;
-  S::step(T, WinNb<typename S::V>{in + idx, W, plane}, q.o[0], sp);
-  S::step(T, WinNb<typename S::V>{in + idx + 1, W, plane}, q.o[1], sp);
-  S::step(T, WinNb<typename S::V>{in + idx + W, W, plane}, q.o[2], sp);
-  S::step(T, WinNb<typename S::V>{in + idx + W + 1, W, plane}, q.o[3], sp);
+  using NB = WinNb<typename S::V, TR>;
+  S::step(T, NB{in + idx, W, plane}, q.o[0], sp);
+  S::step(T, NB{in + idx + 1, W, plane}, q.o[1], sp);
+  S::step(T, NB{in + idx + W, W, plane}, q.o[2], sp);
+  S::step(T, NB{in + idx + W + 1, W, plane}, q.o[3], sp);
 }
 
 template <class S, int WC>
@@ -151,7 +168,7 @@ __device__ __forceinline__ void quad_store(typename S::V* __restrict__ out, int 
 // One level, double buffered: every quad of the window rectangle
 // [x0, x0+w) x [y0, y0+hg) gets sub-step T from `in` into `out`; thread t
 // takes quads t, t + kThreads, ... in row-major quad order.
-template <class S, int WC, int kThreads>
+template <class S, int WC, int kThreads, bool TR>
 __device__ __forceinline__ void compute_quads(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
@@ -159,72 +176,117 @@ __device__ __forceinline__ void compute_quads(const typename S::V* __restrict__ 
   const int bw = w >> 1, nq = bw * (hg >> 1);
   if (nq <= 0) return;
   const float inv = 1.0f / (float)bw;
-  for (int q = threadIdx.x; q < nq; q += kThreads) {
+  for (int q = ltid<kThreads>(); q < nq; q += kThreads) {
     int by, bx;
     fdivmod(q, bw, inv, by, bx);
     const int idx = (y0 + 2 * by) * W + x0 + 2 * bx;
     Quad<S> r;
-    quad_step<S, WC>(in, idx, W, T, sp, r);
+    quad_step<S, WC, TR>(in, idx, W, T, sp, r);
     quad_store<S, WC>(out, idx, W, r);
   }
 }
 
-template <class V, int NV>
+// Neighbour access in registers: rw[row][column][v] around the point (TR as
+// for WinNb).
+template <class V, int NV, bool TR = false>
 struct RegNb {
   const V (*rw)[3][NV];
-  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return rw[dj + 1][di + 1][v]; }
+  __device__ __forceinline__ V operator()(int di, int dj, int v) const {
+    return TR ? rw[di + 1][dj + 1][v] : rw[dj + 1][di + 1][v];
+  }
 };
+
+// Value of the lane one below (SR: lane i receives lane i-1) or one above
+// (lane i receives lane i+1) in the wave, by DPP wave shifts; the end lane
+// of the wave receives 0. 64-bit values move as two 32-bit halves.
+template <bool SR>
+__device__ __forceinline__ int dpp_shift(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, SR ? 0x138 : 0x130, 0xF, 0xF, false);
+}
+template <bool SR>
+__device__ __forceinline__ float dpp_shift(float x) {
+  return __builtin_bit_cast(float, dpp_shift<SR>(__builtin_bit_cast(int, x)));
+}
+template <bool SR>
+__device__ __forceinline__ double dpp_shift(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)dpp_shift<SR>((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)dpp_shift<SR>((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // One level with column ownership: the rows of the thread's column that lie
 // in the rectangle [x0, x0+w) x [y0, y0+hg) get sub-step T from `in` into
-// `out`. The (R+2) x 3 neighbourhood is read into registers with fixed
-// offsets; rows outside the rectangle are computed from whatever the window
-// holds there and not stored. Lanes are consecutive columns, so every LDS
-// access of a wave is one contiguous run.
-template <class S, int WC, int NT>
+// `out`. The thread first reads the R+2 rows of its column it needs (its own
+// value per row) with every lane of the wave active, and takes the columns
+// left and right of it from the neighbouring lanes by DPP (DPP) or from LDS
+// (EDGE levels); then, under one column mask, it computes and stores the
+// rows inside the rectangle. Lanes are consecutive window columns, N of them
+// per row group, so every LDS access of a wave is one contiguous run. A row
+// group's first and last lanes (window columns 1 and N) get no valid
+// neighbour from a shift, so DPP levels must keep the rectangle within
+// columns 2 .. N-1 (true for every level of every component except the
+// downward pyramid's last, full-tile level).
+template <class S, int WC, int NT, bool TR, bool DPP>
 __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                              int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
   constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N, R = Lay<S, WC, NT>::R;
-  const int t = (int)threadIdx.x;
-  const int c = 1 + t % N, r0 = 1 + R * (t / N);
-  if ((unsigned)(c - x0) >= (unsigned)w) return;
-  if (r0 + R <= y0 || r0 >= y0 + hg) return;
-  const V* src = in + (r0 - 1) * W + c - 1;
+  const int t = ltid<NT>();
+  const int c = 1 + t % N;
+  // With N = 64 a wave is one row group, so the row tests are uniform.
+  const int r0 = N == 64 ? 1 + R * lwave<NT>() : 1 + R * (t / N);
+  const bool rows_in = !(r0 + R <= y0 || r0 >= y0 + hg);
+  if (N == 64) {
+    if (!rows_in) return;
+  } else {
+    if (!__builtin_amdgcn_ballot_w64(rows_in)) return;  // wave-uniform exit
+  }
+  const V* src = in + (r0 - 1) * W + c;
   V nb[R + 2][3][NV];
 #pragma unroll
-  for (int i = 0; i < R + 2; ++i)
+  for (int j = 0; j < R + 2; ++j)
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) nb[i][d][v] = src[v * plane + i * W + d];
+    for (int v = 0; v < NV; ++v) {
+      const V m = src[v * plane + j * W];
+      nb[j][1][v] = m;
+      if constexpr (DPP) {
+        nb[j][0][v] = dpp_shift<true>(m);
+        nb[j][2][v] = dpp_shift<false>(m);
+      } else {
+        nb[j][0][v] = src[v * plane + j * W - 1];
+        nb[j][2][v] = src[v * plane + j * W + 1];
+      }
+    }
+  if ((unsigned)(c - x0) >= (unsigned)w) return;
   V* dst = out + r0 * W + c;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    V o[NV];
-    S::step(T, RegNb<V, NV>{&nb[i]}, o, sp);
     if ((unsigned)(r0 + i - y0) < (unsigned)hg) {
+      V o[NV];
+      S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
 #pragma unroll
       for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
     }
   }
 }
 
-// One level of a stage kernel: column ownership where the layout has it,
-// 2x2 quads otherwise.
-template <class S, int WC, int NT>
+// EDGE: the rectangle may touch window columns 1 or N (the downward
+// pyramid's full-tile level); otherwise the column layout uses DPP shifts.
+template <class S, int WC, int NT, bool TR = false, bool EDGE = false>
 __device__ __forceinline__ void compute_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
-  if constexpr (Lay<S, WC, NT>::cols)
-    compute_cols<S, WC, NT>(in, out, x0, y0, w, hg, T, sp);
-  else
-    compute_quads<S, WC, NT>(in, out, Wrt, x0, y0, w, hg, T, sp);
+  if constexpr (Lay<S, WC, NT>::cols) {
+    compute_cols<S, WC, NT, TR, !EDGE>(in, out, x0, y0, w, hg, T, sp);
+  } else {
+    compute_quads<S, WC, NT, TR>(in, out, Wrt, x0, y0, w, hg, T, sp);
+  }
 }
 
 // Window -> state for the rectangle [wx0, wx0+w) x [wy0, wy0+hg); the window
-// origin is global (xw0, yw0).
-template <class S, int kThreads>
+// origin is global (xw0, yw0). TR: the window is transposed.
+template <class S, int kThreads, bool TR = false>
 __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V* __restrict__ state, const Geo& g,
                            int xw0, int yw0, int wx0, int wy0, int w, int hg) {
   const int npts = w * hg;
@@ -232,13 +294,14 @@ __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V*
   const int plane = g.W * g.W;
   const size_t gplane = (size_t)g.nx * g.ny;
   const float invw = 1.0f / (float)w;
-  for (int p = threadIdx.x; p < npts; p += kThreads) {
+  for (int p = ltid<kThreads>(); p < npts; p += kThreads) {
     int y, x;
     fdivmod(p, w, invw, y, x);
     const int wx = wx0 + x, wy = wy0 + y;
     const int gx = wrap(xw0 + wx, g.nx), gy = wrap(yw0 + wy, g.ny);
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) state[v * gplane + (size_t)gy * g.nx + gx] = win[v * plane + wy * g.W + wx];
+    for (int v = 0; v < S::NV; ++v)
+      state[v * gplane + (size_t)gy * g.nx + gx] = win[v * plane + (TR ? wx * g.W + wy : wy * g.W + wx)];
   }
 }
 
@@ -254,7 +317,7 @@ __device__ void emit_up_all(const typename S::V* __restrict__ buf0, const typena
   constexpr int NV = S::NV;
   const int n = g.n, W = g.W, plane = W * W;
   const int per = 8 * NV;
-  for (int u = wave_id(); u < per * H; u += kWaves) {
+  for (int u = lwave<kThreads>(); u < per * H; u += kWaves) {
     const int l = u / per, r8 = u - l * per;
     const int end = r8 / (2 * NV), rem = r8 - end * 2 * NV;  // rem = 2 v + k
     const int v = rem >> 1, k = rem & 1;
@@ -329,40 +392,14 @@ __device__ __forceinline__ void ring_pos(int h, int l, int band, int k, int t, i
   }
 }
 
-// Window position of element t of bridge input strip `side` (0: tile A's
-// facing strip, 1: tile B's) at level l, row/column k.
-__device__ __forceinline__ void strip_pos(bool isx, int h, int l, int side, int k, int t, int& wx, int& wy) {
+// Window index (one value slot) of element t of bridge input strip `side`
+// (0: tile A's facing strip, 1: tile B's) at level l, row/column k. Both
+// bridges use the y-bridge's layout: strips are window rows; the x-bridge's
+// window is the transposed one (row = x, column = y), where its facing
+// columns become rows.
+__device__ __forceinline__ int strip_idx(int W, int h, int l, int side, int k, int t) {
   const int across = side ? (h + 1 + l + k) : (h - l - k);
-  if (isx) {
-    wx = across;
-    wy = l + 1 + t;
-  } else {
-    wy = across;
-    wx = l + 1 + t;
-  }
-}
-
-// Ring of level l into the window from the staged LDS runs
-// [top | bottom | left | right], each of LxH or LyH values.
-template <class S, int kThreads>
-__device__ __forceinline__ void place_ring_staged(const typename S::V* __restrict__ stg, typename S::V* __restrict__ win,
-                                                  const Geo& g, int l, int LxH, int LyH) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int NV = S::NV;
-  const int h = g.h, W = g.W, plane = W * W;
-  for (int u = wave_id(); u < 8 * NV; u += kWaves) {
-    const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
-    const bool horiz = band < 2;
-    const int len = horiz ? 2 * l + 4 : 2 * l;
-    const int base =
-        horiz ? band * LxH + 2 * NV * xb_levels_len(l) : 2 * LxH + (band - 2) * LyH + 2 * NV * yb_levels_len(l);
-    const typename S::V* src = stg + base + rem * len;
-    for (int t = lane_id(); t < len; t += 64) {
-      int wx, wy;
-      ring_pos(h, l, band, k, t, wx, wy);
-      win[v * plane + wy * W + wx] = src[t];
-    }
-  }
+  return across * W + l + 1 + t;
 }
 
 template <class S, int kThreads>
@@ -374,7 +411,7 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads>& f, const Geo& g, 
   const int h = g.h, W = g.W, plane = W * W;
 #pragma unroll
   for (int j = 0; j < Fetch<S, kThreads>::J; ++j) {
-    const int u = wave_id() + j * kWaves;
+    const int u = lwave<kThreads>() + j * kWaves;
 #pragma unroll
     for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
     if (u >= 8 * NV) continue;
@@ -391,19 +428,123 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads>& f, const Geo& g, 
     else
       src = yb + yb_end(g, NV, eRight, 0) + 2 * NV * yb_levels_len(l);
     src += rem * len;
+    if (len == 0) continue;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int t = lane_id() + 64 * i;
-      f.dst[j][i] = -1;
-      if (len > 0) {
-        f.val[j][i] = src[t < len ? t : len - 1];
-        if (t < len) {
-          int wx, wy;
-          ring_pos(h, l, band, k, t, wx, wy);
-          f.dst[j][i] = v * plane + wy * W + wx;
-        }
-      }
+      f.val[j][i] = src[t < len ? t : len - 1];
+      int wx, wy;
+      ring_pos(h, l, band, k, t, wx, wy);
+      f.dst[j][i] = t < len ? v * plane + wy * W + wx : -1;
     }
+  }
+}
+
+// Ring prefetch from the staged LDS runs into registers, placed after the
+// level's compute pass so the LDS read latency hides behind it. Unit u =
+// wave + j kWaves is one (band, slot v, row k) run, lanes along it, two
+// positions per lane (t = lane, lane + 64). Everything that does not depend
+// on the level is set up once: the window index of element t is linear in
+// the level (a0 + l da, from ring_pos), and the run starts at
+// run0 + 2 NV levels_len(l) + rem len(l) in the staged copy.
+template <class S, int kThreads>
+struct RingPre {
+  static constexpr int J = Fetch<S, kThreads>::J;
+  int a0[J][2];
+  int da[J];
+  int run0[J];  // -1: no unit for this wave
+  int rem[J];
+  bool horiz[J];
+};
+
+template <class S, int kThreads>
+__device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads>& r, const Geo& g, int LxH, int LyH) {
+  constexpr int kWaves = kThreads / 64;
+  constexpr int NV = S::NV;
+  const int h = g.h, W = g.W, plane = W * W;
+#pragma unroll
+  for (int j = 0; j < RingPre<S, kThreads>::J; ++j) {
+    const int u = lwave<kThreads>() + j * kWaves;
+    r.run0[j] = -1;
+    if (u >= 8 * NV) continue;
+    const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
+    r.horiz[j] = band < 2;
+    r.rem[j] = rem;
+    r.run0[j] = band < 2 ? band * LxH : 2 * LxH + (band - 2) * LyH;
+    r.da[j] = band == 0 || band == 2 ? -(W + 1) : (band == 1 ? W - 1 : 1 - W);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int wx, wy;
+      ring_pos(h, 0, band, k, lane_id() + 64 * i, wx, wy);
+      r.a0[j][i] = v * plane + wy * W + wx;
+    }
+  }
+}
+
+template <class S, int kThreads>
+__device__ __forceinline__ void fetch_ring_stg(Fetch<S, kThreads>& f, const RingPre<S, kThreads>& r,
+                                               const typename S::V* __restrict__ stg, int l) {
+  constexpr int NV = S::NV;
+#pragma unroll
+  for (int j = 0; j < RingPre<S, kThreads>::J; ++j) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    const int len = r.horiz[j] ? 2 * l + 4 : 2 * l;
+    if (r.run0[j] < 0 || len == 0) continue;
+    const int off = r.run0[j] + 2 * NV * (r.horiz[j] ? xb_levels_len(l) : yb_levels_len(l)) + r.rem[j] * len;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int t = lane_id() + 64 * i;
+      f.val[j][i] = stg[off + (t < len ? t : len - 1)];
+      f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
+    }
+  }
+}
+
+// Ring of level l straight from the staged LDS runs into the window, all
+// threads over the flattened ring (16 (l+1) NV values: per slot and row k,
+// the top and bottom bands of 2l+4 and the left and right bands of 2l).
+template <class S, int kThreads>
+__device__ __forceinline__ void place_ring_flat(const typename S::V* __restrict__ stg, typename S::V* __restrict__ win,
+                                                const Geo& g, int l, int LxH, int LyH) {
+  constexpr int NV = S::NV;
+  const int h = g.h, W = g.W, plane = W * W;
+  const int lh = 2 * l + 4, lv = 2 * l, A = 2 * NV * lh, B = 2 * NV * lv, total = 2 * A + 2 * B;
+  const float ih = 1.0f / (float)lh, iv = lv ? 1.0f / (float)lv : 0.0f;
+  for (int q = ltid<kThreads>(); q < total; q += kThreads) {
+    int band, r;
+    if (q < 2 * A) {
+      band = q < A ? 0 : 1;
+      r = q - band * A;
+    } else {
+      band = q - 2 * A < B ? 2 : 3;
+      r = q - 2 * A - (band - 2) * B;
+    }
+    const bool horiz = band < 2;
+    int rem, t;
+    fdivmod(r, horiz ? lh : lv, horiz ? ih : iv, rem, t);
+    const int base =
+        horiz ? band * LxH + 2 * NV * xb_levels_len(l) : 2 * LxH + (band - 2) * LyH + 2 * NV * yb_levels_len(l);
+    int wx, wy;
+    ring_pos(h, l, band, rem & 1, t, wx, wy);
+    win[(rem >> 1) * plane + wy * W + wx] = stg[base + r];
+  }
+}
+
+// Bridge strips of level l straight from the staged LDS runs, all threads
+// over the flattened strips (4 (n-2l) NV values).
+template <class S, int kThreads>
+__device__ __forceinline__ void place_strips_flat(const typename S::V* __restrict__ stg,
+                                                  typename S::V* __restrict__ win, const Geo& g, int l, int LH) {
+  constexpr int NV = S::NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l, A = 2 * NV * len;
+  const float il = 1.0f / (float)len;
+  for (int q = ltid<kThreads>(); q < 2 * A; q += kThreads) {
+    const int side = q < A ? 0 : 1, r = q - side * A;
+    int rem, t;
+    fdivmod(r, len, il, rem, t);
+    win[(rem >> 1) * plane + strip_idx(W, h, l, side, rem & 1, t)] =
+        stg[side * LH + 2 * NV * up_levels_len(n, l) + r];
   }
 }
 
@@ -417,24 +558,6 @@ __device__ __forceinline__ void place_fetched(const Fetch<S, kThreads>& f, typen
 }
 
 template <class S, int kThreads>
-__device__ __forceinline__ void place_strips_staged(const typename S::V* __restrict__ stg,
-                                                    typename S::V* __restrict__ win, bool isx, const Geo& g, int l,
-                                                    int LH) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int NV = S::NV;
-  const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
-  for (int u = wave_id(); u < 4 * NV; u += kWaves) {
-    const int side = u / (2 * NV), rem = u - side * 2 * NV, v = rem >> 1, k = rem & 1;
-    const typename S::V* src = stg + side * LH + 2 * NV * up_levels_len(n, l) + rem * len;
-    for (int t = lane_id(); t < len; t += 64) {
-      int wx, wy;
-      strip_pos(isx, h, l, side, k, t, wx, wy);
-      win[v * plane + wy * W + wx] = src[t];
-    }
-  }
-}
-
-template <class S, int kThreads>
 __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads>& f, bool isx, const Geo& g, int l,
                                              const typename S::V* __restrict__ up, int tA, int tB) {
   constexpr int kWaves = kThreads / 64;
@@ -442,7 +565,7 @@ __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads>& f, bool isx, co
   const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
 #pragma unroll
   for (int j = 0; j < Fetch<S, kThreads>::J; ++j) {
-    const int u = wave_id() + j * kWaves;
+    const int u = lwave<kThreads>() + j * kWaves;
 #pragma unroll
     for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
     if (u >= 4 * NV) continue;
@@ -453,20 +576,69 @@ __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads>& f, bool isx, co
     for (int i = 0; i < 2; ++i) {
       const int t = lane_id() + 64 * i;
       f.val[j][i] = src[t < len ? t : len - 1];
-      if (t < len) {
-        int wx, wy;
-        strip_pos(isx, h, l, side, k, t, wx, wy);
-        f.dst[j][i] = v * plane + wy * W + wx;
-      }
+      f.dst[j][i] = t < len ? v * plane + strip_idx(W, h, l, side, k, t) : -1;
+    }
+  }
+}
+
+// Strip prefetch from the staged LDS runs (as RingPre): unit u = (side,
+// slot v, row k); the window index of element t is linear in the level
+// (from strip_idx), the run starts at run0 + 2 NV up_levels_len(n, l) +
+// rem (n - 2l).
+template <class S, int kThreads>
+struct StripPre {
+  static constexpr int J = Fetch<S, kThreads>::J;
+  int a0[J][2];
+  int da[J];
+  int run0[J];  // -1: no unit for this wave
+  int rem[J];
+};
+
+template <class S, int kThreads>
+__device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads>& r, const Geo& g, int LH) {
+  constexpr int kWaves = kThreads / 64;
+  constexpr int NV = S::NV;
+  const int h = g.h, W = g.W, plane = W * W;
+#pragma unroll
+  for (int j = 0; j < StripPre<S, kThreads>::J; ++j) {
+    const int u = lwave<kThreads>() + j * kWaves;
+    r.run0[j] = -1;
+    if (u >= 4 * NV) continue;
+    const int side = u / (2 * NV), rem = u - side * 2 * NV, v = rem >> 1, k = rem & 1;
+    r.rem[j] = rem;
+    r.run0[j] = side * LH;
+    r.da[j] = side ? W + 1 : 1 - W;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, lane_id() + 64 * i);
+  }
+}
+
+template <class S, int kThreads>
+__device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads>& f, const StripPre<S, kThreads>& r,
+                                                 const typename S::V* __restrict__ stg, int n, int l) {
+  constexpr int NV = S::NV;
+  const int len = n - 2 * l;
+#pragma unroll
+  for (int j = 0; j < StripPre<S, kThreads>::J; ++j) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    if (r.run0[j] < 0) continue;
+    const int off = r.run0[j] + 2 * NV * up_levels_len(n, l) + r.rem[j] * len;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int t = lane_id() + 64 * i;
+      f.val[j][i] = stg[off + (t < len ? t : len - 1)];
+      f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
     }
   }
 }
 
 // All bridge panels of levels 0..H-1 (Alg. 2-3), written at the end of the
-// bridge from the buffers where each level's bands survive. x-bridge: window
-// rows l+1+k (N end) and n-l-k (S end), columns h-l-1 .. h+l+2 (the band and
-// the pyramid corners placed beside it). y-bridge: columns l+1+k (W end) and
-// n-l-k (E end), rows h+1-l .. h+l.
+// bridge from the buffers where each level's bands survive. x-bridge: rows
+// y = l+1+k (N end) and n-l-k (S end), x = h-l-1 .. h+l+2 (the band and the
+// pyramid corners placed beside it), which in its transposed window are
+// columns. y-bridge: columns x = l+1+k (W end) and n-l-k (E end), rows
+// y = h+1-l .. h+l. Both are window columns read down the rows.
 template <class S, int kThreads>
 __device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1,
                                 typename S::V* __restrict__ out, bool isx, const Geo& g, int e, int H) {
@@ -474,7 +646,7 @@ __device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const ty
   constexpr int NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W;
   const int per = 4 * NV;
-  for (int u = wave_id(); u < per * H; u += kWaves) {
+  for (int u = lwave<kThreads>(); u < per * H; u += kWaves) {
     const int l = u / per, r4 = u - l * per;
     const int end = r4 / (2 * NV), rem = r4 - end * 2 * NV, v = rem >> 1, k = rem & 1;
     const int len = isx ? 2 * l + 4 : 2 * l;
@@ -484,10 +656,8 @@ __device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const ty
                               : yb_end(g, NV, e, end) + 2 * NV * yb_levels_len(l)) +
                          (size_t)rem * len;
     const int across = end ? (n - l - k) : (l + 1 + k);
-    const typename S::V* src =
-        win + v * plane + (isx ? (across * W + (h - l - 1)) : ((h + 1 - l) * W + across));
-    const int stride = isx ? 1 : W;
-    for (int t = lane_id(); t < len; t += 64) dst[t] = src[t * stride];
+    const typename S::V* src = win + v * plane + (isx ? h - l - 1 : h + 1 - l) * W + across;
+    for (int t = lane_id(); t < len; t += 64) dst[t] = src[t * W];
   }
 }
 
@@ -527,55 +697,67 @@ __device__ void up_item(const Geo& g, int H, typename S::V* __restrict__ state, 
   up_levels<S, WC, NT>(buf0, buf1, 0, g, tile, x0, y0, level_base(g), H, state, static_cast<V*>(pp.up), sp);
 }
 
-// Item i < ntiles: the x-bridge over the east edge of tile i; item
-// ntiles + i: the y-bridge over the south edge of tile i (Alg. 2-3).
-template <class S, int WC, int NT>
-__device__ void bridge_item(const Geo& g, int H, int staged, typename S::V* __restrict__ state, const PanelPtrs& pp,
-                            const SchemeParams& sp, int item, double* smem) {
+// The bridge between tiles A = e and B = tB across A's east edge (isx, the
+// x-bridge, Alg. 3) or south edge (the y-bridge, Alg. 2), both in the
+// y-bridge's window layout (the x-bridge's window transposed): at level l the
+// rectangle of window columns l+1 .. n-l and rows h+1-l .. h+l. Runs on a
+// group of NT threads with `smem` as its LDS; the level loop (and its
+// barriers) is the same for both directions, so two groups of one
+// workgroup may run an x- and a y-bridge side by side.
+template <class S, int WC, int NT, bool STAGED>
+__device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
+                                            typename S::V* __restrict__ state, const PanelPtrs& pp,
+                                            const SchemeParams& sp, int e, int tB, int xw0, int yw0, double* smem) {
   using V = typename S::V;
   constexpr int NV = S::NV;
   V* buf0 = reinterpret_cast<V*>(smem);
   V* buf1 = buf0 + NV * g.W * g.W;
   V* stg = buf1 + NV * g.W * g.W;
-  const int ntiles = g.ntx * g.nty;
-  const bool isx = item < ntiles;
-  const int e = isx ? item : item - ntiles;
-  const int a = e % g.ntx, b = e / g.ntx;
   const int n = g.n, h = g.h;
-  int xw0, yw0, tB;
-  if (isx) {
-    xw0 = g.off + (a + 1) * n - h - 1;
-    yw0 = g.off + b * n - 1;
-    tB = b * g.ntx + (a + 1 == g.ntx ? 0 : a + 1);
-  } else {
-    xw0 = g.off + a * n - 1;
-    yw0 = g.off + (b + 1) * n - h - 1;
-    tB = (b + 1 == g.nty ? 0 : b + 1) * g.ntx + a;
-  }
   const V* up = static_cast<const V*>(pp.up);
   V* out = static_cast<V*>(isx ? pp.xb : pp.yb);
   const long long T0 = level_base(g);
   const int LH = 2 * NV * up_levels_len(n, H);
-  if (staged) {
+  // One-wave groups always stage (their panels are a few KB), which keeps
+  // the per-level fetch registers out of them. Staging is a compile-time
+  // choice: with one fetch path per kernel the prefetched values are not
+  // merged between paths, and their loads are waited for only where placed.
+  static_assert(STAGED || NT != 64, "one-wave groups stage");
+  constexpr bool staged = STAGED;
+  constexpr bool prefetch = Fetch<S, NT>::J <= 2;
+  if constexpr (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
     stage_runs<NT, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
     __syncthreads();
   }
-  Fetch<S, NT> f;
+  StripPre<S, NT> pre;
+  if constexpr (staged && prefetch) strip_pre_init<S, NT>(pre, g, LH);
   for (int l = 0; l <= H; ++l) {
+    // Declared per level: the prefetched values are not carried round the
+    // loop.
+    Fetch<S, NT> f;
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
-    if (!staged && l < H) fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
+    if (l < H) {
+      if constexpr (staged) {
+        if constexpr (prefetch) fetch_strips_stg<S, NT>(f, pre, stg, n, l);
+      } else {
+        fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
+      }
+    }
     if (l >= 1 && l <= h - 1) {
-      if (isx)
-        compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, l + 1, 2 * l, n - 2 * l, T0 + l - 1, sp);
+      // The x-bridge's window is transposed; a scheme whose step is
+      // symmetric in x and y reads it with the plain accessor, so both
+      // directions share one compute path.
+      if (S::XY_SYM || !isx)
+        compute_level<S, WC, NT, false>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
       else
-        compute_level<S, WC, NT>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+        compute_level<S, WC, NT, true>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
     }
     if (l < H) {
-      if (staged)
-        place_strips_staged<S, NT>(stg, cur, isx, g, l, LH);
+      if constexpr (staged && !prefetch)
+        place_strips_flat<S, NT>(stg, cur, g, l, LH);
       else
         place_fetched<S, NT>(f, cur);
     }
@@ -585,18 +767,70 @@ __device__ void bridge_item(const Geo& g, int H, int staged, typename S::V* __re
   if (H < h) {
     const V* fin = (H & 1) ? buf1 : buf0;
     if (isx)
-      write_rect<S, NT>(fin, state, g, xw0, yw0, h + 1 - H, H + 1, 2 * H, n - 2 * H);
+      write_rect<S, NT, true>(fin, state, g, xw0, yw0, h + 1 - H, H + 1, 2 * H, n - 2 * H);
     else
       write_rect<S, NT>(fin, state, g, xw0, yw0, H + 1, h + 1 - H, n - 2 * H, 2 * H);
   }
 }
 
+// Window origin and the far tile of the bridge over the east (isx) or south
+// edge of tile e.
+__device__ __forceinline__ void bridge_frame(const Geo& g, bool isx, int e, int& tB, int& xw0, int& yw0) {
+  const int a = e % g.ntx, b = e / g.ntx;
+  const int n = g.n, h = g.h;
+  if (isx) {
+    xw0 = g.off + (a + 1) * n - h - 1;
+    yw0 = g.off + b * n - 1;
+    tB = b * g.ntx + (a + 1 == g.ntx ? 0 : a + 1);
+  } else {
+    xw0 = g.off + a * n - 1;
+    yw0 = g.off + (b + 1) * n - h - 1;
+    tB = (b + 1 == g.nty ? 0 : b + 1) * g.ntx + a;
+  }
+}
+
+// Item i < ntiles: the x-bridge over the east edge of tile i; item
+// ntiles + i: the y-bridge over the south edge of tile i (Alg. 2-3).
+template <class S, int WC, int NT, bool STAGED>
+__device__ void bridge_item(const Geo& g, int H, typename S::V* __restrict__ state, const PanelPtrs& pp,
+                            const SchemeParams& sp, int item, double* smem) {
+  const int ntiles = g.ntx * g.nty;
+  const bool isx = item < ntiles;
+  const int e = isx ? item : item - ntiles;
+  int tB, xw0, yw0;
+  bridge_frame(g, isx, e, tB, xw0, yw0);
+  bridge_body<S, WC, NT, STAGED>(g, H, isx, state, pp, sp, e, tB, xw0, yw0, smem);
+}
+
+// LDS values (doubles) of one bridge group: two windows and, when staged,
+// the two facing strips of all levels.
+template <class S>
+__host__ __device__ inline size_t bridge_group_doubles(int n, bool staged) {
+  const size_t win = 2 * (size_t)(n + 2) * (size_t)(n + 2) * S::NV;
+  const size_t stg = staged ? (size_t)2 * 2 * S::NV * (size_t)up_levels_len(n, n / 2) : 0;
+  return ((win + stg) * sizeof(typename S::V) + 7) / 8;
+}
+
+// Both bridges of tile e in one workgroup of 2 NTI threads: threads
+// 0 .. NTI-1 run the x-bridge, NTI .. 2 NTI-1 the y-bridge, each with its own
+// LDS. The two run the same level loop under the workgroup's barriers, so the
+// bridge stage takes one round of workgroups instead of two.
+template <class S, int WC, int NTI, bool STAGED>
+__device__ void bridge_pair_item(const Geo& g, int H, typename S::V* __restrict__ state, const PanelPtrs& pp,
+                                 const SchemeParams& sp, int e, double* smem) {
+  const bool isx = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / NTI)) == 0;
+  int tB, xw0, yw0;
+  bridge_frame(g, isx, e, tB, xw0, yw0);
+  double* mine = smem + (isx ? 0 : bridge_group_doubles<S>(g.n, STAGED));
+  bridge_body<S, WC, NTI, STAGED>(g, H, isx, state, pp, sp, e, tB, xw0, yw0, mine);
+}
+
 // Downward pyramid at the south-east corner of tile c (Alg. 4), fused with
 // the next half cycle's upward pyramid of the tile centred on that corner
 // (an octahedron): the level-h tile never leaves LDS.
-template <class S, int WC, int NT>
-__device__ void oct_item(const Geo& g, int Hd, int Hu, int staged, typename S::V* __restrict__ state,
-                         const PanelPtrs& pp, const SchemeParams& sp, int c, double* smem) {
+template <class S, int WC, int NT, bool STAGED>
+__device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict__ state, const PanelPtrs& pp,
+                         const SchemeParams& sp, int c, double* smem) {
   using V = typename S::V;
   constexpr int NV = S::NV;
   V* buf0 = reinterpret_cast<V*>(smem);
@@ -623,20 +857,36 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, int staged, typename S::V
     b2 = b1;
   }
   const int tile2 = b2 * g.ntx + a2;
-  if (staged) {
+  static_assert(STAGED || NT != 64, "one-wave groups stage");  // as in the bridges
+  constexpr bool staged = STAGED;
+  constexpr bool prefetch = Fetch<S, NT>::J <= 2;
+  if constexpr (staged) {
     stage_runs<NT, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
                   yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
     __syncthreads();
   }
-  Fetch<S, NT> f;
+  RingPre<S, NT> pre;
+  if constexpr (staged && prefetch) ring_pre_init<S, NT>(pre, g, LxH, LyH);
   for (int l = 0; l <= Hd; ++l) {
+    Fetch<S, NT> f;  // per level, as in the bridges
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
-    if (!staged && l < Hd) fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
-    if (l >= 1) compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
     if (l < Hd) {
-      if (staged)
-        place_ring_staged<S, NT>(stg, cur, g, l, LxH, LyH);
+      if constexpr (staged) {
+        if constexpr (prefetch) fetch_ring_stg<S, NT>(f, pre, stg, l);
+      } else {
+        fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
+      }
+    }
+    if (l >= 1) {
+      if (l < h)
+        compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+      else
+        compute_level<S, WC, NT, false, true>(prv, cur, g.W, 1, 1, n, n, T0 + l - 1, sp);
+    }
+    if (l < Hd) {
+      if constexpr (staged && !prefetch)
+        place_ring_flat<S, NT>(stg, cur, g, l, LxH, LyH);
       else
         place_fetched<S, NT>(f, cur);
     }
@@ -654,27 +904,32 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, int staged, typename S::V
   up_levels<S, WC, NT>(buf0, buf1, h & 1, g2, tile2, xw0 + 1, yw0 + 1, T0 + h, Hu, state, up, sp);
 }
 
-template <class S, int WC>
-__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
+template <class S, int WC, int NT>
+__global__ __launch_bounds__(NT) void k_up(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
+                                           SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  up_item<S, WC, NT>(g, H, state, pp, sp, (int)blockIdx.x, smem_d);
+}
+
+template <class S, int WC, int NT, bool STAGED>
+__global__ __launch_bounds__(NT) void k_bridge(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
+                                               SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  bridge_item<S, WC, NT, STAGED>(g, H, state, pp, sp, (int)blockIdx.x, smem_d);
+}
+
+template <class S, int WC, int NTI, bool STAGED>
+__global__ __launch_bounds__(2 * NTI) void k_bridge_pair(Geo g, int H, typename S::V* __restrict__ state, PanelPtrs pp,
                                                          SchemeParams sp) {
   extern __shared__ double smem_d[];
-  up_item<S, WC, Lay<S, WC>::NT>(g, H, state, pp, sp, (int)blockIdx.x, smem_d);
+  bridge_pair_item<S, WC, NTI, STAGED>(g, H, state, pp, sp, (int)blockIdx.x, smem_d);
 }
 
-template <class S, int WC>
-__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_bridge(Geo g, int H, int staged,
-                                                             typename S::V* __restrict__ state, PanelPtrs pp,
-                                                             SchemeParams sp) {
+template <class S, int WC, int NT, bool STAGED>
+__global__ __launch_bounds__(NT) void k_oct(Geo g, int Hd, int Hu, typename S::V* __restrict__ state, PanelPtrs pp,
+                                            SchemeParams sp) {
   extern __shared__ double smem_d[];
-  bridge_item<S, WC, Lay<S, WC>::NT>(g, H, staged, state, pp, sp, (int)blockIdx.x, smem_d);
-}
-
-template <class S, int WC>
-__global__ __launch_bounds__((Lay<S, WC>::NT)) void k_oct(Geo g, int Hd, int Hu, int staged,
-                                                          typename S::V* __restrict__ state, PanelPtrs pp,
-                                                          SchemeParams sp) {
-  extern __shared__ double smem_d[];
-  oct_item<S, WC, Lay<S, WC>::NT>(g, Hd, Hu, staged, state, pp, sp, (int)blockIdx.x, smem_d);
+  oct_item<S, WC, NT, STAGED>(g, Hd, Hu, state, pp, sp, (int)blockIdx.x, smem_d);
 }
 
 template <class S>
@@ -749,16 +1004,59 @@ SchemeInfo info_of() {
   return SchemeInfo{S::NV, S::NVAR, S::SUB, (int)sizeof(typename S::V)};
 }
 
+// Workgroup size of the generic stage code for tile sides up to 22: one wave
+// for the light schemes.
+template <class S>
+constexpr int small_threads() {
+  return Lay<S, 0>::light ? 64 : Lay<S, 0>::NT;
+}
+
 // Window pitch as a compile-time constant for tile sides 32 and 64; the
-// workgroup size follows the instantiation's layout.
-#define SWEPT_BY_PITCH(KERNEL, S, n, GRID, LDS, STREAM, ...)                                              \
-  do {                                                                                                    \
-    if ((n) == 64)                                                                                        \
-      hipLaunchKernelGGL((KERNEL<S, 66>), GRID, dim3(Lay<S, 66>::NT), LDS, STREAM, __VA_ARGS__);          \
-    else if ((n) == 32)                                                                                   \
-      hipLaunchKernelGGL((KERNEL<S, 34>), GRID, dim3(Lay<S, 34>::NT), LDS, STREAM, __VA_ARGS__);          \
-    else                                                                                                  \
-      hipLaunchKernelGGL((KERNEL<S, 0>), GRID, dim3(Lay<S, 0>::NT), LDS, STREAM, __VA_ARGS__);            \
+// workgroup size follows the instantiation's layout, one wave for small
+// tiles of the light schemes.
+#define SWEPT_BY_PITCH(KERNEL, S, n, GRID, LDS, STREAM, ...)                                                   \
+  do {                                                                                                         \
+    if ((n) == 64)                                                                                             \
+      hipLaunchKernelGGL((KERNEL<S, 66, Lay<S, 66>::NT>), GRID, dim3(Lay<S, 66>::NT), LDS, STREAM, __VA_ARGS__); \
+    else if ((n) == 32)                                                                                        \
+      hipLaunchKernelGGL((KERNEL<S, 34, Lay<S, 34>::NT>), GRID, dim3(Lay<S, 34>::NT), LDS, STREAM, __VA_ARGS__); \
+    else if ((n) <= 22)                                                                                        \
+      hipLaunchKernelGGL((KERNEL<S, 0, small_threads<S>()>), GRID, dim3(small_threads<S>()), LDS, STREAM,       \
+                         __VA_ARGS__);                                                                         \
+    else                                                                                                       \
+      hipLaunchKernelGGL((KERNEL<S, 0, Lay<S, 0>::NT>), GRID, dim3(Lay<S, 0>::NT), LDS, STREAM, __VA_ARGS__);   \
+  } while (0)
+
+// The same with the staging choice ST (a compile-time kernel parameter; the
+// one-wave instantiations exist staged only).
+#define SWEPT_BY_PITCH_ST(KERNEL, S, n, ST, GRID, LDS, STREAM, ...)                                           \
+  do {                                                                                                        \
+    constexpr int nt66 = Lay<S, 66>::NT, nt34 = Lay<S, 34>::NT, nts = small_threads<S>(), nt0 = Lay<S, 0>::NT; \
+    if ((n) == 64) {                                                                                          \
+      if (ST)                                                                                                 \
+        hipLaunchKernelGGL((KERNEL<S, 66, nt66, true>), GRID, dim3(nt66), LDS, STREAM, __VA_ARGS__);          \
+      else                                                                                                    \
+        hipLaunchKernelGGL((KERNEL<S, 66, nt66, false>), GRID, dim3(nt66), LDS, STREAM, __VA_ARGS__);         \
+    } else if ((n) == 32) {                                                                                   \
+      if (ST)                                                                                                 \
+        hipLaunchKernelGGL((KERNEL<S, 34, nt34, true>), GRID, dim3(nt34), LDS, STREAM, __VA_ARGS__);          \
+      else                                                                                                    \
+        hipLaunchKernelGGL((KERNEL<S, 34, nt34, false>), GRID, dim3(nt34), LDS, STREAM, __VA_ARGS__);         \
+    } else if ((n) <= 22) {                                                                                   \
+      if constexpr (nts == 64) {                                                                              \
+        hipLaunchKernelGGL((KERNEL<S, 0, nts, true>), GRID, dim3(nts), LDS, STREAM, __VA_ARGS__);             \
+      } else {                                                                                                \
+        if (ST)                                                                                               \
+          hipLaunchKernelGGL((KERNEL<S, 0, nts, true>), GRID, dim3(nts), LDS, STREAM, __VA_ARGS__);           \
+        else                                                                                                  \
+          hipLaunchKernelGGL((KERNEL<S, 0, nts, false>), GRID, dim3(nts), LDS, STREAM, __VA_ARGS__);          \
+      }                                                                                                       \
+    } else {                                                                                                  \
+      if (ST)                                                                                                 \
+        hipLaunchKernelGGL((KERNEL<S, 0, nt0, true>), GRID, dim3(nt0), LDS, STREAM, __VA_ARGS__);             \
+      else                                                                                                    \
+        hipLaunchKernelGGL((KERNEL<S, 0, nt0, false>), GRID, dim3(nt0), LDS, STREAM, __VA_ARGS__);            \
+    }                                                                                                         \
   } while (0)
 
 template <class S>
@@ -769,21 +1067,63 @@ hipError_t up_t(const Geo& g, int H, void* state, PanelPtrs p, const SchemeParam
   return hipGetLastError();
 }
 
+// Workgroup size of the instantiation that runs tile side n.
 template <class S>
-hipError_t bridge_t(const Geo& g, int H, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
+constexpr int threads_for(int n) {
+  return n == 64 ? Lay<S, 66>::NT : (n == 32 ? Lay<S, 34>::NT : (n <= 22 ? small_threads<S>() : Lay<S, 0>::NT));
+}
+
+// One-wave instantiations always stage their panel inputs.
+template <class S>
+bool forced_staging(int n) {
+  return threads_for<S>(n) == 64;
+}
+
+// Bridge pairs (both bridges of a tile in one workgroup) for the column
+// layouts when two bridge groups fit the workgroup LDS, staged if that
+// fits too.
+template <class S, int WC>
+bool bridge_pair_launch(const Geo& g, int H, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
+                        hipStream_t s, hipError_t* err) {
+  constexpr int NT = Lay<S, WC>::NT;
+  if constexpr (!Lay<S, WC>::cols || NT < 128) {
+    return false;
+  } else {
+    const size_t lim = device_lds_limit();
+    bool st = staged && 2 * 8 * bridge_group_doubles<S>(g.n, true) <= lim;
+    const size_t lds = 2 * 8 * bridge_group_doubles<S>(g.n, st);
+    if (lds > lim) return false;
+    if (st)
+      hipLaunchKernelGGL((k_bridge_pair<S, WC, NT / 2, true>), dim3(g.ntx * g.nty), dim3(NT), lds, s, g, H,
+                         static_cast<typename S::V*>(state), p, sp);
+    else
+      hipLaunchKernelGGL((k_bridge_pair<S, WC, NT / 2, false>), dim3(g.ntx * g.nty), dim3(NT), lds, s, g, H,
+                         static_cast<typename S::V*>(state), p, sp);
+    *err = hipGetLastError();
+    return true;
+  }
+}
+
+template <class S>
+hipError_t bridge_t(const Geo& g, int H, bool staged, bool pair_ok, void* state, PanelPtrs p, const SchemeParams& sp,
                     hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (pair_ok && g.n == 64 && bridge_pair_launch<S, 66>(g, H, staged, state, p, sp, s, &e)) return e;
+  if (pair_ok && g.n == 32 && bridge_pair_launch<S, 34>(g, H, staged, state, p, sp, s, &e)) return e;
+  staged = staged || forced_staging<S>(g.n);
   const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? bridge_stage_bytes(info_of<S>(), g.n) : 0);
-  SWEPT_BY_PITCH(k_bridge, S, g.n, dim3(2 * g.ntx * g.nty), lds, s, g, H, staged ? 1 : 0,
-                 static_cast<typename S::V*>(state), p, sp);
+  SWEPT_BY_PITCH_ST(k_bridge, S, g.n, staged, dim3(2 * g.ntx * g.nty), lds, s, g, H,
+                    static_cast<typename S::V*>(state), p, sp);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t oct_t(const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
                  hipStream_t s) {
+  staged = staged || forced_staging<S>(g.n);
   const size_t lds = window_lds_bytes(info_of<S>(), g.n) + (staged ? oct_stage_bytes(info_of<S>(), g.n) : 0);
-  SWEPT_BY_PITCH(k_oct, S, g.n, dim3(g.ntx * g.nty), lds, s, g, Hd, Hu, staged ? 1 : 0,
-                 static_cast<typename S::V*>(state), p, sp);
+  SWEPT_BY_PITCH_ST(k_oct, S, g.n, staged, dim3(g.ntx * g.nty), lds, s, g, Hd, Hu,
+                    static_cast<typename S::V*>(state), p, sp);
   return hipGetLastError();
 }
 
@@ -797,26 +1137,41 @@ hipError_t plain_t(int nx, int ny, long long T, const long long* tbase, const vo
   return hipGetLastError();
 }
 
-template <class S, int WC>
-hipError_t lds_one(int b) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_up<S, WC>),
+template <class S, int WC, int NT, bool ST>
+hipError_t lds_staged(int b) {
+  if constexpr (WC != 0 && Lay<S, WC>::cols && NT == Lay<S, WC>::NT && NT >= 128) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge_pair<S, WC, NT / 2, ST>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge<S, WC, NT, ST>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, b);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge<S, WC>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          b);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_oct<S, WC, NT, ST>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, b);
+}
+
+template <class S, int WC, int NT>
+hipError_t lds_one(int b) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_up<S, WC, NT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_oct<S, WC>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             b);
+  e = lds_staged<S, WC, NT, true>(b);
+  if (e != hipSuccess) return e;
+  if constexpr (NT != 64) e = lds_staged<S, WC, NT, false>(b);
+  return e;
 }
 
 template <class S>
 hipError_t lds_t(size_t bytes) {
   const int b = (int)bytes;
-  hipError_t e = lds_one<S, 0>(b);
+  hipError_t e = lds_one<S, 0, Lay<S, 0>::NT>(b);
   if (e != hipSuccess) return e;
-  e = lds_one<S, 34>(b);
+  e = lds_one<S, 0, small_threads<S>()>(b);
   if (e != hipSuccess) return e;
-  return lds_one<S, 66>(b);
+  e = lds_one<S, 34, Lay<S, 34>::NT>(b);
+  if (e != hipSuccess) return e;
+  return lds_one<S, 66, Lay<S, 66>::NT>(b);
 }
 
 #define SWEPT_DISPATCH(FN, ...)                       \
@@ -935,10 +1290,18 @@ __device__ __forceinline__ void batch_stage(const BatchGrid& G, const BatchPlan&
   // (a few KB), which keeps the per-level fetch registers out of the kernel.
   constexpr bool always_staged = NT == 64;
   if (p & 1) {
-    bridge_item<S, WC, NT>(g, H, always_staged ? 1 : G.staged_bridge, state, G.pp, G.sp, item, smem);
+    if (always_staged || G.staged_bridge) {
+      bridge_item<S, WC, NT, true>(g, H, state, G.pp, G.sp, item, smem);
+    } else if constexpr (!always_staged) {
+      bridge_item<S, WC, NT, false>(g, H, state, G.pp, G.sp, item, smem);
+    }
   } else {
     const int Hu = (hc + 1 < P.q) ? h : (hc + 1 == P.q ? P.r : 0);
-    oct_item<S, WC, NT>(g, H, Hu, always_staged ? 1 : G.staged_oct, state, G.pp, G.sp, item, smem);
+    if (always_staged || G.staged_oct) {
+      oct_item<S, WC, NT, true>(g, H, Hu, state, G.pp, G.sp, item, smem);
+    } else if constexpr (!always_staged) {
+      oct_item<S, WC, NT, false>(g, H, Hu, state, G.pp, G.sp, item, smem);
+    }
   }
 }
 
@@ -1115,9 +1478,9 @@ hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, void* state, PanelPtrs p,
+hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, bool pair_ok, void* state, PanelPtrs p,
                          const SchemeParams& sp, hipStream_t s) {
-  SWEPT_DISPATCH(bridge_t, g, H, staged, state, p, sp, s)
+  SWEPT_DISPATCH(bridge_t, g, H, staged, pair_ok, state, p, sp, s)
   return hipErrorInvalidValue;
 }
 
