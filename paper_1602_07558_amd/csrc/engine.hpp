@@ -1,5 +1,5 @@
-// Launch descriptors shared by the kernels (swept2d_kernels.hip) and the
-// host planner (swept2d_api.cpp).
+// Launch descriptors shared by the kernels (stages.hpp, swept2d_kernels.hip)
+// and the host planners (swept2d_api.cpp, swept2d_batch.cpp).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -10,10 +10,10 @@
 namespace swept {
 
 // Thread layout of a stage kernel instantiation (WC: compile-time window
-// pitch, 66 for tile side 64, 34 for 32, 0 for any other side).
+// pitch, 66 for tile side 64, 34 for 32, 18 for 16, 0 for any other side).
 //  - Schemes with at most 16 bytes of state per point ("light") run 16 waves
-//    at tile side 64, one wave for sides up to 22 (set by the launcher), 4
-//    waves otherwise; the Euler schemes 8 waves. A level is a short chain of
+//    at tile side 64, one wave at 16 and for other sides up to 22 (set by the
+//    launcher), 4 waves otherwise; the Euler schemes 8 waves. A level is a short chain of
 //    dependent LDS and arithmetic latencies ended by a barrier, so many waves
 //    with few rows each hide it best (4 waves with 16 rows each measured
 //    twice as slow at tile side 64).
@@ -27,7 +27,7 @@ template <class S, int WC, int NTo = 0>
 struct Lay {
   static constexpr bool light = S::NV * (int)sizeof(typename S::V) <= 16;
   static constexpr int N = WC ? WC - 2 : 0;
-  static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 66 ? 1024 : 256));
+  static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 66 ? 1024 : (WC == 18 ? 64 : 256)));
   static constexpr int NW = NT / 64;
   static constexpr bool cols = light && WC != 0 && (N * N) % NT == 0;
   static constexpr int R = cols ? N * N / NT : 0;
@@ -111,7 +111,7 @@ enum Scheme : int {
   kNumSchemes
 };
 
-// Launch entry points (defined in swept2d_kernels.hip). Each returns the
+// Launch entry points (swept2d_kernels.hip dispatches them). Each returns the
 // hipError_t of the launch.
 //   up:     upward pyramid of every tile from the state (height H; emits
 //           panels of levels 0..H-1; if H < h writes its level-H region to
@@ -194,17 +194,21 @@ constexpr int kBatchBlock = 64;  // side of a per-step block
 enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1 };
 
 // Launch classes of the phased batch: the stage code of tile side 64 on 16
-// waves, of tile side 32 on 4 waves, of any other side on 4 waves, and of
-// sides up to 22 on one wave; per-step grids run in the 4-wave generic class.
-// One-wave items always stage their panel inputs.
-enum BatchClass : int { kClass66 = 0, kClass34, kClassGen256, kClassGen64, kNumBatchClasses };
+// waves, of tile side 32 on 4 waves, of tile side 16 on one wave, of any
+// other side on 4 waves, and of other sides up to 22 on one wave; per-step
+// grids run in the 4-wave generic class. One-wave items always stage their
+// panel inputs.
+enum BatchClass : int { kClass66 = 0, kClass34, kClass18, kClassGen256, kClassGen64, kNumBatchClasses };
 inline int batch_class_of(int n) {
   if (n == 64) return kClass66;
   if (n == 32) return kClass34;
+  if (n == 16) return kClass18;
   if (n != 0 && n <= 22) return kClassGen64;
   return kClassGen256;
 }
-inline int batch_class_threads(int c) { return c == kClass66 ? 1024 : (c == kClassGen64 ? 64 : 256); }
+inline int batch_class_threads(int c) {
+  return c == kClass66 ? 1024 : ((c == kClassGen64 || c == kClass18) ? 64 : 256);
+}
 
 struct BatchGrid {
   Geo g0;          // off 0, T0 = the grid's level at the start of an advance
@@ -275,6 +279,28 @@ hipError_t launch_batch_reset(unsigned* done, int ngrids, unsigned long long* he
 // Resident workgroups of the persistent kernel per compute unit at `lds` bytes.
 hipError_t batch_blocks_per_cu(size_t lds, int* out);
 #endif
+
+// Launchers of one scheme's stage kernels (defined in stages.hpp, explicitly
+// instantiated once per scheme in its own translation unit).
+template <class S>
+struct Stages {
+  static SchemeInfo info();
+  static hipError_t up(const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp, hipStream_t s);
+  static hipError_t bridge(const Geo& g, int H, bool staged, bool pair_ok, void* state, PanelPtrs p,
+                           const SchemeParams& sp, hipStream_t s);
+  static hipError_t oct(const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
+                        hipStream_t s);
+  static hipError_t plain(int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
+                          const SchemeParams& sp, hipStream_t s);
+  static hipError_t lds(size_t bytes);
+};
+
+// Kernel of one batch launch class (window pitch WC, NT threads).
+template <int WC, int NT>
+struct BatchPhase {
+  static hipError_t launch(const PhaseLaunch& L, int blocks, size_t lds, hipStream_t st);
+  static hipError_t lds(int bytes);
+};
 
 // Host helpers shared by the host files (swept2d_api.cpp).
 int set_error(int code, const char* fmt, ...);  // message kept per thread

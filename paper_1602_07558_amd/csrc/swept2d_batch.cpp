@@ -31,7 +31,7 @@ int hip_error(hipError_t e, const char* what) {
 
 // Tile sides with compile-time window pitch; other sides run the generic
 // stage code.
-int pitch_of(int n) { return n == 64 ? 66 : (n == 32 ? 34 : 0); }
+int pitch_of(int n) { return n == 64 ? 66 : (n == 32 ? 34 : (n == 16 ? 18 : 0)); }
 
 struct HostGrid {
   int nx = 0, ny = 0, pde = 0, prec = 0, scheme = 0, substeps = 1;
