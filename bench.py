@@ -40,13 +40,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 LDS_PEAK_GBS = 128 * 256 * 2.4
 # Algorithmic work of one heat point update (5-point FTCS): flops
 # (uW+uE, uN+uS, their sum, 4u, the difference, r*lap, u + r*lap) and the
-# LDS bytes of the stage kernels' update (five FP64 reads, one FP64 write).
+# LDS bytes of a point update done in LDS: one FP64 read of the point's own
+# value and one FP64 write (neighbours come from registers and lane shifts).
 HEAT_FLOPS_PER_UPDATE = 7
-HEAT_LDS_BYTES_PER_UPDATE = 6 * 8
+HEAT_LDS_BYTES_PER_UPDATE = 2 * 8
+BATCH_STEPS = 1024
 
 PROFILE_FILE = os.path.join(ROOT, "profiles", "oct_heat1024_fp64_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1602_07558_amd", "csrc", f)
-                  for f in ("swept2d_kernels.hip", "schemes.hpp", "engine.hpp")]
+                  for f in ("stages.hpp", "stages_scheme.hip", "schemes.hpp", "engine.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -105,6 +107,59 @@ def cpu_baseline(budget_s: float = 12.0):
             "sample": f"heat 1024x1024 FP64, first {steps} of the 20000 steps, plain C stepper, {threads} threads"}
 
 
+def other_workloads(sw, si, np):
+    """Throughput of the other workloads at their full sizes over a bounded
+    number of steps (the step counts of their parity tests are longer): the
+    wave 2048^2 and Euler 512^2 grids (swept, FP64 and FP32C) and the
+    uneven 256-grid batch (phased launches, model tile sides)."""
+    out = {}
+
+    def rate(make, steps, pts):
+        g = make()
+        g.advance(steps)   # warm-up (graph capture for the batch)
+        g.synchronize()
+        t0 = time.perf_counter()
+        g.advance(steps)
+        g.synchronize()
+        dt = time.perf_counter() - t0
+        tile = g.tile if isinstance(g, sw.Swept2D) else None
+        g.close()
+        return pts * steps / dt, tile
+
+    s_w = si.wave_field(2048, 2048, seed=0)
+    p_w = si.default_params(si.WAVE_LF)
+    for prec, name in ((sw.FP64, "fp64"), (sw.FP32C, "fp32c")):
+        def mk(prec=prec):
+            g = sw.Swept2D(2048, 2048, si.WAVE_LF, p_w, prec=prec)
+            g.upload(s_w)
+            return g
+        v, tile = rate(mk, 1000, 2048 * 2048)
+        out[f"wave2048_{name}"] = {"value": v, "unit": "point-updates/s", "steps": 1000, "tile": tile}
+    s_e = si.euler_field(512, 512, seed=0)
+    p_e = si.default_params(si.EULER_RUS_RK2, s_e)
+    for prec, name in ((sw.FP64, "fp64"), (sw.FP32C, "fp32c")):
+        def mk(prec=prec):
+            g = sw.Swept2D(512, 512, si.EULER_RUS_RK2, p_e, prec=prec)
+            g.upload(s_e)
+            return g
+        v, tile = rate(mk, 500, 512 * 512)
+        out[f"euler512_{name}"] = {"value": v, "unit": "point-updates/s (full RK2 steps)", "steps": 500, "tile": tile}
+    specs = si.batch_specs(256, seed=0)
+    grids = [dict(nx=b["nx"], ny=b["ny"], pde=b["pde"], prec=b["prec"], params=list(si.default_params(b["pde"])))
+             for b in specs]
+    pts = sum(b["nx"] * b["ny"] for b in specs)
+
+    def mkb():
+        b = sw.Swept2DBatch(grids)
+        for i, sp in enumerate(specs):
+            b.upload(i, si.initial_state(sp["pde"], sp["nx"], sp["ny"], seed=sp["seed"]))
+        return b
+    v, _ = rate(mkb, BATCH_STEPS, pts)
+    out["batch256"] = {"value": v, "unit": "point-updates/s", "steps": BATCH_STEPS, "grids": len(specs),
+                       "points": pts, "mode": "phased launches, model tile sides"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,8 +169,8 @@ def main():
     ap.add_argument("--profile-pass", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the swept decomposition would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (the swept decomposition would "
+              "give each GPU a block of tiles and exchange only its boundary panels)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -221,7 +276,7 @@ def main():
                    "tile": tile, "precision": "fp64"},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_oct<Heat64> (downward pyramid + next upward pyramid)",
+            "kernel": "k_oct<Heat64,66,1024,staged> (downward pyramid + next upward pyramid)",
             "achieved": achieved,
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
@@ -240,6 +295,7 @@ def main():
                   "swept_over_fp64_swept": rate(t_s32) / rate(t_swept)},
         "bitwise_equal_swept_plain": bitwise_equal,
     }
+    result["other_workloads"] = other_workloads(sw, si, np)
     if not args.skip_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result))

@@ -32,13 +32,14 @@ def kernel_stats(directory: str):
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"(k_[a-z0-9]+)<swept::(\w+)(?:, (\d+))?>", name)
+    m = re.search(r"(k_[a-z0-9_]+)<([^()]*)>", name)
     if m:
-        return f"{m.group(1)}<{m.group(2)}>" if not m.group(3) else f"{m.group(1)}<{m.group(2)},{m.group(3)}>"
+        args = m.group(2).replace("swept::", "").replace(" ", "")
+        return f"{m.group(1)}<{args}>"
     m = re.search(r"(k_[a-z0-9]+)INS_(\d+)(\w+)", name)
     if m:
         return f"{m.group(1)}<{m.group(3)[:int(m.group(2))]}>"
-    for key in ("k_copy8", "k_set_base"):
+    for key in ("k_copy8", "k_set_base", "k_batch_bump"):
         if key in name:
             return key
     if "copy" in name.lower() or "elementwise" in name.lower():
@@ -70,7 +71,7 @@ def _pick(values: dict, pred):
 def traffic_summary(fetch_dir: str, write_dir: str, copy_bytes: int):
     f = counter_values(fetch_dir, "FETCH_SIZE")
     w = counter_values(write_dir, "WRITE_SIZE")
-    is_oct = lambda n: "k_oct" in n and "Heat64" in n
+    is_oct = lambda n: "k_oct" in n and "Heat64" in n and "66" in n
     is_copy = lambda n: ("copy" in n.lower() or "elementwise" in n.lower()) and "k_copy8" not in n
     f_oct, w_oct = _pick(f, is_oct), _pick(w, is_oct)
     f_copy, w_copy = _pick(f, is_copy), _pick(w, is_copy)
@@ -86,7 +87,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, copy_bytes: int):
 def main(argv):
     if argv and argv[0] == "stats":
         for k in sorted(kernel_stats(argv[1]), key=lambda r: -r["total_ns"]):
-            print(f"{short_name(k['name']):28s} calls={k['calls']:7d} avg_us={k['avg_ns'] / 1e3:10.2f} "
+            print(f"{short_name(k['name']):40s} calls={k['calls']:7d} avg_us={k['avg_ns'] / 1e3:10.2f} "
                   f"total_ms={k['total_ns'] / 1e6:10.3f} pct={k['pct']:6.2f}")
         return 0
     if argv and argv[0] == "traffic":
@@ -98,7 +99,7 @@ def main(argv):
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import bench
         with open(out, "w") as fo:
-            fo.write("# HBM traffic of k_oct<Heat64> per launch (heat 1024x1024, tile 64, FP64)\n")
+            fo.write("# HBM traffic of k_oct<Heat64,66,1024,true> per launch (heat 1024x1024, tile 64, FP64, staged)\n")
             for k, v in t.items():
                 fo.write(f"{k}: {v:.6g}\n")
             fo.write(f"kernel_source_sha256_16: {bench.kernel_source_hash()}\n")
