@@ -264,6 +264,18 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
     }
   if ((unsigned)(c - x0) >= (unsigned)w) return;
   V* dst = out + r0 * W + c;
+  // A wave whose rows all lie inside the rectangle (uniform when a wave is
+  // one row group) stores them without per-row tests.
+  if (N == 64 && r0 >= y0 && r0 + R <= y0 + hg) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      V o[NV];
+      S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     if ((unsigned)(r0 + i - y0) < (unsigned)hg) {
@@ -737,36 +749,51 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   }
   StripPre<S, NT> pre;
   if constexpr (staged && prefetch) strip_pre_init<S, NT>(pre, g, LH);
-  for (int l = 0; l <= H; ++l) {
+  // Level l: place the strips of level l, after computing the band of level l
+  // (1 <= l <= h-1) from level l-1. The first level only places, the last (H)
+  // only computes (a full half cycle has no level h in a bridge); they are
+  // peeled off so the loop body tests nothing per level. H >= 1.
+  auto strips_fetch = [&](Fetch<S, NT>& f, int l) {
+    if constexpr (staged) {
+      if constexpr (prefetch) fetch_strips_stg<S, NT>(f, pre, stg, n, l);
+    } else {
+      fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
+    }
+  };
+  auto strips_place = [&](const Fetch<S, NT>& f, V* cur, int l) {
+    if constexpr (staged && !prefetch)
+      place_strips_flat<S, NT>(stg, cur, g, l, LH);
+    else
+      place_fetched<S, NT>(f, cur);
+  };
+  // The x-bridge's window is transposed; a scheme whose step is symmetric in
+  // x and y reads it with the plain accessor, so both directions share one
+  // compute path.
+  auto band = [&](const V* prv, V* cur, int l) {
+    if (S::XY_SYM || !isx)
+      compute_level<S, WC, NT, false>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+    else
+      compute_level<S, WC, NT, true>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
+  };
+  {
     // Declared per level: the prefetched values are not carried round the
     // loop.
     Fetch<S, NT> f;
-    V* cur = (l & 1) ? buf1 : buf0;
-    const V* prv = (l & 1) ? buf0 : buf1;
-    if (l < H) {
-      if constexpr (staged) {
-        if constexpr (prefetch) fetch_strips_stg<S, NT>(f, pre, stg, n, l);
-      } else {
-        fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
-      }
-    }
-    if (l >= 1 && l <= h - 1) {
-      // The x-bridge's window is transposed; a scheme whose step is
-      // symmetric in x and y reads it with the plain accessor, so both
-      // directions share one compute path.
-      if (S::XY_SYM || !isx)
-        compute_level<S, WC, NT, false>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
-      else
-        compute_level<S, WC, NT, true>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
-    }
-    if (l < H) {
-      if constexpr (staged && !prefetch)
-        place_strips_flat<S, NT>(stg, cur, g, l, LH);
-      else
-        place_fetched<S, NT>(f, cur);
-    }
+    strips_fetch(f, 0);
+    strips_place(f, buf0, 0);
     __syncthreads();
   }
+  for (int l = 1; l < H; ++l) {
+    Fetch<S, NT> f;
+    V* cur = (l & 1) ? buf1 : buf0;
+    const V* prv = (l & 1) ? buf0 : buf1;
+    strips_fetch(f, l);
+    band(prv, cur, l);
+    strips_place(f, cur, l);
+    __syncthreads();
+  }
+  if (H < h) band((H & 1) ? buf0 : buf1, (H & 1) ? buf1 : buf0, H);
+  __syncthreads();
   emit_bridge_all<S, NT>(buf0, buf1, out, isx, g, e, H);
   if (H < h) {
     const V* fin = (H & 1) ? buf1 : buf0;
@@ -871,29 +898,44 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   }
   RingPre<S, NT> pre;
   if constexpr (staged && prefetch) ring_pre_init<S, NT>(pre, g, LxH, LyH);
-  for (int l = 0; l <= Hd; ++l) {
+  // Level l: place the ring of level l, after computing the square of level l
+  // (l >= 1) from level l-1. The first level only places, the last (Hd) only
+  // computes; they are peeled off so the loop body tests nothing per level.
+  auto ring_fetch = [&](Fetch<S, NT>& f, int l) {
+    if constexpr (staged) {
+      if constexpr (prefetch) fetch_ring_stg<S, NT>(f, pre, stg, l);
+    } else {
+      fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
+    }
+  };
+  auto ring_place = [&](const Fetch<S, NT>& f, V* cur, int l) {
+    if constexpr (staged && !prefetch)
+      place_ring_flat<S, NT>(stg, cur, g, l, LxH, LyH);
+    else
+      place_fetched<S, NT>(f, cur);
+  };
+  if (Hd > 0) {
+    Fetch<S, NT> f;
+    ring_fetch(f, 0);
+    ring_place(f, buf0, 0);
+    __syncthreads();
+  }
+  for (int l = 1; l < Hd; ++l) {
     Fetch<S, NT> f;  // per level, as in the bridges
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
-    if (l < Hd) {
-      if constexpr (staged) {
-        if constexpr (prefetch) fetch_ring_stg<S, NT>(f, pre, stg, l);
-      } else {
-        fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
-      }
-    }
-    if (l >= 1) {
-      if (l < h)
-        compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
-      else
-        compute_level<S, WC, NT, false, true>(prv, cur, g.W, 1, 1, n, n, T0 + l - 1, sp);
-    }
-    if (l < Hd) {
-      if constexpr (staged && !prefetch)
-        place_ring_flat<S, NT>(stg, cur, g, l, LxH, LyH);
-      else
-        place_fetched<S, NT>(f, cur);
-    }
+    ring_fetch(f, l);
+    compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+    ring_place(f, cur, l);
+    __syncthreads();
+  }
+  if (Hd > 0) {
+    V* cur = (Hd & 1) ? buf1 : buf0;
+    const V* prv = (Hd & 1) ? buf0 : buf1;
+    if (Hd < h)
+      compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - Hd, h + 1 - Hd, 2 * Hd, 2 * Hd, T0 + Hd - 1, sp);
+    else
+      compute_level<S, WC, NT, false, true>(prv, cur, g.W, 1, 1, n, n, T0 + Hd - 1, sp);
     __syncthreads();
   }
   const V* top = (Hd & 1) ? buf1 : buf0;
@@ -1087,13 +1129,20 @@ bool forced_staging(int n) {
   return threads_for<S>(n) == 64;
 }
 
+// Threads of one group of a bridge pair: 8 waves at tile side 64, half the
+// stage workgroup otherwise.
+template <class S, int WC>
+constexpr int pair_threads() {
+  return WC == 66 ? 512 : Lay<S, WC>::NT / 2;
+}
+
 // Bridge pairs (both bridges of a tile in one workgroup) for the column
 // layouts when two bridge groups fit the workgroup LDS, staged if that
 // fits too.
 template <class S, int WC>
 bool bridge_pair_launch(const Geo& g, int H, bool staged, void* state, PanelPtrs p, const SchemeParams& sp,
                         hipStream_t s, hipError_t* err) {
-  constexpr int NT = Lay<S, WC>::NT;
+  constexpr int NT = 2 * pair_threads<S, WC>();
   if constexpr (!Lay<S, WC>::cols || NT < 128) {
     return false;
   } else {
@@ -1147,8 +1196,8 @@ hipError_t plain_t(int nx, int ny, long long T, const long long* tbase, const vo
 
 template <class S, int WC, int NT, bool ST>
 hipError_t lds_staged(int b) {
-  if constexpr (WC != 0 && Lay<S, WC>::cols && NT == Lay<S, WC>::NT && NT >= 128) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge_pair<S, WC, NT / 2, ST>),
+  if constexpr (WC != 0 && Lay<S, WC>::cols && NT == Lay<S, WC>::NT && 2 * pair_threads<S, WC>() >= 128) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bridge_pair<S, WC, pair_threads<S, WC>(), ST>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
   }
