@@ -16,7 +16,10 @@
 //            global sub-step index, so St_{T mod SUB} is applied.
 //
 // Every expression is evaluated exactly as written (the library is compiled
-// with -ffp-contract=off): sums are left to right, no fused multiply-add.
+// with -ffp-contract=off): sums are left to right, and the compiler fuses no
+// multiply-add. A step writes a fused multiply-add itself only where the
+// product is exact (a scale by a power of two), so the one rounding of the
+// fused form gives the same bits as the written product and sum.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -43,7 +46,9 @@ struct Heat64 {
     const double u = nb(0, 0, 0);
     const double t1 = nb(-1, 0, 0) + nb(1, 0, 0);
     const double t2 = nb(0, -1, 0) + nb(0, 1, 0);
-    const double lap = (t1 + t2) - 4.0 * u;
+    // 4u is exact (a power-of-two scale), so the fused form rounds once at
+    // the same exact value as the written difference (t1 + t2) - 4u.
+    const double lap = __builtin_fma(-4.0, u, t1 + t2);
     out[0] = u + r * lap;
   }
 };
@@ -61,8 +66,10 @@ struct Wave64 {
     const double q = nb(0, 0, 1);
     const double t1 = nb(-1, 0, 0) + nb(1, 0, 0);
     const double t2 = nb(0, -1, 0) + nb(0, 1, 0);
-    const double lap = (t1 + t2) - 4.0 * u;
-    out[0] = (2.0 * u - q) + c2 * lap;
+    // 4u and 2u are exact, so each fused form rounds once at the value of
+    // the written difference: (t1 + t2) - 4u and 2u - q.
+    const double lap = __builtin_fma(-4.0, u, t1 + t2);
+    out[0] = __builtin_fma(2.0, u, -q) + c2 * lap;
     out[1] = u;
   }
 };

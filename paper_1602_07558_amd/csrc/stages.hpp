@@ -235,54 +235,93 @@ template <class S, int WC, int NT, bool TR, bool DPP>
 __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                              int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
-  constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N, R = Lay<S, WC, NT>::R;
-  const int t = ltid<NT>();
-  const int c = 1 + t % N;
-  // With N = 64 a wave is one row group, so the row tests are uniform.
-  const int r0 = N == 64 ? 1 + R * lwave<NT>() : 1 + R * (t / N);
-  const bool rows_in = !(r0 + R <= y0 || r0 >= y0 + hg);
-  if (N == 64) {
-    if (!rows_in) return;
-  } else {
-    if (!__builtin_amdgcn_ballot_w64(rows_in)) return;  // wave-uniform exit
-  }
-  const V* src = in + (r0 - 1) * W + c;
-  V nb[R + 2][3][NV];
+  constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N;
+  if constexpr (N == 64) {
+    // A wave is one row of groups: the rectangle's rows, from its first,
+    // are cut into groups of four dealt to the waves in turn, so a level
+    // keeps ceil(hg / 4) waves busy, each with at most one partial group,
+    // whatever the rectangle's position in the window.
+    constexpr int R = 4, NW = NT / 64;
+    const int c = 1 + lane_id();
+    const bool col_in = (unsigned)(c - x0) < (unsigned)w;
+    for (int grp = lwave<NT>(); R * grp < hg; grp += NW) {
+      const int r0 = y0 + R * grp;
+      const V* src = in + c;
+      V nb[R + 2][3][NV];
 #pragma unroll
-  for (int j = 0; j < R + 2; ++j)
+      for (int j = 0; j < R + 2; ++j) {
+        // Rows past a partial group's end are clamped into the window; their
+        // values feed no stored point.
+        const int row = min(r0 - 1 + j, W - 1);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const V m = src[v * plane + j * W];
-      nb[j][1][v] = m;
-      if constexpr (DPP) {
-        nb[j][0][v] = dpp_shift<true>(m);
-        nb[j][2][v] = dpp_shift<false>(m);
-      } else {
-        nb[j][0][v] = src[v * plane + j * W - 1];
-        nb[j][2][v] = src[v * plane + j * W + 1];
+        for (int v = 0; v < NV; ++v) {
+          const V m = src[v * plane + row * W];
+          nb[j][1][v] = m;
+          if constexpr (DPP) {
+            nb[j][0][v] = dpp_shift<true>(m);
+            nb[j][2][v] = dpp_shift<false>(m);
+          } else {
+            nb[j][0][v] = src[v * plane + row * W - 1];
+            nb[j][2][v] = src[v * plane + row * W + 1];
+          }
+        }
+      }
+      if (col_in) {
+        V* dst = out + r0 * W + c;
+        if (R * grp + R <= hg) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            V o[NV];
+            S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            if (R * grp + i < hg) {
+              V o[NV];
+              S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+#pragma unroll
+              for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+            }
+          }
+        }
       }
     }
-  if ((unsigned)(c - x0) >= (unsigned)w) return;
-  V* dst = out + r0 * W + c;
-  // A wave whose rows all lie inside the rectangle (uniform when a wave is
-  // one row group) stores them without per-row tests.
-  if (N == 64 && r0 >= y0 && r0 + R <= y0 + hg) {
+  } else {
+    constexpr int R = Lay<S, WC, NT>::R;
+    const int t = ltid<NT>();
+    const int c = 1 + t % N;
+    const int r0 = 1 + R * (t / N);
+    const bool rows_in = !(r0 + R <= y0 || r0 >= y0 + hg);
+    if (!__builtin_amdgcn_ballot_w64(rows_in)) return;  // wave-uniform exit
+    const V* src = in + (r0 - 1) * W + c;
+    V nb[R + 2][3][NV];
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const V m = src[v * plane + j * W];
+        nb[j][1][v] = m;
+        if constexpr (DPP) {
+          nb[j][0][v] = dpp_shift<true>(m);
+          nb[j][2][v] = dpp_shift<false>(m);
+        } else {
+          nb[j][0][v] = src[v * plane + j * W - 1];
+          nb[j][2][v] = src[v * plane + j * W + 1];
+        }
+      }
+    if ((unsigned)(c - x0) >= (unsigned)w) return;
+    V* dst = out + r0 * W + c;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      V o[NV];
-      S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+      if ((unsigned)(r0 + i - y0) < (unsigned)hg) {
+        V o[NV];
+        S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    if ((unsigned)(r0 + i - y0) < (unsigned)hg) {
-      V o[NV];
-      S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+        for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+      }
     }
   }
 }
@@ -382,11 +421,11 @@ __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, cons
 // j * kWaves, j < J (enough for the 8 NV units of a ring and the 4 NV of a
 // bridge), lanes along the run, two positions per lane (runs are at most
 // n + 2 <= 128).
-template <class S, int kThreads>
+template <class S, int kThreads, int P = 2>
 struct Fetch {
   static constexpr int J = (8 * S::NV + kThreads / 64 - 1) / (kThreads / 64);
-  typename S::V val[J][2];
-  int dst[J][2];
+  typename S::V val[J][P];
+  int dst[J][P];
 };
 
 // Window position of element t of ring band `band` (0 top, 1 bottom, 2 left,
@@ -418,18 +457,18 @@ __device__ __forceinline__ int strip_idx(int W, int h, int l, int side, int k, i
   return across * W + l + 1 + t;
 }
 
-template <class S, int kThreads>
-__device__ __forceinline__ void fetch_ring(Fetch<S, kThreads>& f, const Geo& g, int l, const typename S::V* __restrict__ xb,
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_ring(Fetch<S, kThreads, P>& f, const Geo& g, int l, const typename S::V* __restrict__ xb,
                                            const typename S::V* __restrict__ yb, int eTop, int eBot, int eLeft,
                                            int eRight) {
   constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int h = g.h, W = g.W, plane = W * W;
 #pragma unroll
-  for (int j = 0; j < Fetch<S, kThreads>::J; ++j) {
+  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
     const int u = lwave<kThreads>() + j * kWaves;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
     if (u >= 8 * NV) continue;
     const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
     const bool horiz = band < 2;
@@ -446,7 +485,7 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads>& f, const Geo& g, 
     src += rem * len;
     if (len == 0) continue;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
       f.val[j][i] = src[t < len ? t : len - 1];
       int wx, wy;
@@ -463,23 +502,23 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads>& f, const Geo& g, 
 // on the level is set up once: the window index of element t is linear in
 // the level (a0 + l da, from ring_pos), and the run starts at
 // run0 + 2 NV levels_len(l) + rem len(l) in the staged copy.
-template <class S, int kThreads>
+template <class S, int kThreads, int P>
 struct RingPre {
-  static constexpr int J = Fetch<S, kThreads>::J;
-  int a0[J][2];
+  static constexpr int J = Fetch<S, kThreads, P>::J;
+  int a0[J][P];
   int da[J];
   int run0[J];  // -1: no unit for this wave
   int rem[J];
   bool horiz[J];
 };
 
-template <class S, int kThreads>
-__device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads>& r, const Geo& g, int LxH, int LyH) {
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads, P>& r, const Geo& g, int LxH, int LyH) {
   constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int h = g.h, W = g.W, plane = W * W;
 #pragma unroll
-  for (int j = 0; j < RingPre<S, kThreads>::J; ++j) {
+  for (int j = 0; j < RingPre<S, kThreads, P>::J; ++j) {
     const int u = lwave<kThreads>() + j * kWaves;
     r.run0[j] = -1;
     if (u >= 8 * NV) continue;
@@ -489,7 +528,7 @@ __device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads>& r, const Geo
     r.run0[j] = band < 2 ? band * LxH : 2 * LxH + (band - 2) * LyH;
     r.da[j] = band == 0 || band == 2 ? -(W + 1) : (band == 1 ? W - 1 : 1 - W);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < P; ++i) {
       int wx, wy;
       ring_pos(h, 0, band, k, lane_id() + 64 * i, wx, wy);
       r.a0[j][i] = v * plane + wy * W + wx;
@@ -497,19 +536,19 @@ __device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads>& r, const Geo
   }
 }
 
-template <class S, int kThreads>
-__device__ __forceinline__ void fetch_ring_stg(Fetch<S, kThreads>& f, const RingPre<S, kThreads>& r,
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_ring_stg(Fetch<S, kThreads, P>& f, const RingPre<S, kThreads, P>& r,
                                                const typename S::V* __restrict__ stg, int l) {
   constexpr int NV = S::NV;
 #pragma unroll
-  for (int j = 0; j < RingPre<S, kThreads>::J; ++j) {
+  for (int j = 0; j < RingPre<S, kThreads, P>::J; ++j) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
     const int len = r.horiz[j] ? 2 * l + 4 : 2 * l;
     if (r.run0[j] < 0 || len == 0) continue;
     const int off = r.run0[j] + 2 * NV * (r.horiz[j] ? xb_levels_len(l) : yb_levels_len(l)) + r.rem[j] * len;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
       f.val[j][i] = stg[off + (t < len ? t : len - 1)];
       f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
@@ -564,32 +603,32 @@ __device__ __forceinline__ void place_strips_flat(const typename S::V* __restric
   }
 }
 
-template <class S, int kThreads>
-__device__ __forceinline__ void place_fetched(const Fetch<S, kThreads>& f, typename S::V* __restrict__ win) {
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void place_fetched(const Fetch<S, kThreads, P>& f, typename S::V* __restrict__ win) {
 #pragma unroll
-  for (int j = 0; j < Fetch<S, kThreads>::J; ++j)
+  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < P; ++i)
       if (f.dst[j][i] >= 0) win[f.dst[j][i]] = f.val[j][i];
 }
 
-template <class S, int kThreads>
-__device__ __forceinline__ void fetch_strips(Fetch<S, kThreads>& f, bool isx, const Geo& g, int l,
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_strips(Fetch<S, kThreads, P>& f, bool isx, const Geo& g, int l,
                                              const typename S::V* __restrict__ up, int tA, int tB) {
   constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W, len = n - 2 * l;
 #pragma unroll
-  for (int j = 0; j < Fetch<S, kThreads>::J; ++j) {
+  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
     const int u = lwave<kThreads>() + j * kWaves;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
     if (u >= 4 * NV) continue;
     const int side = u / (2 * NV), rem = u - side * 2 * NV, v = rem >> 1, k = rem & 1;
     const int end = isx ? (side ? 2 : 3) : (side ? 0 : 1);
     const typename S::V* src = up + up_end(g, NV, side ? tB : tA, end) + 2 * NV * up_levels_len(n, l) + rem * len;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
       f.val[j][i] = src[t < len ? t : len - 1];
       f.dst[j][i] = t < len ? v * plane + strip_idx(W, h, l, side, k, t) : -1;
@@ -601,22 +640,22 @@ __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads>& f, bool isx, co
 // slot v, row k); the window index of element t is linear in the level
 // (from strip_idx), the run starts at run0 + 2 NV up_levels_len(n, l) +
 // rem (n - 2l).
-template <class S, int kThreads>
+template <class S, int kThreads, int P>
 struct StripPre {
-  static constexpr int J = Fetch<S, kThreads>::J;
-  int a0[J][2];
+  static constexpr int J = Fetch<S, kThreads, P>::J;
+  int a0[J][P];
   int da[J];
   int run0[J];  // -1: no unit for this wave
   int rem[J];
 };
 
-template <class S, int kThreads>
-__device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads>& r, const Geo& g, int LH) {
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads, P>& r, const Geo& g, int LH) {
   constexpr int kWaves = kThreads / 64;
   constexpr int NV = S::NV;
   const int h = g.h, W = g.W, plane = W * W;
 #pragma unroll
-  for (int j = 0; j < StripPre<S, kThreads>::J; ++j) {
+  for (int j = 0; j < StripPre<S, kThreads, P>::J; ++j) {
     const int u = lwave<kThreads>() + j * kWaves;
     r.run0[j] = -1;
     if (u >= 4 * NV) continue;
@@ -625,23 +664,23 @@ __device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads>& r, const G
     r.run0[j] = side * LH;
     r.da[j] = side ? W + 1 : 1 - W;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, lane_id() + 64 * i);
+    for (int i = 0; i < P; ++i) r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, lane_id() + 64 * i);
   }
 }
 
-template <class S, int kThreads>
-__device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads>& f, const StripPre<S, kThreads>& r,
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads, P>& f, const StripPre<S, kThreads, P>& r,
                                                  const typename S::V* __restrict__ stg, int n, int l) {
   constexpr int NV = S::NV;
   const int len = n - 2 * l;
 #pragma unroll
-  for (int j = 0; j < StripPre<S, kThreads>::J; ++j) {
+  for (int j = 0; j < StripPre<S, kThreads, P>::J; ++j) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) f.dst[j][i] = -1;
+    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
     if (r.run0[j] < 0) continue;
     const int off = r.run0[j] + 2 * NV * up_levels_len(n, l) + r.rem[j] * len;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
       f.val[j][i] = stg[off + (t < len ? t : len - 1)];
       f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
@@ -740,31 +779,33 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   // merged between paths, and their loads are waited for only where placed.
   static_assert(STAGED || NT != 64, "one-wave groups stage");
   constexpr bool staged = STAGED;
-  constexpr bool prefetch = Fetch<S, NT>::J <= 2;
+  // Panel runs at window pitches up to 64 fit one position per lane.
+  constexpr int kP = (WC != 0 && WC <= 64) ? 1 : 2;
+  constexpr bool prefetch = Fetch<S, NT, kP>::J * kP <= 16;
   if constexpr (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
     stage_runs<NT, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
     __syncthreads();
   }
-  StripPre<S, NT> pre;
-  if constexpr (staged && prefetch) strip_pre_init<S, NT>(pre, g, LH);
+  StripPre<S, NT, kP> pre;
+  if constexpr (staged && prefetch) strip_pre_init<S, NT, kP>(pre, g, LH);
   // Level l: place the strips of level l, after computing the band of level l
   // (1 <= l <= h-1) from level l-1. The first level only places, the last (H)
   // only computes (a full half cycle has no level h in a bridge); they are
   // peeled off so the loop body tests nothing per level. H >= 1.
-  auto strips_fetch = [&](Fetch<S, NT>& f, int l) {
+  auto strips_fetch = [&](Fetch<S, NT, kP>& f, int l) {
     if constexpr (staged) {
-      if constexpr (prefetch) fetch_strips_stg<S, NT>(f, pre, stg, n, l);
+      if constexpr (prefetch) fetch_strips_stg<S, NT, kP>(f, pre, stg, n, l);
     } else {
-      fetch_strips<S, NT>(f, isx, g, l, up, e, tB);
+      fetch_strips<S, NT, kP>(f, isx, g, l, up, e, tB);
     }
   };
-  auto strips_place = [&](const Fetch<S, NT>& f, V* cur, int l) {
+  auto strips_place = [&](const Fetch<S, NT, kP>& f, V* cur, int l) {
     if constexpr (staged && !prefetch)
       place_strips_flat<S, NT>(stg, cur, g, l, LH);
     else
-      place_fetched<S, NT>(f, cur);
+      place_fetched<S, NT, kP>(f, cur);
   };
   // The x-bridge's window is transposed; a scheme whose step is symmetric in
   // x and y reads it with the plain accessor, so both directions share one
@@ -778,13 +819,13 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   {
     // Declared per level: the prefetched values are not carried round the
     // loop.
-    Fetch<S, NT> f;
+    Fetch<S, NT, kP> f;
     strips_fetch(f, 0);
     strips_place(f, buf0, 0);
     __syncthreads();
   }
   for (int l = 1; l < H; ++l) {
-    Fetch<S, NT> f;
+    Fetch<S, NT, kP> f;
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
     strips_fetch(f, l);
@@ -890,38 +931,40 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   const int tile2 = b2 * g.ntx + a2;
   static_assert(STAGED || NT != 64, "one-wave groups stage");  // as in the bridges
   constexpr bool staged = STAGED;
-  constexpr bool prefetch = Fetch<S, NT>::J <= 2;
+  // Panel runs at window pitches up to 64 fit one position per lane.
+  constexpr int kP = (WC != 0 && WC <= 64) ? 1 : 2;
+  constexpr bool prefetch = Fetch<S, NT, kP>::J * kP <= 16;
   if constexpr (staged) {
     stage_runs<NT, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
                   yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
     __syncthreads();
   }
-  RingPre<S, NT> pre;
-  if constexpr (staged && prefetch) ring_pre_init<S, NT>(pre, g, LxH, LyH);
+  RingPre<S, NT, kP> pre;
+  if constexpr (staged && prefetch) ring_pre_init<S, NT, kP>(pre, g, LxH, LyH);
   // Level l: place the ring of level l, after computing the square of level l
   // (l >= 1) from level l-1. The first level only places, the last (Hd) only
   // computes; they are peeled off so the loop body tests nothing per level.
-  auto ring_fetch = [&](Fetch<S, NT>& f, int l) {
+  auto ring_fetch = [&](Fetch<S, NT, kP>& f, int l) {
     if constexpr (staged) {
-      if constexpr (prefetch) fetch_ring_stg<S, NT>(f, pre, stg, l);
+      if constexpr (prefetch) fetch_ring_stg<S, NT, kP>(f, pre, stg, l);
     } else {
-      fetch_ring<S, NT>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
+      fetch_ring<S, NT, kP>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
     }
   };
-  auto ring_place = [&](const Fetch<S, NT>& f, V* cur, int l) {
+  auto ring_place = [&](const Fetch<S, NT, kP>& f, V* cur, int l) {
     if constexpr (staged && !prefetch)
       place_ring_flat<S, NT>(stg, cur, g, l, LxH, LyH);
     else
-      place_fetched<S, NT>(f, cur);
+      place_fetched<S, NT, kP>(f, cur);
   };
   if (Hd > 0) {
-    Fetch<S, NT> f;
+    Fetch<S, NT, kP> f;
     ring_fetch(f, 0);
     ring_place(f, buf0, 0);
     __syncthreads();
   }
   for (int l = 1; l < Hd; ++l) {
-    Fetch<S, NT> f;  // per level, as in the bridges
+    Fetch<S, NT, kP> f;  // per level, as in the bridges
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
     ring_fetch(f, l);
