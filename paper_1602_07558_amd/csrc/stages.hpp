@@ -816,22 +816,53 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
     else
       compute_level<S, WC, NT, true>(prv, cur, g.W, l + 1, h + 1 - l, n - 2 * l, 2 * l, T0 + l - 1, sp);
   };
-  {
-    // Declared per level: the prefetched values are not carried round the
-    // loop.
-    Fetch<S, NT, kP> f;
-    strips_fetch(f, 0);
-    strips_place(f, buf0, 0);
+  if constexpr (staged) {
+    {
+      // Declared per level: the prefetched values are not carried round the
+      // loop.
+      Fetch<S, NT, kP> f;
+      strips_fetch(f, 0);
+      strips_place(f, buf0, 0);
+      __syncthreads();
+    }
+    for (int l = 1; l < H; ++l) {
+      Fetch<S, NT, kP> f;
+      V* cur = (l & 1) ? buf1 : buf0;
+      const V* prv = (l & 1) ? buf0 : buf1;
+      strips_fetch(f, l);
+      band(prv, cur, l);
+      strips_place(f, cur, l);
+      __syncthreads();
+    }
+  } else {
+    // From HBM, each level's strips are fetched kAhead levels before they
+    // are placed, so their loads have kAhead band passes to arrive: slot
+    // l mod kAhead holds level l, refilled with level l + kAhead once level
+    // l is placed. The loop is unrolled by kAhead so that every slot is a
+    // fixed set of registers. Lookahead is kept to a few registers per slot.
+    constexpr int kAhead = Fetch<S, NT, kP>::J * kP * (int)sizeof(V) <= 32 ? 3 : 1;
+    Fetch<S, NT, kP> f[kAhead];
+#pragma unroll
+    for (int i = 0; i < kAhead; ++i)
+      if (i < H) strips_fetch(f[i], i);
+    strips_place(f[0], buf0, 0);
+    if (kAhead < H) strips_fetch(f[0], kAhead);
     __syncthreads();
-  }
-  for (int l = 1; l < H; ++l) {
-    Fetch<S, NT, kP> f;
-    V* cur = (l & 1) ? buf1 : buf0;
-    const V* prv = (l & 1) ? buf0 : buf1;
-    strips_fetch(f, l);
-    band(prv, cur, l);
-    strips_place(f, cur, l);
-    __syncthreads();
+    for (int l0 = 1; l0 < H; l0 += kAhead) {
+#pragma unroll
+      for (int i = 0; i < kAhead; ++i) {
+        const int l = l0 + i;  // held in slot (1 + i) mod kAhead, as l0 = 1 mod kAhead
+        if (l < H) {
+          Fetch<S, NT, kP>& fl = f[(1 + i) % kAhead];
+          V* cur = (l & 1) ? buf1 : buf0;
+          const V* prv = (l & 1) ? buf0 : buf1;
+          band(prv, cur, l);
+          strips_place(fl, cur, l);
+          if (l + kAhead < H) strips_fetch(fl, l + kAhead);
+          __syncthreads();
+        }
+      }
+    }
   }
   if (H < h) band((H & 1) ? buf0 : buf1, (H & 1) ? buf1 : buf0, H);
   __syncthreads();
