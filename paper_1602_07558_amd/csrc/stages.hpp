@@ -417,13 +417,14 @@ __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, cons
   }
 }
 
-// Per-level panel inputs held in registers (fetch path): unit u = wave +
-// j * kWaves, j < J (enough for the 8 NV units of a ring and the 4 NV of a
-// bridge), lanes along the run, two positions per lane (runs are at most
-// n + 2 <= 128).
-template <class S, int kThreads, int P = 2>
+// Per-level panel inputs held in registers: slot j of a wave covers G units
+// (runs) side by side, 64 / G lanes each, with P positions per lane (runs
+// are at most n + 2 <= 128 long); J slots are enough for the 8 NV units of a
+// ring and the 4 NV of a bridge. The fetch path from HBM uses G = 1: unit
+// u = wave + j * kWaves.
+template <class S, int kThreads, int P = 2, int G = 1>
 struct Fetch {
-  static constexpr int J = (8 * S::NV + kThreads / 64 - 1) / (kThreads / 64);
+  static constexpr int J = ((8 * S::NV + G - 1) / G + kThreads / 64 - 1) / (kThreads / 64);
   typename S::V val[J][P];
   int dst[J][P];
 };
@@ -496,64 +497,72 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads, P>& f, const Geo& 
 }
 
 // Ring prefetch from the staged LDS runs into registers, placed after the
-// level's compute pass so the LDS read latency hides behind it. Unit u =
-// wave + j kWaves is one (band, slot v, row k) run, lanes along it, two
-// positions per lane (t = lane, lane + 64). Everything that does not depend
-// on the level is set up once: the window index of element t is linear in
-// the level (a0 + l da, from ring_pos), and the run starts at
-// run0 + 2 NV levels_len(l) + rem len(l) in the staged copy.
-template <class S, int kThreads, int P>
+// level's compute pass so the LDS read latency hides behind it. Slot j of a
+// wave holds units u = (wave + j kWaves) G + lane / (64 / G), each one
+// (band, slot v, row k) run with its lanes along it (P positions per lane
+// when G = 1). Everything that does not depend on the level is set up once
+// per lane: the window index of element t is linear in the level
+// (a0 + l da, from ring_pos), and its staged offset,
+// run0 + 2 NV levels_len(l) + rem len(l) + t, is a0s + l bs + 2 NV l^2
+// (levels_len(l) = l^2 + 3l and len = 2l + 4 across the tile, l^2 - l and 2l
+// down it). Element t exists at level l when t - (len(l) - 2l) < 2l.
+template <class S, int kThreads, int P, int G>
 struct RingPre {
-  static constexpr int J = Fetch<S, kThreads, P>::J;
+  static constexpr int J = Fetch<S, kThreads, P, G>::J;
   int a0[J][P];
+  int a0s[J][P];  // G > 1
+  int c0[J][P];   // G > 1: t - (len(l) - 2l); large for lanes without a unit
+  int s0[J];      // G = 1 (one unit per wave slot): a0s - t
+  int cz[J];      // G = 1: len(l) - 2l; large for waves without a unit
   int da[J];
-  int run0[J];  // -1: no unit for this wave
-  int rem[J];
-  bool horiz[J];
+  int bs[J];
 };
 
-template <class S, int kThreads, int P>
-__device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads, P>& r, const Geo& g, int LxH, int LyH) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int NV = S::NV;
+template <class S, int kThreads, int P, int G>
+__device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads, P, G>& r, const Geo& g, int LxH, int LyH) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV, LG = 64 / G;
   const int h = g.h, W = g.W, plane = W * W;
+  const int sub = G > 1 ? lane_id() / LG : 0, t0 = lane_id() - sub * LG;
 #pragma unroll
-  for (int j = 0; j < RingPre<S, kThreads, P>::J; ++j) {
-    const int u = lwave<kThreads>() + j * kWaves;
-    r.run0[j] = -1;
-    if (u >= 8 * NV) continue;
-    const int band = u / (2 * NV), rem = u - band * 2 * NV, v = rem >> 1, k = rem & 1;
-    r.horiz[j] = band < 2;
-    r.rem[j] = rem;
-    r.run0[j] = band < 2 ? band * LxH : 2 * LxH + (band - 2) * LyH;
+  for (int j = 0; j < RingPre<S, kThreads, P, G>::J; ++j) {
+    const int u = (lwave<kThreads>() + j * kWaves) * G + sub;
+    const bool has = sub < G && u < 8 * NV;
+    const int uu = has ? u : 0;
+    const int band = uu / (2 * NV), rem = uu - band * 2 * NV, v = rem >> 1, k = rem & 1;
+    const bool horiz = band < 2;
+    const int run0 = horiz ? band * LxH : 2 * LxH + (band - 2) * LyH;
     r.da[j] = band == 0 || band == 2 ? -(W + 1) : (band == 1 ? W - 1 : 1 - W);
+    r.bs[j] = horiz ? 2 * rem + 6 * NV : 2 * rem - 2 * NV;
+    r.s0[j] = run0 + (horiz ? 4 * rem : 0);
+    r.cz[j] = has ? (horiz ? 4 : 0) : -(1 << 28);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
+      const int t = t0 + 64 * i;
       int wx, wy;
-      ring_pos(h, 0, band, k, lane_id() + 64 * i, wx, wy);
+      ring_pos(h, 0, band, k, t, wx, wy);
       r.a0[j][i] = v * plane + wy * W + wx;
+      r.a0s[j][i] = r.s0[j] + t;
+      r.c0[j][i] = has ? t - (horiz ? 4 : 0) : (1 << 28);
     }
   }
 }
 
-template <class S, int kThreads, int P>
-__device__ __forceinline__ void fetch_ring_stg(Fetch<S, kThreads, P>& f, const RingPre<S, kThreads, P>& r,
+template <class S, int kThreads, int P, int G>
+__device__ __forceinline__ void fetch_ring_stg(Fetch<S, kThreads, P, G>& f, const RingPre<S, kThreads, P, G>& r,
                                                const typename S::V* __restrict__ stg, int l) {
   constexpr int NV = S::NV;
+  const int sq = 2 * NV * l * l;
 #pragma unroll
-  for (int j = 0; j < RingPre<S, kThreads, P>::J; ++j) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
-    const int len = r.horiz[j] ? 2 * l + 4 : 2 * l;
-    if (r.run0[j] < 0 || len == 0) continue;
-    const int off = r.run0[j] + 2 * NV * (r.horiz[j] ? xb_levels_len(l) : yb_levels_len(l)) + r.rem[j] * len;
+  for (int j = 0; j < RingPre<S, kThreads, P, G>::J; ++j)
 #pragma unroll
     for (int i = 0; i < P; ++i) {
+      // With one unit per slot the run's terms are wave-uniform (scalar).
       const int t = lane_id() + 64 * i;
-      f.val[j][i] = stg[off + (t < len ? t : len - 1)];
-      f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
+      const bool ok = G == 1 ? t < 2 * l + r.cz[j] : r.c0[j][i] < 2 * l;
+      const int off = G == 1 ? r.s0[j] + l * r.bs[j] + sq + t : r.a0s[j][i] + l * r.bs[j] + sq;
+      f.val[j][i] = stg[ok ? off : 0];
+      f.dst[j][i] = ok ? r.a0[j][i] + l * r.da[j] : -1;
     }
-  }
 }
 
 // Ring of level l straight from the staged LDS runs into the window, all
@@ -603,10 +612,10 @@ __device__ __forceinline__ void place_strips_flat(const typename S::V* __restric
   }
 }
 
-template <class S, int kThreads, int P>
-__device__ __forceinline__ void place_fetched(const Fetch<S, kThreads, P>& f, typename S::V* __restrict__ win) {
+template <class S, int kThreads, int P, int G>
+__device__ __forceinline__ void place_fetched(const Fetch<S, kThreads, P, G>& f, typename S::V* __restrict__ win) {
 #pragma unroll
-  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j)
+  for (int j = 0; j < Fetch<S, kThreads, P, G>::J; ++j)
 #pragma unroll
     for (int i = 0; i < P; ++i)
       if (f.dst[j][i] >= 0) win[f.dst[j][i]] = f.val[j][i];
@@ -638,54 +647,62 @@ __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads, P>& f, bool isx,
 
 // Strip prefetch from the staged LDS runs (as RingPre): unit u = (side,
 // slot v, row k); the window index of element t is linear in the level
-// (from strip_idx), the run starts at run0 + 2 NV up_levels_len(n, l) +
-// rem (n - 2l).
-template <class S, int kThreads, int P>
+// (from strip_idx), its staged offset
+// run0 + 2 NV up_levels_len(n, l) + rem (n - 2l) + t, with
+// up_levels_len(n, l) = l (n + 1 - l), is a0s + l bs - 2 NV l^2, and it
+// exists at level l when 2l < n - t.
+template <class S, int kThreads, int P, int G>
 struct StripPre {
-  static constexpr int J = Fetch<S, kThreads, P>::J;
+  static constexpr int J = Fetch<S, kThreads, P, G>::J;
   int a0[J][P];
+  int a0s[J][P];  // G > 1
+  int lim[J][P];  // G > 1: n - t; negative for lanes without a unit
+  int s0[J];      // G = 1 (one unit per wave slot): a0s - t
+  int lz[J];      // G = 1: n; negative for waves without a unit
   int da[J];
-  int run0[J];  // -1: no unit for this wave
-  int rem[J];
+  int bs[J];
 };
 
-template <class S, int kThreads, int P>
-__device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads, P>& r, const Geo& g, int LH) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int NV = S::NV;
-  const int h = g.h, W = g.W, plane = W * W;
+template <class S, int kThreads, int P, int G>
+__device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads, P, G>& r, const Geo& g, int LH) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV, LG = 64 / G;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W;
+  const int sub = G > 1 ? lane_id() / LG : 0, t0 = lane_id() - sub * LG;
 #pragma unroll
-  for (int j = 0; j < StripPre<S, kThreads, P>::J; ++j) {
-    const int u = lwave<kThreads>() + j * kWaves;
-    r.run0[j] = -1;
-    if (u >= 4 * NV) continue;
-    const int side = u / (2 * NV), rem = u - side * 2 * NV, v = rem >> 1, k = rem & 1;
-    r.rem[j] = rem;
-    r.run0[j] = side * LH;
+  for (int j = 0; j < StripPre<S, kThreads, P, G>::J; ++j) {
+    const int u = (lwave<kThreads>() + j * kWaves) * G + sub;
+    const bool has = sub < G && u < 4 * NV;
+    const int uu = has ? u : 0;
+    const int side = uu / (2 * NV), rem = uu - side * 2 * NV, v = rem >> 1, k = rem & 1;
     r.da[j] = side ? W + 1 : 1 - W;
+    r.bs[j] = 2 * NV * (n + 1) - 2 * rem;
+    r.s0[j] = side * LH + rem * n;
+    r.lz[j] = has ? n : -(1 << 28);
 #pragma unroll
-    for (int i = 0; i < P; ++i) r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, lane_id() + 64 * i);
+    for (int i = 0; i < P; ++i) {
+      const int t = t0 + 64 * i;
+      r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, t);
+      r.a0s[j][i] = r.s0[j] + t;
+      r.lim[j][i] = has ? n - t : -1;
+    }
   }
 }
 
-template <class S, int kThreads, int P>
-__device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads, P>& f, const StripPre<S, kThreads, P>& r,
-                                                 const typename S::V* __restrict__ stg, int n, int l) {
+template <class S, int kThreads, int P, int G>
+__device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads, P, G>& f, const StripPre<S, kThreads, P, G>& r,
+                                                 const typename S::V* __restrict__ stg, int l) {
   constexpr int NV = S::NV;
-  const int len = n - 2 * l;
+  const int sq = 2 * NV * l * l;
 #pragma unroll
-  for (int j = 0; j < StripPre<S, kThreads, P>::J; ++j) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
-    if (r.run0[j] < 0) continue;
-    const int off = r.run0[j] + 2 * NV * up_levels_len(n, l) + r.rem[j] * len;
+  for (int j = 0; j < StripPre<S, kThreads, P, G>::J; ++j)
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
-      f.val[j][i] = stg[off + (t < len ? t : len - 1)];
-      f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
+      const bool ok = G == 1 ? t < r.lz[j] - 2 * l : 2 * l < r.lim[j][i];
+      const int off = G == 1 ? r.s0[j] + l * r.bs[j] - sq + t : r.a0s[j][i] + l * r.bs[j] - sq;
+      f.val[j][i] = stg[ok ? off : 0];
+      f.dst[j][i] = ok ? r.a0[j][i] + l * r.da[j] : -1;
     }
-  }
 }
 
 // All bridge panels of levels 0..H-1 (Alg. 2-3), written at the end of the
@@ -779,33 +796,37 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   // merged between paths, and their loads are waited for only where placed.
   static_assert(STAGED || NT != 64, "one-wave groups stage");
   constexpr bool staged = STAGED;
-  // Panel runs at window pitches up to 64 fit one position per lane.
-  constexpr int kP = (WC != 0 && WC <= 64) ? 1 : 2;
-  constexpr bool prefetch = Fetch<S, NT, kP>::J * kP <= 16;
+  // Staged strips are at most n long: one position per lane up to n = 64,
+  // and 64 / n runs side by side in one slot for n <= 32. From HBM, runs at
+  // window pitches up to 64 take one position per lane.
+  constexpr int kP = staged ? ((WC != 0 && WC <= 66) ? 1 : 2) : ((WC != 0 && WC <= 64) ? 1 : 2);
+  constexpr int kG = (staged && WC != 0 && WC - 2 <= 32) ? 64 / (WC - 2) : 1;
+  using F = Fetch<S, NT, kP, kG>;
+  constexpr bool prefetch = F::J * kP <= 16;
   if constexpr (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
     stage_runs<NT, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
     __syncthreads();
   }
-  StripPre<S, NT, kP> pre;
-  if constexpr (staged && prefetch) strip_pre_init<S, NT, kP>(pre, g, LH);
+  StripPre<S, NT, kP, kG> pre;
+  if constexpr (staged && prefetch) strip_pre_init<S, NT, kP, kG>(pre, g, LH);
   // Level l: place the strips of level l, after computing the band of level l
   // (1 <= l <= h-1) from level l-1. The first level only places, the last (H)
   // only computes (a full half cycle has no level h in a bridge); they are
   // peeled off so the loop body tests nothing per level. H >= 1.
-  auto strips_fetch = [&](Fetch<S, NT, kP>& f, int l) {
+  auto strips_fetch = [&](F& f, int l) {
     if constexpr (staged) {
-      if constexpr (prefetch) fetch_strips_stg<S, NT, kP>(f, pre, stg, n, l);
+      if constexpr (prefetch) fetch_strips_stg<S, NT, kP, kG>(f, pre, stg, l);
     } else {
       fetch_strips<S, NT, kP>(f, isx, g, l, up, e, tB);
     }
   };
-  auto strips_place = [&](const Fetch<S, NT, kP>& f, V* cur, int l) {
+  auto strips_place = [&](const F& f, V* cur, int l) {
     if constexpr (staged && !prefetch)
       place_strips_flat<S, NT>(stg, cur, g, l, LH);
     else
-      place_fetched<S, NT, kP>(f, cur);
+      place_fetched(f, cur);
   };
   // The x-bridge's window is transposed; a scheme whose step is symmetric in
   // x and y reads it with the plain accessor, so both directions share one
@@ -820,13 +841,13 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
     {
       // Declared per level: the prefetched values are not carried round the
       // loop.
-      Fetch<S, NT, kP> f;
+      F f;
       strips_fetch(f, 0);
       strips_place(f, buf0, 0);
       __syncthreads();
     }
     for (int l = 1; l < H; ++l) {
-      Fetch<S, NT, kP> f;
+      F f;
       V* cur = (l & 1) ? buf1 : buf0;
       const V* prv = (l & 1) ? buf0 : buf1;
       strips_fetch(f, l);
@@ -840,8 +861,8 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
     // l mod kAhead holds level l, refilled with level l + kAhead once level
     // l is placed. The loop is unrolled by kAhead so that every slot is a
     // fixed set of registers. Lookahead is kept to a few registers per slot.
-    constexpr int kAhead = Fetch<S, NT, kP>::J * kP * (int)sizeof(V) <= 32 ? 3 : 1;
-    Fetch<S, NT, kP> f[kAhead];
+    constexpr int kAhead = F::J * kP * (int)sizeof(V) <= 32 ? 3 : 1;
+    F f[kAhead];
 #pragma unroll
     for (int i = 0; i < kAhead; ++i)
       if (i < H) strips_fetch(f[i], i);
@@ -853,7 +874,7 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
       for (int i = 0; i < kAhead; ++i) {
         const int l = l0 + i;  // held in slot (1 + i) mod kAhead, as l0 = 1 mod kAhead
         if (l < H) {
-          Fetch<S, NT, kP>& fl = f[(1 + i) % kAhead];
+          F& fl = f[(1 + i) % kAhead];
           V* cur = (l & 1) ? buf1 : buf0;
           const V* prv = (l & 1) ? buf0 : buf1;
           band(prv, cur, l);
@@ -962,40 +983,44 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   const int tile2 = b2 * g.ntx + a2;
   static_assert(STAGED || NT != 64, "one-wave groups stage");  // as in the bridges
   constexpr bool staged = STAGED;
-  // Panel runs at window pitches up to 64 fit one position per lane.
+  // Ring runs are at most n + 2 long: at window pitches up to 64 they take
+  // one position per lane, and up to 32, 64 / (n + 2) of them lie side by
+  // side in one staged slot.
   constexpr int kP = (WC != 0 && WC <= 64) ? 1 : 2;
-  constexpr bool prefetch = Fetch<S, NT, kP>::J * kP <= 16;
+  constexpr int kG = (staged && WC != 0 && WC <= 32) ? 64 / WC : 1;
+  using F = Fetch<S, NT, kP, kG>;
+  constexpr bool prefetch = F::J * kP <= 16;
   if constexpr (staged) {
     stage_runs<NT, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
                   yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
     __syncthreads();
   }
-  RingPre<S, NT, kP> pre;
-  if constexpr (staged && prefetch) ring_pre_init<S, NT, kP>(pre, g, LxH, LyH);
+  RingPre<S, NT, kP, kG> pre;
+  if constexpr (staged && prefetch) ring_pre_init<S, NT, kP, kG>(pre, g, LxH, LyH);
   // Level l: place the ring of level l, after computing the square of level l
   // (l >= 1) from level l-1. The first level only places, the last (Hd) only
   // computes; they are peeled off so the loop body tests nothing per level.
-  auto ring_fetch = [&](Fetch<S, NT, kP>& f, int l) {
+  auto ring_fetch = [&](F& f, int l) {
     if constexpr (staged) {
-      if constexpr (prefetch) fetch_ring_stg<S, NT, kP>(f, pre, stg, l);
+      if constexpr (prefetch) fetch_ring_stg<S, NT, kP, kG>(f, pre, stg, l);
     } else {
       fetch_ring<S, NT, kP>(f, g, l, xb, yb, eTop, eBot, eLeft, eRight);
     }
   };
-  auto ring_place = [&](const Fetch<S, NT, kP>& f, V* cur, int l) {
+  auto ring_place = [&](const F& f, V* cur, int l) {
     if constexpr (staged && !prefetch)
       place_ring_flat<S, NT>(stg, cur, g, l, LxH, LyH);
     else
-      place_fetched<S, NT, kP>(f, cur);
+      place_fetched(f, cur);
   };
   if (Hd > 0) {
-    Fetch<S, NT, kP> f;
+    F f;
     ring_fetch(f, 0);
     ring_place(f, buf0, 0);
     __syncthreads();
   }
   for (int l = 1; l < Hd; ++l) {
-    Fetch<S, NT, kP> f;  // per level, as in the bridges
+    F f;  // per level, as in the bridges
     V* cur = (l & 1) ? buf1 : buf0;
     const V* prv = (l & 1) ? buf0 : buf1;
     ring_fetch(f, l);
