@@ -360,38 +360,73 @@ __device__ void write_rect(const typename S::V* __restrict__ win, typename S::V*
   }
 }
 
-// All upward-pyramid panels of levels 0..H-1 (Alg. 1), written at the end
-// of the pyramid: strip k of side `end` at level l is the row / column at
-// distance l + k from the tile edge, read from buffer (b0 + l) mod 2 where
-// the level's band survives. Unit u = (l, end, v, k) per wave, lanes along
-// the strip.
-template <class S, int kThreads>
-__device__ void emit_up_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1, int b0,
-                            typename S::V* __restrict__ up, const Geo& g, int tile, int H) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int NV = S::NV;
-  const int n = g.n, W = g.W, plane = W * W;
-  const int per = 8 * NV;
-  for (int u = lwave<kThreads>(); u < per * H; u += kWaves) {
-    const int l = u / per, r8 = u - l * per;
-    const int end = r8 / (2 * NV), rem = r8 - end * 2 * NV;  // rem = 2 v + k
-    const int v = rem >> 1, k = rem & 1;
-    const int len = n - 2 * l;
-    const typename S::V* win = ((b0 + l) & 1) ? buf1 : buf0;
-    typename S::V* dst = up + up_end(g, NV, tile, end) + (size_t)2 * NV * up_levels_len(n, l) + (size_t)rem * len;
-    int wx0, wy0, dx, dy;  // window position of t = 0 and step along the strip
+// Panel strips of one level on their way from LDS to HBM, read before a
+// level's compute pass and stored after it, so that the stores of all
+// levels spread over the kernel instead of leaving in one burst at its end
+// (when every workgroup would write at once). Unit u = w + j kWaves with w
+// counted from the last wave (the first to fall idle as a pyramid shrinks),
+// lanes along the strip, P positions per lane.
+template <class S, int kThreads, int P, int UNITS>
+struct EmitSlot {
+  static constexpr int J = (UNITS + kThreads / 64 - 1) / (kThreads / 64);
+  typename S::V val[J][P];
+  typename S::V* dst[J];
+  int len[J];
+};
+
+// Schemes with few values per point read a level's panels before its
+// compute pass (the LDS latency hides behind it); the others read them
+// after it, which keeps the panel registers free during the compute.
+template <class S>
+constexpr bool emit_early() {
+  return S::NV * (int)sizeof(typename S::V) <= 16;
+}
+
+template <class S, int kThreads, int P, int UNITS>
+__device__ __forceinline__ void emit_write(const EmitSlot<S, kThreads, P, UNITS>& e) {
+#pragma unroll
+  for (int j = 0; j < EmitSlot<S, kThreads, P, UNITS>::J; ++j)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      if (t < e.len[j]) e.dst[j][t] = e.val[j][i];
+    }
+}
+
+// Upward-pyramid panel strips of level l (Alg. 1) from `win`, the buffer
+// where level l's band survives: strip k of side `end` is the row (ends 0,
+// 1) or column (ends 2, 3) at distance l + k from the tile edge, n - 2l long.
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void up_strips_read(EmitSlot<S, kThreads, P, 8 * S::NV>& e,
+                                               const typename S::V* __restrict__ win, typename S::V* __restrict__ up,
+                                               const Geo& g, int tile, int l) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV, per = 8 * NV;
+  const int n = g.n, W = g.W, plane = W * W, len = n - 2 * l;
+  const int w = kWaves - 1 - lwave<kThreads>();
+#pragma unroll
+  for (int j = 0; j < EmitSlot<S, kThreads, P, per>::J; ++j) {
+    const int u = w + j * kWaves;
+    e.len[j] = 0;
+    if (u >= per) continue;
+    const int end = u / (2 * NV), rem = u - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    e.len[j] = len;
+    e.dst[j] = up + up_end(g, NV, tile, end) + (size_t)2 * NV * up_levels_len(n, l) + (size_t)rem * len;
+    int wx0, wy0, stride;  // window position of t = 0 and step along the strip
     if (end == 0) {
-      wx0 = l + 1, wy0 = l + 1 + k, dx = 1, dy = 0;
+      wx0 = l + 1, wy0 = l + 1 + k, stride = 1;
     } else if (end == 1) {
-      wx0 = l + 1, wy0 = n - l - k, dx = 1, dy = 0;
+      wx0 = l + 1, wy0 = n - l - k, stride = 1;
     } else if (end == 2) {
-      wx0 = l + 1 + k, wy0 = l + 1, dx = 0, dy = 1;
+      wx0 = l + 1 + k, wy0 = l + 1, stride = W;
     } else {
-      wx0 = n - l - k, wy0 = l + 1, dx = 0, dy = 1;
+      wx0 = n - l - k, wy0 = l + 1, stride = W;
     }
     const typename S::V* src = win + v * plane + wy0 * W + wx0;
-    const int stride = dy * W + dx;
-    for (int t = lane_id(); t < len; t += 64) dst[t] = src[t * stride];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      e.val[j][i] = src[(t < len ? t : 0) * stride];
+    }
   }
 }
 
@@ -404,13 +439,25 @@ __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, cons
                           long long T0, int H, typename S::V* state, typename S::V* up, const SchemeParams& sp) {
   const int n = g.n, h = g.h;
   const int top = H < h - 1 ? H : h - 1;
+  // Strips are at most n long: one position per lane up to n = 64.
+  constexpr int kP = (WC != 0 && WC <= 66) ? 1 : 2;
+  using E = EmitSlot<S, NT, kP, 8 * S::NV>;
+  // Level l's pass also emits the panel strips of level l-1.
   for (int l = 1; l <= top; ++l) {
     typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
     const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
+    E es;
+    if constexpr (emit_early<S>()) up_strips_read<S, NT, kP>(es, prv, up, g, tile, l - 1);
     compute_level<S, WC, NT>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
+    if constexpr (!emit_early<S>()) up_strips_read<S, NT, kP>(es, prv, up, g, tile, l - 1);
+    emit_write(es);
     __syncthreads();
   }
-  emit_up_all<S, NT>(buf0, buf1, b0, up, g, tile, H);
+  for (int l = top; l < H; ++l) {  // the last emitted level (level h-1 of a full half cycle)
+    E es;
+    up_strips_read<S, NT, kP>(es, ((b0 + l) & 1) ? buf1 : buf0, up, g, tile, l);
+    emit_write(es);
+  }
   if (H < h) {
     const typename S::V* fin = ((b0 + H) & 1) ? buf1 : buf0;
     write_rect<S, NT>(fin, state, g, x0 - 1, y0 - 1, H + 1, H + 1, n - 2 * H, n - 2 * H);
@@ -541,8 +588,10 @@ __device__ __forceinline__ void ring_pre_init(RingPre<S, kThreads, P, G>& r, con
       int wx, wy;
       ring_pos(h, 0, band, k, t, wx, wy);
       r.a0[j][i] = v * plane + wy * W + wx;
-      r.a0s[j][i] = r.s0[j] + t;
-      r.c0[j][i] = has ? t - (horiz ? 4 : 0) : (1 << 28);
+      if constexpr (G > 1) {
+        r.a0s[j][i] = r.s0[j] + t;
+        r.c0[j][i] = has ? t - (horiz ? 4 : 0) : (1 << 28);
+      }
     }
   }
 }
@@ -682,8 +731,10 @@ __device__ __forceinline__ void strip_pre_init(StripPre<S, kThreads, P, G>& r, c
     for (int i = 0; i < P; ++i) {
       const int t = t0 + 64 * i;
       r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, t);
-      r.a0s[j][i] = r.s0[j] + t;
-      r.lim[j][i] = has ? n - t : -1;
+      if constexpr (G > 1) {
+        r.a0s[j][i] = r.s0[j] + t;
+        r.lim[j][i] = has ? n - t : -1;
+      }
     }
   }
 }
@@ -705,31 +756,39 @@ __device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads, P, G>& f, co
     }
 }
 
-// All bridge panels of levels 0..H-1 (Alg. 2-3), written at the end of the
-// bridge from the buffers where each level's bands survive. x-bridge: rows
-// y = l+1+k (N end) and n-l-k (S end), x = h-l-1 .. h+l+2 (the band and the
-// pyramid corners placed beside it), which in its transposed window are
-// columns. y-bridge: columns x = l+1+k (W end) and n-l-k (E end), rows
-// y = h+1-l .. h+l. Both are window columns read down the rows.
-template <class S, int kThreads>
-__device__ void emit_bridge_all(const typename S::V* __restrict__ buf0, const typename S::V* __restrict__ buf1,
-                                typename S::V* __restrict__ out, bool isx, const Geo& g, int e, int H) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int NV = S::NV;
+// Bridge panels of level l (Alg. 2-3) from `win`, the buffer where level
+// l's band survives (as up_strips_read). x-bridge: rows y = l+1+k (N end)
+// and n-l-k (S end), x = h-l-1 .. h+l+2 (the band and the pyramid corners
+// placed beside it), which in its transposed window are columns. y-bridge:
+// columns x = l+1+k (W end) and n-l-k (E end), rows y = h+1-l .. h+l. Both
+// are window columns read down the rows.
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void bridge_ends_read(EmitSlot<S, kThreads, P, 4 * S::NV>& es,
+                                                 const typename S::V* __restrict__ win,
+                                                 typename S::V* __restrict__ out, bool isx, const Geo& g, int e,
+                                                 int l) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV, per = 4 * NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W;
-  const int per = 4 * NV;
-  for (int u = lwave<kThreads>(); u < per * H; u += kWaves) {
-    const int l = u / per, r4 = u - l * per;
-    const int end = r4 / (2 * NV), rem = r4 - end * 2 * NV, v = rem >> 1, k = rem & 1;
-    const int len = isx ? 2 * l + 4 : 2 * l;
-    const typename S::V* win = (l & 1) ? buf1 : buf0;
-    typename S::V* dst = out +
-                         (isx ? xb_end(g, NV, e, end) + 2 * NV * xb_levels_len(l)
-                              : yb_end(g, NV, e, end) + 2 * NV * yb_levels_len(l)) +
-                         (size_t)rem * len;
+  const int len = isx ? 2 * l + 4 : 2 * l;
+  const int w = kWaves - 1 - lwave<kThreads>();
+#pragma unroll
+  for (int j = 0; j < EmitSlot<S, kThreads, P, per>::J; ++j) {
+    const int u = w + j * kWaves;
+    es.len[j] = 0;
+    if (u >= per || len == 0) continue;
+    const int end = u / (2 * NV), rem = u - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    es.len[j] = len;
+    es.dst[j] = out +
+                (isx ? xb_end(g, NV, e, end) + 2 * NV * xb_levels_len(l)
+                     : yb_end(g, NV, e, end) + 2 * NV * yb_levels_len(l)) +
+                (size_t)rem * len;
     const int across = end ? (n - l - k) : (l + 1 + k);
     const typename S::V* src = win + v * plane + (isx ? h - l - 1 : h + 1 - l) * W + across;
-    for (int t = lane_id(); t < len; t += 64) dst[t] = src[t * W];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      es.val[j][i] = src[(t < len ? t : 0) * W];
+    }
   }
 }
 
@@ -803,6 +862,10 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   constexpr int kG = (staged && WC != 0 && WC - 2 <= 32) ? 64 / (WC - 2) : 1;
   using F = Fetch<S, NT, kP, kG>;
   constexpr bool prefetch = F::J * kP <= 16;
+  // Level l's pass also emits the panels of level l-1; they are at most
+  // n + 2 long (the x-bridge's), one position per lane up to n = 62.
+  constexpr int kPe = (WC != 0 && WC <= 64) ? 1 : 2;
+  using E = EmitSlot<S, NT, kPe, 4 * NV>;
   if constexpr (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
@@ -848,11 +911,15 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
     }
     for (int l = 1; l < H; ++l) {
       F f;
+      E es;
       V* cur = (l & 1) ? buf1 : buf0;
       const V* prv = (l & 1) ? buf0 : buf1;
+      if constexpr (emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
       strips_fetch(f, l);
       band(prv, cur, l);
       strips_place(f, cur, l);
+      if constexpr (!emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
+      emit_write(es);
       __syncthreads();
     }
   } else {
@@ -875,19 +942,28 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
         const int l = l0 + i;  // held in slot (1 + i) mod kAhead, as l0 = 1 mod kAhead
         if (l < H) {
           F& fl = f[(1 + i) % kAhead];
+          E es;
           V* cur = (l & 1) ? buf1 : buf0;
           const V* prv = (l & 1) ? buf0 : buf1;
+          if constexpr (emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
           band(prv, cur, l);
           strips_place(fl, cur, l);
           if (l + kAhead < H) strips_fetch(fl, l + kAhead);
+          if constexpr (!emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
+          emit_write(es);
           __syncthreads();
         }
       }
     }
   }
-  if (H < h) band((H & 1) ? buf0 : buf1, (H & 1) ? buf1 : buf0, H);
+  {
+    // The last emitted level, H - 1, beside the band of level H when H < h.
+    E es;
+    bridge_ends_read<S, NT, kPe>(es, (H & 1) ? buf0 : buf1, out, isx, g, e, H - 1);
+    if (H < h) band((H & 1) ? buf0 : buf1, (H & 1) ? buf1 : buf0, H);
+    emit_write(es);
+  }
   __syncthreads();
-  emit_bridge_all<S, NT>(buf0, buf1, out, isx, g, e, H);
   if (H < h) {
     const V* fin = (H & 1) ? buf1 : buf0;
     if (isx)
