@@ -18,10 +18,12 @@
 // panel strip is the two-wide boundary band of its rectangle; with double
 // buffering, the band of level l stays untouched in buffer l mod 2 for the
 // rest of the component (later levels of that parity lie strictly inside it),
-// so each kernel writes all its panel levels in one coalesced burst at its
-// end instead of once per level. A consumer either copies all its panel
-// levels into LDS at its start, with every load in flight at once (staged),
-// or fetches level l+1 into registers before it computes level l.
+// so the strips of level l can be stored while level l+1 is computed: the
+// panel stores of a kernel spread over its whole run rather than leaving in
+// one burst at its end, when every workgroup would write at once. A consumer
+// either copies all its panel levels into LDS at its start, with every load
+// in flight at once (staged), or fetches each level into registers a few
+// levels before it places it.
 //
 // The plain kernel advances every point by one sub-step, reading its 3x3
 // neighbourhood from HBM (rows kept in registers as a thread walks down a
