@@ -395,11 +395,69 @@ __device__ __forceinline__ void emit_write(const EmitSlot<S, kThreads, P, UNITS>
     }
 }
 
-// Upward-pyramid panel strips of level l (Alg. 1) from `win`, the buffer
-// where level l's band survives: strip k of side `end` is the row (ends 0,
-// 1) or column (ends 2, 3) at distance l + k from the tile edge, n - 2l long.
+// Upward-pyramid panel strips of level l (Alg. 1): strip k of side `end`
+// is the row (ends 0, 1) or column (ends 2, 3) at distance l + k from the
+// tile edge, n - 2l long, read from the buffer where level l's band
+// survives. A wave's units are fixed, so everything but the level is set up
+// once: the strip's panel offset, 2 NV up_levels_len(n, l) + rem (n - 2l),
+// is d0 + l d1 - 2 NV l^2, and its window start is s0 + l ds.
+template <class S, int kThreads>
+struct UpEmitPre {
+  static constexpr int J = EmitSlot<S, kThreads, 1, 8 * S::NV>::J;
+  typename S::V* base[J];  // panel of the unit's side and slot row, null: no unit
+  int d1[J], s0[J], ds[J], stride[J];
+};
+
+template <class S, int kThreads>
+__device__ __forceinline__ void up_emit_init(UpEmitPre<S, kThreads>& r, typename S::V* __restrict__ up,
+                                             const Geo& g, int tile) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV, per = 8 * NV;
+  const int n = g.n, W = g.W, plane = W * W;
+  const int w = kWaves - 1 - lwave<kThreads>();
+#pragma unroll
+  for (int j = 0; j < UpEmitPre<S, kThreads>::J; ++j) {
+    const int u = w + j * kWaves;
+    const int uu = u < per ? u : 0;
+    const int end = uu / (2 * NV), rem = uu - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    r.base[j] = u < per ? up + up_end(g, NV, tile, end) + rem * n : nullptr;
+    r.d1[j] = 2 * NV * (n + 1) - 2 * rem;
+    if (end == 0) {  // row l+1+k from column l+1
+      r.s0[j] = (1 + k) * W + 1, r.ds[j] = W + 1, r.stride[j] = 1;
+    } else if (end == 1) {  // row n-l-k from column l+1
+      r.s0[j] = (n - k) * W + 1, r.ds[j] = 1 - W, r.stride[j] = 1;
+    } else if (end == 2) {  // column l+1+k from row l+1
+      r.s0[j] = W + 1 + k, r.ds[j] = W + 1, r.stride[j] = W;
+    } else {  // column n-l-k from row l+1
+      r.s0[j] = W + n - k, r.ds[j] = W - 1, r.stride[j] = W;
+    }
+    r.s0[j] += v * plane;
+  }
+}
+
 template <class S, int kThreads, int P>
-__device__ __forceinline__ void up_strips_read(EmitSlot<S, kThreads, P, 8 * S::NV>& e,
+__device__ __forceinline__ void up_strips_read(EmitSlot<S, kThreads, P, 8 * S::NV>& e, const UpEmitPre<S, kThreads>& r,
+                                               const typename S::V* __restrict__ win, const Geo& g, int l) {
+  constexpr int NV = S::NV;
+  const int len = g.n - 2 * l;
+#pragma unroll
+  for (int j = 0; j < EmitSlot<S, kThreads, P, 8 * NV>::J; ++j) {
+    e.len[j] = 0;
+    if (r.base[j] == nullptr) continue;
+    e.len[j] = len;
+    e.dst[j] = r.base[j] + (l * r.d1[j] - 2 * NV * l * l);
+    const typename S::V* src = win + r.s0[j] + l * r.ds[j];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      e.val[j][i] = src[(t < len ? t : 0) * r.stride[j]];
+    }
+  }
+}
+
+// The same strips with every term worked out at each level (groups of few
+// waves, whose many units per wave would not fit precomputed in registers).
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void up_strips_read_direct(EmitSlot<S, kThreads, P, 8 * S::NV>& e,
                                                const typename S::V* __restrict__ win, typename S::V* __restrict__ up,
                                                const Geo& g, int tile, int l) {
   constexpr int kWaves = kThreads / 64, NV = S::NV, per = 8 * NV;
@@ -444,20 +502,31 @@ __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, cons
   // Strips are at most n long: one position per lane up to n = 64.
   constexpr int kP = (WC != 0 && WC <= 66) ? 1 : 2;
   using E = EmitSlot<S, NT, kP, 8 * S::NV>;
+  // Groups of many waves hold each wave's few units precomputed; groups of
+  // few waves work every term out per level.
+  constexpr bool kPre = UpEmitPre<S, NT>::J <= 2;
+  [[maybe_unused]] UpEmitPre<S, NT> ep;
+  if constexpr (kPre) up_emit_init<S, NT>(ep, up, g, tile);
+  auto strips_read = [&](E& es, const typename S::V* win, int l) {
+    if constexpr (kPre)
+      up_strips_read<S, NT, kP>(es, ep, win, g, l);
+    else
+      up_strips_read_direct<S, NT, kP>(es, win, up, g, tile, l);
+  };
   // Level l's pass also emits the panel strips of level l-1.
   for (int l = 1; l <= top; ++l) {
     typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
     const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
     E es;
-    if constexpr (emit_early<S>()) up_strips_read<S, NT, kP>(es, prv, up, g, tile, l - 1);
+    if constexpr (emit_early<S>()) strips_read(es, prv, l - 1);
     compute_level<S, WC, NT>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
-    if constexpr (!emit_early<S>()) up_strips_read<S, NT, kP>(es, prv, up, g, tile, l - 1);
+    if constexpr (!emit_early<S>()) strips_read(es, prv, l - 1);
     emit_write(es);
     __syncthreads();
   }
   for (int l = top; l < H; ++l) {  // the last emitted level (level h-1 of a full half cycle)
     E es;
-    up_strips_read<S, NT, kP>(es, ((b0 + l) & 1) ? buf1 : buf0, up, g, tile, l);
+    strips_read(es, ((b0 + l) & 1) ? buf1 : buf0, l);
     emit_write(es);
   }
   if (H < h) {
@@ -758,14 +827,66 @@ __device__ __forceinline__ void fetch_strips_stg(Fetch<S, kThreads, P, G>& f, co
     }
 }
 
-// Bridge panels of level l (Alg. 2-3) from `win`, the buffer where level
-// l's band survives (as up_strips_read). x-bridge: rows y = l+1+k (N end)
-// and n-l-k (S end), x = h-l-1 .. h+l+2 (the band and the pyramid corners
+// Bridge panels of level l (Alg. 2-3), read from the buffer where level l's
+// band survives (as up_strips_read). x-bridge: rows y = l+1+k (N end) and
+// n-l-k (S end), x = h-l-1 .. h+l+2 (the band and the pyramid corners
 // placed beside it), which in its transposed window are columns. y-bridge:
 // columns x = l+1+k (W end) and n-l-k (E end), rows y = h+1-l .. h+l. Both
-// are window columns read down the rows.
+// are window columns read down the rows. Per wave unit, set up once: the
+// panel offset 2 NV levels_len(l) + rem len(l) is d0 + l d1 + 2 NV l^2
+// (levels_len = l^2 + 3l, len = 2l + 4 for the x-bridge; l^2 - l and 2l for
+// the y-bridge) and the window start s0 + l ds.
+template <class S, int kThreads>
+struct BridgeEmitPre {
+  static constexpr int J = EmitSlot<S, kThreads, 1, 4 * S::NV>::J;
+  typename S::V* base[J];  // panel of the unit's end and slot row, null: no unit
+  int d1[J], s0[J], ds[J];
+};
+
+template <class S, int kThreads>
+__device__ __forceinline__ void bridge_emit_init(BridgeEmitPre<S, kThreads>& r, typename S::V* __restrict__ out,
+                                                 bool isx, const Geo& g, int e) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV, per = 4 * NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W;
+  const int w = kWaves - 1 - lwave<kThreads>();
+#pragma unroll
+  for (int j = 0; j < BridgeEmitPre<S, kThreads>::J; ++j) {
+    const int u = w + j * kWaves;
+    const int uu = u < per ? u : 0;
+    const int end = uu / (2 * NV), rem = uu - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    r.base[j] = u < per ? out + (isx ? xb_end(g, NV, e, end) + 4 * rem : yb_end(g, NV, e, end)) : nullptr;
+    r.d1[j] = isx ? 6 * NV + 2 * rem : 2 * rem - 2 * NV;
+    r.s0[j] = v * plane + (isx ? h - 1 : h + 1) * W + (end ? n - k : 1 + k);
+    r.ds[j] = end ? -W - 1 : 1 - W;
+  }
+}
+
 template <class S, int kThreads, int P>
 __device__ __forceinline__ void bridge_ends_read(EmitSlot<S, kThreads, P, 4 * S::NV>& es,
+                                                 const BridgeEmitPre<S, kThreads>& r,
+                                                 const typename S::V* __restrict__ win, bool isx, const Geo& g,
+                                                 int l) {
+  constexpr int NV = S::NV;
+  const int W = g.W, len = isx ? 2 * l + 4 : 2 * l;
+#pragma unroll
+  for (int j = 0; j < EmitSlot<S, kThreads, P, 4 * NV>::J; ++j) {
+    es.len[j] = 0;
+    if (r.base[j] == nullptr || len == 0) continue;
+    es.len[j] = len;
+    es.dst[j] = r.base[j] + (l * r.d1[j] + 2 * NV * l * l);
+    const typename S::V* src = win + r.s0[j] + l * r.ds[j];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      es.val[j][i] = src[(t < len ? t : 0) * W];
+    }
+  }
+}
+
+// The same panels with every term worked out at each level (as
+// up_strips_read_direct).
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void bridge_ends_read_direct(EmitSlot<S, kThreads, P, 4 * S::NV>& es,
                                                  const typename S::V* __restrict__ win,
                                                  typename S::V* __restrict__ out, bool isx, const Geo& g, int e,
                                                  int l) {
@@ -868,6 +989,15 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   // n + 2 long (the x-bridge's), one position per lane up to n = 62.
   constexpr int kPe = (WC != 0 && WC <= 64) ? 1 : 2;
   using E = EmitSlot<S, NT, kPe, 4 * NV>;
+  constexpr bool kPre = BridgeEmitPre<S, NT>::J <= 2;  // as in up_levels
+  [[maybe_unused]] BridgeEmitPre<S, NT> ep;
+  if constexpr (kPre) bridge_emit_init<S, NT>(ep, out, isx, g, e);
+  auto ends_read = [&](E& es, const V* win, int l) {
+    if constexpr (kPre)
+      bridge_ends_read<S, NT, kPe>(es, ep, win, isx, g, l);
+    else
+      bridge_ends_read_direct<S, NT, kPe>(es, win, out, isx, g, e, l);
+  };
   if constexpr (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
@@ -916,11 +1046,11 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
       E es;
       V* cur = (l & 1) ? buf1 : buf0;
       const V* prv = (l & 1) ? buf0 : buf1;
-      if constexpr (emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
+      if constexpr (emit_early<S>()) ends_read(es, prv, l - 1);
       strips_fetch(f, l);
       band(prv, cur, l);
       strips_place(f, cur, l);
-      if constexpr (!emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
+      if constexpr (!emit_early<S>()) ends_read(es, prv, l - 1);
       emit_write(es);
       __syncthreads();
     }
@@ -947,11 +1077,11 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
           E es;
           V* cur = (l & 1) ? buf1 : buf0;
           const V* prv = (l & 1) ? buf0 : buf1;
-          if constexpr (emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
+          if constexpr (emit_early<S>()) ends_read(es, prv, l - 1);
           band(prv, cur, l);
           strips_place(fl, cur, l);
           if (l + kAhead < H) strips_fetch(fl, l + kAhead);
-          if constexpr (!emit_early<S>()) bridge_ends_read<S, NT, kPe>(es, prv, out, isx, g, e, l - 1);
+          if constexpr (!emit_early<S>()) ends_read(es, prv, l - 1);
           emit_write(es);
           __syncthreads();
         }
@@ -961,7 +1091,7 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   {
     // The last emitted level, H - 1, beside the band of level H when H < h.
     E es;
-    bridge_ends_read<S, NT, kPe>(es, (H & 1) ? buf0 : buf1, out, isx, g, e, H - 1);
+    ends_read(es, (H & 1) ? buf0 : buf1, H - 1);
     if (H < h) band((H & 1) ? buf0 : buf1, (H & 1) ? buf1 : buf0, H);
     emit_write(es);
   }
