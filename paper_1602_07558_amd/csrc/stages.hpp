@@ -241,36 +241,37 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
   if constexpr (N == 64) {
     // A wave is one row of groups: the rectangle's rows, from its first,
     // are cut into groups of four dealt to the waves in turn, so a level
-    // keeps ceil(hg / 4) waves busy, each with at most one partial group,
-    // whatever the rectangle's position in the window.
+    // keeps ceil(hg / 4) waves busy whatever the rectangle's position in the
+    // window. With hg >= 4 the last group is moved up to end on the
+    // rectangle's last row, so every group is whole (rows it shares with the
+    // group before get the same values twice) and every row read lies in the
+    // window; a rectangle of fewer rows (one group from y0, rows tested) lies
+    // in the middle of the window at this pitch.
     constexpr int R = 4, NW = NT / 64;
     const int c = 1 + lane_id();
     const bool col_in = (unsigned)(c - x0) < (unsigned)w;
+    const bool whole = hg >= R;
     for (int grp = lwave<NT>(); R * grp < hg; grp += NW) {
-      const int r0 = y0 + R * grp;
-      const V* src = in + c;
+      const int r0 = whole ? min(y0 + R * grp, y0 + hg - R) : y0;
+      const V* src = in + (r0 - 1) * W + c;
       V nb[R + 2][3][NV];
 #pragma unroll
-      for (int j = 0; j < R + 2; ++j) {
-        // Rows past a partial group's end are clamped into the window; their
-        // values feed no stored point.
-        const int row = min(r0 - 1 + j, W - 1);
+      for (int j = 0; j < R + 2; ++j)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const V m = src[v * plane + row * W];
+          const V m = src[v * plane + j * W];
           nb[j][1][v] = m;
           if constexpr (DPP) {
             nb[j][0][v] = dpp_shift<true>(m);
             nb[j][2][v] = dpp_shift<false>(m);
           } else {
-            nb[j][0][v] = src[v * plane + row * W - 1];
-            nb[j][2][v] = src[v * plane + row * W + 1];
+            nb[j][0][v] = src[v * plane + j * W - 1];
+            nb[j][2][v] = src[v * plane + j * W + 1];
           }
         }
-      }
       if (col_in) {
         V* dst = out + r0 * W + c;
-        if (R * grp + R <= hg) {
+        if (whole) {
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             V o[NV];
@@ -281,7 +282,7 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
         } else {
 #pragma unroll
           for (int i = 0; i < R; ++i) {
-            if (R * grp + i < hg) {
+            if (i < hg) {
               V o[NV];
               S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
 #pragma unroll
@@ -765,6 +766,57 @@ __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads, P>& f, bool isx,
   }
 }
 
+// The fetch path's per-wave terms, set up once for groups of many waves:
+// a unit's HBM run starts at base + l d1 - 2 NV l^2 (its panel offset
+// 2 NV up_levels_len(n, l) + rem (n - 2l) with the level-0 part in base),
+// and element t goes to window index a0 + l da.
+template <class S, int kThreads, int P>
+struct StripFetchPre {
+  static constexpr int J = Fetch<S, kThreads, P>::J;
+  const typename S::V* base[J];  // null: no unit for this wave
+  int d1[J], da[J];
+  int a0[J][P];
+};
+
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void strip_fetch_init(StripFetchPre<S, kThreads, P>& r, bool isx, const Geo& g,
+                                                 const typename S::V* __restrict__ up, int tA, int tB) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W;
+#pragma unroll
+  for (int j = 0; j < StripFetchPre<S, kThreads, P>::J; ++j) {
+    const int u = lwave<kThreads>() + j * kWaves;
+    const int uu = u < 4 * NV ? u : 0;
+    const int side = uu / (2 * NV), rem = uu - side * 2 * NV, v = rem >> 1, k = rem & 1;
+    const int end = isx ? (side ? 2 : 3) : (side ? 0 : 1);
+    r.base[j] = u < 4 * NV ? up + up_end(g, NV, side ? tB : tA, end) + rem * n : nullptr;
+    r.d1[j] = 2 * NV * (n + 1) - 2 * rem;
+    r.da[j] = side ? W + 1 : 1 - W;
+#pragma unroll
+    for (int i = 0; i < P; ++i) r.a0[j][i] = v * plane + strip_idx(W, h, 0, side, k, lane_id() + 64 * i);
+  }
+}
+
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_strips_pre(Fetch<S, kThreads, P>& f, const StripFetchPre<S, kThreads, P>& r,
+                                                 const Geo& g, int l) {
+  constexpr int NV = S::NV;
+  const int len = g.n - 2 * l;
+#pragma unroll
+  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
+    if (r.base[j] == nullptr) continue;
+    const typename S::V* src = r.base[j] + (l * r.d1[j] - 2 * NV * l * l);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      f.val[j][i] = src[t < len ? t : len - 1];
+      f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
+    }
+  }
+}
+
 // Strip prefetch from the staged LDS runs (as RingPre): unit u = (side,
 // slot v, row k); the window index of element t is linear in the level
 // (from strip_idx), its staged offset
@@ -1010,9 +1062,16 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   // (1 <= l <= h-1) from level l-1. The first level only places, the last (H)
   // only computes (a full half cycle has no level h in a bridge); they are
   // peeled off so the loop body tests nothing per level. H >= 1.
+  // The fetch path keeps each wave's run terms precomputed when a wave has
+  // at most two units.
+  constexpr bool kFetchPre = !staged && F::J <= 2;
+  [[maybe_unused]] StripFetchPre<S, NT, kP> fpre;
+  if constexpr (kFetchPre) strip_fetch_init<S, NT, kP>(fpre, isx, g, up, e, tB);
   auto strips_fetch = [&](F& f, int l) {
     if constexpr (staged) {
       if constexpr (prefetch) fetch_strips_stg<S, NT, kP, kG>(f, pre, stg, l);
+    } else if constexpr (kFetchPre) {
+      fetch_strips_pre<S, NT, kP>(f, fpre, g, l);
     } else {
       fetch_strips<S, NT, kP>(f, isx, g, l, up, e, tB);
     }
