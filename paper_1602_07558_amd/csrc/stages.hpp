@@ -245,16 +245,15 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
     // window. With hg >= 4 the last group is moved up to end on the
     // rectangle's last row, so every group is whole (rows it shares with the
     // group before get the same values twice) and every row read lies in the
-    // window; a rectangle of fewer rows (one group from y0, rows tested) lies
-    // in the middle of the window at this pitch.
+    // window; a rectangle of fewer rows (one group from y0 on wave 0, rows
+    // tested) lies in the middle of the window at this pitch.
     constexpr int R = 4, NW = NT / 64;
     const int c = 1 + lane_id();
     const bool col_in = (unsigned)(c - x0) < (unsigned)w;
-    const bool whole = hg >= R;
-    for (int grp = lwave<NT>(); R * grp < hg; grp += NW) {
-      const int r0 = whole ? min(y0 + R * grp, y0 + hg - R) : y0;
+    // Rows r0-1 .. r0+R into registers, the side neighbours by DPP (or LDS
+    // at EDGE levels), for every lane of the wave.
+    auto load = [&](V (&nb)[R + 2][3][NV], int r0) {
       const V* src = in + (r0 - 1) * W + c;
-      V nb[R + 2][3][NV];
 #pragma unroll
       for (int j = 0; j < R + 2; ++j)
 #pragma unroll
@@ -269,9 +268,14 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
             nb[j][2][v] = src[v * plane + j * W + 1];
           }
         }
-      if (col_in) {
-        V* dst = out + r0 * W + c;
-        if (whole) {
+    };
+    if (hg >= R) {
+      for (int grp = lwave<NT>(); R * grp < hg; grp += NW) {
+        const int r0 = min(y0 + R * grp, y0 + hg - R);
+        V nb[R + 2][3][NV];
+        load(nb, r0);
+        if (col_in) {
+          V* dst = out + r0 * W + c;
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             V o[NV];
@@ -279,15 +283,20 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
 #pragma unroll
             for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
           }
-        } else {
+        }
+      }
+    } else if (lwave<NT>() == 0) {
+      V nb[R + 2][3][NV];
+      load(nb, y0);
+      if (col_in) {
+        V* dst = out + y0 * W + c;
 #pragma unroll
-          for (int i = 0; i < R; ++i) {
-            if (i < hg) {
-              V o[NV];
-              S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+        for (int i = 0; i < R - 1; ++i) {
+          if (i < hg) {
+            V o[NV];
+            S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
 #pragma unroll
-              for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
-            }
+            for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
           }
         }
       }
