@@ -99,6 +99,7 @@ extern "C" {
 #define SWEPT2D_STAGING_AUTO 0
 #define SWEPT2D_STAGING_OFF 1
 #define SWEPT2D_STAGING_SINGLE_BRIDGES 2
+#define SWEPT2D_STAGING_ON 3
 
 typedef struct swept2d swept2d; /* opaque, owned by the library */
 
@@ -189,13 +190,17 @@ int swept2d_set_substep_counter(swept2d *h, long long T);
 /* Launch mode (SWEPT2D_LAUNCH_DIRECT or SWEPT2D_LAUNCH_GRAPH). */
 int swept2d_set_launch_mode(swept2d *h, int mode);
 
-/* Panel staging mode. SWEPT2D_STAGING_AUTO copies a component's panel
- * inputs into LDS at its start where they fit, and at tile sides 32 and 64
- * runs a tile's two bridges in one workgroup where both fit its LDS;
- * SWEPT2D_STAGING_OFF fetches each level's inputs from HBM one level ahead
- * (bridges still paired; tile sides up to 22 of the one-wave light schemes
- * always stage); SWEPT2D_STAGING_SINGLE_BRIDGES is AUTO with one workgroup
- * per bridge. All modes give identical results. */
+/* Panel staging mode: whether a component copies all its panel inputs into
+ * LDS at its start (staged) or fetches each level's inputs from HBM a few
+ * levels before it places them. At tile sides 32 and 64 a tile's two
+ * bridges run in one workgroup where both fit its LDS. SWEPT2D_STAGING_AUTO
+ * stages an octahedron only where its workgroup has too few waves to keep
+ * each wave's ring runs precomputed, and fetches the bridges' inputs;
+ * SWEPT2D_STAGING_ON stages every component whose inputs fit the LDS;
+ * SWEPT2D_STAGING_OFF stages nothing; SWEPT2D_STAGING_SINGLE_BRIDGES is AUTO
+ * with one staged workgroup per bridge. The one-wave groups (tile sides up
+ * to 22 of the light schemes) always stage. All modes give identical
+ * results. */
 int swept2d_set_staging(swept2d *h, int mode);
 
 /* Per-kernel timing. While on, every kernel the handle launches is bracketed

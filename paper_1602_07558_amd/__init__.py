@@ -44,6 +44,7 @@ LAUNCH_GRAPH = 1
 STAGING_AUTO = 0
 STAGING_OFF = 1
 STAGING_SINGLE_BRIDGES = 2
+STAGING_ON = 3
 
 TUNE_MODEL = 0
 TUNE_MEASURE = 1

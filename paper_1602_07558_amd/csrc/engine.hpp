@@ -131,6 +131,9 @@ hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, 
                      hipStream_t s);
 hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, bool pair_ok, void* state, PanelPtrs p,
                          const SchemeParams& sp, hipStream_t s);
+// Whether the octahedron of tile side n fetches its ring runs from HBM a few
+// levels ahead with precomputed per-wave terms (then staging gains nothing).
+bool oct_fetch_ahead(int scheme, int n);
 hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p,
                       const SchemeParams& sp, hipStream_t s);
 hipError_t launch_plain(int scheme, int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
@@ -293,6 +296,7 @@ struct Stages {
   static hipError_t plain(int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
                           const SchemeParams& sp, hipStream_t s);
   static hipError_t lds(size_t bytes);
+  static bool fetch_ahead(int n);
 };
 
 // Kernel of one batch launch class (window pitch WC, NT threads).

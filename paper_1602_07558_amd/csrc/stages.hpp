@@ -624,6 +624,69 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads, P>& f, const Geo& 
   }
 }
 
+// The ring fetch path's per-wave terms, set up once for groups of many
+// waves (as StripFetchPre): a unit's HBM run at level l starts at
+// base + l d1 + 2 NV l^2 (2 NV levels_len(l) + rem len(l), with
+// levels_len = l^2 + 3l and len = 2l + 4 across the tile, l^2 - l and 2l
+// down it), and element t goes to window index a0 + l da.
+template <class S, int kThreads, int P>
+struct RingFetchPre {
+  static constexpr int J = Fetch<S, kThreads, P>::J;
+  const typename S::V* base[J];  // null: no unit for this wave
+  int d1[J], da[J], cz[J];       // cz = len(l) - 2l
+  int a0[J][P];
+};
+
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void ring_fetch_init(RingFetchPre<S, kThreads, P>& r, const Geo& g,
+                                                const typename S::V* __restrict__ xb,
+                                                const typename S::V* __restrict__ yb, int eTop, int eBot,
+                                                int eLeft, int eRight) {
+  constexpr int kWaves = kThreads / 64, NV = S::NV;
+  const int h = g.h, W = g.W, plane = W * W;
+#pragma unroll
+  for (int j = 0; j < RingFetchPre<S, kThreads, P>::J; ++j) {
+    const int u = lwave<kThreads>() + j * kWaves;
+    const int uu = u < 8 * NV ? u : 0;
+    const int band = uu / (2 * NV), rem = uu - band * 2 * NV, v = rem >> 1, k = rem & 1;
+    const bool horiz = band < 2;
+    const typename S::V* run = band == 0   ? xb + xb_end(g, NV, eTop, 1)
+                               : band == 1 ? xb + xb_end(g, NV, eBot, 0)
+                               : band == 2 ? yb + yb_end(g, NV, eLeft, 1)
+                                           : yb + yb_end(g, NV, eRight, 0);
+    r.base[j] = u < 8 * NV ? run + (horiz ? 4 * rem : 0) : nullptr;
+    r.d1[j] = horiz ? 6 * NV + 2 * rem : 2 * rem - 2 * NV;
+    r.cz[j] = horiz ? 4 : 0;
+    r.da[j] = band == 0 || band == 2 ? -(W + 1) : (band == 1 ? W - 1 : 1 - W);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      int wx, wy;
+      ring_pos(h, 0, band, k, lane_id() + 64 * i, wx, wy);
+      r.a0[j][i] = v * plane + wy * W + wx;
+    }
+  }
+}
+
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_ring_pre(Fetch<S, kThreads, P>& f, const RingFetchPre<S, kThreads, P>& r,
+                                               int l) {
+  constexpr int NV = S::NV;
+#pragma unroll
+  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
+    const int len = 2 * l + r.cz[j];
+    if (r.base[j] == nullptr || len == 0) continue;
+    const typename S::V* src = r.base[j] + (l * r.d1[j] + 2 * NV * l * l);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int t = lane_id() + 64 * i;
+      f.val[j][i] = src[t < len ? t : len - 1];
+      f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
+    }
+  }
+}
+
 // Ring prefetch from the staged LDS runs into registers, placed after the
 // level's compute pass so the LDS read latency hides behind it. Slot j of a
 // wave holds units u = (wave + j kWaves) G + lane / (64 / G), each one
@@ -1289,20 +1352,53 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
     else
       place_fetched(f, cur);
   };
-  if (Hd > 0) {
-    F f;
-    ring_fetch(f, 0);
-    ring_place(f, buf0, 0);
-    __syncthreads();
-  }
-  for (int l = 1; l < Hd; ++l) {
-    F f;  // per level, as in the bridges
-    V* cur = (l & 1) ? buf1 : buf0;
-    const V* prv = (l & 1) ? buf0 : buf1;
-    ring_fetch(f, l);
-    compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
-    ring_place(f, cur, l);
-    __syncthreads();
+  // From HBM with few units per wave, each level's ring is fetched kAhead
+  // levels before it is placed (slots as in the bridges).
+  constexpr bool kFetchPre = !staged && F::J <= 2;
+  if constexpr (kFetchPre) {
+    constexpr int kAhead = F::J * kP * (int)sizeof(V) <= 32 ? 3 : 1;
+    RingFetchPre<S, NT, kP> fpre;
+    ring_fetch_init<S, NT, kP>(fpre, g, xb, yb, eTop, eBot, eLeft, eRight);
+    F f[kAhead];
+    if (Hd > 0) {
+#pragma unroll
+      for (int i = 0; i < kAhead; ++i)
+        if (i < Hd) fetch_ring_pre<S, NT, kP>(f[i], fpre, i);
+      place_fetched(f[0], buf0);
+      if (kAhead < Hd) fetch_ring_pre<S, NT, kP>(f[0], fpre, kAhead);
+      __syncthreads();
+    }
+    for (int l0 = 1; l0 < Hd; l0 += kAhead) {
+#pragma unroll
+      for (int i = 0; i < kAhead; ++i) {
+        const int l = l0 + i;  // held in slot (1 + i) mod kAhead
+        if (l < Hd) {
+          F& fl = f[(1 + i) % kAhead];
+          V* cur = (l & 1) ? buf1 : buf0;
+          const V* prv = (l & 1) ? buf0 : buf1;
+          compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+          place_fetched(fl, cur);
+          if (l + kAhead < Hd) fetch_ring_pre<S, NT, kP>(fl, fpre, l + kAhead);
+          __syncthreads();
+        }
+      }
+    }
+  } else {
+    if (Hd > 0) {
+      F f;
+      ring_fetch(f, 0);
+      ring_place(f, buf0, 0);
+      __syncthreads();
+    }
+    for (int l = 1; l < Hd; ++l) {
+      F f;  // per level, as in the bridges
+      V* cur = (l & 1) ? buf1 : buf0;
+      const V* prv = (l & 1) ? buf0 : buf1;
+      ring_fetch(f, l);
+      compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+      ring_place(f, cur, l);
+      __syncthreads();
+    }
   }
   if (Hd > 0) {
     V* cur = (Hd & 1) ? buf1 : buf0;
@@ -1502,6 +1598,16 @@ constexpr int threads_for(int n) {
 template <class S>
 bool forced_staging(int n) {
   return threads_for<S>(n) == 64;
+}
+
+// Whether the octahedron of tile side n, fetching its ring runs from HBM,
+// keeps each wave's run terms precomputed and fetches a few levels ahead
+// (a wave holds at most two of the 8 NV ring units); it then has no need
+// to stage the runs in LDS.
+template <class S>
+bool oct_fetch_ahead(int n) {
+  const int waves = threads_for<S>(n) / 64;
+  return (8 * S::NV + waves - 1) / waves <= 2;
 }
 
 // Threads of one group of a bridge pair: 8 waves at tile side 64, half the
@@ -1900,6 +2006,10 @@ template <class S>
 hipError_t Stages<S>::plain(int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
                             const SchemeParams& sp, hipStream_t s) {
   return plain_t<S>(nx, ny, T, tbase, in, out, sp, s);
+}
+template <class S>
+bool Stages<S>::fetch_ahead(int n) {
+  return oct_fetch_ahead<S>(n);
 }
 template <class S>
 hipError_t Stages<S>::lds(size_t bytes) {

@@ -240,14 +240,20 @@ const char* tile_problem(const swept2d* h, int n) {
   return nullptr;
 }
 
+// Staging policy (one-wave groups stage whatever is asked). ON stages every
+// component whose inputs fit the LDS; AUTO stages an octahedron only when it
+// cannot fetch its ring runs ahead with precomputed per-wave terms, and no
+// bridge (their fetch path runs three levels ahead); SINGLE_BRIDGES is AUTO
+// with one staged workgroup per bridge; OFF stages nothing.
 bool oct_staged(const swept2d* h) {
-  return h->staging != SWEPT2D_STAGING_OFF &&
-         window_lds_bytes(h->si, h->n) + oct_stage_bytes(h->si, h->n) <= g_lds_limit;
+  if (h->staging == SWEPT2D_STAGING_OFF) return false;
+  if (window_lds_bytes(h->si, h->n) + oct_stage_bytes(h->si, h->n) > g_lds_limit) return false;
+  return h->staging == SWEPT2D_STAGING_ON || !oct_fetch_ahead(h->scheme, h->n);
 }
 
 bool bridge_staged(const swept2d* h) {
-  return h->staging != SWEPT2D_STAGING_OFF &&
-         window_lds_bytes(h->si, h->n) + bridge_stage_bytes(h->si, h->n) <= g_lds_limit;
+  if (h->staging == SWEPT2D_STAGING_OFF || h->staging == SWEPT2D_STAGING_AUTO) return false;
+  return window_lds_bytes(h->si, h->n) + bridge_stage_bytes(h->si, h->n) <= g_lds_limit;
 }
 
 // Relative cost of one point sub-step of a scheme (heat FP64 = 1), for the
@@ -677,7 +683,8 @@ int swept2d_set_launch_mode(swept2d* h, int mode) {
 
 int swept2d_set_staging(swept2d* h, int mode) {
   if (!h) return fail(SWEPT2D_EINVAL, "null handle");
-  if (mode != SWEPT2D_STAGING_AUTO && mode != SWEPT2D_STAGING_OFF && mode != SWEPT2D_STAGING_SINGLE_BRIDGES)
+  if (mode != SWEPT2D_STAGING_AUTO && mode != SWEPT2D_STAGING_OFF && mode != SWEPT2D_STAGING_SINGLE_BRIDGES &&
+      mode != SWEPT2D_STAGING_ON)
     return fail(SWEPT2D_EINVAL, "unknown staging mode");
   if (mode != h->staging) drop_graphs(h);
   h->staging = mode;

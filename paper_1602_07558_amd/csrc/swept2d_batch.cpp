@@ -86,13 +86,19 @@ namespace {
 
 size_t state_bytes(const HostGrid& g) { return (size_t)g.nx * g.ny * g.si.nv * g.si.vbytes; }
 
+// Staging as the single-grid AUTO policy: an octahedron stages its ring runs
+// only when its workgroup has too few waves to keep each wave's runs
+// precomputed for the fetch path (a wave would hold more than two of the
+// 8 NV units); bridges fetch (one-wave classes stage everything).
 size_t stage_lds(const HostGrid& g, bool* staged_oct, bool* staged_bridge) {
   *staged_oct = *staged_bridge = false;
   if (g.n == 0) return 0;
   const size_t lim = device_lds_limit();
   const size_t win = window_lds_bytes(g.si, g.n);
-  *staged_oct = win + oct_stage_bytes(g.si, g.n) <= lim;
-  *staged_bridge = win + bridge_stage_bytes(g.si, g.n) <= lim;
+  const int waves = batch_class_threads(batch_class_of(g.n)) / 64;
+  const bool fetch_ahead = (8 * g.si.nv + waves - 1) / waves <= 2;
+  *staged_oct = !fetch_ahead && win + oct_stage_bytes(g.si, g.n) <= lim;
+  *staged_bridge = false;
   return std::max(win + (*staged_oct ? oct_stage_bytes(g.si, g.n) : 0),
                   win + (*staged_bridge ? bridge_stage_bytes(g.si, g.n) : 0));
 }

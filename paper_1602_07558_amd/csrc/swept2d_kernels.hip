@@ -72,6 +72,11 @@ hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, bool pair
   return hipErrorInvalidValue;
 }
 
+bool oct_fetch_ahead(int scheme, int n) {
+  SWEPT_DISPATCH(fetch_ahead, n)
+  return false;
+}
+
 hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p,
                       const SchemeParams& sp, hipStream_t s) {
   SWEPT_DISPATCH(oct, g, Hd, Hu, staged, state, p, sp, s)

@@ -50,7 +50,7 @@ def tiles_of(nx, ny, limit=64):
 HASH_GRIDS = [(8, 8), (16, 16), (24, 16), (12, 12), (32, 32), (18, 12), (64, 32)]
 
 
-@pytest.mark.parametrize("staging", [sw.STAGING_AUTO, sw.STAGING_OFF, sw.STAGING_SINGLE_BRIDGES])
+@pytest.mark.parametrize("staging", [sw.STAGING_AUTO, sw.STAGING_OFF, sw.STAGING_SINGLE_BRIDGES, sw.STAGING_ON])
 @pytest.mark.parametrize("nx,ny", HASH_GRIDS)
 def test_hash_every_tile_and_remainder(nx, ny, staging):
     s0 = si.hash_field(nx, ny, seed=nx * 100 + ny)
@@ -70,7 +70,7 @@ def test_hash_large_tiles_both_paths():
         s0 = si.hash_field(nx, ny, seed=n)
         for S in (n // 2 + 3, 2 * n + 1):
             ref = oracle.advance_f64(si.TEST_HASH, s0, [], S, t0=1)
-            for staging in (sw.STAGING_AUTO, sw.STAGING_OFF, sw.STAGING_SINGLE_BRIDGES):
+            for staging in (sw.STAGING_AUTO, sw.STAGING_OFF, sw.STAGING_SINGLE_BRIDGES, sw.STAGING_ON):
                 got = gpu_run(si.TEST_HASH, s0, [], S, tile=n, T=1, staging=staging)
                 assert np.array_equal(got, ref), (nx, ny, n, S, staging)
 
@@ -108,6 +108,7 @@ def test_heat_64x64_1000_steps_every_tile():
         assert np.array_equal(gpu_run(si.HEAT5, s0, p, 1000, tile=n), ref), n
         assert np.array_equal(gpu_run(si.HEAT5, s0, p, 1000, tile=n, staging=sw.STAGING_OFF), ref), n
         assert np.array_equal(gpu_run(si.HEAT5, s0, p, 1000, tile=n, staging=sw.STAGING_SINGLE_BRIDGES), ref), n
+        assert np.array_equal(gpu_run(si.HEAT5, s0, p, 1000, tile=n, staging=sw.STAGING_ON), ref), n
     assert np.array_equal(gpu_run(si.HEAT5, s0, p, 1000, method="plain"), ref)
 
 
