@@ -276,7 +276,8 @@ def main():
                    "tile": tile, "precision": "fp64"},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_oct<Heat64,66,1024,staged> (downward pyramid + next upward pyramid)",
+            "kernel": "k_oct<Heat64,66,1024,false> (downward pyramid + next upward pyramid, ring runs fetched "
+                      "from HBM three levels ahead)",
             "achieved": achieved,
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -99,7 +99,8 @@ def main(argv):
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import bench
         with open(out, "w") as fo:
-            fo.write("# HBM traffic of k_oct<Heat64,66,1024,true> per launch (heat 1024x1024, tile 64, FP64, staged)\n")
+            fo.write("# HBM traffic of the octahedron kernel k_oct<Heat64,66,1024,false> per launch "
+                     "(heat 1024x1024, tile 64, FP64, ring runs fetched from HBM)\n")
             for k, v in t.items():
                 fo.write(f"{k}: {v:.6g}\n")
             fo.write(f"kernel_source_sha256_16: {bench.kernel_source_hash()}\n")
