@@ -252,8 +252,8 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
     const bool col_in = (unsigned)(c - x0) < (unsigned)w;
     // Rows r0-1 .. r0+R into registers, the side neighbours by DPP (or LDS
     // at EDGE levels), for every lane of the wave.
-    auto load = [&](V (&nb)[R + 2][3][NV], int r0) {
-      const V* src = in + (r0 - 1) * W + c;
+    auto load = [&](V (&nb)[R + 2][3][NV], int r0, int col) {
+      const V* src = in + (r0 - 1) * W + col;
 #pragma unroll
       for (int j = 0; j < R + 2; ++j)
 #pragma unroll
@@ -269,11 +269,33 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
           }
         }
     };
-    if (hg >= R) {
+    if (w + 2 <= 32 && hg > R * NW) {
+      // A tall rectangle at most 30 columns wide (a bridge's band in its
+      // later levels): each half wave takes a row group, lane i of a half on
+      // window column x0 - 1 + i, so a wave carries half the rows. A half
+      // without a group of its own repeats the last one.
+      const int half = lane_id() >> 5, i = lane_id() & 31, col = x0 - 1 + i;
+      const bool in_half = i >= 1 && i <= w;
+      for (int g0 = 2 * lwave<NT>(); R * g0 < hg; g0 += 2 * NW) {
+        const int r0 = min(y0 + R * (g0 + half), y0 + hg - R);
+        V nb[R + 2][3][NV];
+        load(nb, r0, col);
+        if (in_half) {
+          V* dst = out + r0 * W + col;
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            V o[NV];
+            S::step(T, RegNb<V, NV, TR>{&nb[k]}, o, sp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[v * plane + k * W] = o[v];
+          }
+        }
+      }
+    } else if (hg >= R) {
       for (int grp = lwave<NT>(); R * grp < hg; grp += NW) {
         const int r0 = min(y0 + R * grp, y0 + hg - R);
         V nb[R + 2][3][NV];
-        load(nb, r0);
+        load(nb, r0, c);
         if (col_in) {
           V* dst = out + r0 * W + c;
 #pragma unroll
@@ -287,7 +309,7 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
       }
     } else if (lwave<NT>() == 0) {
       V nb[R + 2][3][NV];
-      load(nb, y0);
+      load(nb, y0, c);
       if (col_in) {
         V* dst = out + y0 * W + c;
 #pragma unroll
