@@ -666,9 +666,12 @@ __device__ __forceinline__ void ring_fetch_init(RingFetchPre<S, kThreads, P>& r,
                                                 int eLeft, int eRight) {
   constexpr int kWaves = kThreads / 64, NV = S::NV;
   const int h = g.h, W = g.W, plane = W * W;
+  // Units go to the last waves first: small levels are computed by the
+  // first waves, so the fetch and placement stay off their path.
+  const int w = kWaves - 1 - lwave<kThreads>();
 #pragma unroll
   for (int j = 0; j < RingFetchPre<S, kThreads, P>::J; ++j) {
-    const int u = lwave<kThreads>() + j * kWaves;
+    const int u = w + j * kWaves;
     const int uu = u < 8 * NV ? u : 0;
     const int band = uu / (2 * NV), rem = uu - band * 2 * NV, v = rem >> 1, k = rem & 1;
     const bool horiz = band < 2;
@@ -877,6 +880,7 @@ __device__ __forceinline__ void strip_fetch_init(StripFetchPre<S, kThreads, P>& 
                                                  const typename S::V* __restrict__ up, int tA, int tB) {
   constexpr int kWaves = kThreads / 64, NV = S::NV;
   const int n = g.n, h = g.h, W = g.W, plane = W * W;
+  // First waves first: a bridge's last waves store its panels.
 #pragma unroll
   for (int j = 0; j < StripFetchPre<S, kThreads, P>::J; ++j) {
     const int u = lwave<kThreads>() + j * kWaves;
