@@ -68,6 +68,16 @@ __device__ __forceinline__ int lwave() {
   return __builtin_amdgcn_readfirstlane((int)((threadIdx.x & (kThreads - 1)) >> 6));
 }
 
+// A (wave-uniform) level hidden from the optimiser. The prefetch loops
+// fetch the first levels before their loop with every load issued
+// unconditionally, as inside it; with a known small level the compiler would
+// drop a load it proves unused, and the loads in flight would then differ
+// between the paths into the loop, which makes it wait for all of them.
+__device__ __forceinline__ int opaque_level(int l) {
+  __asm__ volatile("" : "+v"(l));
+  return __builtin_amdgcn_readfirstlane(l);
+}
+
 __device__ __forceinline__ int wrap(int x, int m) {
   if (x < 0) x += m;
   if (x >= m) x -= m;
@@ -654,7 +664,8 @@ __device__ __forceinline__ void fetch_ring(Fetch<S, kThreads, P>& f, const Geo& 
 template <class S, int kThreads, int P>
 struct RingFetchPre {
   static constexpr int J = Fetch<S, kThreads, P>::J;
-  const typename S::V* base[J];  // null: no unit for this wave
+  const typename S::V* base[J];  // a valid address even for waves without a unit
+  bool has[J];                   // the wave has a unit in this slot
   int d1[J], da[J], cz[J];       // cz = len(l) - 2l
   int a0[J][P];
 };
@@ -679,7 +690,8 @@ __device__ __forceinline__ void ring_fetch_init(RingFetchPre<S, kThreads, P>& r,
                                : band == 1 ? xb + xb_end(g, NV, eBot, 0)
                                : band == 2 ? yb + yb_end(g, NV, eLeft, 1)
                                            : yb + yb_end(g, NV, eRight, 0);
-    r.base[j] = u < 8 * NV ? run + (horiz ? 4 * rem : 0) : nullptr;
+    r.has[j] = u < 8 * NV;
+    r.base[j] = run + (horiz ? 4 * rem : 0);
     r.d1[j] = horiz ? 6 * NV + 2 * rem : 2 * rem - 2 * NV;
     r.cz[j] = horiz ? 4 : 0;
     r.da[j] = band == 0 || band == 2 ? -(W + 1) : (band == 1 ? W - 1 : 1 - W);
@@ -692,21 +704,22 @@ __device__ __forceinline__ void ring_fetch_init(RingFetchPre<S, kThreads, P>& r,
   }
 }
 
+// Every wave issues its loads, clamped into the panel where it has no unit
+// or the run is short, so the number of loads in flight is the same on
+// every path and the wait before a slot's placement counts only the loads
+// issued after it.
 template <class S, int kThreads, int P>
 __device__ __forceinline__ void fetch_ring_pre(Fetch<S, kThreads, P>& f, const RingFetchPre<S, kThreads, P>& r,
                                                int l) {
   constexpr int NV = S::NV;
 #pragma unroll
   for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
-    const int len = 2 * l + r.cz[j];
-    if (r.base[j] == nullptr || len == 0) continue;
+    const int len = r.has[j] ? 2 * l + r.cz[j] : 0;
     const typename S::V* src = r.base[j] + (l * r.d1[j] + 2 * NV * l * l);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
-      f.val[j][i] = src[t < len ? t : len - 1];
+      f.val[j][i] = src[t < len ? t : 0];
       f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
     }
   }
@@ -870,7 +883,8 @@ __device__ __forceinline__ void fetch_strips(Fetch<S, kThreads, P>& f, bool isx,
 template <class S, int kThreads, int P>
 struct StripFetchPre {
   static constexpr int J = Fetch<S, kThreads, P>::J;
-  const typename S::V* base[J];  // null: no unit for this wave
+  const typename S::V* base[J];  // a valid address even for waves without a unit
+  bool has[J];                   // the wave has a unit in this slot
   int d1[J], da[J];
   int a0[J][P];
 };
@@ -887,7 +901,8 @@ __device__ __forceinline__ void strip_fetch_init(StripFetchPre<S, kThreads, P>& 
     const int uu = u < 4 * NV ? u : 0;
     const int side = uu / (2 * NV), rem = uu - side * 2 * NV, v = rem >> 1, k = rem & 1;
     const int end = isx ? (side ? 2 : 3) : (side ? 0 : 1);
-    r.base[j] = u < 4 * NV ? up + up_end(g, NV, side ? tB : tA, end) + rem * n : nullptr;
+    r.has[j] = u < 4 * NV;
+    r.base[j] = up + up_end(g, NV, side ? tB : tA, end) + rem * n;
     r.d1[j] = 2 * NV * (n + 1) - 2 * rem;
     r.da[j] = side ? W + 1 : 1 - W;
 #pragma unroll
@@ -899,17 +914,15 @@ template <class S, int kThreads, int P>
 __device__ __forceinline__ void fetch_strips_pre(Fetch<S, kThreads, P>& f, const StripFetchPre<S, kThreads, P>& r,
                                                  const Geo& g, int l) {
   constexpr int NV = S::NV;
-  const int len = g.n - 2 * l;
 #pragma unroll
   for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) f.dst[j][i] = -1;
-    if (r.base[j] == nullptr) continue;
+    // Loads issued on every path, as in fetch_ring_pre.
+    const int len = r.has[j] ? g.n - 2 * l : 0;
     const typename S::V* src = r.base[j] + (l * r.d1[j] - 2 * NV * l * l);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int t = lane_id() + 64 * i;
-      f.val[j][i] = src[t < len ? t : len - 1];
+      f.val[j][i] = src[t < len ? t : 0];
       f.dst[j][i] = t < len ? r.a0[j][i] + l * r.da[j] : -1;
     }
   }
@@ -1221,28 +1234,33 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
     F f[kAhead];
 #pragma unroll
     for (int i = 0; i < kAhead; ++i)
-      if (i < H) strips_fetch(f[i], i);
+      strips_fetch(f[i], opaque_level(i < H ? i : H - 1));
     strips_place(f[0], buf0, 0);
-    if (kAhead < H) strips_fetch(f[0], kAhead);
+    strips_fetch(f[0], opaque_level(kAhead < H ? kAhead : H - 1));
     __syncthreads();
-    for (int l0 = 1; l0 < H; l0 += kAhead) {
+    auto level = [&](F& fl, int l, bool refill) {
+      E es;
+      V* cur = (l & 1) ? buf1 : buf0;
+      const V* prv = (l & 1) ? buf0 : buf1;
+      if constexpr (emit_early<S>()) ends_read(es, prv, l - 1);
+      band(prv, cur, l);
+      strips_place(fl, cur, l);
+      if (refill) strips_fetch(fl, l + kAhead);
+      if constexpr (!emit_early<S>()) ends_read(es, prv, l - 1);
+      emit_write(es);
+      __syncthreads();
+    };
+    // Unconditional refills in whole blocks, then the last levels with tests
+    // (as in the octahedron's fetch loop).
+    int l0 = 1;  // level l0 + i is held in slot (1 + i) mod kAhead
+    for (; l0 + 2 * kAhead - 1 < H; l0 += kAhead) {
 #pragma unroll
-      for (int i = 0; i < kAhead; ++i) {
-        const int l = l0 + i;  // held in slot (1 + i) mod kAhead, as l0 = 1 mod kAhead
-        if (l < H) {
-          F& fl = f[(1 + i) % kAhead];
-          E es;
-          V* cur = (l & 1) ? buf1 : buf0;
-          const V* prv = (l & 1) ? buf0 : buf1;
-          if constexpr (emit_early<S>()) ends_read(es, prv, l - 1);
-          band(prv, cur, l);
-          strips_place(fl, cur, l);
-          if (l + kAhead < H) strips_fetch(fl, l + kAhead);
-          if constexpr (!emit_early<S>()) ends_read(es, prv, l - 1);
-          emit_write(es);
-          __syncthreads();
-        }
-      }
+      for (int i = 0; i < kAhead; ++i) level(f[(1 + i) % kAhead], l0 + i, true);
+    }
+    for (; l0 < H; l0 += kAhead) {
+#pragma unroll
+      for (int i = 0; i < kAhead; ++i)
+        if (l0 + i < H) level(f[(1 + i) % kAhead], l0 + i, l0 + i + kAhead < H);
     }
   }
   {
@@ -1389,25 +1407,32 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
     if (Hd > 0) {
 #pragma unroll
       for (int i = 0; i < kAhead; ++i)
-        if (i < Hd) fetch_ring_pre<S, NT, kP>(f[i], fpre, i);
+        fetch_ring_pre<S, NT, kP>(f[i], fpre, opaque_level(i < Hd ? i : Hd - 1));
       place_fetched(f[0], buf0);
-      if (kAhead < Hd) fetch_ring_pre<S, NT, kP>(f[0], fpre, kAhead);
+      fetch_ring_pre<S, NT, kP>(f[0], fpre, opaque_level(kAhead < Hd ? kAhead : Hd - 1));
       __syncthreads();
     }
-    for (int l0 = 1; l0 < Hd; l0 += kAhead) {
+    auto level = [&](F& fl, int l, bool refill) {
+      V* cur = (l & 1) ? buf1 : buf0;
+      const V* prv = (l & 1) ? buf0 : buf1;
+      compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+      place_fetched(fl, cur);
+      if (refill) fetch_ring_pre<S, NT, kP>(fl, fpre, l + kAhead);
+      __syncthreads();
+    };
+    // Blocks whose every level refills its slot issue their loads
+    // unconditionally, so the wait before a slot's placement counts only the
+    // loads of the later slots (a refill that might be skipped would make the
+    // compiler wait for all of them); the last levels follow with tests.
+    int l0 = 1;  // level l0 + i is held in slot (1 + i) mod kAhead
+    for (; l0 + 2 * kAhead - 1 < Hd; l0 += kAhead) {
 #pragma unroll
-      for (int i = 0; i < kAhead; ++i) {
-        const int l = l0 + i;  // held in slot (1 + i) mod kAhead
-        if (l < Hd) {
-          F& fl = f[(1 + i) % kAhead];
-          V* cur = (l & 1) ? buf1 : buf0;
-          const V* prv = (l & 1) ? buf0 : buf1;
-          compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
-          place_fetched(fl, cur);
-          if (l + kAhead < Hd) fetch_ring_pre<S, NT, kP>(fl, fpre, l + kAhead);
-          __syncthreads();
-        }
-      }
+      for (int i = 0; i < kAhead; ++i) level(f[(1 + i) % kAhead], l0 + i, true);
+    }
+    for (; l0 < Hd; l0 += kAhead) {
+#pragma unroll
+      for (int i = 0; i < kAhead; ++i)
+        if (l0 + i < Hd) level(f[(1 + i) % kAhead], l0 + i, l0 + i + kAhead < Hd);
     }
   } else {
     if (Hd > 0) {
