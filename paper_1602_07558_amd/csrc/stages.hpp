@@ -231,6 +231,119 @@ __device__ __forceinline__ double dpp_shift(double x) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// One level at window pitch 66 (64 lanes on the 64 interior columns), as
+// this wave runs it. A wave is one row of groups: the rectangle's rows, from
+// its first, are cut into groups of four dealt to the waves in turn, so a
+// level keeps ceil(hg / 4) waves busy whatever the rectangle's position in
+// the window. With hg >= 4 the last group is moved up to end on the
+// rectangle's last row, so every group is whole (rows it shares with the
+// group before get the same values twice) and every row read lies in the
+// window; a rectangle of fewer rows (one group from y0 on wave 0, rows
+// tested) lies in the middle of the window at this pitch. A tall rectangle at
+// most 30 columns wide (a bridge's band in its later levels) gives each half
+// wave a row group of its own, lane i of a half on window column x0 - 1 + i
+// (a half without a group repeats the last one). The plan is worked out
+// before the barrier that precedes the level, so that after it only the row
+// reads' addresses stand between the barrier and the LDS reads.
+template <int NT>
+struct ColsPlan {
+  static constexpr int R = 4, NW = NT / 64, KG = (64 / R + NW - 1) / NW;  // groups per wave at most
+  int off[KG];    // window offset of the first row read, (r0 - 1) W + column
+  bool act[KG];   // the group exists (wave-uniform)
+  bool store;     // this lane's column lies in the rectangle
+  int nrows;      // rows stored per group: 4, or hg < 4
+};
+
+template <int WC, int NT>
+__device__ __forceinline__ ColsPlan<NT> cols_plan(int x0, int y0, int w, int hg) {
+  using P = ColsPlan<NT>;
+  constexpr int R = P::R, NW = P::NW, W = WC;
+  const int wave = lwave<NT>(), lane = lane_id();
+  P p;
+  if (w + 2 <= 32 && hg > R * NW) {
+    const int half = lane >> 5, i = lane & 31, col = x0 - 1 + i;
+    const int r0 = min(y0 + R * (2 * wave + half), y0 + hg - R);
+#pragma unroll
+    for (int k = 0; k < P::KG; ++k) {
+      p.act[k] = k == 0 && 2 * R * wave < hg;  // a second pass would need hg > 8 NW rows
+      p.off[k] = (r0 - 1) * W + col;
+    }
+    p.store = i >= 1 && i <= w;
+    p.nrows = R;
+  } else if (hg >= R) {
+    const int col = 1 + lane;
+#pragma unroll
+    for (int k = 0; k < P::KG; ++k) {
+      const int grp = wave + k * NW;
+      p.act[k] = R * grp < hg;
+      p.off[k] = (min(y0 + R * grp, y0 + hg - R) - 1) * W + col;
+    }
+    p.store = (unsigned)(col - x0) < (unsigned)w;
+    p.nrows = R;
+  } else {
+    const int col = 1 + lane;
+#pragma unroll
+    for (int k = 0; k < P::KG; ++k) {
+      p.act[k] = k == 0 && wave == 0;
+      p.off[k] = (y0 - 1) * W + col;
+    }
+    p.store = (unsigned)(col - x0) < (unsigned)w;
+    p.nrows = hg;
+  }
+  return p;
+}
+
+template <class S, int WC, int NT, bool TR, bool DPP>
+__device__ __forceinline__ void cols_run(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                         const ColsPlan<NT>& p, long long T, const SchemeParams& sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV, W = WC, plane = W * W, R = ColsPlan<NT>::R;
+#pragma unroll
+  for (int k = 0; k < ColsPlan<NT>::KG; ++k) {
+    if (!p.act[k]) continue;
+    // Rows r0-1 .. r0+R into registers, the side neighbours by DPP (or LDS
+    // at EDGE levels), for every lane of the wave.
+    const V* src = in + p.off[k];
+    V nb[R + 2][3][NV];
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const V m = src[v * plane + j * W];
+        nb[j][1][v] = m;
+        if constexpr (DPP) {
+          nb[j][0][v] = dpp_shift<true>(m);
+          nb[j][2][v] = dpp_shift<false>(m);
+        } else {
+          nb[j][0][v] = src[v * plane + j * W - 1];
+          nb[j][2][v] = src[v * plane + j * W + 1];
+        }
+      }
+    if (p.store) {
+      V* dst = out + p.off[k] + W;
+      if (p.nrows == R) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          V o[NV];
+          S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < R - 1; ++i) {
+          if (i < p.nrows) {
+            V o[NV];
+            S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
+          }
+        }
+      }
+    }
+  }
+}
+
 // One level with column ownership: the rows of the thread's column that lie
 // in the rectangle [x0, x0+w) x [y0, y0+hg) get sub-step T from `in` into
 // `out`. The thread first reads the R+2 rows of its column it needs (its own
@@ -249,90 +362,7 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
   using V = typename S::V;
   constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N;
   if constexpr (N == 64) {
-    // A wave is one row of groups: the rectangle's rows, from its first,
-    // are cut into groups of four dealt to the waves in turn, so a level
-    // keeps ceil(hg / 4) waves busy whatever the rectangle's position in the
-    // window. With hg >= 4 the last group is moved up to end on the
-    // rectangle's last row, so every group is whole (rows it shares with the
-    // group before get the same values twice) and every row read lies in the
-    // window; a rectangle of fewer rows (one group from y0 on wave 0, rows
-    // tested) lies in the middle of the window at this pitch.
-    constexpr int R = 4, NW = NT / 64;
-    const int c = 1 + lane_id();
-    const bool col_in = (unsigned)(c - x0) < (unsigned)w;
-    // Rows r0-1 .. r0+R into registers, the side neighbours by DPP (or LDS
-    // at EDGE levels), for every lane of the wave.
-    auto load = [&](V (&nb)[R + 2][3][NV], int r0, int col) {
-      const V* src = in + (r0 - 1) * W + col;
-#pragma unroll
-      for (int j = 0; j < R + 2; ++j)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const V m = src[v * plane + j * W];
-          nb[j][1][v] = m;
-          if constexpr (DPP) {
-            nb[j][0][v] = dpp_shift<true>(m);
-            nb[j][2][v] = dpp_shift<false>(m);
-          } else {
-            nb[j][0][v] = src[v * plane + j * W - 1];
-            nb[j][2][v] = src[v * plane + j * W + 1];
-          }
-        }
-    };
-    if (w + 2 <= 32 && hg > R * NW) {
-      // A tall rectangle at most 30 columns wide (a bridge's band in its
-      // later levels): each half wave takes a row group, lane i of a half on
-      // window column x0 - 1 + i, so a wave carries half the rows. A half
-      // without a group of its own repeats the last one.
-      const int half = lane_id() >> 5, i = lane_id() & 31, col = x0 - 1 + i;
-      const bool in_half = i >= 1 && i <= w;
-      for (int g0 = 2 * lwave<NT>(); R * g0 < hg; g0 += 2 * NW) {
-        const int r0 = min(y0 + R * (g0 + half), y0 + hg - R);
-        V nb[R + 2][3][NV];
-        load(nb, r0, col);
-        if (in_half) {
-          V* dst = out + r0 * W + col;
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            V o[NV];
-            S::step(T, RegNb<V, NV, TR>{&nb[k]}, o, sp);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dst[v * plane + k * W] = o[v];
-          }
-        }
-      }
-    } else if (hg >= R) {
-      for (int grp = lwave<NT>(); R * grp < hg; grp += NW) {
-        const int r0 = min(y0 + R * grp, y0 + hg - R);
-        V nb[R + 2][3][NV];
-        load(nb, r0, c);
-        if (col_in) {
-          V* dst = out + r0 * W + c;
-#pragma unroll
-          for (int i = 0; i < R; ++i) {
-            V o[NV];
-            S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
-          }
-        }
-      }
-    } else if (lwave<NT>() == 0) {
-      V nb[R + 2][3][NV];
-      load(nb, y0, c);
-      if (col_in) {
-        V* dst = out + y0 * W + c;
-#pragma unroll
-        for (int i = 0; i < R - 1; ++i) {
-          if (i < hg) {
-            V o[NV];
-            S::step(T, RegNb<V, NV, TR>{&nb[i]}, o, sp);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dst[v * plane + i * W] = o[v];
-          }
-        }
-      }
-    }
+    cols_run<S, WC, NT, TR, DPP>(in, out, cols_plan<WC, NT>(x0, y0, w, hg), T, sp);
   } else {
     constexpr int R = Lay<S, WC, NT>::R;
     const int t = ltid<NT>();
@@ -381,6 +411,35 @@ __device__ __forceinline__ void compute_level(const typename S::V* __restrict__ 
   } else {
     compute_quads<S, WC, NT, TR>(in, out, Wrt, x0, y0, w, hg, T, sp);
   }
+}
+
+// A level's rectangle, planned ahead of its barrier where the layout allows
+// (window pitch 66), and run after it.
+template <class S, int WC, int NT, bool C66 = (WC == 66 && Lay<S, WC, NT>::cols)>
+struct LevelPlan {
+  int x0, y0, w, hg;
+};
+template <class S, int WC, int NT>
+struct LevelPlan<S, WC, NT, true> {
+  ColsPlan<NT> cp;
+};
+
+template <class S, int WC, int NT>
+__device__ __forceinline__ LevelPlan<S, WC, NT> level_plan(int x0, int y0, int w, int hg) {
+  if constexpr (WC == 66 && Lay<S, WC, NT>::cols)
+    return LevelPlan<S, WC, NT>{cols_plan<WC, NT>(x0, y0, w, hg)};
+  else
+    return LevelPlan<S, WC, NT>{x0, y0, w, hg};
+}
+
+template <class S, int WC, int NT, bool TR = false>
+__device__ __forceinline__ void level_run(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                          int Wrt, const LevelPlan<S, WC, NT>& p, long long T,
+                                          const SchemeParams& sp) {
+  if constexpr (WC == 66 && Lay<S, WC, NT>::cols)
+    cols_run<S, WC, NT, TR, true>(in, out, p.cp, T, sp);
+  else
+    compute_level<S, WC, NT, TR>(in, out, Wrt, p.x0, p.y0, p.w, p.hg, T, sp);
 }
 
 // Window -> state for the rectangle [wx0, wx0+w) x [wy0, wy0+hg); the window
@@ -555,15 +614,19 @@ __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, cons
     else
       up_strips_read_direct<S, NT, kP>(es, win, up, g, tile, l);
   };
-  // Level l's pass also emits the panel strips of level l-1.
+  // Level l's pass also emits the panel strips of level l-1; the next
+  // level's rectangle is planned before the barrier.
+  auto plan = [&](int l) { return level_plan<S, WC, NT>(l + 1, l + 1, n - 2 * l, n - 2 * l); };
+  auto pl = plan(1);
   for (int l = 1; l <= top; ++l) {
     typename S::V* cur = ((b0 + l) & 1) ? buf1 : buf0;
     const typename S::V* prv = ((b0 + l) & 1) ? buf0 : buf1;
     E es;
     if constexpr (emit_early<S>()) strips_read(es, prv, l - 1);
-    compute_level<S, WC, NT>(prv, cur, g.W, l + 1, l + 1, n - 2 * l, n - 2 * l, T0 + l - 1, sp);
+    level_run<S, WC, NT>(prv, cur, g.W, pl, T0 + l - 1, sp);
     if constexpr (!emit_early<S>()) strips_read(es, prv, l - 1);
     emit_write(es);
+    pl = plan(l + 1);
     __syncthreads();
   }
   for (int l = top; l < H; ++l) {  // the last emitted level (level h-1 of a full half cycle)
@@ -1238,16 +1301,23 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
     strips_place(f[0], buf0, 0);
     strips_fetch(f[0], opaque_level(kAhead < H ? kAhead : H - 1));
     __syncthreads();
+    // Each level's band is planned before the barrier that precedes it.
+    auto plan = [&](int l) { return level_plan<S, WC, NT>(l + 1, h + 1 - l, n - 2 * l, 2 * l); };
+    auto pl = plan(1);
     auto level = [&](F& fl, int l, bool refill) {
       E es;
       V* cur = (l & 1) ? buf1 : buf0;
       const V* prv = (l & 1) ? buf0 : buf1;
       if constexpr (emit_early<S>()) ends_read(es, prv, l - 1);
-      band(prv, cur, l);
+      if (S::XY_SYM || !isx)
+        level_run<S, WC, NT, false>(prv, cur, g.W, pl, T0 + l - 1, sp);
+      else
+        level_run<S, WC, NT, true>(prv, cur, g.W, pl, T0 + l - 1, sp);
       strips_place(fl, cur, l);
       if (refill) strips_fetch(fl, l + kAhead);
       if constexpr (!emit_early<S>()) ends_read(es, prv, l - 1);
       emit_write(es);
+      pl = plan(l + 1);
       __syncthreads();
     };
     // Unconditional refills in whole blocks, then the last levels with tests
@@ -1370,7 +1440,7 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   // one position per lane, and up to 32, 64 / (n + 2) of them lie side by
   // side in one staged slot.
   constexpr int kP = (WC != 0 && WC <= 64) ? 1 : 2;
-  constexpr int kG = (staged && WC != 0 && WC <= 32) ? 64 / WC : 1;
+  constexpr int kG = (staged && WC != 0 && WC <= 32) ? 64 / (WC ? WC : 1) : 1;
   using F = Fetch<S, NT, kP, kG>;
   constexpr bool prefetch = F::J * kP <= 16;
   if constexpr (staged) {
@@ -1412,12 +1482,16 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
       fetch_ring_pre<S, NT, kP>(f[0], fpre, opaque_level(kAhead < Hd ? kAhead : Hd - 1));
       __syncthreads();
     }
+    // Each level's square is planned before the barrier that precedes it.
+    auto plan = [&](int l) { return level_plan<S, WC, NT>(h + 1 - l, h + 1 - l, 2 * l, 2 * l); };
+    auto pl = plan(1);
     auto level = [&](F& fl, int l, bool refill) {
       V* cur = (l & 1) ? buf1 : buf0;
       const V* prv = (l & 1) ? buf0 : buf1;
-      compute_level<S, WC, NT>(prv, cur, g.W, h + 1 - l, h + 1 - l, 2 * l, 2 * l, T0 + l - 1, sp);
+      level_run<S, WC, NT>(prv, cur, g.W, pl, T0 + l - 1, sp);
       place_fetched(fl, cur);
       if (refill) fetch_ring_pre<S, NT, kP>(fl, fpre, l + kAhead);
+      pl = plan(l + 1);
       __syncthreads();
     };
     // Blocks whose every level refills its slot issue their loads
