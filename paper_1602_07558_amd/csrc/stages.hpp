@@ -1204,10 +1204,9 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   // merged between paths, and their loads are waited for only where placed.
   static_assert(STAGED || NT != 64, "one-wave groups stage");
   constexpr bool staged = STAGED;
-  // Staged strips are at most n long: one position per lane up to n = 64,
-  // and 64 / n runs side by side in one slot for n <= 32. From HBM, runs at
-  // window pitches up to 64 take one position per lane.
-  constexpr int kP = staged ? ((WC != 0 && WC <= 66) ? 1 : 2) : ((WC != 0 && WC <= 64) ? 1 : 2);
+  // Strips are at most n long: one position per lane up to n = 64, and
+  // when staged 64 / n runs side by side in one slot for n <= 32.
+  constexpr int kP = (WC != 0 && WC <= 66) ? 1 : 2;
   constexpr int kG = (staged && WC != 0 && WC - 2 <= 32) ? 64 / (WC - 2) : 1;
   using F = Fetch<S, NT, kP, kG>;
   constexpr bool prefetch = F::J * kP <= 16;
