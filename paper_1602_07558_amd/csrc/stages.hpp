@@ -731,6 +731,7 @@ struct RingFetchPre {
   bool has[J];                   // the wave has a unit in this slot
   int d1[J], da[J], cz[J];       // cz = len(l) - 2l
   int a0[J][P];
+  int a0x[J];                    // window index at level 0 of element 64 P + lane (runs past 64 P)
 };
 
 template <class S, int kThreads, int P>
@@ -764,6 +765,32 @@ __device__ __forceinline__ void ring_fetch_init(RingFetchPre<S, kThreads, P>& r,
       ring_pos(h, 0, band, k, lane_id() + 64 * i, wx, wy);
       r.a0[j][i] = v * plane + wy * W + wx;
     }
+    int wx, wy;
+    ring_pos(h, 0, band, k, lane_id() + 64 * P, wx, wy);
+    r.a0x[j] = v * plane + wy * W + wx;
+  }
+}
+
+// Elements 64 P + lane of the runs of level l, which fetch_ring_pre leaves
+// out: at window pitch 66 only the 66-long runs across the tile at level
+// h - 1 reach past 64. Loaded once, at the start.
+template <class S, int kThreads, int P>
+struct RingPast {
+  typename S::V val[Fetch<S, kThreads, P>::J];
+  int dst[Fetch<S, kThreads, P>::J];  // -1: nothing to place
+};
+
+template <class S, int kThreads, int P>
+__device__ __forceinline__ void fetch_ring_past(RingPast<S, kThreads, P>& x, const RingFetchPre<S, kThreads, P>& r,
+                                                int l) {
+  constexpr int NV = S::NV;
+#pragma unroll
+  for (int j = 0; j < Fetch<S, kThreads, P>::J; ++j) {
+    const int len = r.has[j] ? 2 * l + r.cz[j] : 0;
+    const int t = lane_id() + 64 * P;
+    const typename S::V* src = r.base[j] + (l * r.d1[j] + 2 * NV * l * l);
+    x.val[j] = src[t < len ? t : 0];
+    x.dst[j] = t < len ? r.a0x[j] + l * r.da[j] : -1;
   }
 }
 
@@ -1437,8 +1464,13 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   constexpr bool staged = STAGED;
   // Ring runs are at most n + 2 long: at window pitches up to 64 they take
   // one position per lane, and up to 32, 64 / (n + 2) of them lie side by
-  // side in one staged slot.
-  constexpr int kP = (WC != 0 && WC <= 64) ? 1 : 2;
+  // side in one staged slot. The fetch path with per-wave terms (a wave
+  // holds at most two of the 8 NV units) takes one position per lane at
+  // pitch 66 as well and places the two elements past 64 of its last level's
+  // runs across the tile from values loaded at its start (kPast).
+  constexpr int kWavesO = NT / 64;
+  constexpr bool kPast = !staged && WC == 66 && (8 * NV + kWavesO - 1) / kWavesO <= 2;
+  constexpr int kP = (kPast || (WC != 0 && WC <= 64)) ? 1 : 2;
   constexpr int kG = (staged && WC != 0 && WC <= 32) ? 64 / (WC ? WC : 1) : 1;
   using F = Fetch<S, NT, kP, kG>;
   constexpr bool prefetch = F::J * kP <= 16;
@@ -1472,6 +1504,8 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
     constexpr int kAhead = F::J * kP * (int)sizeof(V) <= 32 ? 3 : 1;
     RingFetchPre<S, NT, kP> fpre;
     ring_fetch_init<S, NT, kP>(fpre, g, xb, yb, eTop, eBot, eLeft, eRight);
+    [[maybe_unused]] RingPast<S, NT, kP> past;
+    if constexpr (kPast) fetch_ring_past<S, NT, kP>(past, fpre, h - 1);
     F f[kAhead];
     if (Hd > 0) {
 #pragma unroll
@@ -1489,6 +1523,13 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
       const V* prv = (l & 1) ? buf0 : buf1;
       level_run<S, WC, NT>(prv, cur, g.W, pl, T0 + l - 1, sp);
       place_fetched(fl, cur);
+      if constexpr (kPast) {
+        if (l == h - 1) {
+#pragma unroll
+          for (int j = 0; j < F::J; ++j)
+            if (past.dst[j] >= 0) cur[past.dst[j]] = past.val[j];
+        }
+      }
       if (refill) fetch_ring_pre<S, NT, kP>(fl, fpre, l + kAhead);
       pl = plan(l + 1);
       __syncthreads();
