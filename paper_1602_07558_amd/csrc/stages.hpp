@@ -591,6 +591,115 @@ __device__ __forceinline__ void up_strips_read_direct(EmitSlot<S, kThreads, P, 8
   }
 }
 
+// Panel emission with several short runs side by side in one wave slot
+// (tile side 16 on one wave): G runs of 64 / G lanes each, every term of a
+// lane's element set up once. An element's panel address is
+// base + l d1 +- 2 NV l^2 and its window index s0 + l ds; it exists at level
+// l when c0 < 2l.
+template <class S, int J>
+struct EmitLanes {
+  typename S::V val[J];
+  typename S::V* dst[J];
+  bool ok[J];
+};
+
+template <class S, int J>
+__device__ __forceinline__ void emit_write(const EmitLanes<S, J>& e) {
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    if (e.ok[j]) *e.dst[j] = e.val[j];
+}
+
+template <class S, int kThreads, int G, int UNITS>
+struct PackPre {
+  static constexpr int kWaves = kThreads / 64, LG = 64 / G;
+  static constexpr int J = ((UNITS + G - 1) / G + kWaves - 1) / kWaves;
+  typename S::V* base[J];
+  int d1[J], s0[J], ds[J], c0[J];
+};
+
+// Upward-pyramid strips (as up_strips_read), packed: element t of a strip
+// exists while t < n - 2l, that is while c0 + 2l < 0 with c0 = t - n.
+template <class S, int kThreads, int G>
+__device__ __forceinline__ void up_pack_init(PackPre<S, kThreads, G, 8 * S::NV>& r, typename S::V* __restrict__ up,
+                                             const Geo& g, int tile) {
+  using R = PackPre<S, kThreads, G, 8 * S::NV>;
+  constexpr int NV = S::NV;
+  const int n = g.n, W = g.W, plane = W * W;
+  const int sub = lane_id() / R::LG, t = lane_id() - sub * R::LG;
+#pragma unroll
+  for (int j = 0; j < R::J; ++j) {
+    const int u = (lwave<kThreads>() + j * R::kWaves) * G + sub;
+    const bool has = sub < G && u < 8 * NV;
+    const int uu = has ? u : 0;
+    const int end = uu / (2 * NV), rem = uu - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    r.base[j] = up + up_end(g, NV, tile, end) + rem * n + t;
+    r.d1[j] = 2 * NV * (n + 1) - 2 * rem;
+    int s0, ds, stride;
+    if (end == 0) {
+      s0 = (1 + k) * W + 1, ds = W + 1, stride = 1;
+    } else if (end == 1) {
+      s0 = (n - k) * W + 1, ds = 1 - W, stride = 1;
+    } else if (end == 2) {
+      s0 = W + 1 + k, ds = W + 1, stride = W;
+    } else {
+      s0 = W + n - k, ds = W - 1, stride = W;
+    }
+    r.s0[j] = v * plane + s0 + t * stride;
+    r.ds[j] = ds;
+    r.c0[j] = has ? t - n : 1 << 28;
+  }
+}
+
+template <class S, int kThreads, int G>
+__device__ __forceinline__ void up_pack_read(EmitLanes<S, PackPre<S, kThreads, G, 8 * S::NV>::J>& e,
+                                             const PackPre<S, kThreads, G, 8 * S::NV>& r,
+                                             const typename S::V* __restrict__ win, int l) {
+  constexpr int NV = S::NV;
+#pragma unroll
+  for (int j = 0; j < PackPre<S, kThreads, G, 8 * S::NV>::J; ++j) {
+    e.ok[j] = r.c0[j] + 2 * l < 0;
+    e.val[j] = win[e.ok[j] ? r.s0[j] + l * r.ds[j] : 0];
+    e.dst[j] = r.base[j] + (l * r.d1[j] - 2 * NV * l * l);
+  }
+}
+
+// Bridge panels (as bridge_ends_read), packed: element t exists while
+// t < len(l) = 2l + cz, stored as c0 = t - cz (exists when c0 < 2l).
+template <class S, int kThreads, int G>
+__device__ __forceinline__ void bridge_pack_init(PackPre<S, kThreads, G, 4 * S::NV>& r,
+                                                 typename S::V* __restrict__ out, bool isx, const Geo& g, int e) {
+  using R = PackPre<S, kThreads, G, 4 * S::NV>;
+  constexpr int NV = S::NV;
+  const int n = g.n, h = g.h, W = g.W, plane = W * W;
+  const int sub = lane_id() / R::LG, t = lane_id() - sub * R::LG;
+#pragma unroll
+  for (int j = 0; j < R::J; ++j) {
+    const int u = (lwave<kThreads>() + j * R::kWaves) * G + sub;
+    const bool has = sub < G && u < 4 * NV;
+    const int uu = has ? u : 0;
+    const int end = uu / (2 * NV), rem = uu - end * 2 * NV, v = rem >> 1, k = rem & 1;
+    r.base[j] = out + (isx ? xb_end(g, NV, e, end) + 4 * rem : yb_end(g, NV, e, end)) + t;
+    r.d1[j] = isx ? 6 * NV + 2 * rem : 2 * rem - 2 * NV;
+    r.s0[j] = v * plane + (isx ? h - 1 : h + 1) * W + (end ? n - k : 1 + k) + t * W;
+    r.ds[j] = end ? -W - 1 : 1 - W;
+    r.c0[j] = has ? t - (isx ? 4 : 0) : 1 << 28;
+  }
+}
+
+template <class S, int kThreads, int G>
+__device__ __forceinline__ void bridge_pack_read(EmitLanes<S, PackPre<S, kThreads, G, 4 * S::NV>::J>& e,
+                                                 const PackPre<S, kThreads, G, 4 * S::NV>& r,
+                                                 const typename S::V* __restrict__ win, int l) {
+  constexpr int NV = S::NV;
+#pragma unroll
+  for (int j = 0; j < PackPre<S, kThreads, G, 4 * S::NV>::J; ++j) {
+    e.ok[j] = r.c0[j] < 2 * l;
+    e.val[j] = win[e.ok[j] ? r.s0[j] + l * r.ds[j] : 0];
+    e.dst[j] = r.base[j] + (l * r.d1[j] + 2 * NV * l * l);
+  }
+}
+
 // Levels 1..H of the upward pyramid of `tile` whose level 0 (the whole tile,
 // window interior) is in buffer b0, then its panels of levels 0..H-1; when
 // H < h (reduced last half cycle) it also writes the level-H square to the
@@ -602,15 +711,23 @@ __device__ void up_levels(typename S::V* buf0, typename S::V* buf1, int b0, cons
   const int top = H < h - 1 ? H : h - 1;
   // Strips are at most n long: one position per lane up to n = 64.
   constexpr int kP = (WC != 0 && WC <= 66) ? 1 : 2;
-  using E = EmitSlot<S, NT, kP, 8 * S::NV>;
   // Groups of many waves hold each wave's few units precomputed; groups of
   // few waves work every term out per level.
+  // At tile sides up to 32 on few waves, 64 / n strips share a wave slot.
   constexpr bool kPre = UpEmitPre<S, NT>::J <= 2;
+  constexpr bool kPack = !kPre && WC != 0 && WC <= 34;
+  constexpr int kG = kPack ? 64 / (WC > 2 ? WC - 2 : 1) : 1;
+  using PK = PackPre<S, NT, kG, 8 * S::NV>;
+  using E = std::conditional_t<kPack, EmitLanes<S, PK::J>, EmitSlot<S, NT, kP, 8 * S::NV>>;
   [[maybe_unused]] UpEmitPre<S, NT> ep;
+  [[maybe_unused]] PK pk;
   if constexpr (kPre) up_emit_init<S, NT>(ep, up, g, tile);
+  if constexpr (kPack) up_pack_init<S, NT, kG>(pk, up, g, tile);
   auto strips_read = [&](E& es, const typename S::V* win, int l) {
     if constexpr (kPre)
       up_strips_read<S, NT, kP>(es, ep, win, g, l);
+    else if constexpr (kPack)
+      up_pack_read<S, NT, kG>(es, pk, win, l);
     else
       up_strips_read_direct<S, NT, kP>(es, win, up, g, tile, l);
   };
@@ -1240,13 +1357,20 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   // Level l's pass also emits the panels of level l-1; they are at most
   // n + 2 long (the x-bridge's), one position per lane up to n = 62.
   constexpr int kPe = (WC != 0 && WC <= 64) ? 1 : 2;
-  using E = EmitSlot<S, NT, kPe, 4 * NV>;
   constexpr bool kPre = BridgeEmitPre<S, NT>::J <= 2;  // as in up_levels
+  constexpr bool kPack = !kPre && WC != 0 && WC <= 32;   // 64 / (n + 2) runs per wave slot
+  constexpr int kGb = kPack ? 64 / (WC ? WC : 1) : 1;
+  using PK = PackPre<S, NT, kGb, 4 * NV>;
+  using E = std::conditional_t<kPack, EmitLanes<S, PK::J>, EmitSlot<S, NT, kPe, 4 * NV>>;
   [[maybe_unused]] BridgeEmitPre<S, NT> ep;
+  [[maybe_unused]] PK pk;
   if constexpr (kPre) bridge_emit_init<S, NT>(ep, out, isx, g, e);
+  if constexpr (kPack) bridge_pack_init<S, NT, kGb>(pk, out, isx, g, e);
   auto ends_read = [&](E& es, const V* win, int l) {
     if constexpr (kPre)
       bridge_ends_read<S, NT, kPe>(es, ep, win, isx, g, l);
+    else if constexpr (kPack)
+      bridge_pack_read<S, NT, kGb>(es, pk, win, l);
     else
       bridge_ends_read_direct<S, NT, kPe>(es, win, out, isx, g, e, l);
   };
