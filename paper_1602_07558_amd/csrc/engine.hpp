@@ -248,6 +248,7 @@ struct PhaseLaunch {
 };
 
 hipError_t launch_batch_phase(int cls, const PhaseLaunch& L, int blocks, size_t lds, hipStream_t st);
+hipError_t batch_phase_resident(int cls, size_t lds, int* out);
 // grids[i].g0.T0 += plans[i].S for every grid.
 hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st);
 bool batch_scheme_supported(int scheme);
@@ -304,6 +305,8 @@ template <int WC, int NT>
 struct BatchPhase {
   static hipError_t launch(const PhaseLaunch& L, int blocks, size_t lds, hipStream_t st);
   static hipError_t lds(int bytes);
+  // Workgroups resident per compute unit at `lds` bytes of dynamic LDS.
+  static hipError_t resident(size_t lds, int* out);
 };
 
 // Host helpers shared by the host files (swept2d_api.cpp).

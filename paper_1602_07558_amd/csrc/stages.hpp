@@ -2315,5 +2315,9 @@ hipError_t BatchPhase<WC, NT>::lds(int bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_phase<WC, NT>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
+template <int WC, int NT>
+hipError_t BatchPhase<WC, NT>::resident(size_t lds, int* out) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_batch_phase<WC, NT>, NT, lds);
+}
 
 }  // namespace swept

@@ -297,8 +297,14 @@ int capture_graph(swept2d_batch* b, Plan& pl, const std::function<hipError_t()>&
 }
 
 // Phased schedule: grid g's phase j goes to slot floor(j L / P_g) (strictly
-// increasing in j since P_g <= L); a slot is one launch per launch class
-// holding that class's entries.
+// increasing in j since P_g <= L); a slot is one or two launches per launch
+// class holding that class's entries. A slot's entries are independent (one
+// phase each of distinct grids), so they may be split between launches: a
+// launch's LDS is its largest entry's, and items of a small footprint (a
+// one-variable scheme) sharing a launch with large ones (two variables)
+// would run at the residency of the large. Entries sorted by LDS are cut
+// where the estimated rounds of items on the compute units, plus about one
+// round per launch for its fill and drain, are fewest.
 int plan_phased(swept2d_batch* b, const std::vector<BatchPlan>& plans, Plan& pl) {
   const int G = b->count;
   int L = 0;
@@ -312,30 +318,73 @@ int plan_phased(swept2d_batch* b, const std::vector<BatchPlan>& plans, Plan& pl)
     int cls, first, count, cumoff, blocks;
     size_t lds;
   };
+  struct Ent {
+    int grid, phase;
+    long long items;
+    size_t lds;
+  };
+  std::map<std::pair<int, size_t>, int> resident_cache;
+  auto resident = [&](int cls, size_t lds, int* out) -> int {
+    auto it = resident_cache.find({cls, lds});
+    if (it == resident_cache.end()) {
+      int r = 0;
+      BHIP(batch_phase_resident(cls, lds, &r), "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+      it = resident_cache.emplace(std::make_pair(cls, lds), std::max(r, 1)).first;
+    }
+    *out = it->second;
+    return 0;
+  };
+  const double cus = std::max(b->cu_count, 1);
   std::vector<int> egrid, ephase, cum;
   std::vector<Rec> recs;
+  int rc;
   for (int sidx = 0; sidx < L; ++sidx) {
     for (int cls = 0; cls < kNumBatchClasses; ++cls) {
-      Rec r{cls, (int)egrid.size(), 0, (int)cum.size(), 0, 0};
-      long long tot = 0;
+      std::vector<Ent> es;
       for (const auto& e : slot[sidx]) {
         const HostGrid& g = b->grids[e.first];
         if (batch_class_of(g.n) != cls) continue;
-        if (r.count == 0) cum.push_back(0);
-        egrid.push_back(e.first);
-        ephase.push_back(e.second);
-        tot += phase_items(g, e.second);
-        if (tot >= (1LL << 31)) return set_error(SWEPT2D_EINVAL, "batch launch exceeds 2^31 workgroups");
-        cum.push_back((int)tot);
-        r.lds = std::max(r.lds, entry_lds(g, e.second));
-        ++r.count;
+        es.push_back({e.first, e.second, phase_items(g, e.second), entry_lds(g, e.second)});
       }
-      if (r.count == 0) continue;
-      r.blocks = (int)tot;
-      recs.push_back(r);
+      if (es.empty()) continue;
+      std::stable_sort(es.begin(), es.end(), [](const Ent& a, const Ent& c) { return a.lds < c.lds; });
+      const size_t m = es.size();
+      std::vector<long long> pre(m + 1, 0);
+      for (size_t i = 0; i < m; ++i) pre[i + 1] = pre[i] + es[i].items;
+      // Cost of entries [i, j) as one launch, in rounds.
+      auto cost = [&](size_t i, size_t j, double* out) -> int {
+        int r = 1;
+        if ((rc = resident(cls, es[j - 1].lds, &r))) return rc;
+        *out = (double)(pre[j] - pre[i]) / (r * cus) + 1.0;
+        return 0;
+      };
+      size_t cut = m;
+      double best = 0.0;
+      if ((rc = cost(0, m, &best))) return rc;
+      for (size_t k = 1; k < m; ++k) {
+        if (es[k].lds == es[k - 1].lds) continue;
+        double c0 = 0.0, c1 = 0.0;
+        if ((rc = cost(0, k, &c0)) || (rc = cost(k, m, &c1))) return rc;
+        if (c0 + c1 < best * (1.0 - 1e-9)) best = c0 + c1, cut = k;
+      }
+      for (size_t lo = 0; lo < m; lo = cut, cut = m) {
+        Rec r{cls, (int)egrid.size(), 0, (int)cum.size(), 0, 0};
+        long long tot = 0;
+        cum.push_back(0);
+        for (size_t i = lo; i < cut; ++i) {
+          egrid.push_back(es[i].grid);
+          ephase.push_back(es[i].phase);
+          tot += es[i].items;
+          if (tot >= (1LL << 31)) return set_error(SWEPT2D_EINVAL, "batch launch exceeds 2^31 workgroups");
+          cum.push_back((int)tot);
+          r.lds = std::max(r.lds, es[i].lds);
+          ++r.count;
+        }
+        r.blocks = (int)tot;
+        recs.push_back(r);
+      }
     }
   }
-  int rc;
   if ((rc = upload_array(&pl.d_egrid, egrid)) || (rc = upload_array(&pl.d_ephase, ephase)) ||
       (rc = upload_array(&pl.d_cum, cum)))
     return rc;

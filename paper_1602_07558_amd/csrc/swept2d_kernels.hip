@@ -131,6 +131,17 @@ hipError_t launch_batch_phase(int cls, const PhaseLaunch& L, int blocks, size_t 
   }
 }
 
+hipError_t batch_phase_resident(int cls, size_t lds, int* out) {
+  switch (cls) {
+    case kClass66: return BatchPhase<66, 1024>::resident(lds, out);
+    case kClass34: return BatchPhase<34, 256>::resident(lds, out);
+    case kClass18: return BatchPhase<18, 64>::resident(lds, out);
+    case kClassGen256: return BatchPhase<0, 256>::resident(lds, out);
+    case kClassGen64: return BatchPhase<0, 64>::resident(lds, out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrids, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_bump, dim3((ngrids + 255) / 256), dim3(256), 0, st, grids, plans, ngrids);
   return hipGetLastError();
