@@ -152,7 +152,12 @@ int model_tile(const HostGrid& g, int cus) {
     const double tiles = (double)(g.nx / n) * (g.ny / n);
     const double rounds = std::ceil(2.0 * tiles / (per_cu * std::max(cus, 1)));
     double cost = (2.0 * tau + 3.0 * h * lambda * threads / 1024.0) * rounds / h;
-    if (pitch_of(n) == 0) cost *= 1.25;  // generic stage code
+    // Generic stage code (window pitch known only at run time). In a batch
+    // the tile-16 grids set the number of phases, so a larger generic side
+    // gains no latency there and costs throughput: measured on the uneven
+    // 256-grid workload, side 16 beat the generic sides 34-60 that a factor
+    // of 1.25 chose.
+    if (pitch_of(n) == 0) cost *= 2.0;
     if (cost < best_cost * (1.0 - 1e-9)) {
       best_cost = cost;
       best = n;
