@@ -344,6 +344,41 @@ __device__ __forceinline__ void cols_run(const typename S::V* __restrict__ in, t
   }
 }
 
+// One level on one wave at tile side 16, one rectangle point per lane: lane
+// i of pass q takes point k = i + 64 q of the rectangle in row order (row
+// k / w, column k mod w) and reads its 3x3 neighbourhood from LDS. A level of
+// w hg points takes ceil(w hg / 64) passes, where the column layout would
+// take one pass over all sixteen rows whatever the rectangle; the pyramids'
+// and bridges' small levels fit one pass. The row index comes from a float
+// product: for k < 4096 and w <= 64, (k + 1/2) / w lies at least 1/(2w) from
+// an integer, far beyond the product's rounding error.
+template <class S, int WC, bool TR>
+__device__ __forceinline__ void compute_compact(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                                int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV, W = WC, plane = W * W;
+  const int npts = w * hg;
+  const float inv_w = 1.0f / (float)(w > 0 ? w : 1);
+  for (int base = 0; base < npts; base += 64) {
+    const int k = base + lane_id();
+    if (k < npts) {
+      const int dy = (int)(((float)k + 0.5f) * inv_w);
+      const int o = (y0 + dy) * W + x0 + (k - dy * w);
+      V nb[3][3][NV];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) nb[r][c][v] = in[v * plane + o + (r - 1) * W + (c - 1)];
+      V res[NV];
+      S::step(T, RegNb<V, NV, TR>{&nb[0]}, res, sp);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v * plane + o] = res[v];
+    }
+  }
+}
+
 // One level with column ownership: the rows of the thread's column that lie
 // in the rectangle [x0, x0+w) x [y0, y0+hg) get sub-step T from `in` into
 // `out`. The thread first reads the R+2 rows of its column it needs (its own
@@ -363,6 +398,8 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
   constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N;
   if constexpr (N == 64) {
     cols_run<S, WC, NT, TR, DPP>(in, out, cols_plan<WC, NT>(x0, y0, w, hg), T, sp);
+  } else if constexpr (NT == 64 && WC == 18) {
+    compute_compact<S, WC, TR>(in, out, x0, y0, w, hg, T, sp);
   } else {
     constexpr int R = Lay<S, WC, NT>::R;
     const int t = ltid<NT>();
