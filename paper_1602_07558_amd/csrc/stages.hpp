@@ -344,23 +344,23 @@ __device__ __forceinline__ void cols_run(const typename S::V* __restrict__ in, t
   }
 }
 
-// One level on one wave at tile side 16, one rectangle point per lane: lane
-// i of pass q takes point k = i + 64 q of the rectangle in row order (row
-// k / w, column k mod w) and reads its 3x3 neighbourhood from LDS. A level of
-// w hg points takes ceil(w hg / 64) passes, where the column layout would
-// take one pass over all sixteen rows whatever the rectangle; the pyramids'
-// and bridges' small levels fit one pass. The row index comes from a float
+// One level at tile sides 16 and 32 (a few waves), one rectangle point per
+// thread: thread i of pass q takes point k = i + NT q of the rectangle in row
+// order (row k / w, column k mod w) and reads its 3x3 neighbourhood from LDS.
+// A level of w hg points takes ceil(w hg / NT) passes, where the column layout
+// would take one pass over every row of the tile whatever the rectangle; the
+// pyramids' and bridges' small levels fit one pass. The row index comes from a float
 // product: for k < 4096 and w <= 64, (k + 1/2) / w lies at least 1/(2w) from
 // an integer, far beyond the product's rounding error.
-template <class S, int WC, bool TR>
+template <class S, int WC, int NT, bool TR>
 __device__ __forceinline__ void compute_compact(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                                 int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
   constexpr int NV = S::NV, W = WC, plane = W * W;
   const int npts = w * hg;
   const float inv_w = 1.0f / (float)(w > 0 ? w : 1);
-  for (int base = 0; base < npts; base += 64) {
-    const int k = base + lane_id();
+  for (int base = 0; base < npts; base += NT) {
+    const int k = base + ltid<NT>();
     if (k < npts) {
       const int dy = (int)(((float)k + 0.5f) * inv_w);
       const int o = (y0 + dy) * W + x0 + (k - dy * w);
@@ -398,8 +398,8 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
   constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N;
   if constexpr (N == 64) {
     cols_run<S, WC, NT, TR, DPP>(in, out, cols_plan<WC, NT>(x0, y0, w, hg), T, sp);
-  } else if constexpr (NT == 64 && WC == 18) {
-    compute_compact<S, WC, TR>(in, out, x0, y0, w, hg, T, sp);
+  } else if constexpr (WC == 18 || WC == 34) {
+    compute_compact<S, WC, NT, TR>(in, out, x0, y0, w, hg, T, sp);
   } else {
     constexpr int R = Lay<S, WC, NT>::R;
     const int t = ltid<NT>();
