@@ -148,6 +148,47 @@ __device__ __forceinline__ void stage_runs(V* __restrict__ lds, const V* s0, int
       [&](int q, V v) { lds[q] = v; });
 }
 
+// The same copy for NR runs of at most C kThreads elements each: every run
+// is read from its own base, so a load costs an index clamp and its offset
+// instead of a choice among the runs per element; all loads are issued
+// before the first store. Runs past NR are ignored.
+template <int kThreads, int C, int NR, class V>
+__device__ __forceinline__ void stage_runs_fixed(V* __restrict__ lds, const V* s0, int n0, const V* s1, int n1,
+                                                 const V* s2, int n2, const V* s3, int n3) {
+  const V* src[4] = {s0, s1, s2, s3};
+  const int cnt[4] = {n0, n1, n2, n3};
+  const int t = ltid<kThreads>();
+  V r[NR][C];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const int last = cnt[k] > 0 ? cnt[k] - 1 : 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int q = t + c * kThreads;
+      r[k][c] = src[k][q < last ? q : last];
+    }
+  }
+  int off = 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int q = t + c * kThreads;
+      if (q < cnt[k]) lds[off + q] = r[k][c];
+    }
+    off += cnt[k];
+  }
+}
+
+// Elements per thread of the longest of `runs` staged runs of `len` values
+// at a compiled window pitch, or 0 where the fixed copy does not apply (run
+// time pitch, or more than 192 bytes of loads in flight per thread).
+template <class V, int kThreads>
+constexpr int stage_fixed_count(int len, int runs) {
+  const int c = (len + kThreads - 1) / kThreads;
+  return (len > 0 && c * runs * (int)sizeof(V) <= 192) ? c : 0;
+}
+
 // ------------------------------------------------------------------ quads
 
 // The four points of a quad: o[0] = (x, y), o[1] = (x+1, y), o[2] = (x, y+1),
@@ -1414,7 +1455,13 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   if constexpr (staged) {
     const V* sA = up + up_end(g, NV, e, isx ? 3 : 1);
     const V* sB = up + up_end(g, NV, tB, isx ? 2 : 0);
-    stage_runs<NT, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
+    // Runs of at most 2 NV up_levels_len(n, h) values.
+    constexpr int kH = (WC - 2) / 2;
+    constexpr int kC = stage_fixed_count<V, NT>(WC ? 2 * NV * kH * (WC - 2 - kH + 1) : 0, 2);
+    if constexpr (kC > 0)
+      stage_runs_fixed<NT, kC, 2, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
+    else
+      stage_runs<NT, V>(stg, sA, LH, sB, LH, sA, 0, sA, 0);
     __syncthreads();
   }
   StripPre<S, NT, kP, kG> pre;
@@ -1636,8 +1683,16 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   using F = Fetch<S, NT, kP, kG>;
   constexpr bool prefetch = F::J * kP <= 16;
   if constexpr (staged) {
-    stage_runs<NT, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
-                  yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
+    // Runs of at most 2 NV xb_levels_len(h) values (the x-bridges'; the
+    // y-bridges' are shorter).
+    constexpr int kH = (WC - 2) / 2;
+    constexpr int kC = stage_fixed_count<V, NT>(WC ? 2 * NV * kH * (kH + 3) : 0, 4);
+    if constexpr (kC > 0)
+      stage_runs_fixed<NT, kC, 4, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
+                                     yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
+    else
+      stage_runs<NT, V>(stg, xb + xb_end(g, NV, eTop, 1), LxH, xb + xb_end(g, NV, eBot, 0), LxH,
+                        yb + yb_end(g, NV, eLeft, 1), LyH, yb + yb_end(g, NV, eRight, 0), LyH);
     __syncthreads();
   }
   RingPre<S, NT, kP, kG> pre;
