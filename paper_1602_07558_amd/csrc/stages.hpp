@@ -391,15 +391,16 @@ __device__ __forceinline__ void cols_run(const typename S::V* __restrict__ in, t
 // A level of w hg points takes ceil(w hg / NT) passes, where the column layout
 // would take one pass over every row of the tile whatever the rectangle; the
 // pyramids' and bridges' small levels fit one pass. The row index comes from a float
-// product: for k < 4096 and w <= 64, (k + 1/2) / w lies at least 1/(2w) from
-// an integer, far beyond the product's rounding error.
+// product with the hardware reciprocal of w (within one ulp): for k < 4096
+// and w <= 64, (k + 1/2) / w lies at least 1/(2w) from an integer, far
+// beyond the product's error.
 template <class S, int WC, int NT, bool TR>
 __device__ __forceinline__ void compute_compact(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                                 int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
   constexpr int NV = S::NV, W = WC, plane = W * W;
   const int npts = w * hg;
-  const float inv_w = 1.0f / (float)(w > 0 ? w : 1);
+  const float inv_w = __builtin_amdgcn_rcpf((float)(w > 0 ? w : 1));
   for (int base = 0; base < npts; base += NT) {
     const int k = base + ltid<NT>();
     if (k < npts) {
