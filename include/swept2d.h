@@ -195,7 +195,8 @@ int swept2d_set_launch_mode(swept2d *h, int mode);
  * levels before it places them. At tile sides 32 and 64 a tile's two
  * bridges run in one workgroup where both fit its LDS. SWEPT2D_STAGING_AUTO
  * stages an octahedron only where its workgroup has too few waves to keep
- * each wave's ring runs precomputed, and fetches the bridges' inputs;
+ * each wave's ring runs precomputed, and fetches the bridges' inputs (at
+ * tile side 32 it runs the bridges as SWEPT2D_STAGING_SINGLE_BRIDGES does);
  * SWEPT2D_STAGING_ON stages every component whose inputs fit the LDS;
  * SWEPT2D_STAGING_OFF stages nothing; SWEPT2D_STAGING_SINGLE_BRIDGES is AUTO
  * with one staged workgroup per bridge. The one-wave groups (tile sides up

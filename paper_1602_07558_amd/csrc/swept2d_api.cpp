@@ -251,8 +251,15 @@ bool oct_staged(const swept2d* h) {
   return h->staging == SWEPT2D_STAGING_ON || !oct_fetch_ahead(h->scheme, h->n);
 }
 
+// At tile side 32, AUTO runs the bridges as SINGLE_BRIDGES does: one staged
+// workgroup per bridge measured as fast as the pairs for heat and wave in
+// FP64, Euler and wave FP32C, and faster for heat FP32C (7.1 against 7.6 ms
+// per 2048 steps of 1024^2).
+bool auto_single_bridges(const swept2d* h) { return h->staging == SWEPT2D_STAGING_AUTO && h->n == 32; }
+
 bool bridge_staged(const swept2d* h) {
-  if (h->staging == SWEPT2D_STAGING_OFF || h->staging == SWEPT2D_STAGING_AUTO) return false;
+  if (h->staging == SWEPT2D_STAGING_OFF) return false;
+  if (h->staging == SWEPT2D_STAGING_AUTO && !auto_single_bridges(h)) return false;
   return window_lds_bytes(h->si, h->n) + bridge_stage_bytes(h->si, h->n) <= g_lds_limit;
 }
 
@@ -367,7 +374,7 @@ int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, 
   Launcher L{h, timed};
   const int sc = h->scheme;
   const bool so = oct_staged(h), sb = bridge_staged(h);
-  const bool pairs = h->staging != SWEPT2D_STAGING_SINGLE_BRIDGES;
+  const bool pairs = h->staging != SWEPT2D_STAGING_SINGLE_BRIDGES && !auto_single_bridges(h);
   const long long q = S / hh;
   const int r = (int)(S % hh);
   int rc;
