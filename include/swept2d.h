@@ -137,12 +137,20 @@ int swept2d_set_tile(swept2d *h, int n);
 /* Current tile side. */
 int swept2d_get_tile(const swept2d *h);
 
+/* Stream selector for swept2d_bind: the HIP null stream (hipStream_t 0,
+ * which is torch's default stream on ROCm). NULL itself selects the
+ * library's own stream. */
+#define SWEPT2D_NULL_STREAM ((void *)(~(size_t)0))
+
 /* Use a caller-owned device buffer as the state and a caller stream for all
  * launches. dev_state must hold swept2d_state_bytes(h) bytes in the layout
  * of the handle's precision and stay valid until the handle is destroyed or
- * rebound. hip_stream is a hipStream_t; NULL selects the library's own
- * stream. Passing dev_state = NULL returns to a library-owned state
- * (zeroed). */
+ * rebound. hip_stream is a hipStream_t, SWEPT2D_NULL_STREAM for the null
+ * stream, or NULL for the library's own stream (created with
+ * hipStreamNonBlocking, so it is not ordered with the null stream). Graphs
+ * of SWEPT2D_LAUNCH_GRAPH are captured on the library's own stream and
+ * launched on the bound one. Passing dev_state = NULL returns to a
+ * library-owned state (zeroed). Waits for the previous stream first. */
 int swept2d_bind(swept2d *h, void *dev_state, void *hip_stream);
 
 /* Bytes of the device state: nvars*nx*ny*8 for both precisions (FP32C keeps

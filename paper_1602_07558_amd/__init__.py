@@ -183,6 +183,11 @@ def swept2d_get_tile(h: int) -> int:
     return _check(load_library().swept2d_get_tile(h))
 
 
+# swept2d_bind's selector of the HIP null stream (stream handle 0, torch's
+# default stream); None selects the library's own stream.
+NULL_STREAM = ctypes.c_size_t(-1).value
+
+
 def swept2d_bind(h: int, dev_ptr: int | None, stream: int | None) -> int:
     return _check(load_library().swept2d_bind(h, dev_ptr or None, stream or None))
 
@@ -406,14 +411,16 @@ class Swept2D:
         return out
 
     def bind_tensor(self, t, stream=None):
-        """Use a torch CUDA tensor as the state (and torch's current stream)."""
+        """Use a torch CUDA tensor as the state, and a torch stream (default:
+        torch's current stream; its default stream is the HIP null stream,
+        handle 0) for every launch."""
         import torch
         shape, dt = self.raw_shape()
         tdt = torch.float64 if dt == np.float64 else torch.float32
         if tuple(t.shape) != shape or t.dtype != tdt or not t.is_contiguous() or not t.is_cuda:
             raise ValueError(f"state tensor must be a contiguous CUDA {tdt} tensor of shape {shape}")
         s = stream if stream is not None else torch.cuda.current_stream(t.device)
-        swept2d_bind(self.h, t.data_ptr(), s.cuda_stream)
+        swept2d_bind(self.h, t.data_ptr(), s.cuda_stream if s.cuda_stream else NULL_STREAM)
         self._bound = t
 
     def unbind(self):

@@ -257,8 +257,13 @@ struct Heat32C {
   }
 };
 
-// Leapfrog as u' = u + v, v = ((u - q) - (c_u - c_q)) + C2 lap(u) with Kahan
-// on u; q' = u and c_q' = c_u. Slots: u, q, c_u, c_q.
+// Leapfrog as u' = u + v, v = ((u - q) - (c_u - c_q)) + C2 lap, with Kahan
+// on u; q' = u and c_q' = c_u. Slots: u, q, c_u, c_q. lap is the Laplacian
+// of the compensated values u - c_u: that of the u's (differences against
+// the centre, exact for a smooth field) minus that of the c_u's (rounding
+// errors in size, so their plain sum is accurate far below the unit of u).
+// Leapfrog keeps every error of v in the displacement, so both corrections
+// matter over long runs.
 struct Wave32C {
   using V = float;
   static constexpr int NV = 4, NVAR = 2, SUB = 1;
@@ -270,7 +275,10 @@ struct Wave32C {
     const float q = nb(0, 0, 1);
     const float cu = nb(0, 0, 2);
     const float cq = nb(0, 0, 3);
-    const float lap = ((nb(-1, 0, 0) - u) + (nb(1, 0, 0) - u)) + ((nb(0, -1, 0) - u) + (nb(0, 1, 0) - u));
+    const float lapu = ((nb(-1, 0, 0) - u) + (nb(1, 0, 0) - u)) + ((nb(0, -1, 0) - u) + (nb(0, 1, 0) - u));
+    // 4 c_u is exact, so the fused form rounds once at the written difference.
+    const float lapc = __builtin_fmaf(-4.0f, cu, (nb(-1, 0, 2) + nb(1, 0, 2)) + (nb(0, -1, 2) + nb(0, 1, 2)));
+    const float lap = lapu - lapc;
     const float v = ((u - q) - (cu - cq)) + c2 * lap;
     const float y = v - cu;
     const float t = u + y;

@@ -471,10 +471,17 @@ int run_method(swept2d* h, int method, long long nsteps) {
   auto it = h->graphs.find({method, S});
   if (it != h->graphs.end()) exec = it->second;
   if (!exec) {
-    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    // The null stream cannot be captured: record the launches on the
+    // library's own stream (capture executes nothing) and launch the graph
+    // on the bound stream.
+    const hipStream_t run_stream = h->stream;
+    const hipStream_t cap = run_stream ? run_stream : h->own_stream;
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    h->stream = cap;
     rc = method == 0 ? enqueue_swept(h, S, 0, h->d_tbase, false) : enqueue_plain(h, S, 0, h->d_tbase, false);
+    h->stream = run_stream;
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    hipError_t e = hipStreamEndCapture(cap, &graph);
     if (rc) {
       if (graph) hipGraphDestroy(graph);
       return rc;
@@ -548,7 +555,8 @@ swept2d* swept2d_create(int nx, int ny, int nvars, int pde, int substeps) {
 
 void swept2d_destroy(swept2d* h) {
   if (!h) return;
-  if (h->stream) hipStreamSynchronize(h->stream);
+  hipStreamSynchronize(h->stream);
+  if (h->own_stream && h->own_stream != h->stream) hipStreamSynchronize(h->own_stream);
   drop_graphs(h);
   free_panels(h);
   if (h->scratch) hipFree(h->scratch);
@@ -608,7 +616,10 @@ int swept2d_bind(swept2d* h, void* dev_state, void* hip_stream) {
   if (!h) return fail(SWEPT2D_EINVAL, "null handle");
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   drop_graphs(h);
-  h->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->own_stream;
+  if (hip_stream == SWEPT2D_NULL_STREAM)
+    h->stream = nullptr;
+  else
+    h->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->own_stream;
   if (dev_state) {
     if (h->owns_state && h->state) hipFree(h->state);
     h->state = dev_state;

@@ -40,6 +40,7 @@ def _swept(pde, params, s0, steps, prec=sw.FP64):
         return g.download(), g.tile
 
 
+@pytest.mark.timeout(900)
 def test_heat_1024_20000_steps_fp64_bitwise():
     s0 = si.heat_field(1024, 1024, seed=0)
     p = si.default_params(si.HEAT5)
@@ -49,6 +50,7 @@ def test_heat_1024_20000_steps_fp64_bitwise():
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.timeout(900)
 def test_heat_1024_20000_steps_fp32c_error():
     s0 = si.heat_field(1024, 1024, seed=0)
     p = si.default_params(si.HEAT5)
@@ -68,19 +70,44 @@ def test_heat_1024_fp32c_bitwise_against_compensated_oracle():
     assert np.array_equal(got, u.astype(np.float64) - c.astype(np.float64))
 
 
-def test_wave_2048_fp64_bitwise_and_fp32c_error():
-    steps = 2000
+WAVE_STEPS = 10000
+
+
+@pytest.mark.timeout(900)
+def test_wave_2048_10000_steps_fp64_bitwise():
     s0 = si.wave_field(2048, 2048, seed=0)
     p = si.default_params(si.WAVE_LF)
-    got, tile = _swept(si.WAVE_LF, p, s0, steps)
-    ref = _oracle64("wave2048", si.WAVE_LF, s0, p, steps)
+    got, tile = _swept(si.WAVE_LF, p, s0, WAVE_STEPS)
+    assert tile == 64
+    ref = _oracle64("wave2048", si.WAVE_LF, s0, p, WAVE_STEPS)
     assert np.array_equal(got, ref), tile
-    got32, _ = _swept(si.WAVE_LF, p, s0, steps, prec=sw.FP32C)
+
+
+@pytest.mark.timeout(900)
+def test_wave_2048_10000_steps_fp32c_error():
+    s0 = si.wave_field(2048, 2048, seed=0)
+    p = si.default_params(si.WAVE_LF)
+    got32, _ = _swept(si.WAVE_LF, p, s0, WAVE_STEPS, prec=sw.FP32C)
+    ref = _oracle64("wave2048", si.WAVE_LF, s0, p, WAVE_STEPS)
     err = _normwise(got32, ref)
-    print(f"wave 2048^2 FP32C after {steps} steps: normwise relative error {err:.3e}")
+    print(f"wave 2048^2 FP32C after {WAVE_STEPS} steps: normwise relative error {err:.3e}")
     assert err <= 1e-6
 
 
+@pytest.mark.timeout(900)
+def test_wave_2048_fp32c_bitwise_against_compensated_oracle():
+    """The benchmark's wave path (tile side 64, 1024 tiles) in FP32C, bit for
+    bit against the FP32C oracle."""
+    s0 = si.wave_field(2048, 2048, seed=0)
+    p = si.default_params(si.WAVE_LF)
+    got, tile = _swept(si.WAVE_LF, p, s0, 1000, prec=sw.FP32C)
+    assert tile == 64
+    u, c = oracle.split_f32c(s0)
+    u, c = oracle.advance_f32c(si.WAVE_LF, u, c, p, 1000, threads=oracle.default_threads())
+    assert np.array_equal(got, u.astype(np.float64) - c.astype(np.float64))
+
+
+@pytest.mark.timeout(900)
 def test_euler_512_5000_steps_fp64_bitwise_and_fp32c_error():
     s0 = si.euler_field(512, 512, seed=0)
     p = si.default_params(si.EULER_RUS_RK2, s0)

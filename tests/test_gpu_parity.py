@@ -184,6 +184,36 @@ def test_torch_bound_state():
         g.unbind()
 
 
+def test_torch_default_stream_ordering():
+    """Bound to torch's default stream (the HIP null stream), launches are
+    ordered with torch work on it: a copy queued just before an advance is
+    seen by it, and a read queued just after sees its result, with only
+    stream-level synchronisation. A long torch product ahead of the copy
+    keeps the stream busy, so a launch on an unordered stream would run
+    before the copy lands."""
+    import torch
+    nx, ny = 256, 128
+    s0 = si.heat_field(nx, ny, seed=6)
+    p = si.default_params(si.HEAT5)
+    src = torch.tensor(s0, device="cuda:0")
+    a = torch.randn(4096, 4096, device="cuda:0")
+    for launch_mode in (sw.LAUNCH_DIRECT, sw.LAUNCH_GRAPH):
+        t = torch.zeros_like(src)
+        with sw.Swept2D(nx, ny, si.HEAT5, p, tile=32) as g:
+            g.set_launch_mode(launch_mode)
+            g.bind_tensor(t)
+            stream = torch.cuda.current_stream()
+            assert stream.cuda_stream == 0
+            for _ in range(3):
+                a = a @ a / 64.0
+            t.copy_(src)
+            g.advance(40)
+            out = t.clone()
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), oracle.advance_f64(si.HEAT5, s0, p, 40)), launch_mode
+            g.unbind()
+
+
 # ------------------------------------------------------------ other schemes
 
 def test_wave_bitwise():
@@ -222,6 +252,8 @@ def test_euler_bitwise():
 @pytest.mark.parametrize("pde,nx,ny,steps,tiles", [
     (si.HEAT5, 64, 64, 300, (8, 32, 64)),
     (si.WAVE_LF, 64, 32, 200, (8, 16, 32)),
+    (si.HEAT5, 128, 128, 150, (64,)),
+    (si.WAVE_LF, 128, 128, 150, (16, 32, 64)),
     (si.EULER_RUS_RK2, 32, 32, 20, (8, 16, 32)),
 ])
 def test_fp32c_bitwise_against_compensated_oracle(pde, nx, ny, steps, tiles):
