@@ -187,6 +187,38 @@ int swept2d_plain_advance(swept2d *h, long long nsteps);
 /* Wait for the handle's stream; reports a pending kernel fault as EHIP. */
 int swept2d_synchronize(swept2d *h);
 
+/* ---------------------------------------------- advance without allocation
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * swept advance as swept2d_advance (same kernels, schedule and bits) on a
+ * caller state, without a handle. Its panels live in one static device
+ * array of SWEPT2D_NOALLOC_SCRATCH_BYTES, which every GPU the library runs
+ * on holds from library load until the process ends; the call makes no
+ * hipMalloc, hipFree or other allocating call.
+ *
+ *   nx, ny, nvars, pde, substeps  as swept2d_create
+ *   prec          SWEPT2D_FP64 or SWEPT2D_FP32C (state layout as a handle's)
+ *   params, np    as swept2d_set_params
+ *   tile          tile side as swept2d_set_tile; 0 lets the cost model pick
+ *   dev_state     caller device buffer [nvars][ny][nx] in the precision's
+ *                 layout, advanced in place (borrowed for the call's work)
+ *   T             the state's level in sub-steps (a multiple of substeps);
+ *                 the operation applied at level T is sub-step T mod substeps
+ *   nsteps        full steps to advance (0: only validation)
+ *   hip_stream    a hipStream_t, or NULL / SWEPT2D_NULL_STREAM for the null
+ *                 stream; the call is asynchronous on it
+ *
+ * EINVAL for bad arguments and when the panels of the grid at that tile
+ * side exceed the static array (1024 x 1024 heat at tile side 64 needs
+ * 34.6 MB in FP64 and in FP32C); EHIP if the array's device address cannot
+ * be looked up. Every call on a GPU shares that GPU's array and leaves its
+ * last contents in it (every panel value an advance reads, it first writes,
+ * so nothing needs clearing): calls that overlap on one GPU, on different
+ * streams or from different threads, race and give undefined results. */
+#define SWEPT2D_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int swept2d_advance_noalloc(int nx, int ny, int nvars, int pde, int substeps, int prec, const double *params,
+                            int np, int tile, void *dev_state, long long T, long long nsteps, void *hip_stream);
+
 /* Global sub-step counter T: the level of the state, counted in sub-steps
  * since creation (or since the last swept2d_set_substep_counter). The
  * scheme applied at level T is sub-step T mod substeps, so checkpoint and

@@ -66,7 +66,7 @@ EXPORTS = [
     "swept2d_batch_get_tile", "swept2d_batch_autotune", "swept2d_batch_upload", "swept2d_batch_download",
     "swept2d_batch_advance", "swept2d_batch_synchronize", "swept2d_batch_substep_counter",
     "swept2d_batch_set_wait_limit", "swept2d_batch_set_mode", "swept2d_batch_get_mode",
-    "swept2d_batch_launches",
+    "swept2d_batch_launches", "swept2d_advance_noalloc",
 ]
 
 _lib = None
@@ -135,6 +135,7 @@ def load_library():
         "swept2d_batch_set_mode": (i, [vp, i]),
         "swept2d_batch_get_mode": (i, [vp]),
         "swept2d_batch_launches": (i, [vp, ll]),
+        "swept2d_advance_noalloc": (i, [i, i, i, i, i, i, ctypes.POINTER(d), i, i, vp, ll, ll, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -341,6 +342,21 @@ def swept2d_batch_launches(b: int, nsteps: int) -> int:
 
 PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), TEST_HASH: (1, 1),
              TEST_INCR: (1, 1), TEST_PUSH5: (5, 2)}
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def swept2d_advance_noalloc(nx: int, ny: int, pde: int, prec: int, params, tile: int, dev_ptr: int, T: int,
+                            nsteps: int, stream: int | None = None) -> int:
+    """The swept advance without allocation (panels in the library's static
+    device array) of a caller device state; `stream` a HIP stream handle,
+    None or 0 for the null stream."""
+    nvars, sub = PDE_SHAPE[pde]
+    p = np.ascontiguousarray(np.asarray(params if params is not None else [], dtype=np.float64))
+    pp = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
+    return _check(load_library().swept2d_advance_noalloc(nx, ny, nvars, pde, sub, prec, pp, int(p.size), tile,
+                                                         dev_ptr, T, nsteps, stream or NULL_STREAM))
 
 
 class Swept2D:

@@ -28,7 +28,8 @@ SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C"
 BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64)]
 
 SOURCES = [os.path.join(CSRC, f) for f in ("stages_scheme.hip", "stages_batch.hip", "swept2d_kernels.hip",
-                                           "swept2d_api.cpp", "swept2d_batch.cpp")]
+                                           "swept2d_api.cpp", "swept2d_batch.cpp",
+                                           "swept2d_noalloc.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("engine.hpp", "schemes.hpp", "stages.hpp")] + \
     [os.path.join(ROOT, "include", "swept2d.h")]
 

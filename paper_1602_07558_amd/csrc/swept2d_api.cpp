@@ -500,6 +500,73 @@ int run_method(swept2d* h, int method, long long nsteps) {
 
 }  // namespace
 
+namespace swept {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// The swept advance of swept2d_advance_noalloc (its contract is in
+// swept2d.h): validated like a handle's calls, panels carved from the
+// caller's scratch at 256-byte boundaries, the same kernels and schedule on
+// `stream` with direct launches. Uses no device allocation: the handle below
+// lives on the host stack and only names the buffers.
+int noalloc_advance(int nx, int ny, int nvars, int pde, int substeps, int prec, const double* params, int np,
+                    int tile, void* dev_state, long long T, long long nsteps, hipStream_t stream, void* scratch,
+                    size_t scratch_bytes) {
+  g_err.clear();
+  if (pde_nvars(pde) < 0) return fail(SWEPT2D_EINVAL, "unknown pde id %d", pde);
+  if (nvars != pde_nvars(pde) || substeps != pde_substeps(pde))
+    return fail(SWEPT2D_EINVAL, "pde %d takes nvars=%d substeps=%d (got %d, %d)", pde, pde_nvars(pde),
+                pde_substeps(pde), nvars, substeps);
+  if (nx < 2 || ny < 2 || nx > (1 << 16) || ny > (1 << 16))
+    return fail(SWEPT2D_EINVAL, "grid %d x %d out of range (2..65536 per side)", nx, ny);
+  const int need = pde_nparams(pde);
+  if (np < need || np > 4 || (need > 0 && !params)) return fail(SWEPT2D_EINVAL, "pde %d takes %d parameters", pde, need);
+  if (prec != SWEPT2D_FP64 && prec != SWEPT2D_FP32C) return fail(SWEPT2D_EINVAL, "unknown precision %d", prec);
+  const int sc = scheme_of(pde, prec);
+  if (sc < 0) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no FP32-compensated form", pde);
+  if (!dev_state) return fail(SWEPT2D_EINVAL, "null state");
+  if (nsteps < 0 || nsteps > (1LL << 40)) return fail(SWEPT2D_EINVAL, "nsteps out of range");
+  if (T < 0 || T % substeps) return fail(SWEPT2D_EINVAL, "level must be >= 0 and a multiple of substeps");
+  int dev = 0;
+  if (int rc = ensure_device_setup(&dev)) return rc;
+  swept2d h;
+  h.nx = nx;
+  h.ny = ny;
+  h.nvars = nvars;
+  h.pde = pde;
+  h.substeps = substeps;
+  h.prec = prec;
+  h.scheme = sc;
+  h.si = scheme_info(sc);
+  for (int i = 0; i < 4; ++i) h.sp.p[i] = (i < np) ? params[i] : 0.0;
+  h.device = dev;
+  hipDeviceGetAttribute(&h.cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+  if (h.cu_count <= 0) h.cu_count = 256;
+  h.n = tile ? tile : model_tile(&h);
+  if (h.n == 0) return fail(SWEPT2D_EINVAL, "no usable tile side for %d x %d", nx, ny);
+  if (const char* why = tile_problem(&h, h.n)) return fail(SWEPT2D_EINVAL, "tile %d: %s", h.n, why);
+  const int ntiles = (nx / h.n) * (ny / h.n);
+  const size_t vb = h.si.vbytes;
+  const size_t ub = align_up(up_panel_values(ntiles, h.n, h.si.nv) * vb, 256);
+  const size_t xbb = align_up(xb_panel_values(ntiles, h.n, h.si.nv) * vb, 256);
+  const size_t ybb = align_up(yb_panel_values(ntiles, h.n, h.si.nv) * vb, 256);
+  if (ub + xbb + ybb > scratch_bytes)
+    return fail(SWEPT2D_EINVAL, "%d x %d at tile side %d needs %zu bytes of panels; the static scratch holds %zu", nx,
+                ny, h.n, ub + xbb + ybb, scratch_bytes);
+  if (nsteps == 0) return 0;
+  h.state = dev_state;
+  h.owns_state = false;
+  h.stream = stream;
+  h.up = scratch;
+  h.xb = static_cast<char*>(scratch) + ub;
+  h.yb = static_cast<char*>(scratch) + ub + xbb;
+  h.panel_tile = (size_t)h.n;
+  h.staging = SWEPT2D_STAGING_AUTO;
+  return enqueue_swept(&h, nsteps * substeps, T, nullptr, false);
+}
+
+}  // namespace swept
+
 extern "C" {
 
 const char* swept2d_last_error(void) { return g_err.c_str(); }
