@@ -9,9 +9,11 @@ the two share no code; both start from the seeded fields of ``swept_inputs``.
   ``-O2 -ffp-contract=off``). This is the definition that the swept rule
   reproduces exactly: no redundant computation, every point computed from its
   full 3x3 neighbourhood one level below (abstract; Sec. 4).
-* ``swept_model``: the paper's Algorithms 1-5 (upward pyramid, the two
-  bridges, downward pyramid and the driver) executed literally on small grids
-  in pure Python, used to pin the readings of the algorithms' index ranges.
+* ``swept_model``: the swept decomposition of Sec. 3-4 (the level function
+  that assigns every point and level of a half cycle to an upward pyramid, a
+  bridge or a downward pyramid) executed component by component on small
+  grids in pure Python, with its dependency order checked; it pins the
+  component sizes, the panels and the reading of the bridges' printed bound.
 """
 from __future__ import annotations
 

@@ -2,9 +2,10 @@
 
 CPU only. Each test checks the oracle (``oracle/``) against something other
 than itself: closed forms (von Neumann factors, discrete energy), exact
-arithmetic on small inputs, conservation, symmetry, the worked example of the
-paper (``tests/golden/worked_example.json``) and the paper's Algorithms 1-5
-run literally (``oracle.swept_model``).
+arithmetic on small inputs, conservation, symmetry, mutation-sensitive
+closed forms (linear modes, a stationary contact), the worked example of the
+paper (``tests/golden/worked_example.json``) and the swept decomposition of
+Sec. 3-4 executed component by component (``oracle.swept_model``).
 """
 import json
 import math
@@ -448,12 +449,13 @@ def test_f32c_euler_error():
     assert _norm_rel(got[:4], ref[:4]) < 1e-6
 
 
-# ------------------------------------------- the paper's algorithms, literally
+# ------------------------------------- the swept decomposition (Sec. 3-4)
 
 @pytest.mark.parametrize("nx,ny,n", [(16, 16, 8), (8, 8, 8), (16, 16, 4), (24, 16, 8), (12, 12, 4), (8, 12, 2)])
-def test_algorithms_1_to_5_equal_plain_stepping(nx, ny, n):
-    """Every half cycle of Algorithm 5 (with the readings of the printed index
-    ranges) lands on the plain result; the hash stencil makes any misplaced
+def test_decomposition_equals_plain_stepping(nx, ny, n):
+    """Every half cycle of the component-by-component model (pyramids, then
+    bridges, then downward pyramids, the tiling shifted by n/2 between half
+    cycles) lands on the plain result; the hash stencil makes any misplaced
     neighbour or level visible."""
     g = si.hash_field(nx, ny, seed=3)
     got = {}
@@ -464,18 +466,24 @@ def test_algorithms_1_to_5_equal_plain_stepping(nx, ny, n):
         assert np.array_equal(grid, ref)
 
 
-def test_algorithms_heat_equal_plain_stepping():
+def test_decomposition_heat_and_reduced_half_cycle():
     g = si.heat_field(16, 24, seed=2)
     out = sm.swept2d(sm.st_heat(si.HEAT_R), g[0], 8, cycles=2)
     assert np.array_equal(out, oracle.advance_f64(si.HEAT5, g, [si.HEAT_R], 16)[0])
+    # a half cycle of reduced height H < n/2 (the remainder of a step count)
+    h3 = sm.half_cycle(sm.st_heat(si.HEAT_R), g[0], 8, 4, 0, 3)
+    assert np.array_equal(h3, oracle.advance_f64(si.HEAT5, g, [si.HEAT_R], 3)[0])
 
 
-@pytest.mark.parametrize("flag", ["LITERAL_BRIDGE_LOOP", "LITERAL_LAT_OUTPUTS"])
-def test_printed_ranges_do_not_reproduce_plain_stepping(flag, monkeypatch):
-    monkeypatch.setattr(sm, flag, True)
+def test_printed_bridge_band_does_not_cover_the_half_cycle(monkeypatch):
+    """The bridges' compute loop as printed (a two-point band on one side of
+    the edge at every level) leaves points of the bridges' space-time
+    uncomputed, so a downward pyramid or the next level needs a value nothing
+    produced."""
+    monkeypatch.setattr(sm, "LITERAL_BRIDGE_BAND", True)
     g = si.hash_field(16, 16, seed=3)
-    out = sm.swept2d(sm.st_hash, g[0], 8, cycles=1)
-    assert not np.array_equal(out, oracle.advance_f64(si.TEST_HASH, g, [], 8)[0])
+    with pytest.raises(sm.ModelError):
+        sm.swept2d(sm.st_hash, g[0], 8, cycles=1)
 
 
 @pytest.mark.parametrize("n", [2, 4, 6, 8])
@@ -487,28 +495,53 @@ def test_component_sizes(n):
     st = sm.Stats()
     sm.swept2d(sm.st_hash, si.hash_field(nx, ny)[0], n, cycles=1, stats=st)
     tiles_halves = (nx // n) * (ny // n) * 2
-    assert st.computed["up"] == tiles_halves * n * (n - 1) * (n - 2) // 6
-    assert st.computed["long"] == tiles_halves * (n ** 3 - 4 * n) // 12
-    assert st.computed["lat"] == tiles_halves * (n ** 3 - 4 * n) // 12
-    assert st.computed["down"] == tiles_halves * n * (n + 1) * (n + 2) // 6
+    assert st.computed.get(sm.UP, 0) == tiles_halves * n * (n - 1) * (n - 2) // 6
+    assert st.computed.get(sm.YB, 0) == tiles_halves * (n ** 3 - 4 * n) // 12
+    assert st.computed.get(sm.XB, 0) == tiles_halves * (n ** 3 - 4 * n) // 12
+    assert st.computed[sm.DOWN] == tiles_halves * n * (n + 1) * (n + 2) // 6
     assert sum(st.computed.values()) == tiles_halves * n * n * (n // 2)
+
+
+def test_downward_pyramid_ring():
+    """At each level k a downward pyramid reads a ring two wide around its
+    level-k square: 16k values from the four bridges' bands and the four 2x2
+    corners (16 values) from the upward pyramids."""
+    n = 8
+    st = sm.Stats()
+    sm.half_cycle(sm.st_hash, si.hash_field(16, 16)[0], n, 0, 0, n // 2, st)
+    corners = 4
+    for k in range(n // 2):
+        from_bridges = sum(len(v) for key, v in st.crossing.items()
+                           if key[1] == sm.DOWN and key[2] == k and key[0] in (sm.XB, sm.YB))
+        from_up = sum(len(v) for key, v in st.crossing.items() if key[1] == sm.DOWN and key[2] == k and key[0] == sm.UP)
+        assert from_bridges == corners * 16 * k
+        assert from_up == corners * 16
+
+
+def _square(n, k):
+    return {(x, y) for x in range(k, n - k) for y in range(k, n - k)}
 
 
 def test_worked_example_values():
     gold = json.load(open(GOLDEN))
     n = gold["upward_panel_values_per_level"]["n"]
+    h = n // 2
+    # What an upward pyramid sends at level k is the band two wide along the
+    # edges of its level-k square (a 2x2 tip at the last level); each side's
+    # strip holds 16, 12, 8, 4 values for n = 8.
     st = sm.Stats()
-    base = np.ones((n, n))
-    N, S, W, E = sm.upward_pyramid(sm.st_incr, base, 0, st)
-    assert [p.size for p in N] == gold["upward_panel_values_per_level"]["values"]
-    assert [p.size for p in S] == [p.size for p in W] == [p.size for p in E] == [p.size for p in N]
-    # Every value equals its level; the last panel level is the 2x2 tip.
+    sm.half_cycle(sm.st_hash, si.hash_field(2 * n, 2 * n)[0], n, 0, 0, h, st)
+    per_level = []
+    for k in range(h):
+        sent = st.up_sent[((0, 0), k)]
+        assert sent == _square(n, k) - _square(n, k + 2)
+        per_level.append(len({p for p in sent if p[1] in (k, k + 1)}))
+    assert per_level == gold["upward_panel_values_per_level"]["values"]
+    # From level 1 on 8x8 subdomains the tip of each upward pyramid (2x2) is
+    # at level 4.
     start = gold["pyramid_tip_level"]["start_level"]
-    base = np.full((n, n), float(start))
-    N, S, W, E = sm.upward_pyramid(sm.st_incr, base, 0)
-    for k, p in enumerate(N):
-        assert np.all(p == start + k)
-    assert N[-1].shape == (2, 2) and N[-1][0, 0] == gold["pyramid_tip_level"]["tip_level"]
+    assert start + h - 1 == gold["pyramid_tip_level"]["tip_level"]
+    assert len(_square(n, h - 1)) == 4
     # A full cycle on 8x8 subdomains advances 8 levels with 4 communications.
     cyc = gold["cycle"]
     st = sm.Stats()
@@ -517,10 +550,14 @@ def test_worked_example_values():
     assert st.exchanges == cyc["communications"]
     # The downward pyramid computes squares of side 2, 4, ..., n.
     sq = gold["downward_first_square"]["computed_squares"]
-    assert sum(s * s for s in sq) == n * (n + 1) * (n + 2) // 6
+    st = sm.Stats()
+    sm.half_cycle(sm.st_hash, si.hash_field(n, n)[0], n, 0, 0, h, st)
+    assert st.computed[sm.DOWN] == sum(s * s for s in sq) == n * (n + 1) * (n + 2) // 6
     half = gold["half_cycle_substeps"]
     got = {}
-    sm.swept2d(sm.st_incr, np.ones((2 * n, 2 * n)), half["n"], cycles=1,
+    st = sm.Stats()
+    sm.swept2d(sm.st_incr, np.ones((2 * n, 2 * n)), half["n"], cycles=1, stats=st,
                after_half=lambda T, grid: got.__setitem__(T, grid))
     assert sorted(got)[0] == half["substeps"]
     assert np.all(got[half["substeps"]] == 1 + half["substeps"])
+    assert st.exchanges == 2 * half["communications"]
