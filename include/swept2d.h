@@ -81,9 +81,19 @@ extern "C" {
  *        for u - c); the time update is compensated (Kahan), Euler fluxes and
  *        pressure are evaluated in FP64. Available for HEAT5, WAVE_LF and
  *        EULER_RUS_RK2. Device layout: nvars u-planes then nvars c-planes,
+ *        each [ny][nx] float. Swept and per-step results are identical.
+ * FP32R: FP32 values u only in the state and the panels (half the bytes of
+ *        FP32C); the compensations of the same updates live only in a
+ *        workgroup's LDS window while it computes a point's successive
+ *        levels, and start at zero whenever a value arrives from the state
+ *        or a panel. Results therefore depend on the method and tile side:
+ *        swept2d_plain_advance keeps no compensation (plain FP32), the swept
+ *        advance keeps it within each pyramid, bridge and octahedron.
+ *        Available for HEAT5 and WAVE_LF. Device layout: nvars u-planes,
  *        each [ny][nx] float. */
 #define SWEPT2D_FP64 0
 #define SWEPT2D_FP32C 1
+#define SWEPT2D_FP32R 2
 
 /* ---------------------------------------------------------- launch modes
  * DIRECT: every kernel is launched with hipLaunchKernel.
@@ -122,9 +132,9 @@ void swept2d_destroy(swept2d *h);
  * least the number the scheme uses; p is copied. EINVAL otherwise. */
 int swept2d_set_params(swept2d *h, const double *p, int np);
 
-/* Select FP64 or FP32C. Reallocates a library-owned state (zeroed); fails
- * with EINVAL while a caller buffer is bound, EUNSUPPORTED for schemes
- * without an FP32C form. */
+/* Select FP64, FP32C or FP32R. Reallocates a library-owned state (zeroed);
+ * fails with EINVAL while a caller buffer is bound, EUNSUPPORTED for schemes
+ * without that form. */
 int swept2d_set_precision(swept2d *h, int prec);
 
 /* Tile side n of the swept decomposition (Sec. 3: square subdomains of side
@@ -153,16 +163,16 @@ int swept2d_get_tile(const swept2d *h);
  * library-owned state (zeroed). Waits for the previous stream first. */
 int swept2d_bind(swept2d *h, void *dev_state, void *hip_stream);
 
-/* Bytes of the device state: nvars*nx*ny*8 for both precisions (FP32C keeps
- * 4-byte u and 4-byte c per value). */
+/* Bytes of the device state: nvars*nx*ny*8 for FP64 and FP32C (4-byte u and
+ * 4-byte c per value), nvars*nx*ny*4 for FP32R. */
 size_t swept2d_state_bytes(const swept2d *h);
 
 /* Copy a host FP64 state [nvars][ny][nx] in (synchronous). FP32C stores
- * u = (float)x and c = 0. */
+ * u = (float)x and c = 0, FP32R u = (float)x. */
 int swept2d_upload(swept2d *h, const double *host);
 
 /* Copy the state out as FP64 [nvars][ny][nx] (synchronous; waits for the
- * stream). FP32C returns (double)u - (double)c. */
+ * stream). FP32C returns (double)u - (double)c, FP32R (double)u. */
 int swept2d_download(swept2d *h, double *host);
 
 /* Copy the raw device state (swept2d_state_bytes bytes, precision layout)
@@ -197,7 +207,8 @@ int swept2d_synchronize(swept2d *h);
  * hipMalloc, hipFree or other allocating call.
  *
  *   nx, ny, nvars, pde, substeps  as swept2d_create
- *   prec          SWEPT2D_FP64 or SWEPT2D_FP32C (state layout as a handle's)
+ *   prec          SWEPT2D_FP64, SWEPT2D_FP32C or SWEPT2D_FP32R (state layout
+ *                 as a handle's)
  *   params, np    as swept2d_set_params
  *   tile          tile side as swept2d_set_tile; 0 lets the cost model pick
  *   dev_state     caller device buffer [nvars][ny][nx] in the precision's

@@ -5,7 +5,8 @@ leg use this package. The GPU library never imports, links or calls it, and
 the two share no code; both start from the seeded fields of ``swept_inputs``.
 
 * ``advance_f64`` / ``advance_f32c``: the plain FP64 (and FP32-compensated)
-  step-by-step stepper written in C (``stepper.c``, built with
+  step-by-step stepper written in C; ``advance_f32r`` the FP32 stepper whose
+  compensation survives only within one residency of the swept schedule (``stepper.c``, built with
   ``-O2 -ffp-contract=off``). This is the definition that the swept rule
   reproduces exactly: no redundant computation, every point computed from its
   full 3x3 neighbourhood one level below (abstract; Sec. 4).
@@ -59,6 +60,15 @@ def _load():
             ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
         ]
+        lib.oracle_advance_f32r.restype = ctypes.c_int
+        lib.oracle_advance_f32r.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
+        ]
+        lib.oracle_residency.restype = ctypes.c_longlong
+        lib.oracle_residency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -96,6 +106,27 @@ def advance_f32c(pde: int, u: np.ndarray, c: np.ndarray, params, nsub: int, t0: 
     if rc != 0:
         raise ValueError(f"oracle_advance_f32c failed with {rc}")
     return uu, cc
+
+
+def advance_f32r(pde: int, u: np.ndarray, params, nsub: int, tile: int, t0: int = 0,
+                 threads: int | None = None) -> np.ndarray:
+    """FP32 state whose compensation lives only within a residency of the
+    swept schedule on tiles of side ``tile`` (0: the per-step method), as one
+    advance of ``nsub`` sub-steps; ``u`` is ``[nvars][ny][nx]`` float32."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float32).copy()
+    nvars, ny, nx = uu.shape
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    rc = lib.oracle_advance_f32r(int(pde), nx, ny, nvars, p.ctypes.data, int(p.size), uu.ctypes.data, int(tile),
+                                 int(t0), int(nsub), int(threads or default_threads()))
+    if rc != 0:
+        raise ValueError(f"oracle_advance_f32r failed with {rc}")
+    return uu
+
+
+def residency(x: int, y: int, L: int, tile: int, nx: int, ny: int) -> int:
+    """Residency number of point (x, y) at level L of a swept advance."""
+    return int(_load().oracle_residency(x, y, L, tile, nx, ny))
 
 
 def split_f32c(state64: np.ndarray) -> tuple[np.ndarray, np.ndarray]:

@@ -428,3 +428,144 @@ int oracle_advance_f32c(int pde, int nx, int ny, int nvars, const double *params
     free(tc);
     return 0;
 }
+
+/* ------------------------------- FP32, compensation kept within a residency
+ *
+ * The same compensated heat and wave updates, with only the values u part of
+ * the state: what the swept rule's components exchange (panels) and store is
+ * u, and a compensation c lives only while the point's successive levels are
+ * computed by one workgroup in one window (a residency). A value that arrives
+ * from another component, or from the stored state, comes with c = 0.
+ *
+ * Residencies of the swept schedule (Sec. 3-4) for an advance of S sub-steps
+ * on tiles of side n, h = n/2: half cycle k holds levels L = k h + 1 ..
+ * (k + 1) h of the advance (the last one possibly shorter), on the tiling
+ * offset by (k mod 2) h in x and y. With dx, dy the point's distances to the
+ * nearest tile edge of that tiling and l = L - k h, level L belongs to
+ *   the upward pyramid          if dx >= l and dy >= l,
+ *   the downward pyramid        if dx <  l and dy <  l,
+ *   a bridge                    otherwise.
+ * The first upward pyramid (holding level 0 too) is one residency. A downward
+ * pyramid continues in its window as the next half cycle's upward pyramid on
+ * the shifted tiling (the tile centred on its corner), so the two share one
+ * residency; each half cycle's bridges are another. Numbered per point:
+ * upward pyramid of half cycle k -> 2k, its bridge -> 2k + 1, its downward
+ * pyramid -> 2k + 2. A point at level L reads a neighbour's level L - 1 with
+ * its compensation only when both numbers agree (then they are the same
+ * workgroup: components of one phase never read each other's points).
+ * Tile side 0 stands for the per-step method: every level its own launch, so
+ * no compensation survives a sub-step (plain FP32). */
+
+static long long residency(int x, int y, long long L, int n, int nx, int ny)
+{
+    if (n == 0) return L;
+    if (L == 0) return 0;
+    int h = n / 2;
+    long long k = (L - 1) / h;
+    int l = (int)((L - 1) % h) + 1;
+    int off = (k & 1) ? h : 0;
+    int lx = ((x - off) % nx + nx) % nx % n;
+    int ly = ((y - off) % ny + ny) % ny % n;
+    int dx = lx < n - 1 - lx ? lx : n - 1 - lx;
+    int dy = ly < n - 1 - ly ? ly : n - 1 - ly;
+    if (dx >= l && dy >= l) return 2 * k;
+    if (dx < l && dy < l) return 2 * k + 2;
+    return 2 * k + 1;
+}
+
+/* Residency number of point (x, y) at level L of an advance on tile side n
+ * (exported for the pins). */
+long long oracle_residency(int x, int y, long long L, int n, int nx, int ny)
+{
+    return residency(x, y, L, n, nx, ny);
+}
+
+/* Advance u ([nvars][ny][nx] FP32) by nsub sub-steps from global sub-step t0
+ * as one advance on tiles of side n (0: the per-step method). Heat and wave
+ * only. Returns 0, or -1 on invalid arguments, -3 when out of memory. */
+int oracle_advance_f32r(int pde, int nx, int ny, int nvars, const double *params, int nparams, float *u, int n,
+                        long long t0, long long nsub, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nsub < 0 || t0 < 0 || !u || !pde_shape_ok(pde, nvars))
+        return -1;
+    if (pde != PDE_HEAT5 && pde != PDE_WAVE_LF)
+        return -1;
+    if (nparams < nparams_needed(pde) || !params)
+        return -1;
+    if (n != 0 && (n < 2 || (n & 1) || nx % n || ny % n))
+        return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t plane = (size_t)nx * (size_t)ny;
+    size_t tot = plane * (size_t)nvars;
+    float *tu = (float *)malloc(tot * sizeof(float));
+    float *c0 = (float *)calloc(tot, sizeof(float));
+    float *c1 = (float *)malloc(tot * sizeof(float));
+    long long *r0 = (long long *)malloc(plane * sizeof(long long));
+    long long *r1 = (long long *)malloc(plane * sizeof(long long));
+    if (!tu || !c0 || !c1 || !r0 || !r1) {
+        free(tu);
+        free(c0);
+        free(c1);
+        free(r0);
+        free(r1);
+        return -3;
+    }
+    float *cu = u, *cc = c0, *xu = tu, *xc = c1;
+    long long *rprev = r0, *rcur = r1;  /* residency of every point at levels L - 1 and L */
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            rprev[(size_t)j * nx + i] = residency(i, j, 0, n, nx, ny);
+    (void)t0; /* heat and wave apply the same operation at every sub-step */
+    for (long long s = 0; s < nsub; ++s) {
+        long long L = s + 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                rcur[(size_t)j * nx + i] = residency(i, j, L, n, nx, ny);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int j = 0; j < ny; ++j) {
+            float nu[9][MAXV], ncp[9][MAXV];
+            float ou[MAXV], oc[MAXV];
+            for (int i = 0; i < nx; ++i) {
+                long long rp = rcur[(size_t)j * nx + i];
+                for (int dj = -1; dj <= 1; ++dj) {
+                    int jj = (j + dj + ny) % ny;
+                    for (int di = -1; di <= 1; ++di) {
+                        int ii = (i + di + nx) % nx;
+                        int k = 3 * (dj + 1) + (di + 1);
+                        int same = rprev[(size_t)jj * nx + ii] == rp;
+                        for (int v = 0; v < nvars; ++v) {
+                            nu[k][v] = cu[(size_t)v * plane + (size_t)jj * nx + ii];
+                            ncp[k][v] = same ? cc[(size_t)v * plane + (size_t)jj * nx + ii] : 0.0f;
+                        }
+                    }
+                }
+                switch (pde) {
+                case PDE_HEAT5: st_heat_f32c(nu, ncp[4], ou, oc, params); break;
+                case PDE_WAVE_LF: st_wave_f32c(nu, ncp, ou, oc, params); break;
+                }
+                for (int v = 0; v < nvars; ++v) {
+                    xu[(size_t)v * plane + (size_t)j * nx + i] = ou[v];
+                    xc[(size_t)v * plane + (size_t)j * nx + i] = oc[v];
+                }
+            }
+        }
+        float *t = cu;
+        cu = xu;
+        xu = t;
+        t = cc;
+        cc = xc;
+        xc = t;
+        long long *tr = rprev;
+        rprev = rcur;
+        rcur = tr;
+    }
+    if (cu != u)
+        memcpy(u, cu, tot * sizeof(float));
+    free(tu);
+    free(c0);
+    free(c1);
+    free(r0);
+    free(r1);
+    return 0;
+}

@@ -37,6 +37,7 @@ TEST_PUSH5 = 102
 
 FP64 = 0
 FP32C = 1
+FP32R = 2
 
 LAUNCH_DIRECT = 0
 LAUNCH_GRAPH = 1
@@ -415,6 +416,8 @@ class Swept2D:
     def raw_shape(self):
         if self.prec == FP64:
             return (self.nvars, self.ny, self.nx), np.float64
+        if self.prec == FP32R:
+            return (self.nvars, self.ny, self.nx), np.float32
         return (2 * self.nvars, self.ny, self.nx), np.float32
 
     def upload_raw(self, a: np.ndarray):

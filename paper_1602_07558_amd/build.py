@@ -23,7 +23,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswept2d.so")
 
-SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C", "Wave32C", "Euler32C"]
+SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C", "Wave32C", "Euler32C",
+           "Heat32R", "Wave32R"]
 # Batch launch classes: (window pitch, workgroup size).
 BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64)]
 

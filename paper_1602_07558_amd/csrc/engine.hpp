@@ -25,7 +25,7 @@ namespace swept {
 //    every stage with one size).
 template <class S, int WC, int NTo = 0>
 struct Lay {
-  static constexpr bool light = S::NV * (int)sizeof(typename S::V) <= 16;
+  static constexpr bool light = S::NW * (int)sizeof(typename S::V) <= 16;
   static constexpr int N = WC ? WC - 2 : 0;
   static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 66 ? 1024 : (WC == 18 ? 64 : 256)));
   static constexpr int NW = NT / 64;
@@ -108,6 +108,8 @@ enum Scheme : int {
   kHeat32C,
   kWave32C,
   kEuler32C,
+  kHeat32R,
+  kWave32R,
   kNumSchemes
 };
 
@@ -145,7 +147,8 @@ hipError_t launch_set_base(long long* tbase, long long value, hipStream_t s);
 
 // Static facts about a scheme.
 struct SchemeInfo {
-  int nv;          // values per point
+  int nv;          // values per point in the state and the panels
+  int nw;          // values per point in the LDS window (nv plus window-only values)
   int nvar;        // the scheme's nvars
   int sub;         // sub-steps per step
   int vbytes;      // bytes per value
@@ -153,9 +156,9 @@ struct SchemeInfo {
 SchemeInfo scheme_info(int scheme);
 
 // LDS bytes of the stage kernels for tile side n: a double-buffered
-// (n+2)^2 window per value slot, plus the staged panel inputs.
+// (n+2)^2 window per window value, plus the staged panel inputs.
 inline size_t window_lds_bytes(const SchemeInfo& si, int n) {
-  return (size_t)2 * (size_t)(n + 2) * (size_t)(n + 2) * (size_t)si.nv * (size_t)si.vbytes;
+  return (size_t)2 * (size_t)(n + 2) * (size_t)(n + 2) * (size_t)si.nw * (size_t)si.vbytes;
 }
 inline size_t oct_stage_bytes(const SchemeInfo& si, int n) {
   const int h = n / 2;

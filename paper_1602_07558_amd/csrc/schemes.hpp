@@ -3,7 +3,13 @@
 //
 // Each scheme is a struct with
 //   V        value type stored in the state, LDS and panels
-//   NV       values per grid point (FP32C schemes: nvars u's then nvars c's)
+//   NV       values per grid point in the state and the panels (FP32C
+//            schemes: nvars u's then nvars c's)
+//   NW       values per point in a workgroup's LDS window: NV, or more for
+//            schemes with window-only values (the compensations of the FP32
+//            schemes whose compensation stays within a residency), which
+//            start at zero whenever a point's value arrives from the state or
+//            a panel and never leave the window
 //   NVAR     the scheme's nvars, SUB its sub-steps per time step
 //   XY_SYM   step gives the same bits when x and y are exchanged (every
 //            neighbour (di, dj) read as (dj, di)): true where the x terms
@@ -38,7 +44,7 @@ struct SchemeParams {
 // lap = ((uW + uE) + (uN + uS)) - 4u.
 struct Heat64 {
   using V = double;
-  static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  static constexpr int NV = 1, NW = 1, NVAR = 1, SUB = 1;
   static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
@@ -57,7 +63,7 @@ struct Heat64 {
 // (u, q) -> ((2u - q) + C2 lap(u), u).
 struct Wave64 {
   using V = double;
-  static constexpr int NV = 2, NVAR = 2, SUB = 1;
+  static constexpr int NV = 2, NW = 2, NVAR = 2, SUB = 1;
   static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
@@ -79,7 +85,7 @@ struct Wave64 {
 // the sub-step index; the top 52 bits are the new value.
 struct Hash64 {
   using V = double;
-  static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  static constexpr int NV = 1, NW = 1, NVAR = 1, SUB = 1;
   static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
@@ -100,7 +106,7 @@ struct Hash64 {
 // when the nine neighbours are not all at the centre's value (level).
 struct Incr64 {
   using V = double;
-  static constexpr int NV = 1, NVAR = 1, SUB = 1;
+  static constexpr int NV = 1, NW = 1, NVAR = 1, SUB = 1;
   static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams&) {
@@ -119,7 +125,7 @@ struct Incr64 {
 // the 2-ring stencil of Eq. (1), and clears slots 1..4.
 struct Push5 {
   using V = double;
-  static constexpr int NV = 5, NVAR = 5, SUB = 2;
+  static constexpr int NV = 5, NW = 5, NVAR = 5, SUB = 2;
   static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
@@ -202,7 +208,7 @@ __device__ __forceinline__ void increment(const double* W, const double* E, cons
 // U' = 0.5 U + 0.5 (U* + dt L(U*)), written to both halves.
 struct Euler64 {
   using V = double;
-  static constexpr int NV = 8, NVAR = 8, SUB = 2;
+  static constexpr int NV = 8, NW = 8, NVAR = 8, SUB = 2;
   static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
@@ -242,7 +248,7 @@ struct Euler64 {
 
 struct Heat32C {
   using V = float;
-  static constexpr int NV = 2, NVAR = 1, SUB = 1;
+  static constexpr int NV = 2, NW = 2, NVAR = 1, SUB = 1;
   static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
@@ -266,7 +272,7 @@ struct Heat32C {
 // matter over long runs.
 struct Wave32C {
   using V = float;
-  static constexpr int NV = 4, NVAR = 2, SUB = 1;
+  static constexpr int NV = 4, NW = 4, NVAR = 2, SUB = 1;
   static constexpr bool XY_SYM = true;
   template <class NB>
   __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
@@ -294,7 +300,7 @@ struct Wave32C {
 // u = fl32(t), c = fl32(u - t). Slots 0..7 values, 8..15 compensations.
 struct Euler32C {
   using V = float;
-  static constexpr int NV = 16, NVAR = 8, SUB = 2;
+  static constexpr int NV = 16, NW = 16, NVAR = 8, SUB = 2;
   static constexpr bool XY_SYM = false;
   template <class NB>
   __device__ __forceinline__ static double wide(const NB& nb, int di, int dj, int v) {
@@ -336,6 +342,20 @@ struct Euler32C {
       }
     }
   }
+};
+
+// FP32 with the compensation kept only within a residency: the state and
+// the panels hold the values u alone (half the bytes of FP32C); the
+// compensations are window-only values, zero when a point's value arrives
+// from the state or a panel, so a value keeps its compensation while one
+// workgroup computes its successive levels and loses it when it moves on.
+// The updates are those of the FP32C schemes (slots as there, the
+// compensations after the values).
+struct Heat32R : Heat32C {
+  static constexpr int NV = 1, NW = 2;
+};
+struct Wave32R : Wave32C {
+  static constexpr int NV = 2, NW = 4;
 };
 
 }  // namespace swept

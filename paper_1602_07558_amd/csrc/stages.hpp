@@ -195,7 +195,7 @@ constexpr int stage_fixed_count(int len, int runs) {
 // o[3] = (x+1, y+1).
 template <class S>
 struct Quad {
-  typename S::V o[4][S::NV];
+  typename S::V o[4][S::NW];
 };
 
 template <class S, int WC, bool TR>
@@ -213,7 +213,7 @@ template <class S, int WC>
 __device__ __forceinline__ void quad_store(typename S::V* __restrict__ out, int idx, int Wrt, const Quad<S>& q) {
   const int W = WC ? WC : Wrt, plane = W * W;
 #pragma unroll
-  for (int v = 0; v < S::NV; ++v) {
+  for (int v = 0; v < S::NW; ++v) {
     out[v * plane + idx] = q.o[0][v];
     out[v * plane + idx + 1] = q.o[1][v];
     out[v * plane + idx + W] = q.o[2][v];
@@ -338,7 +338,7 @@ template <class S, int WC, int NT, bool TR, bool DPP>
 __device__ __forceinline__ void cols_run(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                          const ColsPlan<NT>& p, long long T, const SchemeParams& sp) {
   using V = typename S::V;
-  constexpr int NV = S::NV, W = WC, plane = W * W, R = ColsPlan<NT>::R;
+  constexpr int NV = S::NW, W = WC, plane = W * W, R = ColsPlan<NT>::R;  // every window value
 #pragma unroll
   for (int k = 0; k < ColsPlan<NT>::KG; ++k) {
     if (!p.act[k]) continue;
@@ -398,7 +398,7 @@ template <class S, int WC, int NT, bool TR>
 __device__ __forceinline__ void compute_compact(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                                 int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
-  constexpr int NV = S::NV, W = WC, plane = W * W;
+  constexpr int NV = S::NW, W = WC, plane = W * W;  // every window value
   const int npts = w * hg;
   const float inv_w = __builtin_amdgcn_rcpf((float)(w > 0 ? w : 1));
   for (int base = 0; base < npts; base += NT) {
@@ -437,7 +437,7 @@ template <class S, int WC, int NT, bool TR, bool DPP>
 __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                              int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
-  constexpr int NV = S::NV, W = WC, plane = W * W, N = Lay<S, WC, NT>::N;
+  constexpr int NV = S::NW, W = WC, plane = W * W, N = Lay<S, WC, NT>::N;  // every window value
   if constexpr (N == 64) {
     cols_run<S, WC, NT, TR, DPP>(in, out, cols_plan<WC, NT>(x0, y0, w, hg), T, sp);
   } else if constexpr (WC == 18 || WC == 34) {
@@ -1364,6 +1364,25 @@ __device__ __forceinline__ void bridge_ends_read_direct(EmitSlot<S, kThreads, P,
   }
 }
 
+// Window-only values (NW > NV) start at zero in both buffers: a point's
+// value that arrives from the state or a panel comes without them, and a
+// point computed in this window overwrites them level by level. (A value
+// placed at level l never sits where this window computed an earlier level
+// of the same parity.) The caller's first barrier orders this before any
+// read.
+template <class S, int NT>
+__device__ __forceinline__ void clear_window_only(typename S::V* buf0, typename S::V* buf1, int W) {
+  if constexpr (S::NW > S::NV) {
+    const int cnt = (S::NW - S::NV) * W * W;
+    typename S::V* a = buf0 + S::NV * W * W;
+    typename S::V* b = buf1 + S::NV * W * W;
+    for (int q = ltid<NT>(); q < cnt; q += NT) {
+      a[q] = 0;
+      b[q] = 0;
+    }
+  }
+}
+
 // ----------------------------------------------------------------- kernels
 
 // Stage items. Each runs on one workgroup of NT threads with `smem` as its
@@ -1376,7 +1395,8 @@ __device__ void up_item(const Geo& g, int H, typename S::V* __restrict__ state, 
                         const SchemeParams& sp, int tile, double* smem) {
   using V = typename S::V;
   V* buf0 = reinterpret_cast<V*>(smem);
-  V* buf1 = buf0 + S::NV * g.W * g.W;
+  V* buf1 = buf0 + S::NW * g.W * g.W;
+  clear_window_only<S, NT>(buf0, buf1, g.W);  // ordered by the barrier after the gather
   const int a = tile % g.ntx, b = tile / g.ntx;
   const int x0 = g.off + a * g.n, y0 = g.off + b * g.n;
   const int n = g.n, W = g.W, plane = W * W;
@@ -1414,8 +1434,9 @@ __device__ __forceinline__ void bridge_body(const Geo& g, int H, bool isx,
   using V = typename S::V;
   constexpr int NV = S::NV;
   V* buf0 = reinterpret_cast<V*>(smem);
-  V* buf1 = buf0 + NV * g.W * g.W;
-  V* stg = buf1 + NV * g.W * g.W;
+  V* buf1 = buf0 + S::NW * g.W * g.W;
+  V* stg = buf1 + S::NW * g.W * g.W;
+  clear_window_only<S, NT>(buf0, buf1, g.W);  // ordered by the barrier after level 0 is placed
   const int n = g.n, h = g.h;
   const V* up = static_cast<const V*>(pp.up);
   V* out = static_cast<V*>(isx ? pp.xb : pp.yb);
@@ -1618,7 +1639,7 @@ __device__ void bridge_item(const Geo& g, int H, typename S::V* __restrict__ sta
 // the two facing strips of all levels.
 template <class S>
 __host__ __device__ inline size_t bridge_group_doubles(int n, bool staged) {
-  const size_t win = 2 * (size_t)(n + 2) * (size_t)(n + 2) * S::NV;
+  const size_t win = 2 * (size_t)(n + 2) * (size_t)(n + 2) * S::NW;
   const size_t stg = staged ? (size_t)2 * 2 * S::NV * (size_t)up_levels_len(n, n / 2) : 0;
   return ((win + stg) * sizeof(typename S::V) + 7) / 8;
 }
@@ -1646,8 +1667,9 @@ __device__ void oct_item(const Geo& g, int Hd, int Hu, typename S::V* __restrict
   using V = typename S::V;
   constexpr int NV = S::NV;
   V* buf0 = reinterpret_cast<V*>(smem);
-  V* buf1 = buf0 + NV * g.W * g.W;
-  V* stg = buf1 + NV * g.W * g.W;
+  V* buf1 = buf0 + S::NW * g.W * g.W;
+  V* stg = buf1 + S::NW * g.W * g.W;
+  clear_window_only<S, NT>(buf0, buf1, g.W);  // ordered by the barrier after level 0 is placed
   const int a = c % g.ntx, b = c / g.ntx;
   const int n = g.n, h = g.h;
   const int a1 = (a + 1 == g.ntx) ? 0 : a + 1, b1 = (b + 1 == g.nty) ? 0 : b + 1;
@@ -1844,7 +1866,7 @@ __global__ __launch_bounds__(256) void k_plain(const typename S::V* __restrict__
                                                int nx, int ny, long long Trel, const long long* tbase,
                                                SchemeParams sp) {
   using V = typename S::V;
-  constexpr int NV = S::NV;
+  constexpr int NV = S::NV, NW = S::NW;
   constexpr int R = plain_rows<S>();
   const long long T = Trel + (tbase ? *tbase : 0LL);
   const int x = blockIdx.x * 64 + threadIdx.x;
@@ -1853,8 +1875,10 @@ __global__ __launch_bounds__(256) void k_plain(const typename S::V* __restrict__
   const int xw = (x == 0) ? nx - 1 : x - 1;
   const int xe = (x == nx - 1) ? 0 : x + 1;
   const size_t plane = (size_t)nx * ny;
-  V rw[3][3][NV];
-  auto load = [&](V(&row)[3][NV], int y) {
+  // window-only values of the scheme are zero here: every sub-step is a
+  // launch of its own, so none survives one
+  V rw[3][3][NW] = {};
+  auto load = [&](V(&row)[3][NW], int y) {
     if (y < 0) y += ny;
     if (y >= ny) y -= ny;
     const V* base = in + (size_t)y * nx;
@@ -1872,15 +1896,15 @@ __global__ __launch_bounds__(256) void k_plain(const typename S::V* __restrict__
     const int y = ys + r;
     if (y >= ny) break;
     load(rw[2], y + 1);
-    const RegNb<V, NV> nb{rw};
-    V o[NV];
+    const RegNb<V, NW> nb{rw};
+    V o[NW];
     S::step(T, nb, o, sp);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v * plane + (size_t)y * nx + x] = o[v];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
+      for (int v = 0; v < NW; ++v) {
         rw[0][i][v] = rw[1][i][v];
         rw[1][i][v] = rw[2][i][v];
       }
@@ -1891,7 +1915,7 @@ __global__ __launch_bounds__(256) void k_plain(const typename S::V* __restrict__
 
 template <class S>
 SchemeInfo info_of() {
-  return SchemeInfo{S::NV, S::NVAR, S::SUB, (int)sizeof(typename S::V)};
+  return SchemeInfo{S::NV, S::NW, S::NVAR, S::SUB, (int)sizeof(typename S::V)};
 }
 
 // Workgroup size of the generic stage code for tile sides up to 22: one wave
@@ -2104,7 +2128,7 @@ template <class S, int NT>
 __device__ void plain_item(const typename S::V* __restrict__ in, typename S::V* __restrict__ out, int nx, int ny,
                            long long T, const SchemeParams& sp, int blk) {
   using V = typename S::V;
-  constexpr int NV = S::NV, TY = NT / 64, R = kBatchBlock / TY;
+  constexpr int NV = S::NV, NW = S::NW, TY = NT / 64, R = kBatchBlock / TY;
   static_assert(TY * R == kBatchBlock, "block geometry");
   const int bx = (nx + kBatchBlock - 1) / kBatchBlock;
   const int x = (blk % bx) * kBatchBlock + (int)(threadIdx.x & 63);
@@ -2113,8 +2137,10 @@ __device__ void plain_item(const typename S::V* __restrict__ in, typename S::V* 
   const int xw = (x == 0) ? nx - 1 : x - 1;
   const int xe = (x == nx - 1) ? 0 : x + 1;
   const size_t plane = (size_t)nx * ny;
-  V rw[3][3][NV];
-  auto load = [&](V(&row)[3][NV], int y) {
+  // window-only values of the scheme are zero here: every sub-step is a
+  // launch of its own, so none survives one
+  V rw[3][3][NW] = {};
+  auto load = [&](V(&row)[3][NW], int y) {
     if (y < 0) y += ny;
     if (y >= ny) y -= ny;
     const V* base = in + (size_t)y * nx;
@@ -2132,14 +2158,14 @@ __device__ void plain_item(const typename S::V* __restrict__ in, typename S::V* 
     const int y = ys + r;
     if (y >= ny) break;
     load(rw[2], y + 1);
-    V o[NV];
-    S::step(T, RegNb<V, NV>{rw}, o, sp);
+    V o[NW];
+    S::step(T, RegNb<V, NW>{rw}, o, sp);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v * plane + (size_t)y * nx + x] = o[v];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
+      for (int v = 0; v < NW; ++v) {
         rw[0][i][v] = rw[1][i][v];
         rw[1][i][v] = rw[2][i][v];
       }

@@ -95,6 +95,11 @@ int scheme_of(int pde, int prec) {
       case SWEPT2D_WAVE_LF: return kWave32C;
       case SWEPT2D_EULER_RUS_RK2: return kEuler32C;
     }
+  } else if (prec == SWEPT2D_FP32R) {
+    switch (pde) {
+      case SWEPT2D_HEAT5: return kHeat32R;
+      case SWEPT2D_WAVE_LF: return kWave32R;
+    }
   }
   return -1;
 }
@@ -273,6 +278,8 @@ double scheme_cost(int scheme) {
     case kPush5: return 2.5;
     case kHeat32C: return 1.5;
     case kWave32C: return 2.2;
+    case kHeat32R: return 1.5;
+    case kWave32R: return 2.2;
     case kEuler32C: return 36.0;
     default: return 1.0;
   }
@@ -521,9 +528,10 @@ int noalloc_advance(int nx, int ny, int nvars, int pde, int substeps, int prec, 
     return fail(SWEPT2D_EINVAL, "grid %d x %d out of range (2..65536 per side)", nx, ny);
   const int need = pde_nparams(pde);
   if (np < need || np > 4 || (need > 0 && !params)) return fail(SWEPT2D_EINVAL, "pde %d takes %d parameters", pde, need);
-  if (prec != SWEPT2D_FP64 && prec != SWEPT2D_FP32C) return fail(SWEPT2D_EINVAL, "unknown precision %d", prec);
+  if (prec != SWEPT2D_FP64 && prec != SWEPT2D_FP32C && prec != SWEPT2D_FP32R)
+    return fail(SWEPT2D_EINVAL, "unknown precision %d", prec);
   const int sc = scheme_of(pde, prec);
-  if (sc < 0) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no FP32-compensated form", pde);
+  if (sc < 0) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no form in precision %d", pde, prec);
   if (!dev_state) return fail(SWEPT2D_EINVAL, "null state");
   if (nsteps < 0 || nsteps > (1LL << 40)) return fail(SWEPT2D_EINVAL, "nsteps out of range");
   if (T < 0 || T % substeps) return fail(SWEPT2D_EINVAL, "level must be >= 0 and a multiple of substeps");
@@ -645,9 +653,10 @@ int swept2d_set_params(swept2d* h, const double* p, int np) {
 
 int swept2d_set_precision(swept2d* h, int prec) {
   if (!h) return fail(SWEPT2D_EINVAL, "null handle");
-  if (prec != SWEPT2D_FP64 && prec != SWEPT2D_FP32C) return fail(SWEPT2D_EINVAL, "unknown precision %d", prec);
+  if (prec != SWEPT2D_FP64 && prec != SWEPT2D_FP32C && prec != SWEPT2D_FP32R)
+    return fail(SWEPT2D_EINVAL, "unknown precision %d", prec);
   const int sc = scheme_of(h->pde, prec);
-  if (sc < 0) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no FP32-compensated form", h->pde);
+  if (sc < 0) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no form in precision %d", h->pde, prec);
   if (!h->owns_state) return fail(SWEPT2D_EINVAL, "unbind the caller buffer before changing precision");
   if (prec == h->prec) return 0;
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -724,7 +733,8 @@ int swept2d_upload(swept2d* h, const double* host) {
   if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
   if (h->prec == SWEPT2D_FP64) return swept2d_upload_raw(h, host);
   const size_t cnt = (size_t)h->nx * h->ny * h->nvars;
-  std::vector<float> buf(2 * cnt, 0.0f);
+  // FP32C: u then zero compensations; FP32R: u only
+  std::vector<float> buf(h->prec == SWEPT2D_FP32C ? 2 * cnt : cnt, 0.0f);
   for (size_t i = 0; i < cnt; ++i) buf[i] = (float)host[i];
   return swept2d_upload_raw(h, buf.data());
 }
@@ -733,10 +743,11 @@ int swept2d_download(swept2d* h, double* host) {
   if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
   if (h->prec == SWEPT2D_FP64) return swept2d_download_raw(h, host);
   const size_t cnt = (size_t)h->nx * h->ny * h->nvars;
-  std::vector<float> buf(2 * cnt);
+  const bool comp = h->prec == SWEPT2D_FP32C;
+  std::vector<float> buf(comp ? 2 * cnt : cnt);
   int rc = swept2d_download_raw(h, buf.data());
   if (rc) return rc;
-  for (size_t i = 0; i < cnt; ++i) host[i] = (double)buf[i] - (double)buf[cnt + i];
+  for (size_t i = 0; i < cnt; ++i) host[i] = comp ? (double)buf[i] - (double)buf[cnt + i] : (double)buf[i];
   return 0;
 }
 

@@ -17,6 +17,8 @@ extern template struct Stages<Push5>;
 extern template struct Stages<Heat32C>;
 extern template struct Stages<Wave32C>;
 extern template struct Stages<Euler32C>;
+extern template struct Stages<Heat32R>;
+extern template struct Stages<Wave32R>;
 extern template struct BatchPhase<66, 1024>;
 extern template struct BatchPhase<34, 256>;
 extern template struct BatchPhase<18, 64>;
@@ -50,6 +52,8 @@ __global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrid
     case kHeat32C: return Stages<Heat32C>::FN(__VA_ARGS__);   \
     case kWave32C: return Stages<Wave32C>::FN(__VA_ARGS__);   \
     case kEuler32C: return Stages<Euler32C>::FN(__VA_ARGS__); \
+    case kHeat32R: return Stages<Heat32R>::FN(__VA_ARGS__);   \
+    case kWave32R: return Stages<Wave32R>::FN(__VA_ARGS__);   \
     default: break;                                          \
   }
 
@@ -57,7 +61,7 @@ __global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrid
 
 SchemeInfo scheme_info(int scheme) {
   SWEPT_DISPATCH(info)
-  return SchemeInfo{0, 0, 0, 0};
+  return SchemeInfo{0, 0, 0, 0, 0};
 }
 
 hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp,

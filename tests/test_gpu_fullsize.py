@@ -70,6 +70,24 @@ def test_heat_1024_fp32c_bitwise_against_compensated_oracle():
     assert np.array_equal(got, u.astype(np.float64) - c.astype(np.float64))
 
 
+@pytest.mark.timeout(900)
+def test_heat_1024_20000_steps_fp32r_error_and_bitwise():
+    """FP32 values only in HBM (the compensations stay in the LDS windows):
+    within 1e-6 of the FP64 oracle after the full 20000 steps, and bit for
+    bit the residency oracle over the first 2000."""
+    s0 = si.heat_field(1024, 1024, seed=0)
+    p = si.default_params(si.HEAT5)
+    got, tile = _swept(si.HEAT5, p, s0, 20000, prec=sw.FP32R)
+    assert tile == 64
+    ref = _oracle64("heat1024", si.HEAT5, s0, p, 20000)
+    err = _normwise(got, ref)
+    print(f"heat 1024^2 FP32R after 20000 steps: normwise relative error {err:.3e}")
+    assert err <= 1e-6
+    got2, _ = _swept(si.HEAT5, p, s0, 2000, prec=sw.FP32R)
+    u = oracle.advance_f32r(si.HEAT5, s0.astype(np.float32), p, 2000, 64, threads=oracle.default_threads())
+    assert np.array_equal(got2, u.astype(np.float64))
+
+
 WAVE_STEPS = 10000
 
 

@@ -271,6 +271,50 @@ def test_fp32c_bitwise_against_compensated_oracle(pde, nx, ny, steps, tiles):
     assert np.array_equal(got, np.concatenate([ru, rc]))
 
 
+# ------------------------------- FP32 with the compensation in a residency
+
+STAGINGS = (sw.STAGING_AUTO, sw.STAGING_OFF, sw.STAGING_SINGLE_BRIDGES, sw.STAGING_ON)
+
+
+@pytest.mark.parametrize("pde,nx,ny,steps,tiles", [
+    (si.HEAT5, 64, 64, 300, (8, 16, 32, 64)),
+    (si.WAVE_LF, 128, 64, 150, (8, 16, 32, 64)),
+    (si.HEAT5, 96, 80, 37, (4, 8, 16)),
+    (si.WAVE_LF, 36, 24, 29, (4, 6, 12)),
+])
+def test_fp32r_bitwise_against_residency_oracle(pde, nx, ny, steps, tiles):
+    """Only u in the state and the panels, the compensations in the LDS
+    windows: bit for bit the oracle that keeps a compensation exactly while
+    one pyramid, bridge or octahedron computes the point, for every tile side
+    and staging mode; the per-step method keeps none."""
+    s0 = si.initial_state(pde, nx, ny, seed=4)
+    p = si.default_params(pde)
+    u0 = s0.astype(np.float32)
+    for n in tiles:
+        ref = oracle.advance_f32r(pde, u0, p, steps, n)
+        for staging in STAGINGS:
+            got = gpu_run(pde, u0, p, steps, tile=n, prec=sw.FP32R, staging=staging)
+            assert np.array_equal(got, ref), (n, staging)
+    got = gpu_run(pde, u0, p, steps, prec=sw.FP32R, method="plain")
+    assert np.array_equal(got, oracle.advance_f32r(pde, u0, p, steps, 0))
+
+
+def test_fp32r_split_advances_restart_residencies():
+    """Each advance starts from a state of values only, so an advance split
+    in two equals two oracle advances."""
+    s0 = si.heat_field(128, 64, seed=2)
+    p = si.default_params(si.HEAT5)
+    u = s0.astype(np.float32)
+    with sw.Swept2D(128, 64, si.HEAT5, p, prec=sw.FP32R, tile=32) as g:
+        g.upload_raw(u)
+        g.advance(13)
+        g.advance(40)
+        got = g.download_raw()
+    ref = oracle.advance_f32r(si.HEAT5, oracle.advance_f32r(si.HEAT5, u, p, 13, 32), p, 40, 32)
+    assert np.array_equal(got, ref)
+    assert not np.array_equal(got, oracle.advance_f32r(si.HEAT5, u, p, 53, 32))
+
+
 # ------------------------------------------------------------------ errors
 
 def test_error_codes():

@@ -561,3 +561,110 @@ def test_worked_example_values():
     assert sorted(got)[0] == half["substeps"]
     assert np.all(got[half["substeps"]] == 1 + half["substeps"])
     assert st.exchanges == 2 * half["communications"]
+
+
+# ------------------------------------ FP32 with the compensation in a residency
+
+def _model_residency_keys(nx, ny, n, S):
+    """Residency of every point at levels 0..S of one swept advance, from the
+    level-function model: the first upward pyramid (with level 0); each half
+    cycle's bridges one by one; a downward pyramid together with the upward
+    pyramid of the next half cycle whose tile is exactly the set of points
+    the downward pyramid holds at its last level."""
+    h = n // 2
+    keys = {}
+    for y in range(ny):
+        for x in range(nx):
+            keys[(x, y, 0)] = ("first",)
+    k = 0
+    prev_down_sets = None
+    while k * h < S:
+        off = (k % 2) * h
+        H = min(h, S - k * h)
+        comp = {(x, y, l): sm.component(x, y, l, n, off, nx, ny)
+                for l in range(0, H + 1) for y in range(ny) for x in range(nx)}
+        # upward pyramids of this half cycle: which downward pyramid of the
+        # previous one (if any) covers exactly the same points
+        up_home = {}
+        tiles = {}
+        for (x, y, l), c in comp.items():
+            if l == 0:
+                tiles.setdefault(c[1], set()).add((x, y))
+        for t, pts in tiles.items():
+            if k == 0:
+                up_home[t] = ("first",)
+            else:
+                match = [d for d, dpts in prev_down_sets.items() if dpts == pts]
+                assert len(match) == 1
+                up_home[t] = ("oct", k - 1, match[0])
+        down_sets = {}
+        for (x, y, l), c in comp.items():
+            if l == 0:
+                continue
+            L = k * h + l
+            if c[0] == sm.UP:
+                keys[(x, y, L)] = up_home[c[1]]
+            elif c[0] == sm.DOWN:
+                keys[(x, y, L)] = ("oct", k, c[1])
+                if l == h:
+                    down_sets.setdefault(c[1], set()).add((x, y))
+            else:
+                keys[(x, y, L)] = ("bridge", k, c)
+        prev_down_sets = down_sets
+        k += 1
+    return keys
+
+
+@pytest.mark.parametrize("nx,ny,n,S", [(16, 24, 8, 11), (12, 12, 4, 9), (8, 8, 8, 4), (6, 10, 2, 3)])
+def test_residency_rule_matches_the_decomposition(nx, ny, n, S):
+    """The oracle's residency numbers (a formula in the edge distances) give,
+    for every point, level and neighbour, the same answer to "computed in the
+    same window as the point reading it" as the model's components."""
+    keys = _model_residency_keys(nx, ny, n, S)
+    res = {(x, y, L): oracle.residency(x, y, L, n, nx, ny) for (x, y, L) in keys}
+    for (x, y, L), key in keys.items():
+        if L == 0:
+            continue
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                q = ((x + di) % nx, (y + dj) % ny, L - 1)
+                assert (keys[q] == key) == (res[q] == res[(x, y, L)]), ((x, y, L), q)
+
+
+@pytest.mark.parametrize("pde,shape", [(si.HEAT5, (48, 32)), (si.WAVE_LF, (32, 48))])
+def test_f32r_per_step_method_is_plain_fp32(pde, shape):
+    """Tile side 0 (a launch per sub-step) keeps no compensation across a
+    sub-step: it equals the compensated stepper with c reset every step."""
+    s0 = si.initial_state(pde, *shape, seed=2)
+    p = si.default_params(pde)
+    u = s0.astype(np.float32)
+    got = oracle.advance_f32r(pde, u, p, 25, 0)
+    ref = u.copy()
+    for _ in range(25):
+        ref, _ = oracle.advance_f32c(pde, ref, np.zeros_like(ref), p, 1)
+    assert np.array_equal(got, ref)
+
+
+def test_f32r_exact_when_fp32_is_exact():
+    rng = np.random.default_rng(5)
+    u0 = rng.integers(-8, 9, size=(1, 16, 16)).astype(np.float64)
+    for n in (4, 8, 16, 0):
+        got = oracle.advance_f32r(si.HEAT5, u0.astype(np.float32), [0.125], 6, n)
+        assert np.array_equal(got.astype(np.float64), oracle.advance_f64(si.HEAT5, u0, [0.125], 6))
+
+
+@pytest.mark.parametrize("pde,steps", [(si.HEAT5, 1500), (si.WAVE_LF, 600)])
+def test_f32r_error_between_full_compensation_and_plain_fp32(pde, steps):
+    """Dropping the compensation only where a value changes window loses part
+    of its benefit: the error lies between that of the full compensated
+    stepper and that of plain FP32, and deeper pyramids (larger tiles, fewer
+    changes of window) keep more of it."""
+    s0 = si.initial_state(pde, 256, 256, seed=0)
+    p = si.default_params(pde)
+    ref = oracle.advance_f64(pde, s0, p, steps)
+    u, c = oracle.split_f32c(s0)
+    ub, cb = oracle.advance_f32c(pde, u, c, p, steps)
+    err_b = _norm_rel(ub.astype(np.float64) - cb.astype(np.float64), ref)
+    errs = {n: _norm_rel(oracle.advance_f32r(pde, u, p, steps, n).astype(np.float64), ref) for n in (0, 16, 64)}
+    assert err_b < errs[64] < errs[16] < errs[0]
+    assert errs[64] < 1e-6
