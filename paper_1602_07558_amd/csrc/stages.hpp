@@ -1858,6 +1858,85 @@ constexpr int plain_rows() {
   return S::NV >= 8 ? 2 : 8;
 }
 
+// Neighbour access for the per-step kernel below: rw[row][column][v] with
+// CW register columns; the point sits at column c + 1 of row 1.
+template <class V, int NWv, int CW>
+struct ColsNb {
+  const V (*rw)[CW][NWv];
+  int c;
+  __device__ __forceinline__ V operator()(int di, int dj, int v) const { return rw[dj + 1][c + di + 1][v]; }
+};
+
+// Per-step kernel of the light schemes (at most 16 bytes per point in the
+// window). A thread computes C adjacent columns (C = 2 on grids of even
+// width: one 2-value load and store per row and value) of PR rows, with all
+// PR + 2 input rows loaded before the first update, so every load of a
+// thread is in flight at once; 128 threads cover 128 C columns. Workgroups
+// are dealt round robin to the 8 XCDs in workgroup order, so the blocks are
+// renumbered to give each XCD a contiguous band of rows: the rows two
+// vertically adjacent blocks both read then meet in one XCD's L2.
+constexpr int kPlainRows = 4;
+constexpr int kXcds = 8;
+template <class S, int C>
+__global__ __launch_bounds__(128) void k_plain_cols(const typename S::V* __restrict__ in,
+                                                    typename S::V* __restrict__ out, int nx, int ny, long long Trel,
+                                                    const long long* tbase, SchemeParams sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV, NW = S::NW, PR = kPlainRows, CW = C + 2;
+  const long long T = Trel + (tbase ? *tbase : 0LL);
+  const int nbx = (nx + 128 * C - 1) / (128 * C);
+  const int nb = nbx * ((ny + PR - 1) / PR);
+  const int per = (nb + kXcds - 1) / kXcds;
+  const int L = (int)blockIdx.x;
+  const int t = (L % kXcds) * per + L / kXcds;
+  if (t >= nb) return;
+  const int bx = t % nbx, by = t / nbx;
+  const int x = (bx * 128 + (int)threadIdx.x) * C;
+  if (x >= nx) return;
+  const int ys = by * PR;
+  const int xw = x == 0 ? nx - 1 : x - 1;
+  const int xe = x + C == nx ? 0 : x + C;
+  const size_t plane = (size_t)nx * ny;
+  // window-only values of the scheme are zero: every sub-step is a launch of
+  // its own, so none survives one
+  V rw[PR + 2][CW][NW] = {};
+#pragma unroll
+  for (int k = 0; k < PR + 2; ++k) {
+    const int y = ((ys + k - 1) % ny + ny) % ny;
+    const V* row = in + (size_t)y * nx;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (C == 2) {
+        using V2 = HIP_vector_type<V, 2>;
+        const V2 m = *reinterpret_cast<const V2*>(row + v * plane + x);
+        rw[k][1][v] = m.x;
+        rw[k][2][v] = m.y;
+      } else {
+        rw[k][1][v] = row[v * plane + x];
+      }
+      rw[k][0][v] = row[v * plane + xw];
+      rw[k][CW - 1][v] = row[v * plane + xe];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PR; ++k) {
+    if (ys + k >= ny) break;
+    V o[C][NW];
+#pragma unroll
+    for (int c = 0; c < C; ++c) S::step(T, ColsNb<V, NW, CW>{&rw[k], c}, o[c], sp);
+    V* dst = out + (size_t)(ys + k) * nx + x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (C == 2) {
+        using V2 = HIP_vector_type<V, 2>;
+        *reinterpret_cast<V2*>(dst + v * plane) = V2(o[0][v], o[1][v]);
+      } else {
+        dst[v * plane] = o[0][v];
+      }
+    }
+  }
+}
+
 // One sub-step of every point (the classical per-step update). Block 64 x 4;
 // each thread walks plain_rows rows of one column, keeping three rows of its
 // 3-wide neighbourhood in registers.
@@ -2074,6 +2153,22 @@ hipError_t oct_t(const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPt
 template <class S>
 hipError_t plain_t(int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
                    const SchemeParams& sp, hipStream_t s) {
+  if constexpr (Lay<S, 0>::light) {
+    // two columns per thread need an even width and buffers aligned to two values
+    const uintptr_t al = 2 * sizeof(typename S::V);
+    const bool two = nx % 2 == 0 && (reinterpret_cast<uintptr_t>(in) % al) == 0 &&
+                     (reinterpret_cast<uintptr_t>(out) % al) == 0;
+    const int C = two ? 2 : 1;
+    const int nb = ((nx + 128 * C - 1) / (128 * C)) * ((ny + kPlainRows - 1) / kPlainRows);
+    const dim3 grid(((nb + kXcds - 1) / kXcds) * kXcds);
+    if (C == 2)
+      hipLaunchKernelGGL((k_plain_cols<S, 2>), grid, dim3(128), 0, s, static_cast<const typename S::V*>(in),
+                         static_cast<typename S::V*>(out), nx, ny, T, tbase, sp);
+    else
+      hipLaunchKernelGGL((k_plain_cols<S, 1>), grid, dim3(128), 0, s, static_cast<const typename S::V*>(in),
+                         static_cast<typename S::V*>(out), nx, ny, T, tbase, sp);
+    return hipGetLastError();
+  }
   constexpr int R = plain_rows<S>();
   const dim3 grid((nx + 63) / 64, (ny + 4 * R - 1) / (4 * R));
   hipLaunchKernelGGL(k_plain<S>, grid, dim3(64, 4), 0, s, static_cast<const typename S::V*>(in),

@@ -75,7 +75,7 @@ def test_hash_large_tiles_both_paths():
                 assert np.array_equal(got, ref), (nx, ny, n, S, staging)
 
 
-@pytest.mark.parametrize("nx,ny", [(16, 16), (24, 16), (66, 34)])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (24, 16), (66, 34), (15, 9), (130, 3), (2, 2)])
 def test_hash_plain(nx, ny):
     s0 = si.hash_field(nx, ny, seed=3)
     for S in (1, 2, 7):
