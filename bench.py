@@ -4,13 +4,17 @@ Workload (one bench step): the 1024 x 1024 periodic heat problem, 5-point
 FTCS with r = 0.2, initial field of 8 seeded Fourier modes, advanced 20000
 time steps with swept2d_advance (FP64). The state is resident in HBM before
 timing starts. Alongside, the same workload is timed with the per-step method
-(swept2d_plain_advance) and in FP32 with compensated update, and the oracle
-(plain C stepper, host cores) is timed on a bounded sample.
+(swept2d_plain_advance), in FP32 with compensated update (FP32C: value and
+compensation in HBM; FP32R: values alone in HBM, compensations kept in the
+LDS windows), and the oracle (plain C stepper, host cores) on a bounded
+sample; the other workloads (wave 2048^2, Euler 512^2, the 256-grid batch)
+are timed at their full sizes.
 
-Prints one JSON line. `value` is the swept FP64 rate. `roofline` is for the
-dominant kernel (the octahedron: downward pyramid fused with the next upward
-pyramid), timed per launch with HIP events on the library's stream during the
-timed region.
+Prints one JSON line. `value` is the swept FP64 rate. `roofline` is the HBM
+roofline of the dominant kernel (the octahedron: downward pyramid fused with
+the next upward pyramid), its launches timed with HIP events on the
+library's stream; the LDS and FP64 rooflines of the same kernel sit beside
+it, the LDS peak measured on the device.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu]
   python bench.py --profile-pass     (short run used under rocprofv3 --pmc)
@@ -18,9 +22,11 @@ timed region.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -36,8 +42,7 @@ WORKLOAD = ("heat 1024x1024 periodic, 5-point FTCS r=0.2, 20000 steps, "
 # MI355X published peaks.
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-# LDS: 128 bytes per clock per compute unit, 256 CUs at 2.4 GHz.
-LDS_PEAK_GBS = 128 * 256 * 2.4
+CLOCK_HZ = 2.4e9
 # Algorithmic work of one heat point update (5-point FTCS): flops
 # (uW+uE, uN+uS, their sum, 4u, the difference, r*lap, u + r*lap) and the
 # LDS bytes of a point update done in LDS: one FP64 read of the point's own
@@ -45,8 +50,9 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 HEAT_FLOPS_PER_UPDATE = 7
 HEAT_LDS_BYTES_PER_UPDATE = 2 * 8
 BATCH_STEPS = 1024
+BATCH_LITERAL_STEPS = 50000
 
-PROFILE_FILE = os.path.join(ROOT, "profiles", "oct_heat1024_fp64_counters.txt")
+PROFILE_FILE = os.path.join(ROOT, "profiles", "heat1024_fp64_hbm_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1602_07558_amd", "csrc", f)
                   for f in ("stages.hpp", "stages_scheme.hip", "schemes.hpp", "engine.hpp")]
 
@@ -59,8 +65,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(launch_kind: str = "oct"):
-    """HBM bytes per octahedron launch from the committed rocprofv3 counter
+def read_counters():
+    """Per-kernel HBM bytes per launch from the committed rocprofv3 counter
     summary, or None when it is missing or the kernels changed since."""
     if not os.path.exists(PROFILE_FILE):
         return None
@@ -71,10 +77,27 @@ def read_traffic(launch_kind: str = "oct"):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
+    out = {}
     try:
-        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+        for kind in ("oct", "bridge_pair", "up", "plain"):
+            out[kind] = float(vals[f"{kind}.fetch_bytes_per_launch"]) + float(vals[f"{kind}.write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+    return out
+
+
+def heat_panel_bytes(n: int, vb: int = 8) -> dict:
+    """Algorithmic HBM bytes per tile and half cycle of the heat stage
+    kernels (one value per point): the octahedron reads the ring of its
+    downward pyramid (two x-bridge ends of h(h+3) values per row pair, two
+    y-bridge ends of h(h-1)) and writes the four strips of its upward pyramid
+    (h(n-h+1) values per row pair); the bridge pair reads four pyramid strips
+    and writes its own four ends."""
+    h = n // 2
+    up = 2 * h * (n - h + 1)
+    xb = 2 * h * (h + 3)
+    yb = 2 * h * (h - 1)
+    return {"oct": (2 * xb + 2 * yb + 4 * up) * vb, "bridge_pair": (4 * up + 2 * xb + 2 * yb) * vb}
 
 
 def timed_runs(g, fn, steps, k):
@@ -91,27 +114,71 @@ def timed_runs(g, fn, steps, k):
     return times
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(budget_s: float = 12.0):
+    """The oracle on the host: all host cores (threads = nproc) and one
+    thread, each on the first steps of the heat workload sized to about
+    budget_s seconds."""
     import oracle
     import swept_inputs as si
     s = si.heat_field(NX, NY, seed=0)
-    threads = oracle.default_threads()
-    t0 = time.perf_counter()
-    oracle.advance_f64(si.HEAT5, s, [si.HEAT_R], 20, threads=threads)
-    probe = time.perf_counter() - t0
-    steps = max(20, min(TIMESTEPS, int(20 * budget_s / max(probe, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.advance_f64(si.HEAT5, s, [si.HEAT_R], steps, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": NX * NY * steps / dt, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"heat 1024x1024 FP64, first {steps} of the 20000 steps, plain C stepper, {threads} threads"}
+    ncores = os.cpu_count() or 1
+
+    def rate(threads, budget):
+        t0 = time.perf_counter()
+        oracle.advance_f64(si.HEAT5, s, [si.HEAT_R], 5, threads=threads)
+        probe = time.perf_counter() - t0
+        steps = max(5, min(TIMESTEPS, int(5 * budget / max(probe, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.advance_f64(si.HEAT5, s, [si.HEAT_R], steps, threads=threads)
+        return NX * NY * steps / (time.perf_counter() - t0), steps
+
+    v_all, st_all = rate(ncores, budget_s)
+    v_one, st_one = rate(1, budget_s / 2)
+    return {"value": v_all, "unit": "point-updates/s", "cores": ncores, "kind": "oracle",
+            "sample": f"heat 1024x1024 FP64, first {st_all} of the 20000 steps, plain C stepper, {ncores} threads",
+            "cpu_model": cpu_model(), "nproc": ncores,
+            "single_thread": {"value": v_one, "unit": "point-updates/s", "cores": 1,
+                              "sample": f"first {st_one} steps, 1 thread"}}
+
+
+def lds_peak():
+    """Measured LDS read bandwidth (bytes/s) of the device."""
+    import paper_1602_07558_amd.build as b
+    if not os.path.exists(b.PROBE_LIB):
+        return None
+    lib = ctypes.CDLL(b.PROBE_LIB)
+    lib.lds_probe_read_bandwidth.restype = ctypes.c_int
+    lib.lds_probe_read_bandwidth.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int)]
+    b64, b128, cus = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    if lib.lds_probe_read_bandwidth(ctypes.byref(b64), ctypes.byref(b128), ctypes.byref(cus)) != 0:
+        return None
+    return {"b64_GBs": b64.value / 1e9, "b128_GBs": b128.value / 1e9, "cus": cus.value,
+            "b64_bytes_per_clk_cu": b64.value / (cus.value * CLOCK_HZ),
+            "b128_bytes_per_clk_cu": b128.value / (cus.value * CLOCK_HZ)}
+
+
+def normwise(x, ref):
+    import numpy as np
+    return max(float(np.abs(x[v] - ref[v]).max() / np.abs(ref[v]).max()) for v in range(ref.shape[0]))
 
 
 def other_workloads(sw, si, np):
     """Throughput of the other workloads at their full sizes over a bounded
-    number of steps (the step counts of their parity tests are longer): the
-    wave 2048^2 and Euler 512^2 grids (swept, FP64 and FP32C) and the
-    uneven 256-grid batch (phased launches, model tile sides)."""
+    number of steps (the step counts of their parity tests are longer), with
+    the FP32 forms' normwise error against the FP64 result of the same run:
+    the wave 2048^2 and Euler 512^2 grids (swept) and the uneven 256-grid
+    batches (phased launches, model tile sides)."""
     out = {}
 
     def rate(make, steps, pts):
@@ -123,40 +190,63 @@ def other_workloads(sw, si, np):
         g.synchronize()
         dt = time.perf_counter() - t0
         tile = g.tile if isinstance(g, sw.Swept2D) else None
+        res = g.download() if isinstance(g, sw.Swept2D) else None
         g.close()
-        return pts * steps / dt, tile
+        return pts * steps / dt, tile, res
 
     s_w = si.wave_field(2048, 2048, seed=0)
     p_w = si.default_params(si.WAVE_LF)
-    for prec, name in ((sw.FP64, "fp64"), (sw.FP32C, "fp32c")):
+    ref = None
+    for prec, name in ((sw.FP64, "fp64"), (sw.FP32C, "fp32c"), (sw.FP32R, "fp32r")):
         def mk(prec=prec):
             g = sw.Swept2D(2048, 2048, si.WAVE_LF, p_w, prec=prec)
             g.upload(s_w)
             return g
-        v, tile = rate(mk, 1000, 2048 * 2048)
-        out[f"wave2048_{name}"] = {"value": v, "unit": "point-updates/s", "steps": 1000, "tile": tile}
+        v, tile, res = rate(mk, 1000, 2048 * 2048)
+        rec = {"value": v, "unit": "point-updates/s", "steps": 1000, "tile": tile}
+        if ref is None:
+            ref = res
+        else:
+            rec["error_vs_fp64_after_2000_steps"] = normwise(res, ref)
+        out[f"wave2048_{name}"] = rec
     s_e = si.euler_field(512, 512, seed=0)
     p_e = si.default_params(si.EULER_RUS_RK2, s_e)
+    ref = None
     for prec, name in ((sw.FP64, "fp64"), (sw.FP32C, "fp32c")):
         def mk(prec=prec):
             g = sw.Swept2D(512, 512, si.EULER_RUS_RK2, p_e, prec=prec)
             g.upload(s_e)
             return g
-        v, tile = rate(mk, 500, 512 * 512)
-        out[f"euler512_{name}"] = {"value": v, "unit": "point-updates/s (full RK2 steps)", "steps": 500, "tile": tile}
-    specs = si.batch_specs(256, seed=0)
-    grids = [dict(nx=b["nx"], ny=b["ny"], pde=b["pde"], prec=b["prec"], params=list(si.default_params(b["pde"])))
-             for b in specs]
-    pts = sum(b["nx"] * b["ny"] for b in specs)
+        v, tile, res = rate(mk, 500, 512 * 512)
+        rec = {"value": v, "unit": "point-updates/s (full RK2 steps)", "steps": 500, "tile": tile}
+        if ref is None:
+            ref = res
+        else:
+            rec["error_vs_fp64_after_1000_steps"] = normwise(res[:4], ref[:4])
+        out[f"euler512_{name}"] = rec
+    for quantum, steps, key in ((16, BATCH_STEPS, "batch256"), (1, BATCH_LITERAL_STEPS, "batch256_literal")):
+        specs = si.batch_specs(256, seed=0, quantum=quantum)
+        grids = [dict(nx=b["nx"], ny=b["ny"], pde=b["pde"], prec=b["prec"], params=list(si.default_params(b["pde"])))
+                 for b in specs]
+        pts = sum(b["nx"] * b["ny"] for b in specs)
 
-    def mkb():
-        b = sw.Swept2DBatch(grids)
-        for i, sp in enumerate(specs):
-            b.upload(i, si.initial_state(sp["pde"], sp["nx"], sp["ny"], seed=sp["seed"]))
-        return b
-    v, _ = rate(mkb, BATCH_STEPS, pts)
-    out["batch256"] = {"value": v, "unit": "point-updates/s", "steps": BATCH_STEPS, "grids": len(specs),
-                       "points": pts, "mode": "phased launches, model tile sides"}
+        def mkb(specs=specs, grids=grids):
+            b = sw.Swept2DBatch(grids)
+            for i, sp in enumerate(specs):
+                b.upload(i, si.initial_state(sp["pde"], sp["nx"], sp["ny"], seed=sp["seed"]))
+            return b
+        b = mkb()
+        swept_grids = sum(1 for i in range(len(specs)) if b.tile(i) > 0)
+        b.advance(BATCH_STEPS)
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.advance(steps)
+        b.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        out[key] = {"value": pts * steps / dt, "unit": "point-updates/s", "steps": steps, "grids": len(specs),
+                    "points": pts, "swept_grids": swept_grids, "side_quantum": quantum,
+                    "mode": "phased launches, model tile sides"}
     return out
 
 
@@ -185,11 +275,13 @@ def main():
     p = si.default_params(si.HEAT5)
 
     if args.profile_pass:
-        # Short run for counter collection: the swept FP64 path plus a plain
-        # copy of known size that calibrates the byte counters.
+        # Short run for counter collection: the swept FP64 path (20 half
+        # cycles), 64 per-step launches, and a plain copy of known size that
+        # calibrates the byte counters.
         g = sw.Swept2D(NX, NY, si.HEAT5, p)
         g.upload(s0)
         g.advance(640)
+        g.plain_advance(64)
         g.synchronize()
         a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -198,16 +290,21 @@ def main():
         print(json.dumps({"profile_pass": True, "tile": g.tile, "copy_bytes": a.numel()}))
         return
 
-    result = {}
+    upd = NX * NY * TIMESTEPS
+    rate = lambda ts: upd / float(np.median(ts))
 
-    # ---- swept FP64 (value), with per-kernel HIP events on its stream
+    # ---- swept FP64 (value)
     g = sw.Swept2D(NX, NY, si.HEAT5, p)
     tile = g.tile
     g.upload(s0)
     for _ in range(args.warmup):
         g.advance(TIMESTEPS)
     t_swept = timed_runs(g, g.advance, TIMESTEPS, args.steps)
-    swept_out = g.download()
+    # The FP64 result after exactly 20000 steps (the oracle's bits, by the
+    # full-size parity test): the reference for the FP32 forms' error.
+    g.upload(s0)
+    g.advance(TIMESTEPS)
+    ref64 = g.download()
     # Per-kernel durations from HIP events on the library's stream, in a pass
     # of its own (the events would add gaps to the timed region).
     g.set_timing(True)
@@ -217,7 +314,8 @@ def main():
     g.set_timing(False)
     g.close()
 
-    # ---- plain per-step FP64 on the same workload (direct launches)
+    # ---- plain per-step FP64 on the same workload (direct launches, then a
+    # captured graph)
     gp = sw.Swept2D(NX, NY, si.HEAT5, p)
     gp.upload(s0)
     for _ in range(args.warmup):
@@ -226,38 +324,62 @@ def main():
     gp.set_launch_mode(sw.LAUNCH_GRAPH)
     gp.plain_advance(TIMESTEPS)
     t_plain_graph = timed_runs(gp, gp.plain_advance, TIMESTEPS, args.steps)
-    gp.upload(s0)
     gp.set_launch_mode(sw.LAUNCH_DIRECT)
-    gp.plain_advance(TIMESTEPS * (args.warmup + args.steps))
+    gp.upload(s0)
+    gp.plain_advance(TIMESTEPS)
     plain_out = gp.download()
+    gp.set_timing(True)
+    gp.plain_advance(200)
+    gp.synchronize()
+    kern_plain = {r["kind"]: r for r in gp.timing()}["plain"]
+    gp.set_timing(False)
     gp.close()
-    bitwise_equal = bool(np.array_equal(swept_out, plain_out))
+    bitwise_equal = bool(np.array_equal(ref64, plain_out))
 
-    # ---- FP32 with compensated update, swept and plain
-    g32 = sw.Swept2D(NX, NY, si.HEAT5, p, prec=sw.FP32C)
-    g32.upload(s0)
-    for _ in range(args.warmup):
+    # ---- FP32 forms, swept and plain, with their error after 20000 steps
+    fp32 = {}
+    for prec, name in ((sw.FP32C, "fp32c"), (sw.FP32R, "fp32r")):
+        g32 = sw.Swept2D(NX, NY, si.HEAT5, p, prec=prec)
+        g32.upload(s0)
+        for _ in range(args.warmup):
+            g32.advance(TIMESTEPS)
+        t_s = timed_runs(g32, g32.advance, TIMESTEPS, args.steps)
+        g32.upload(s0)
         g32.advance(TIMESTEPS)
-    t_s32 = timed_runs(g32, g32.advance, TIMESTEPS, args.steps)
-    g32.close()
-    g32p = sw.Swept2D(NX, NY, si.HEAT5, p, prec=sw.FP32C)
-    g32p.upload(s0)
-    for _ in range(args.warmup):
-        g32p.plain_advance(TIMESTEPS)
-    t_p32 = timed_runs(g32p, g32p.plain_advance, TIMESTEPS, args.steps)
-    g32p.close()
+        err_s = normwise(g32.download(), ref64)
+        g32.upload(s0)
+        for _ in range(args.warmup):
+            g32.plain_advance(TIMESTEPS)
+        t_p = timed_runs(g32, g32.plain_advance, TIMESTEPS, args.steps)
+        g32.upload(s0)
+        g32.plain_advance(TIMESTEPS)
+        err_p = normwise(g32.download(), ref64)
+        g32.close()
+        fp32[name] = {"swept_value": rate(t_s), "plain_value": rate(t_p),
+                      "swept_over_fp64_swept": rate(t_s) / rate(t_swept),
+                      "error_vs_fp64_swept": err_s, "error_vs_fp64_plain": err_p,
+                      "state_bytes_per_value": 8 if prec == sw.FP32C else 4}
+    fp32["fp32c"]["form"] = "FP32 value + FP32 compensation in HBM, LDS and panels (swept == plain bitwise)"
+    fp32["fp32r"]["form"] = ("FP32 value only in HBM and panels; compensation in the LDS windows within a residency "
+                             "(per-step method = plain FP32)")
 
-    upd = NX * NY * TIMESTEPS
-    ms = 1e3 * float(np.median(t_swept))
-    rate = lambda ts: upd / float(np.median(ts))
-
+    # ---- rooflines of the dominant kernel (octahedron) and the per-step kernel
     oct_k = kern["oct"]
     oct_avg_s = oct_k["ms"] * 1e-3 / oct_k["launches"]
     oct_pts = oct_k["points"] / oct_k["launches"]
-    flops = oct_pts * HEAT_FLOPS_PER_UPDATE
-    achieved = flops / oct_avg_s / 1e12
-    traffic = read_traffic()
+    ntiles = (NX // tile) * (NY // tile)
+    algo = heat_panel_bytes(tile)
+    oct_bytes = algo["oct"] * ntiles
+    counters = read_counters()
+    lds = lds_peak()
+    lds_peak_gbs = lds["b64_GBs"] if lds else None
     lds_gbs = oct_pts * HEAT_LDS_BYTES_PER_UPDATE / oct_avg_s / 1e9
+    flops = oct_pts * HEAT_FLOPS_PER_UPDATE / oct_avg_s / 1e12
+    plain_avg_s = kern_plain["ms"] * 1e-3 / kern_plain["launches"]
+    plain_bytes = 2 * 8 * NX * NY
+    half_pts = NX * NY * (tile // 2)
+    swept_bytes_algo = (algo["oct"] + algo["bridge_pair"]) * ntiles / half_pts
+    swept_bytes_cnt = ((counters["oct"] + counters["bridge_pair"]) / half_pts) if counters else None
 
     result = {
         "metric": METRIC,
@@ -266,7 +388,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": 1e3 * float(np.median(t_swept)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -275,26 +397,40 @@ def main():
         "config": {"workload": WORKLOAD, "nx": NX, "ny": NY, "timesteps": TIMESTEPS, "method": "swept",
                    "tile": tile, "precision": "fp64"},
         "roofline": {
-            "bound": "alu",
+            "bound": "hbm",
             "kernel": "k_oct<Heat64,66,1024,false> (downward pyramid + next upward pyramid, ring runs fetched "
                       "from HBM three levels ahead)",
-            "achieved": achieved,
-            "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": traffic,
-            "flops_per_launch": flops,
+            "achieved": oct_bytes / oct_avg_s / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": oct_bytes / oct_avg_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": counters["oct"] if counters else None,
+            "algorithmic_bytes_per_launch": oct_bytes,
             "avg_launch_us": oct_avg_s * 1e6,
+            "limiter": "none of HBM, LDS or FP64 issue is saturated: per-level latency (LDS round trip, lane "
+                       "shifts, the FP64 chain, the workgroup barrier) of one 16-wave workgroup per CU",
         },
-        "lds_roofline": {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": lds_gbs / LDS_PEAK_GBS,
-                         "bytes_per_update": HEAT_LDS_BYTES_PER_UPDATE},
+        "lds_roofline": {"achieved": lds_gbs, "peak": lds_peak_gbs, "unit": "GB/s",
+                         "frac": (lds_gbs / lds_peak_gbs) if lds_peak_gbs else None,
+                         "bytes_per_update": HEAT_LDS_BYTES_PER_UPDATE, "peak_measured": lds},
+        "alu_roofline": {"achieved": flops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / FP64_VECTOR_PEAK_TFLOPS, "flops_per_update": HEAT_FLOPS_PER_UPDATE},
+        "hbm_bytes_per_point_update": {
+            "swept": {"algorithmic": swept_bytes_algo, "counters": swept_bytes_cnt},
+            "plain": {"algorithmic": 16.0, "counters": (counters["plain"] / (NX * NY)) if counters else None},
+        },
         "kernels": {k: {"launches": r["launches"], "avg_us": r["ms"] * 1e3 / r["launches"]} for k, r in kern.items()},
         "plain": {"value": rate(t_plain), "graph_value": rate(t_plain_graph),
-                  "ms_per_step": 1e3 * float(np.median(t_plain))},
+                  "ms_per_step": 1e3 * float(np.median(t_plain)),
+                  "roofline": {"bound": "hbm", "kernel": "k_plain_cols<Heat64,2>", "avg_launch_us": plain_avg_s * 1e6,
+                               "achieved": plain_bytes / plain_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": plain_bytes / plain_avg_s / 1e9 / HBM_PEAK_GBS,
+                               "traffic": counters["plain"] if counters else None,
+                               "note": "the 8 MB state stays in the 256 MB Infinity Cache; traffic counts HBM bytes"}},
         "swept_over_plain": rate(t_swept) / rate(t_plain),
-        "fp32c": {"swept_value": rate(t_s32), "plain_value": rate(t_p32),
-                  "swept_over_fp64_swept": rate(t_s32) / rate(t_swept)},
+        "fp32": fp32,
         "bitwise_equal_swept_plain": bitwise_equal,
+        "counter_summary": os.path.relpath(PROFILE_FILE, ROOT) if counters else None,
     }
     result["other_workloads"] = other_workloads(sw, si, np)
     if not args.skip_cpu:

@@ -22,6 +22,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswept2d.so")
+# The LDS bandwidth probe the benchmark reports as the LDS roofline peak (not
+# part of the swept2d library).
+PROBE_SRC = os.path.join(CSRC, "probe_lds.hip")
+PROBE_LIB = os.path.join(HERE, "libswept2d_probe.so")
 
 SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C", "Wave32C", "Euler32C",
            "Heat32R", "Wave32R"]
@@ -90,7 +94,18 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
     os.replace(tmp, LIB)
+    build_probe(cc)
     return LIB
+
+
+def build_probe(cc: str | None = None) -> str:
+    cc = cc or hipcc()
+    tmp = PROBE_LIB + ".tmp"
+    res = subprocess.run([cc, *FLAGS, "-shared", "-o", tmp, PROBE_SRC], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("probe build failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 def stale() -> bool:

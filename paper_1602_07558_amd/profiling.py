@@ -3,9 +3,11 @@
   python -m paper_1602_07558_amd.profiling stats DIR
       per-kernel calls / average / total duration from *_kernel_stats.csv
   python -m paper_1602_07558_amd.profiling traffic FETCH_DIR WRITE_DIR OUT [--copy-bytes B]
-      HBM bytes per octahedron launch from two --pmc runs (FETCH_SIZE, then
-      WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter
-      reads for the plain copy of B bytes that `bench.py --profile-pass` runs.
+      HBM bytes per launch of the heat benchmark's kernels (octahedron, bridge
+      pair, first upward pyramid, per-step kernel) from two --pmc runs
+      (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by what
+      the same counter reads for the plain copy of B bytes that
+      `bench.py --profile-pass` runs.
 """
 from __future__ import annotations
 
@@ -68,20 +70,40 @@ def _pick(values: dict, pred):
     return sum(got) / len(got) if got else None
 
 
+# Kernels of the heat 1024^2 FP64 benchmark whose HBM traffic is summarised.
+HEAT_KERNELS = {
+    "oct": lambda n: "k_oct" in n and "Heat64" in n and "66" in n,
+    "bridge_pair": lambda n: "k_bridge_pair" in n and "Heat64" in n and "66" in n,
+    "up": lambda n: "k_up" in n and "Heat64" in n and "66" in n,
+    "plain": lambda n: "k_plain_cols" in n and "Heat64" in n,
+}
+
+
+def _is_copy(n: str) -> bool:
+    return ("copy" in n.lower() or "elementwise" in n.lower()) and "k_copy8" not in n
+
+
 def traffic_summary(fetch_dir: str, write_dir: str, copy_bytes: int):
+    """Per kernel: FETCH_SIZE and WRITE_SIZE per launch (KiB, summed over
+    channels), scaled to bytes by what the same counter reads for a plain copy
+    of copy_bytes (calibration run in the same process)."""
     f = counter_values(fetch_dir, "FETCH_SIZE")
     w = counter_values(write_dir, "WRITE_SIZE")
-    is_oct = lambda n: "k_oct" in n and "Heat64" in n and "66" in n
-    is_copy = lambda n: ("copy" in n.lower() or "elementwise" in n.lower()) and "k_copy8" not in n
-    f_oct, w_oct = _pick(f, is_oct), _pick(w, is_oct)
-    f_copy, w_copy = _pick(f, is_copy), _pick(w, is_copy)
-    if None in (f_oct, w_oct, f_copy, w_copy) or not f_copy or not w_copy:
-        raise RuntimeError("counter runs did not contain both the octahedron and the copy kernel")
+    f_copy, w_copy = _pick(f, _is_copy), _pick(w, _is_copy)
+    if not f_copy or not w_copy:
+        raise RuntimeError("counter runs did not contain the calibration copy")
     fs = copy_bytes / (f_copy * 1024.0)
     ws = copy_bytes / (w_copy * 1024.0)
-    return {"fetch_kib_per_launch": f_oct, "write_kib_per_launch": w_oct, "copy_fetch_kib": f_copy,
-            "copy_write_kib": w_copy, "fetch_scale": fs, "write_scale": ws,
-            "fetch_bytes_per_launch": f_oct * 1024.0 * fs, "write_bytes_per_launch": w_oct * 1024.0 * ws}
+    out = {"copy_fetch_kib": f_copy, "copy_write_kib": w_copy, "fetch_scale": fs, "write_scale": ws}
+    for kind, pred in HEAT_KERNELS.items():
+        fk, wk = _pick(f, pred), _pick(w, pred)
+        if fk is None or wk is None:
+            raise RuntimeError(f"counter runs did not contain the {kind} kernel")
+        out[f"{kind}.fetch_kib_per_launch"] = fk
+        out[f"{kind}.write_kib_per_launch"] = wk
+        out[f"{kind}.fetch_bytes_per_launch"] = fk * 1024.0 * fs
+        out[f"{kind}.write_bytes_per_launch"] = wk * 1024.0 * ws
+    return out
 
 
 def main(argv):
@@ -99,8 +121,19 @@ def main(argv):
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import bench
         with open(out, "w") as fo:
-            fo.write("# HBM traffic of the octahedron kernel k_oct<Heat64,66,1024,false> per launch "
-                     "(heat 1024x1024, tile 64, FP64, ring runs fetched from HBM)\n")
+            fo.write("# HBM traffic per launch of the heat 1024x1024 FP64 kernels (tile 64): k_oct<Heat64,66,1024,false>\n"
+                     "# (downward pyramid + next upward pyramid), k_bridge_pair<Heat64,66,512,false>, k_up<Heat64,66,1024>\n"
+                     "# and the per-step kernel k_plain_cols<Heat64,2>, from bench.py --profile-pass\n"
+                     "# Commands (from the repository root, one MI355X; each counter in a run of its own):\n"
+                     "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/pmc_fetch -o fetch -- "
+                     "python3 bench.py --profile-pass\n"
+                     "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/pmc_write -o write -- "
+                     "python3 bench.py --profile-pass\n"
+                     "#   python3 -m paper_1602_07558_amd.profiling traffic gpurun_out/prof/pmc_fetch "
+                     "gpurun_out/prof/pmc_write OUT\n"
+                     "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the ratio of the known bytes "
+                     "(64 MiB) of the\n# torch copy that --profile-pass runs to what the same counter reads for that "
+                     "copy (fetch_scale, write_scale).\n")
             for k, v in t.items():
                 fo.write(f"{k}: {v:.6g}\n")
             fo.write(f"kernel_source_sha256_16: {bench.kernel_source_hash()}\n")

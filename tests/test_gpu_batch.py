@@ -191,6 +191,31 @@ def test_uneven_batch_sampled_against_oracle(mode):
             assert np.array_equal(b.download(int(i)), ref), (int(i), specs[i], b.tile(int(i)))
 
 
+@pytest.mark.timeout(900)
+def test_literal_batch_50000_steps_sampled_against_oracle():
+    """The 256-grid workload with sides drawn from every integer in 64..512
+    (heat or wave, FP64 or FP32C) advanced its full 50000 steps in phased
+    launches; the three smallest grids that run swept and the three smallest
+    that fall back to the per-step method equal the oracle bit for bit."""
+    specs = si.batch_specs(256, seed=0, quantum=1)
+    inits = _inits(specs)
+    steps = 50000
+    _say("literal 256-grid batch, 50000 steps")
+    with _make(specs, sw.BATCH_PHASED) as b:
+        for i, s0 in enumerate(inits):
+            b.upload(i, s0)
+        b.advance(steps)
+        b.synchronize()
+        by_size = sorted(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])
+        swept = [i for i in by_size if b.tile(i) > 0][:3]
+        plain = [i for i in by_size if b.tile(i) == 0][:3]
+        assert len(swept) == 3 and len(plain) == 3
+        for i in swept + plain:
+            _say("grid", i, specs[i], "tile", b.tile(i))
+            ref = _oracle(specs[i], inits[i], steps)
+            assert np.array_equal(b.download(i), ref), (i, specs[i], b.tile(i))
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_any_sides_batch(mode):
     """Sides drawn from every integer: most grids fall back to the per-step
