@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "schemes.hpp"
 
 namespace swept {
@@ -23,11 +25,18 @@ namespace swept {
 //    quads handed out round robin.
 //  - NTo overrides the workgroup size (the batched persistent kernel runs
 //    every stage with one size).
+// Schemes whose levels run as a column walk (S::WALK, the Euler schemes).
+template <class S, class = void>
+struct walks : std::false_type {};
+template <class S>
+struct walks<S, std::void_t<decltype(S::WALK)>> : std::bool_constant<S::WALK> {};
+
 template <class S, int WC, int NTo = 0>
 struct Lay {
   static constexpr bool light = S::NW * (int)sizeof(typename S::V) <= 16;
   static constexpr int N = WC ? WC - 2 : 0;
-  static constexpr int NT = NTo ? NTo : (!light ? 512 : (WC == 66 ? 1024 : (WC == 18 ? 64 : 256)));
+  static constexpr int NT =
+      NTo ? NTo : (!light ? 512 : (WC == 66 ? 1024 : (WC == 18 ? 64 : 256)));
   static constexpr int NW = NT / 64;
   static constexpr bool cols = light && WC != 0 && (N * N) % NT == 0;
   static constexpr int R = cols ? N * N / NT : 0;

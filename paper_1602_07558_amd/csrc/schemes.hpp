@@ -177,13 +177,19 @@ __device__ __forceinline__ void phys(const double* U, int d, double gamma, doubl
   }
 }
 
+// Face flux from both sides' physical fluxes and signal speeds.
+__device__ __forceinline__ void face(const double* FL, double aL, const double* L, const double* FR, double aR,
+                                     const double* R, double* Fh) {
+  const double a = fmax(aL, aR);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Fh[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * (a * (R[k] - L[k]));
+}
+
 __device__ __forceinline__ void rusanov(const double* L, const double* R, int d, double gamma, double* Fh) {
   double FL[4], FR[4], aL, aR;
   phys(L, d, gamma, FL, aL);
   phys(R, d, gamma, FR, aR);
-  const double a = fmax(aL, aR);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) Fh[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * (a * (R[k] - L[k]));
+  face(FL, aL, L, FR, aR, R, Fh);
 }
 
 // dt L(U) at the centre from the 5-point states W, E, N, S, C (4 values each).
@@ -210,6 +216,30 @@ struct Euler64 {
   using V = double;
   static constexpr int NV = 8, NW = 8, NVAR = 8, SUB = 2;
   static constexpr bool XY_SYM = false;
+  // Levels run by the column walk of the stage kernels, which computes each
+  // cell's physical fluxes once and each face flux once, through wload (the
+  // value of slot v at p) and finish (the cell's new slots from its own old
+  // slots at `own`, its stage values C and dt L(U) = du); the same
+  // expressions as step.
+  static constexpr bool WALK = true;
+  __device__ __forceinline__ static double wload(const V* p, int plane, int v) { return p[v * plane]; }
+  __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double* C,
+                                                const double* du, V* dst) {
+    if ((T & 1) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dst[k * plane] = own[k * plane];
+        dst[(4 + k) * plane] = C[k] + du[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = 0.5 * own[k * plane] + 0.5 * (C[k] + du[k]);
+        dst[k * plane] = v;
+        dst[(4 + k) * plane] = v;
+      }
+    }
+  }
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
     const double gamma = sp.p[0], dtoh = sp.p[1];
@@ -302,6 +332,35 @@ struct Euler32C {
   using V = float;
   static constexpr int NV = 16, NW = 16, NVAR = 8, SUB = 2;
   static constexpr bool XY_SYM = false;
+  static constexpr bool WALK = true;  // as Euler64
+  __device__ __forceinline__ static double wload(const V* p, int plane, int v) {
+    return (double)p[v * plane] - (double)p[(8 + v) * plane];
+  }
+  __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double* C,
+                                                const double* du, V* dst) {
+    if ((T & 1) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dst[k * plane] = own[k * plane];
+        dst[(8 + k) * plane] = own[(8 + k) * plane];
+        float u, c;
+        split(C[k] + du[k], u, c);
+        dst[(4 + k) * plane] = u;
+        dst[(12 + k) * plane] = c;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = 0.5 * wload(own, plane, k) + 0.5 * (C[k] + du[k]);
+        float u, c;
+        split(v, u, c);
+        dst[k * plane] = u;
+        dst[(8 + k) * plane] = c;
+        dst[(4 + k) * plane] = u;
+        dst[(12 + k) * plane] = c;
+      }
+    }
+  }
   template <class NB>
   __device__ __forceinline__ static double wide(const NB& nb, int di, int dj, int v) {
     return (double)nb(di, dj, v) - (double)nb(di, dj, 8 + v);

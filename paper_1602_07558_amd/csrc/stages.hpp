@@ -30,6 +30,7 @@
 // column strip).
 #pragma once
 #include <algorithm>
+#include <type_traits>
 
 #include "engine.hpp"
 
@@ -479,13 +480,115 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
   }
 }
 
+// One Euler level over the rectangle [x0, x0+w) x [y0, y0+hg) as a column
+// walk. The rectangle is cut into segments of at most 30 columns (one or two
+// chunks across) by kWalkRows rows; a segment runs on cw + 2 consecutive
+// lanes of one wave (lane i on window column xa - 1 + i: the chunk's columns
+// and one on each side; lanes past them repeat the last one), as many
+// segments per wave as fit. Each lane walks its segment's rows with one row
+// above and below it. Per row a lane computes its cell's physical fluxes
+// along both axes once (the pressure, velocity and sound speed: four
+// divisions and a square root), takes the east lane's state and flux by a
+// DPP lane shift, forms the face flux between them, and passes it west by
+// another shift (the shifts cross segments only at their side lanes, which
+// store nothing); the face between consecutive rows is formed once as the
+// walk reaches the lower row. Every face flux is the same expression on the
+// same operands as in the per-point step (left/lower state first), so the
+// results are bit for bit the same. TR (transposed window, the x-bridge):
+// window rows run along x, so the walk is the x axis and the lanes the y
+// axis.
+// Rows per segment: one (measured on 512^2 Euler at tile side 32 in full RK2
+// steps per second: 1 row 1.27e10, 2 rows 1.23e10, 4 rows 9.6e9, 6 rows
+// 7.6e9). The levels are latency-bound at one 8-wave workgroup per CU (the
+// window fills the LDS), so independent lanes pay more than the flux work a
+// lane repeats for the rows above and below it.
+constexpr int kWalkRows = 1;
+template <class S, int WC, int NT, bool TR>
+__device__ __forceinline__ void euler_walk(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                           int Wrt, int x0, int y0, int w, int hg, long long T,
+                                           const SchemeParams& sp) {
+  constexpr int R = kWalkRows, NWv = NT / 64;
+  const int W = WC ? WC : Wrt, plane = W * W;
+  const double gamma = sp.p[0], dtoh = sp.p[1];
+  const int o = (T & 1) ? 4 : 0;
+  constexpr int dl = TR ? 1 : 0;  // axis along the lanes (window columns)
+  constexpr int dw = TR ? 0 : 1;  // axis along the walk (window rows)
+  if (w <= 0 || hg <= 0) return;
+  const int nch = w + 2 <= 32 ? 1 : 2;          // chunks across
+  const int cw = (w + nch - 1) / nch;            // columns per chunk (the last may have fewer)
+  const int lps = cw + 2;                        // lanes per segment
+  const int spw = 64 / lps;                      // segments per wave
+  const int nseg = nch * ((hg + R - 1) / R);
+  const int nunit = (nseg + spw - 1) / spw;
+  const int lane = lane_id();
+  int slot, li;
+  fdivmod(lane, lps, __builtin_amdgcn_rcpf((float)lps), slot, li);
+  for (int unit = lwave<NT>(); unit < nunit; unit += NWv) {
+    const int sraw = unit * spw + slot;
+    const bool real = slot < spw && sraw < nseg;
+    const int seg = real ? sraw : unit * spw;    // idle lanes repeat a real segment and store nothing
+    const int rs = seg / nch, ch = seg - rs * nch;
+    const int xa = x0 + ch * cw;
+    const int cwc = min(cw, x0 + w - xa);        // this chunk's columns
+    const int col = xa - 1 + (li <= cwc + 1 ? li : cwc + 1);
+    const bool store = real && li >= 1 && li <= cwc;
+    const int ys = y0 + rs * R;
+    const int ye = min(ys + R, y0 + hg);         // rows ys .. ye-1 are computed
+    // Rows ys-1 .. ys+R (rows past ye repeat row ye and store nothing): all
+    // rows' physical fluxes first, independent of one another, then the
+    // faces, then the updates.
+    double C[R + 2][4], Fl[R + 2][4], al[R + 2], Fw_[R + 2][4], aw[R + 2];
+#pragma unroll
+    for (int i = 0; i < R + 2; ++i) {
+      const int r = min(ys - 1 + i, ye);
+      const typename S::V* src = in + r * W + col;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) C[i][k] = S::wload(src, plane, o + k);
+      euler::phys(C[i], dl, gamma, Fl[i], al[i]);
+      euler::phys(C[i], dw, gamma, Fw_[i], aw[i]);
+    }
+    double G[R + 1][4];  // G[i]: face between rows i and i+1 (walk axis)
+#pragma unroll
+    for (int i = 0; i < R + 1; ++i) euler::face(Fw_[i], aw[i], C[i], Fw_[i + 1], aw[i + 1], C[i + 1], G[i]);
+#pragma unroll
+    for (int i = 1; i <= R; ++i) {
+      // faces along the lanes: with the east lane, then the west one's
+      // passed over
+      double Ce[4], Fe_[4], FeL[4], FwL[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Ce[k] = dpp_shift<false>(C[i][k]);
+        Fe_[k] = dpp_shift<false>(Fl[i][k]);
+      }
+      const double ae = dpp_shift<false>(al[i]);
+      euler::face(Fl[i], al[i], C[i], Fe_, ae, Ce, FeL);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) FwL[k] = dpp_shift<true>(FeL[k]);
+      double du[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double div = TR ? (G[i][k] - G[i - 1][k]) + (FeL[k] - FwL[k])
+                              : (FeL[k] - FwL[k]) + (G[i][k] - G[i - 1][k]);
+        du[k] = -(dtoh * div);
+      }
+      const int r = ys - 1 + i;
+      if (store && r < ye) {
+        const int q = r * W + col;
+        S::finish(T, in + q, plane, C[i], du, out + q);
+      }
+    }
+  }
+}
+
 // EDGE: the rectangle may touch window columns 1 or N (the downward
 // pyramid's full-tile level); otherwise the column layout uses DPP shifts.
 template <class S, int WC, int NT, bool TR = false, bool EDGE = false>
 __device__ __forceinline__ void compute_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
-  if constexpr (Lay<S, WC, NT>::cols) {
+  if constexpr (walks<S>::value) {
+    euler_walk<S, WC, NT, TR>(in, out, Wrt, x0, y0, w, hg, T, sp);
+  } else if constexpr (Lay<S, WC, NT>::cols) {
     compute_cols<S, WC, NT, TR, !EDGE>(in, out, x0, y0, w, hg, T, sp);
   } else {
     compute_quads<S, WC, NT, TR>(in, out, Wrt, x0, y0, w, hg, T, sp);
