@@ -67,13 +67,23 @@ extern "C" {
  *   TEST_INCR      1 / 1  u' = u + 1 if all 9 neighbours equal u, else NaN
  *                         (the worked example of Sec. 3.1)
  *   TEST_PUSH5     5 / 2  Eq. (2) then Eq. (3): the 2-ring stencil of Eq. (1)
- *                         decomposed into nearest-neighbour sub-steps */
+ *                         decomposed into nearest-neighbour sub-steps
+ *   TEST_HASH25    9 / 2  a stencil reaching two rings (an order-sensitive
+ *                         mix of the 25 values at offsets |di|, |dj| <= 2 and
+ *                         the step index) split automatically into two
+ *                         nearest-neighbour sub-steps (Sec. 2): slot 0 holds
+ *                         the value, slots 1..8 the values pushed by the
+ *                         first sub-step (zero at full steps)
+ * User schemes registered with swept2d_register_scheme get ids from
+ * SWEPT2D_USER_PDE_BASE on. */
 #define SWEPT2D_HEAT5 1
 #define SWEPT2D_WAVE_LF 2
 #define SWEPT2D_EULER_RUS_RK2 3
 #define SWEPT2D_TEST_HASH 100
 #define SWEPT2D_TEST_INCR 101
 #define SWEPT2D_TEST_PUSH5 102
+#define SWEPT2D_TEST_HASH25 103
+#define SWEPT2D_USER_PDE_BASE 1000
 
 /* ------------------------------------------------------------- precisions
  * FP64:  one double per value.
@@ -264,6 +274,47 @@ int swept2d_set_staging(swept2d *h, int mode);
  * of that kind computed. */
 int swept2d_set_timing(swept2d *h, int on);
 int swept2d_get_timing(swept2d *h, double *out, int cap);
+
+/* ------------------------------------------------------------ user schemes
+ * The paper's interface (Sec. 6): a scheme is an initialisation function
+ * Init(i, j, p) and a time-stepping function timestep(k, p) of a point's
+ * 9-point neighbourhood. Here both are device functions of a C++ struct
+ * compiled by the user in a HIP source against include/swept2d_scheme.hpp,
+ * which turns the struct into this table of launchers of the library's stage
+ * kernels instantiated for it (stencils reaching two rings go through the
+ * automatic split into nearest-neighbour sub-steps there). The launchers
+ * take the library's internal descriptors (tile geometry, panel pointers,
+ * parameters) by pointer, with the layout of that header; they return a
+ * hipError_t value. */
+#define SWEPT2D_SCHEME_ABI 1
+typedef struct swept2d_scheme_ops {
+  int abi;                 /* SWEPT2D_SCHEME_ABI */
+  int nvars, substeps;     /* as swept2d_create takes them */
+  int nparams;             /* parameters swept2d_set_params must supply (at most 4) */
+  int nv, nw, vbytes;      /* values per point in the state, in the LDS window; bytes per value */
+  int (*up)(const void *geo, int H, void *state, const void *panels, const void *params, void *stream);
+  int (*bridge)(const void *geo, int H, int staged, int pair_ok, void *state, const void *panels,
+                const void *params, void *stream);
+  int (*oct)(const void *geo, int Hd, int Hu, int staged, void *state, const void *panels, const void *params,
+             void *stream);
+  int (*plain)(int nx, int ny, long long T, const long long *tbase, const void *in, void *out, const void *params,
+               void *stream);
+  int (*lds)(size_t bytes);     /* raise the stage kernels' dynamic LDS limit */
+  int (*fetch_ahead)(int n);    /* octahedra of tile side n fetch ring runs ahead (1) or stage them (0) */
+  int (*init)(int nx, int ny, void *state, const void *params, void *stream); /* Init on every point, or NULL */
+} swept2d_scheme_ops;
+
+/* Register a user scheme; ops is copied. Returns its pde id (from
+ * SWEPT2D_USER_PDE_BASE, for swept2d_create with ops->nvars and
+ * ops->substeps; FP64 precision only; not in batches), or EINVAL for a wrong
+ * ABI version, inconsistent sizes or a missing launcher, EUNSUPPORTED when
+ * 32 schemes are registered already. Uses the current device. */
+int swept2d_register_scheme(const swept2d_scheme_ops *ops);
+
+/* Set every point of the state with the scheme's Init (asynchronous on the
+ * handle's stream; the level counter is left as it is). EUNSUPPORTED for
+ * schemes without one (the built-in schemes' fields come from the host). */
+int swept2d_init_state(swept2d *h);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *swept2d_last_error(void);

@@ -66,6 +66,9 @@ def _load():
             ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
             ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
         ]
+        lib.oracle_advance_hash25.restype = ctypes.c_int
+        lib.oracle_advance_hash25.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
+                                              ctypes.c_longlong, ctypes.c_int]
         lib.oracle_residency.restype = ctypes.c_longlong
         lib.oracle_residency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
@@ -121,6 +124,19 @@ def advance_f32r(pde: int, u: np.ndarray, params, nsub: int, tile: int, t0: int 
                                  int(t0), int(nsub), int(threads or default_threads()))
     if rc != 0:
         raise ValueError(f"oracle_advance_f32r failed with {rc}")
+    return uu
+
+
+def advance_hash25(u: np.ndarray, nsteps: int, k0: int = 0, threads: int | None = None) -> np.ndarray:
+    """The 25-point test hash (a stencil reaching two rings) applied directly
+    nsteps times to the scalar field u ([ny][nx] float64), the first with step
+    index k0."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    ny, nx = uu.shape
+    rc = lib.oracle_advance_hash25(nx, ny, uu.ctypes.data, int(k0), int(nsteps), int(threads or default_threads()))
+    if rc != 0:
+        raise ValueError(f"oracle_advance_hash25 failed with {rc}")
     return uu
 
 

@@ -569,3 +569,52 @@ int oracle_advance_f32r(int pde, int nx, int ny, int nvars, const double *params
     free(r1);
     return 0;
 }
+
+/* ------------------------------------------ a stencil reaching two rings
+ *
+ * Sec. 2 asks a stencil that reads beyond its nearest neighbours to be split
+ * into nearest-neighbour sub-steps; the split must compute the same values
+ * as the stencil itself, so the oracle is the stencil applied directly, one
+ * full step at a time: the 25-point test hash, an order-sensitive 64-bit mix
+ * of the values at offsets |di|, |dj| <= 2 in row-major order (north west
+ * first) seeded with the step index k (integers below 2^52 held in doubles). */
+static double st_hash25(long long k, const double *u, int nx, int ny, int i, int j)
+{
+    uint64_t h = 0xC2B2AE3D27D4EB4Full ^ (uint64_t)k;
+    for (int dj = -2; dj <= 2; ++dj) {
+        int jj = ((j + dj) % ny + ny) % ny;
+        for (int di = -2; di <= 2; ++di) {
+            int ii = ((i + di) % nx + nx) % nx;
+            h ^= (uint64_t)u[(size_t)jj * nx + ii];
+            h *= 0xFF51AFD7ED558CCDull;
+            h ^= h >> 32;
+        }
+    }
+    return (double)(h >> 12);
+}
+
+/* Advance the scalar field u ([ny][nx]) by nsteps applications of the
+ * 25-point hash, the first with step index k0. */
+int oracle_advance_hash25(int nx, int ny, double *u, long long k0, long long nsteps, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nsteps < 0 || k0 < 0 || !u)
+        return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t plane = (size_t)nx * (size_t)ny;
+    double *tmp = (double *)malloc(plane * sizeof(double));
+    if (!tmp) return -3;
+    double *cur = u, *nxt = tmp;
+    for (long long s = 0; s < nsteps; ++s) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                nxt[(size_t)j * nx + i] = st_hash25(k0 + s, cur, nx, ny, i, j);
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != u)
+        memcpy(u, cur, plane * sizeof(double));
+    free(tmp);
+    return 0;
+}

@@ -34,6 +34,9 @@ EULER_RUS_RK2 = 3
 TEST_HASH = 100
 TEST_INCR = 101
 TEST_PUSH5 = 102
+TEST_HASH25 = 103
+USER_PDE_BASE = 1000
+SCHEME_ABI = 1
 
 FP64 = 0
 FP32C = 1
@@ -67,7 +70,7 @@ EXPORTS = [
     "swept2d_batch_get_tile", "swept2d_batch_autotune", "swept2d_batch_upload", "swept2d_batch_download",
     "swept2d_batch_advance", "swept2d_batch_synchronize", "swept2d_batch_substep_counter",
     "swept2d_batch_set_wait_limit", "swept2d_batch_set_mode", "swept2d_batch_get_mode",
-    "swept2d_batch_launches", "swept2d_advance_noalloc",
+    "swept2d_batch_launches", "swept2d_advance_noalloc", "swept2d_register_scheme", "swept2d_init_state",
 ]
 
 _lib = None
@@ -137,6 +140,8 @@ def load_library():
         "swept2d_batch_get_mode": (i, [vp]),
         "swept2d_batch_launches": (i, [vp, ll]),
         "swept2d_advance_noalloc": (i, [i, i, i, i, i, i, ctypes.POINTER(d), i, i, vp, ll, ll, vp]),
+        "swept2d_register_scheme": (i, [vp]),
+        "swept2d_init_state": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -342,7 +347,24 @@ def swept2d_batch_launches(b: int, nsteps: int) -> int:
 
 
 PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), TEST_HASH: (1, 1),
-             TEST_INCR: (1, 1), TEST_PUSH5: (5, 2)}
+             TEST_INCR: (1, 1), TEST_PUSH5: (5, 2), TEST_HASH25: (9, 2)}
+
+
+class SchemeOps(ctypes.Structure):
+    """The C swept2d_scheme_ops table (launchers as opaque pointers)."""
+    _fields_ = [("abi", ctypes.c_int), ("nvars", ctypes.c_int), ("substeps", ctypes.c_int),
+                ("nparams", ctypes.c_int), ("nv", ctypes.c_int), ("nw", ctypes.c_int), ("vbytes", ctypes.c_int)] + \
+               [(n, ctypes.c_void_p) for n in ("up", "bridge", "oct", "plain", "lds", "fetch_ahead", "init")]
+
+
+def swept2d_register_scheme(ops_ptr: int) -> int:
+    """Register a user scheme from the address of its swept2d_scheme_ops
+    table; returns its pde id."""
+    return _check(load_library().swept2d_register_scheme(ops_ptr))
+
+
+def swept2d_init_state(h: int) -> int:
+    return _check(load_library().swept2d_init_state(h))
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -363,8 +385,8 @@ def swept2d_advance_noalloc(nx: int, ny: int, pde: int, prec: int, params, tile:
 class Swept2D:
     """Owner of one swept2d handle."""
 
-    def __init__(self, nx: int, ny: int, pde: int, params=None, prec: int = FP64, tile: int = 0):
-        nvars, sub = PDE_SHAPE[pde]
+    def __init__(self, nx: int, ny: int, pde: int, params=None, prec: int = FP64, tile: int = 0, shape=None):
+        nvars, sub = shape if shape is not None else PDE_SHAPE[pde]
         self.nx, self.ny, self.pde, self.nvars, self.substeps = nx, ny, pde, nvars, sub
         self.h = swept2d_create(nx, ny, nvars, pde, sub)
         try:
@@ -445,6 +467,10 @@ class Swept2D:
     def unbind(self):
         swept2d_bind(self.h, None, None)
         self._bound = None
+
+    def init_state(self):
+        """Set the state with the scheme's device Init (user schemes)."""
+        swept2d_init_state(self.h)
 
     def advance(self, nsteps: int):
         swept2d_advance(self.h, nsteps)

@@ -26,9 +26,13 @@ LIB = os.path.join(HERE, "libswept2d.so")
 # part of the swept2d library).
 PROBE_SRC = os.path.join(CSRC, "probe_lds.hip")
 PROBE_LIB = os.path.join(HERE, "libswept2d_probe.so")
+# A user scheme built against include/swept2d_scheme.hpp and linked with the
+# library (the GPU tests register it through swept2d_register_scheme).
+PLUGIN_SRC = os.path.join(ROOT, "tests", "plugin", "paper_eq1_scheme.hip")
+PLUGIN_LIB = os.path.join(ROOT, "tests", "plugin", "libpaper_eq1_scheme.so")
 
 SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C", "Wave32C", "Euler32C",
-           "Heat32R", "Wave32R"]
+           "Heat32R", "Wave32R", "Hash25x2"]
 # Batch launch classes: (window pitch, workgroup size).
 BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64)]
 
@@ -95,7 +99,19 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
     os.replace(tmp, LIB)
     build_probe(cc)
+    build_plugin(cc)
     return LIB
+
+
+def build_plugin(cc: str | None = None) -> str:
+    cc = cc or hipcc()
+    tmp = PLUGIN_LIB + ".tmp"
+    res = subprocess.run([cc, *FLAGS, "-shared", "-o", tmp, PLUGIN_SRC, "-L" + HERE, "-lswept2d",
+                          "-Wl,-rpath,$ORIGIN/../../paper_1602_07558_amd"], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("plugin build failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, PLUGIN_LIB)
+    return PLUGIN_LIB
 
 
 def build_probe(cc: str | None = None) -> str:

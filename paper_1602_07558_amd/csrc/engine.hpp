@@ -7,6 +7,7 @@
 
 #include <type_traits>
 
+#include "../../include/swept2d.h"
 #include "schemes.hpp"
 
 namespace swept {
@@ -119,8 +120,15 @@ enum Scheme : int {
   kEuler32C,
   kHeat32R,
   kWave32R,
+  kHash25x2,
   kNumSchemes
 };
+
+// User schemes (swept2d_register_scheme) take scheme ids kNumSchemes + k;
+// their launchers are the registered table's.
+constexpr int kMaxUserSchemes = 32;
+const swept2d_scheme_ops* user_scheme(int k);  // k-th registered table, or null
+int add_user_scheme(const swept2d_scheme_ops& ops);  // its index, or -1 when full
 
 // Launch entry points (swept2d_kernels.hip dispatches them). Each returns the
 // hipError_t of the launch.

@@ -403,6 +403,124 @@ struct Euler32C {
   }
 };
 
+// ------------------------------------------- stencils reaching two rings
+//
+// Sec. 2 asks a stencil that reads beyond its nearest neighbours to be split
+// into sub-steps that each read only those, and shows the split for one
+// example (Eq. (1) into Eq. (2)-(3)): the first sub-step pushes neighbour
+// values into extra slots of every point, the second reads them one hop
+// away. PushTwoRing<WS> does that split for any one-step scheme WS whose
+// step reads offsets (di, dj) with |di|, |dj| <= 2 (the offsets it declares
+// in OFF). Offset (di, dj) is reached as the hop (a, b) = (di / 2, dj / 2)
+// (rounded toward zero) to a neighbour, then the value that neighbour pushed
+// from its own offset (di - a, dj - b); both hops lie within one ring.
+// Slots: for each of WS's variables, one per distinct pushed offset, the
+// offset (0, 0) first, so slot v * P of a point at a full step holds
+// variable v and the other slots are zero. Sub-step 0 pushes; sub-step 1
+// evaluates WS's step on the pushed values (the same values in the same
+// expression as a direct evaluation, so the same bits) and clears them.
+namespace wide {
+constexpr int hop1(int d) { return d / 2; }
+constexpr int hop2(int d) { return d - d / 2; }
+// Index of pushed offset (c, d) among WS's pushed offsets, or -1.
+template <class WS>
+constexpr int pushed_index(int c, int d) {
+  int k = 1;  // (0, 0) is index 0
+  if (c == 0 && d == 0) return 0;
+  bool seen[9] = {};
+  seen[4] = true;
+  for (int i = 0; i < WS::NOFF; ++i) {
+    const int pc = hop2(WS::OFF[i][0]), pd = hop2(WS::OFF[i][1]);
+    const int key = 3 * (pd + 1) + (pc + 1);
+    if (seen[key]) continue;
+    seen[key] = true;
+    if (pc == c && pd == d) return k;
+    ++k;
+  }
+  return -1;
+}
+template <class WS>
+constexpr int pushed_count() {
+  bool seen[9] = {};
+  seen[4] = true;
+  int k = 1;
+  for (int i = 0; i < WS::NOFF; ++i) {
+    const int key = 3 * (hop2(WS::OFF[i][1]) + 1) + (hop2(WS::OFF[i][0]) + 1);
+    if (!seen[key]) {
+      seen[key] = true;
+      ++k;
+    }
+  }
+  return k;
+}
+}  // namespace wide
+
+template <class WS>
+struct PushTwoRing {
+  using V = typename WS::V;
+  static constexpr int P = wide::pushed_count<WS>();
+  static constexpr int NV = WS::NVAR * P, NW = NV, NVAR = NV, SUB = 2;
+  static constexpr bool XY_SYM = false;
+  static_assert(WS::SUB == 1, "a one-step wide scheme");
+  // The wide step's view of the pushed values: offset (di, dj), variable v.
+  template <class NB>
+  struct Far {
+    const NB& nb;
+    __device__ __forceinline__ V operator()(int di, int dj, int v) const {
+      return nb(wide::hop1(di), wide::hop1(dj), v * P + wide::pushed_index<WS>(wide::hop2(di), wide::hop2(dj)));
+    }
+  };
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
+    if ((T & 1) == 0) {
+#pragma unroll
+      for (int v = 0; v < WS::NVAR; ++v) {
+        out[v * P] = nb(0, 0, v * P);
+#pragma unroll
+        for (int i = 0; i < WS::NOFF; ++i) {
+          const int c = wide::hop2(WS::OFF[i][0]), d = wide::hop2(WS::OFF[i][1]);
+          out[v * P + wide::pushed_index<WS>(c, d)] = nb(c, d, v * P);
+        }
+      }
+    } else {
+      V res[WS::NVAR];
+      WS::step(T >> 1, Far<NB>{nb}, res, sp);
+#pragma unroll
+      for (int v = 0; v < WS::NVAR; ++v) {
+        out[v * P] = res[v];
+#pragma unroll
+        for (int k = 1; k < P; ++k) out[v * P + k] = V(0);
+      }
+    }
+  }
+};
+
+// Test stencil reaching two rings: a 64-bit mix, in row-major order (north
+// west first), of the 25 values at offsets |di|, |dj| <= 2 (integers below
+// 2^52 held in doubles), seeded with the step index; the top 52 bits are the
+// new value.
+struct Hash25 {
+  using V = double;
+  static constexpr int NVAR = 1, SUB = 1, NOFF = 25;
+  static constexpr int OFF[25][2] = {{-2, -2}, {-1, -2}, {0, -2}, {1, -2}, {2, -2}, {-2, -1}, {-1, -1}, {0, -1}, {1, -1},
+                                     {2, -1},  {-2, 0},  {-1, 0}, {0, 0},  {1, 0},  {2, 0},   {-2, 1},  {-1, 1}, {0, 1},
+                                     {1, 1},   {2, 1},   {-2, 2}, {-1, 2}, {0, 2},  {1, 2},   {2, 2}};
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams&) {
+    uint64_t m = 0xC2B2AE3D27D4EB4Full ^ (uint64_t)T;
+#pragma unroll
+    for (int dj = -2; dj <= 2; ++dj)
+#pragma unroll
+      for (int di = -2; di <= 2; ++di) {
+        m ^= (uint64_t)nb(di, dj, 0);
+        m *= 0xFF51AFD7ED558CCDull;
+        m ^= m >> 32;
+      }
+    out[0] = (double)(m >> 12);
+  }
+};
+using Hash25x2 = PushTwoRing<Hash25>;
+
 // FP32 with the compensation kept only within a residency: the state and
 // the panels hold the values u alone (half the bytes of FP32C); the
 // compensations are window-only values, zero when a point's value arrives

@@ -50,7 +50,12 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 
+const swept2d_scheme_ops* user_pde(int pde) {
+  return pde >= SWEPT2D_USER_PDE_BASE ? user_scheme(pde - SWEPT2D_USER_PDE_BASE) : nullptr;
+}
+
 int pde_nvars(int pde) {
+  if (const swept2d_scheme_ops* u = user_pde(pde)) return u->nvars;
   switch (pde) {
     case SWEPT2D_HEAT5: return 1;
     case SWEPT2D_WAVE_LF: return 2;
@@ -58,19 +63,23 @@ int pde_nvars(int pde) {
     case SWEPT2D_TEST_HASH: return 1;
     case SWEPT2D_TEST_INCR: return 1;
     case SWEPT2D_TEST_PUSH5: return 5;
+    case SWEPT2D_TEST_HASH25: return Hash25x2::NVAR;
     default: return -1;
   }
 }
 
 int pde_substeps(int pde) {
+  if (const swept2d_scheme_ops* u = user_pde(pde)) return u->substeps;
   switch (pde) {
     case SWEPT2D_EULER_RUS_RK2:
-    case SWEPT2D_TEST_PUSH5: return 2;
+    case SWEPT2D_TEST_PUSH5:
+    case SWEPT2D_TEST_HASH25: return 2;
     default: return pde_nvars(pde) > 0 ? 1 : -1;
   }
 }
 
 int pde_nparams(int pde) {
+  if (const swept2d_scheme_ops* u = user_pde(pde)) return u->nparams;
   switch (pde) {
     case SWEPT2D_HEAT5: return 1;
     case SWEPT2D_WAVE_LF: return 1;
@@ -88,7 +97,9 @@ int scheme_of(int pde, int prec) {
       case SWEPT2D_TEST_HASH: return kHash64;
       case SWEPT2D_TEST_INCR: return kIncr64;
       case SWEPT2D_TEST_PUSH5: return kPush5;
+      case SWEPT2D_TEST_HASH25: return kHash25x2;
     }
+    if (pde >= SWEPT2D_USER_PDE_BASE && user_pde(pde)) return kNumSchemes + (pde - SWEPT2D_USER_PDE_BASE);
   } else if (prec == SWEPT2D_FP32C) {
     switch (pde) {
       case SWEPT2D_HEAT5: return kHeat32C;
@@ -748,6 +759,32 @@ int swept2d_download(swept2d* h, double* host) {
   int rc = swept2d_download_raw(h, buf.data());
   if (rc) return rc;
   for (size_t i = 0; i < cnt; ++i) host[i] = comp ? (double)buf[i] - (double)buf[cnt + i] : (double)buf[i];
+  return 0;
+}
+
+int swept2d_register_scheme(const swept2d_scheme_ops* ops) {
+  g_err.clear();
+  if (!ops) return fail(SWEPT2D_EINVAL, "null scheme table");
+  if (ops->abi != SWEPT2D_SCHEME_ABI) return fail(SWEPT2D_EINVAL, "scheme table ABI %d, library %d", ops->abi,
+                                                 SWEPT2D_SCHEME_ABI);
+  if (ops->nvars < 1 || ops->substeps < 1 || ops->nparams < 0 || ops->nparams > 4 || ops->nv != ops->nvars ||
+      ops->nw < ops->nv || (ops->vbytes != 4 && ops->vbytes != 8))
+    return fail(SWEPT2D_EINVAL, "inconsistent scheme sizes");
+  if (!ops->up || !ops->bridge || !ops->oct || !ops->plain || !ops->lds || !ops->fetch_ahead)
+    return fail(SWEPT2D_EINVAL, "scheme table lacks a launcher");
+  int dev = 0;
+  if (int rc = ensure_device_setup(&dev)) return rc;
+  HIP_TRY(static_cast<hipError_t>(ops->lds(g_lds_limit)), "scheme LDS limit");
+  const int k = add_user_scheme(*ops);
+  if (k < 0) return fail(SWEPT2D_EUNSUPPORTED, "%d user schemes are registered already", kMaxUserSchemes);
+  return SWEPT2D_USER_PDE_BASE + k;
+}
+
+int swept2d_init_state(swept2d* h) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  const swept2d_scheme_ops* u = user_pde(h->pde);
+  if (!u || !u->init) return fail(SWEPT2D_EUNSUPPORTED, "pde %d has no device initialisation", h->pde);
+  HIP_TRY(static_cast<hipError_t>(u->init(h->nx, h->ny, h->state, &h->sp, h->stream)), "init launch");
   return 0;
 }
 

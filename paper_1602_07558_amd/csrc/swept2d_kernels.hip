@@ -3,6 +3,8 @@
 // The stage kernels themselves are in stages.hpp, instantiated once per
 // scheme (stages_scheme.hip) and per batch launch class (stages_batch.hip).
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -19,6 +21,7 @@ extern template struct Stages<Wave32C>;
 extern template struct Stages<Euler32C>;
 extern template struct Stages<Heat32R>;
 extern template struct Stages<Wave32R>;
+extern template struct Stages<Hash25x2>;
 extern template struct BatchPhase<66, 1024>;
 extern template struct BatchPhase<34, 256>;
 extern template struct BatchPhase<18, 64>;
@@ -54,41 +57,74 @@ __global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrid
     case kEuler32C: return Stages<Euler32C>::FN(__VA_ARGS__); \
     case kHeat32R: return Stages<Heat32R>::FN(__VA_ARGS__);   \
     case kWave32R: return Stages<Wave32R>::FN(__VA_ARGS__);   \
+    case kHash25x2: return Stages<Hash25x2>::FN(__VA_ARGS__); \
     default: break;                                          \
   }
 
+std::mutex g_user_mu;
+swept2d_scheme_ops g_user[kMaxUserSchemes];
+std::atomic<int> g_user_count{0};
+
+const swept2d_scheme_ops* user_of(int scheme) {
+  const int k = scheme - kNumSchemes;
+  return (k >= 0 && k < g_user_count.load()) ? &g_user[k] : nullptr;
+}
+
+hipError_t as_hip(int e) { return static_cast<hipError_t>(e); }
+
 }  // namespace
 
+const swept2d_scheme_ops* user_scheme(int k) {
+  return (k >= 0 && k < g_user_count.load()) ? &g_user[k] : nullptr;
+}
+
+int add_user_scheme(const swept2d_scheme_ops& ops) {
+  std::lock_guard<std::mutex> lock(g_user_mu);
+  const int k = g_user_count.load();
+  if (k >= kMaxUserSchemes) return -1;
+  g_user[k] = ops;
+  g_user_count.store(k + 1);
+  return k;
+}
+
 SchemeInfo scheme_info(int scheme) {
+  if (const swept2d_scheme_ops* u = user_of(scheme)) return SchemeInfo{u->nv, u->nw, u->nvars, u->substeps, u->vbytes};
   SWEPT_DISPATCH(info)
   return SchemeInfo{0, 0, 0, 0, 0};
 }
 
 hipError_t launch_up(int scheme, const Geo& g, int H, void* state, PanelPtrs p, const SchemeParams& sp,
                      hipStream_t s) {
+  if (const swept2d_scheme_ops* u = user_of(scheme)) return as_hip(u->up(&g, H, state, &p, &sp, s));
   SWEPT_DISPATCH(up, g, H, state, p, sp, s)
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_bridge(int scheme, const Geo& g, int H, bool staged, bool pair_ok, void* state, PanelPtrs p,
                          const SchemeParams& sp, hipStream_t s) {
+  if (const swept2d_scheme_ops* u = user_of(scheme))
+    return as_hip(u->bridge(&g, H, staged ? 1 : 0, pair_ok ? 1 : 0, state, &p, &sp, s));
   SWEPT_DISPATCH(bridge, g, H, staged, pair_ok, state, p, sp, s)
   return hipErrorInvalidValue;
 }
 
 bool oct_fetch_ahead(int scheme, int n) {
+  if (const swept2d_scheme_ops* u = user_of(scheme)) return u->fetch_ahead(n) != 0;
   SWEPT_DISPATCH(fetch_ahead, n)
   return false;
 }
 
 hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, void* state, PanelPtrs p,
                       const SchemeParams& sp, hipStream_t s) {
+  if (const swept2d_scheme_ops* u = user_of(scheme))
+    return as_hip(u->oct(&g, Hd, Hu, staged ? 1 : 0, state, &p, &sp, s));
   SWEPT_DISPATCH(oct, g, Hd, Hu, staged, state, p, sp, s)
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_plain(int scheme, int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
                         const SchemeParams& sp, hipStream_t s) {
+  if (const swept2d_scheme_ops* u = user_of(scheme)) return as_hip(u->plain(nx, ny, T, tbase, in, out, &sp, s));
   SWEPT_DISPATCH(plain, nx, ny, T, tbase, in, out, sp, s)
   return hipErrorInvalidValue;
 }

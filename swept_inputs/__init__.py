@@ -24,6 +24,7 @@ with the shapes of those workloads):
 * hash: uniform random integers in [0, 2^52) stored exactly as doubles.
 * incr: constant field (the paper's worked example starts at value 1).
 * push5: random small integers in slot 0, zeros in slots 1..4.
+* hash25: random integers in [0, 2^52) in slot 0, zeros in slots 1..8.
 """
 from __future__ import annotations
 
@@ -37,6 +38,7 @@ EULER_RUS_RK2 = 3
 TEST_HASH = 100
 TEST_INCR = 101
 TEST_PUSH5 = 102
+TEST_HASH25 = 103
 
 PDE_NAMES = {
     HEAT5: "heat5",
@@ -45,6 +47,7 @@ PDE_NAMES = {
     TEST_HASH: "test_hash",
     TEST_INCR: "test_incr",
     TEST_PUSH5: "test_push5",
+    TEST_HASH25: "test_hash25",
 }
 
 # (nvars, substeps) per pde; hash and incr are scalar single-step stencils.
@@ -55,6 +58,7 @@ PDE_SHAPE = {
     TEST_HASH: (1, 1),
     TEST_INCR: (1, 1),
     TEST_PUSH5: (5, 2),
+    TEST_HASH25: (9, 2),
 }
 
 HEAT_R = 0.2          # r = alpha dt / h^2
@@ -190,6 +194,14 @@ def push5_field(nx: int, ny: int, seed: int = 0) -> np.ndarray:
     return s
 
 
+def hash25_field(nx: int, ny: int, seed: int = 0) -> np.ndarray:
+    """The two-ring test stencil's state: random integers below 2^52 in slot
+    0 (the value), zeros in the 8 slots of pushed values."""
+    s = np.zeros((9, ny, nx), dtype=np.float64)
+    s[0] = hash_field(nx, ny, seed)[0]
+    return s
+
+
 def initial_state(pde: int, nx: int, ny: int, seed: int = 0) -> np.ndarray:
     if pde == HEAT5:
         return heat_field(nx, ny, seed)
@@ -203,6 +215,8 @@ def initial_state(pde: int, nx: int, ny: int, seed: int = 0) -> np.ndarray:
         return incr_field(nx, ny)
     if pde == TEST_PUSH5:
         return push5_field(nx, ny, seed)
+    if pde == TEST_HASH25:
+        return hash25_field(nx, ny, seed)
     raise ValueError(f"unknown pde {pde}")
 
 

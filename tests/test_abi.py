@@ -126,3 +126,19 @@ def test_batch_create_without_device_fails_loudly(lib):
     iv = lambda *v: (ctypes.c_int * len(v))(*v)
     assert not lib.swept2d_batch_create(1, iv(64), iv(64), iv(sw.TEST_HASH), iv(sw.FP64), None, 0)
     assert sw.swept2d_last_error()
+
+
+def test_user_scheme_table_is_checked_before_any_device_call(lib):
+    """A scheme table with another ABI version is rejected (EINVAL) without
+    touching a device."""
+    ops = sw.SchemeOps(abi=sw.SCHEME_ABI + 1, nvars=1, substeps=1, nparams=0, nv=1, nw=1, vbytes=8)
+    import ctypes
+    rc = lib.swept2d_register_scheme(ctypes.addressof(ops))
+    assert rc == sw.EINVAL
+    assert "ABI" in sw.swept2d_last_error()
+
+
+def test_user_scheme_plugin_builds_and_exports(lib):
+    import ctypes
+    plug = ctypes.CDLL(sw._build.PLUGIN_LIB)
+    assert hasattr(plug, "paper_eq1_register") and plug.paper_eq1_slots() == 5

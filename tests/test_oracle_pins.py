@@ -668,3 +668,30 @@ def test_f32r_error_between_full_compensation_and_plain_fp32(pde, steps):
     errs = {n: _norm_rel(oracle.advance_f32r(pde, u, p, steps, n).astype(np.float64), ref) for n in (0, 16, 64)}
     assert err_b < errs[64] < errs[16] < errs[0]
     assert errs[64] < 1e-6
+
+
+# ------------------------------------------------- stencils reaching two rings
+
+def test_hash25_is_local_to_two_rings_and_position_sensitive():
+    """One step of the 25-point hash changes exactly the 5x5 neighbourhood of
+    a changed input (periodic wrap included); swapping two inputs of a
+    neighbourhood, or changing the step index, changes the result."""
+    nx, ny = 11, 9
+    u = si.hash_field(nx, ny, seed=2)[0]
+    base = oracle.advance_hash25(u, 1, k0=4)
+    for (ci, cj) in [(0, 0), (10, 8), (5, 4)]:
+        t = u.copy()
+        t[cj, ci] += 1.0
+        diff = oracle.advance_hash25(t, 1, k0=4) != base
+        want = np.zeros_like(diff)
+        for dj in range(-2, 3):
+            for di in range(-2, 3):
+                want[(cj + dj) % ny, (ci + di) % nx] = True
+        assert np.array_equal(diff, want)
+    w = u.copy()
+    w[4, 3], w[4, 5] = u[4, 5], u[4, 3]
+    assert oracle.advance_hash25(w, 1, k0=4)[4, 4] != base[4, 4]
+    assert np.all(oracle.advance_hash25(u, 1, k0=5) != base)
+    assert np.all(base < 2.0 ** 52) and np.all(base == np.floor(base))
+    two = oracle.advance_hash25(u, 2, k0=4)
+    assert np.array_equal(two, oracle.advance_hash25(base, 1, k0=5))
