@@ -136,12 +136,16 @@ const char* batch_tile_problem(const HostGrid& g, int n) {
 // items it needs when its items outnumber the workgroups resident on `cus`
 // compute units (residency from the item's LDS and its launch class's
 // workgroup size). Cost per sub-step, in the spirit of Sec. 5, Eq. (4):
-// [2 tau + 3 h lambda] * rounds / h.
+// [2 tau + 3 h lambda] * rounds / h. The per-step method competes at one
+// launch per sub-step, tau times its rounds of 64 x 64 blocks: a grid whose
+// only usable sides are small (a half cycle of a few levels) runs per step.
 int model_tile(const HostGrid& g, int cus) {
   const double tau = 6.0e-6, lambda = 0.75e-6;
   const size_t lim = std::max<size_t>(device_lds_limit(), 1);
+  const double blocks = (double)((g.nx + kBatchBlock - 1) / kBatchBlock) * ((g.ny + kBatchBlock - 1) / kBatchBlock);
+  const double plain_per_cu = 2048.0 / batch_class_threads(kClassGen256);
   int best = 0;
-  double best_cost = 1e300;
+  double best_cost = tau * std::ceil(blocks / (plain_per_cu * std::max(cus, 1)));
   for (int n = 4; n <= 64; n += 2) {
     if (batch_tile_problem(g, n)) continue;
     const int h = n / 2;
