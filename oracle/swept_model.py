@@ -23,6 +23,17 @@ a point at level l reads its 3x3 neighbourhood at level l - 1 from its own
 component or from a component of an earlier phase; anything else is an
 error (ModelError). The next half cycle shifts the tiling by h in x and y.
 
+The same level function partitions a half cycle of H levels over any
+tiling of the periodic axes into rectangles whose sides are at least 2H
+(a tile wider than 2H gives a frustum instead of a pyramid: its level-H top
+is not empty). ``rect_axis`` splits an axis of any length L into
+floor(L / 2h) tiles whose widths differ by at most one, and ``mid_axis``
+gives the tiling whose edges lie at the tiles' midpoints; the two
+alternate between half cycles (``swept2d_rect``). Every tile of either
+contains exactly one edge of the other at a distance of at least h from
+its own edges, which is what lets a downward pyramid continue as the next
+half cycle's upward one.
+
 So the model checks that the partition covers every point and level once,
 that its dependencies respect the phase order, and that the result equals
 plain stepping; it also counts each component's points and the values that
@@ -95,28 +106,68 @@ def edge_distance(t: int, n: int) -> int:
     return min(t, n - 1 - t)
 
 
-def component(x: int, y: int, l: int, n: int, off: int, nx: int, ny: int):
-    """Component holding level l (0..h) of global point (x, y) in the half
-    cycle whose tiling has side n and offset off, as (kind, id), or None
-    when no component holds it (only under the printed bridge band)."""
-    h = n // 2
-    tx, ty = (x - off) % nx, (y - off) % ny
-    a, b = tx // n, ty // n
-    lx, ly = tx % n, ty % n
-    dx, dy = edge_distance(lx, n), edge_distance(ly, n)
-    ntx, nty = nx // n, ny // n
+@dataclass(frozen=True)
+class Axis:
+    """The tiles of one periodic axis of length L: tile a covers the cells
+    edges[a] .. edges[a+1] - 1, the last one wrapping round to edges[0]."""
+    L: int
+    edges: tuple
+
+    def widths(self) -> list:
+        t = len(self.edges)
+        return [(self.edges[(a + 1) % t] - self.edges[a]) % self.L or self.L for a in range(t)]
+
+    def locate(self, x: int):
+        """(tile, tile-local coordinate, tile width) of cell x."""
+        for a, w in enumerate(self.widths()):
+            lx = (x - self.edges[a]) % self.L
+            if lx < w:
+                return a, lx, w
+        raise AssertionError("axis tiles do not cover the axis")
+
+
+def uniform_axis(L: int, n: int, off: int) -> Axis:
+    assert L % n == 0
+    return Axis(L, tuple(sorted((off + k * n) % L for k in range(L // n))))
+
+
+def rect_axis(L: int, h: int) -> Axis:
+    """floor(L / 2h) tiles of widths floor(L/t) or floor(L/t) + 1 (the wider
+    ones first), starting at cell 0."""
+    t = L // (2 * h)
+    assert t >= 1, "the axis is shorter than 2h"
+    edges, e = [], 0
+    for a in range(t):
+        edges.append(e)
+        e += L // t + (1 if a < L % t else 0)
+    assert e == L
+    return Axis(L, tuple(edges))
+
+
+def mid_axis(ax: Axis) -> Axis:
+    """The tiling whose edges are the midpoints edges[a] + floor(w_a / 2)."""
+    return Axis(ax.L, tuple(sorted((e + w // 2) % ax.L for e, w in zip(ax.edges, ax.widths()))))
+
+
+def component_at(x: int, y: int, l: int, ax: Axis, ay: Axis):
+    """Component holding level l of point (x, y) in a half cycle on the
+    tiling ax x ay, as (kind, id); None only under the printed bridge band."""
+    a, lx, wx = ax.locate(x)
+    b, ly, wy = ay.locate(y)
+    dx, dy = edge_distance(lx, wx), edge_distance(ly, wy)
+    ntx, nty = len(ax.edges), len(ay.edges)
     # the edge (and corner) nearest to the point, named by the tile to its
     # west (x-edges) or north (y-edges)
-    ea = a if lx >= h else (a - 1) % ntx
-    eb = b if ly >= h else (b - 1) % nty
+    ea = a if lx >= wx // 2 else (a - 1) % ntx
+    eb = b if ly >= wy // 2 else (b - 1) % nty
     if l == 0 or (dx >= l and dy >= l):
         return (UP, (a, b))
     if LITERAL_BRIDGE_BAND:
         # printed loop: a two-point band on the west (x-bridge) / north
         # (y-bridge) side of the edge only
-        if dy >= l and lx >= h and dx in (l - 1, l - 2):
+        if dy >= l and lx >= wx // 2 and dx in (l - 1, l - 2):
             return (XB, (ea, b))
-        if dx >= l and ly >= h and dy in (l - 1, l - 2):
+        if dx >= l and ly >= wy // 2 and dy in (l - 1, l - 2):
             return (YB, (a, eb))
         if dx < l and dy < l:
             return (DOWN, (ea, eb))
@@ -126,6 +177,11 @@ def component(x: int, y: int, l: int, n: int, off: int, nx: int, ny: int):
     if dx >= l and dy < l:
         return (YB, (a, eb))
     return (DOWN, (ea, eb))
+
+
+def component(x: int, y: int, l: int, n: int, off: int, nx: int, ny: int):
+    """component_at on the tiling of n x n squares offset by off in x and y."""
+    return component_at(x, y, l, uniform_axis(nx, n, off), uniform_axis(ny, n, off))
 
 
 @dataclass
@@ -145,14 +201,22 @@ def half_cycle(St, grid: np.ndarray, n: int, off: int, T0: int, H: int, stats: S
     """Advance grid[y][x] (at level T0) by H <= n/2 levels on the tiling of
     side n and offset off, component by component; returns level T0 + H."""
     ny, nx = grid.shape
-    h = n // 2
-    assert n % 2 == 0 and n >= 2 and nx % n == 0 and ny % n == 0 and 0 < H <= h
+    assert n % 2 == 0 and n >= 2 and nx % n == 0 and ny % n == 0 and 0 < H <= n // 2
+    return half_cycle_on(St, grid, uniform_axis(nx, n, off), uniform_axis(ny, n, off), T0, H, stats)
+
+
+def half_cycle_on(St, grid: np.ndarray, ax: Axis, ay: Axis, T0: int, H: int,
+                  stats: Stats | None = None) -> np.ndarray:
+    """Advance grid[y][x] (at level T0) by H levels on the tiling ax x ay,
+    component by component; returns level T0 + H."""
+    ny, nx = grid.shape
+    assert ax.L == nx and ay.L == ny and H > 0
     owner = {}
     members = {}
     for l in range(H + 1):
         for y in range(ny):
             for x in range(nx):
-                c = component(x, y, l, n, off, nx, ny)
+                c = component_at(x, y, l, ax, ay)
                 if c is None:
                     if l == H:
                         raise ModelError(f"level {T0 + l} of point ({x}, {y}) belongs to no component")
@@ -207,6 +271,27 @@ def swept2d(St, grid: np.ndarray, n: int, cycles: int, T0: int = 0, stats: Stats
         g = half_cycle(St, g, n, off, T, h, stats)
         T += h
         off = h - off
+        if after_half is not None:
+            after_half(T, g.copy())
+    return g
+
+
+def swept2d_rect(St, grid: np.ndarray, h: int, levels: int, T0: int = 0, stats: Stats | None = None,
+                 after_half=None) -> np.ndarray:
+    """Advance grid[y][x] by `levels` levels in half cycles of h levels (the
+    last one shorter when h does not divide `levels`), alternating the
+    tiling rect_axis(nx, h) x rect_axis(ny, h) and its midpoint tiling."""
+    ny, nx = grid.shape
+    tilings = [(rect_axis(nx, h), rect_axis(ny, h))]
+    tilings.append((mid_axis(tilings[0][0]), mid_axis(tilings[0][1])))
+    g = np.array(grid, dtype=np.float64)
+    T, k = T0, 0
+    while T < T0 + levels:
+        H = min(h, T0 + levels - T)
+        ax, ay = tilings[k % 2]
+        g = half_cycle_on(St, g, ax, ay, T, H, stats)
+        T += H
+        k += 1
         if after_half is not None:
             after_half(T, g.copy())
     return g

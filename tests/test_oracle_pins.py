@@ -695,3 +695,77 @@ def test_hash25_is_local_to_two_rings_and_position_sensitive():
     assert np.all(base < 2.0 ** 52) and np.all(base == np.floor(base))
     two = oracle.advance_hash25(u, 2, k0=4)
     assert np.array_equal(two, oracle.advance_hash25(base, 1, k0=5))
+
+
+# ------------------------- rectangular tiles of any side (the level function)
+
+@pytest.mark.parametrize("nx,ny,h,levels", [(11, 9, 2, 7), (13, 17, 3, 10), (10, 7, 2, 5), (9, 9, 4, 9),
+                                            (20, 14, 3, 8), (12, 12, 3, 6)])
+def test_rect_decomposition_equals_plain_stepping(nx, ny, h, levels):
+    """Tiles of widths floor(L/t) and floor(L/t)+1 with t = floor(L/2h) on
+    each axis (odd, uneven and single-tile axes included), alternating with
+    the tiling whose edges are the tiles' midpoints: every half cycle lands
+    on the plain result, the last one of reduced height included."""
+    g = si.hash_field(nx, ny, seed=7)
+    got = {}
+    sm.swept2d_rect(sm.st_hash, g[0], h, levels, T0=3, after_half=lambda T, grid: got.__setitem__(T, grid))
+    want = [3 + min(levels, k * h) for k in range(1, -(-levels // h) + 1)]
+    assert sorted(got) == want
+    for T, grid in got.items():
+        ref = oracle.advance_f64(si.TEST_HASH, g, [], T - 3, t0=3)[0]
+        assert np.array_equal(grid, ref)
+
+
+def test_rect_decomposition_heat():
+    g = si.heat_field(15, 13, seed=4)
+    out = sm.swept2d_rect(sm.st_heat(si.HEAT_R), g[0], 3, 11)
+    assert np.array_equal(out, oracle.advance_f64(si.HEAT5, g, [si.HEAT_R], 11)[0])
+
+
+def test_rect_tiles_narrower_than_2H_break_the_order():
+    """The bound w >= 2H is needed: on a tile of width 2H - 1 a point lies
+    within l of both its edges at the top level, and the level function
+    makes a bridge read a value of the other bridge of the same phase."""
+    g = si.hash_field(10, 10, seed=1)
+    ax = sm.Axis(10, (0, 5))  # widths 5 = 2H - 1 for H = 3
+    with pytest.raises(sm.ModelError):
+        sm.half_cycle_on(sm.st_hash, g[0], ax, ax, 0, 3)
+    sm.half_cycle_on(sm.st_hash, g[0], ax, ax, 0, 2)  # 5 >= 2 * 2: fine
+
+
+@pytest.mark.parametrize("wx,wy,H", [(7, 9, 3), (6, 11, 2), (8, 8, 4), (10, 5, 2)])
+def test_rect_component_sizes(wx, wy, H):
+    """Per tile of wx x wy and half cycle of H levels: the upward frustum
+    computes sum (wx-2l)(wy-2l), the bridge across its east edge sum
+    2l(wy-2l), the one across its south edge sum 2l(wx-2l), the downward
+    pyramid at its south-east corner sum (2l)^2, l = 1..H; together wx wy H."""
+    ax = sm.Axis(2 * wx, (0, wx))
+    ay = sm.Axis(2 * wy, (0, wy))
+    st = sm.Stats()
+    sm.half_cycle_on(sm.st_hash, si.hash_field(2 * wx, 2 * wy)[0], ax, ay, 0, H, st)
+    L = range(1, H + 1)
+    assert st.computed.get(sm.UP, 0) == 4 * sum((wx - 2 * l) * (wy - 2 * l) for l in L)
+    assert st.computed[sm.XB] == 4 * sum(2 * l * (wy - 2 * l) for l in L)
+    assert st.computed[sm.YB] == 4 * sum(2 * l * (wx - 2 * l) for l in L)
+    assert st.computed[sm.DOWN] == 4 * sum(4 * l * l for l in L)
+    assert sum(st.computed.values()) == 4 * wx * wy * H
+
+
+def test_rect_axis_and_midpoint_tiling():
+    """For every axis length and h: floor(L/2h) tiles of two widths w, w+1
+    (w >= 2h) in both tilings; each tile of one tiling holds exactly one
+    edge of the other, at least h cells from either of its own edges (so a
+    downward pyramid's 2h x 2h square lies inside one tile of the next
+    tiling)."""
+    for h in range(1, 9):
+        for L in range(2 * h, 8 * h + 3):
+            ax = sm.rect_axis(L, h)
+            mx = sm.mid_axis(ax)
+            for one, other in ((ax, mx), (mx, ax)):
+                ws = one.widths()
+                assert len(ws) == L // (2 * h) and sum(ws) == L
+                assert min(ws) >= 2 * h and max(ws) - min(ws) <= 1
+                for a, w in enumerate(ws):
+                    inside = [(e - one.edges[a]) % L for e in other.edges if (e - one.edges[a]) % L < w]
+                    assert len(inside) == 1
+                    assert h <= inside[0] <= w - h
