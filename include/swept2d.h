@@ -151,11 +151,32 @@ int swept2d_set_precision(swept2d *h, int prec);
  * n; a half cycle advances n/2 levels). n must be even, at least 2, divide nx
  * and ny, and fit the tile's working set in one workgroup's LDS. n = 0 lets
  * the built-in tuner choose (cost model of Sec. 5, Eq. (4)-(5), constrained
- * by LDS size and compute-unit count). EINVAL if n is not usable. */
+ * by LDS size and compute-unit count), falling back to rectangular tiles
+ * (swept2d_set_rect) when no square side is usable. EINVAL if n is not
+ * usable. Selecting a square side leaves rectangular tiles. */
 int swept2d_set_tile(swept2d *h, int n);
 
-/* Current tile side. */
+/* Current tile side (0 while rectangular tiles are selected). */
 int swept2d_get_tile(const swept2d *h);
+
+/* Rectangular tiles (the level function of Sec. 3 generalised: it
+ * partitions a half cycle of H levels over any tiling into rectangles whose
+ * sides are all at least 2H, so grids of any side, odd or prime, run the
+ * swept rule). hh >= 1 is the half-cycle height: each axis of length L is cut
+ * into floor(L / 2hh) tiles of widths floor(L / t) and floor(L / t) + 1
+ * (tiles wider than 2hh are frustums, whose flat tops and bridge middles
+ * pass through the state between half cycles), alternating between half
+ * cycles with the tiling whose edges are those tiles' midpoints. Results
+ * are those of plain stepping, bit for bit, as for square tiles. hh = 0
+ * returns to square tiles (the tuner's side). EINVAL if nx or ny is below
+ * 2 hh or a tile's window (2 (widest + 2)^2 values per value slot) exceeds
+ * the workgroup LDS; EUNSUPPORTED for FP32R and registered user schemes.
+ * swept2d_create and swept2d_set_tile(h, 0) select rectangular tiles of the
+ * cost model's height when no even square side divides nx and ny. */
+int swept2d_set_rect(swept2d *h, int hh);
+
+/* Half-cycle height of the rectangular tiles in use, 0 for square tiles. */
+int swept2d_get_rect(const swept2d *h);
 
 /* Stream selector for swept2d_bind: the HIP null stream (hipStream_t 0,
  * which is torch's default stream on ROCm). NULL itself selects the

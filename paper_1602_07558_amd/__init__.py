@@ -60,7 +60,8 @@ KIND_NAMES = {0: "plain", 1: "up", 2: "bridge", 3: "oct"}
 
 EXPORTS = [
     "swept2d_create", "swept2d_destroy", "swept2d_set_params", "swept2d_set_precision",
-    "swept2d_set_tile", "swept2d_get_tile", "swept2d_bind", "swept2d_state_bytes",
+    "swept2d_set_tile", "swept2d_get_tile", "swept2d_set_rect", "swept2d_get_rect", "swept2d_bind",
+    "swept2d_state_bytes",
     "swept2d_upload", "swept2d_download", "swept2d_upload_raw", "swept2d_download_raw",
     "swept2d_advance", "swept2d_plain_advance", "swept2d_synchronize",
     "swept2d_substep_counter", "swept2d_set_substep_counter", "swept2d_set_launch_mode",
@@ -107,6 +108,8 @@ def load_library():
         "swept2d_set_precision": (i, [vp, i]),
         "swept2d_set_tile": (i, [vp, i]),
         "swept2d_get_tile": (i, [vp]),
+        "swept2d_set_rect": (i, [vp, i]),
+        "swept2d_get_rect": (i, [vp]),
         "swept2d_bind": (i, [vp, vp, vp]),
         "swept2d_state_bytes": (ctypes.c_size_t, [vp]),
         "swept2d_upload": (i, [vp, vp]),
@@ -188,6 +191,14 @@ def swept2d_set_tile(h: int, n: int) -> int:
 
 def swept2d_get_tile(h: int) -> int:
     return _check(load_library().swept2d_get_tile(h))
+
+
+def swept2d_set_rect(h: int, hh: int) -> int:
+    return _check(load_library().swept2d_set_rect(h, hh))
+
+
+def swept2d_get_rect(h: int) -> int:
+    return _check(load_library().swept2d_get_rect(h))
 
 
 # swept2d_bind's selector of the HIP null stream (stream handle 0, torch's
@@ -425,6 +436,15 @@ class Swept2D:
     @tile.setter
     def tile(self, n: int):
         swept2d_set_tile(self.h, n)
+
+    @property
+    def rect(self) -> int:
+        """Half-cycle height of the rectangular tiles in use (0: square tiles)."""
+        return swept2d_get_rect(self.h)
+
+    @rect.setter
+    def rect(self, hh: int):
+        swept2d_set_rect(self.h, hh)
 
     def upload(self, state: np.ndarray):
         assert state.shape == (self.nvars, self.ny, self.nx)

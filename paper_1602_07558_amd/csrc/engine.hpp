@@ -124,6 +124,84 @@ enum Scheme : int {
   kNumSchemes
 };
 
+// Rectangular tiles of any side (the level function above partitions a half
+// cycle of H levels over any tiling whose tile sides are all at least 2H).
+// An axis of length L >= 2h is cut into t = floor(L / 2h) tiles: tiling 0
+// has tile i at start i*base + min(i, rem), width base + (i < rem ? 1 : 0)
+// (base = floor(L / t), rem = L mod t), so widths differ by at most one and
+// are at least 2h. Tiling 1 has its edges at tiling 0's midpoints, tile i
+// starting at start0(i) + floor(width0(i) / 2); its widths are again base or
+// base + 1. The two alternate between half cycles: every tile of one holds
+// exactly one edge (corner) of the other at least h cells from its own
+// edges, so a downward pyramid's 2h x 2h square at a corner of one tiling
+// lies inside a tile of the next, and the stage that finishes the downward
+// pyramid continues as that tile's upward frustum. A tile wider than 2H
+// leaves regions that no downward pyramid covers at level H (the frustum's
+// flat top, the bridges' middles); their stages write them to the state,
+// and the next half cycle's frustum reads them back from there.
+struct RAxis {
+  int L;     // cells
+  int t;     // tiles
+  int base;  // floor(L / t)
+  int rem;   // L mod t: the first rem tiles of tiling 0 are one wider
+};
+
+__host__ __device__ inline int rect_width0(const RAxis& a, int i) { return a.base + (i < a.rem ? 1 : 0); }
+__host__ __device__ inline int rect_start0(const RAxis& a, int i) { return i * a.base + (i < a.rem ? i : a.rem); }
+// Start (0 <= s < L) and width of tile i of tiling par.
+__host__ __device__ inline void rect_span(const RAxis& a, int par, int i, int& s, int& w) {
+  const int s0 = rect_start0(a, i), w0 = rect_width0(a, i);
+  if (par == 0) {
+    s = s0;
+    w = w0;
+    return;
+  }
+  const int j = (i + 1 == a.t) ? 0 : i + 1;
+  const int s1 = rect_start0(a, j) + rect_width0(a, j) / 2 + (j == 0 ? a.L : 0);
+  s = s0 + w0 / 2;
+  w = s1 - s;
+}
+
+struct RGeo {
+  RAxis ax, ay;
+  int h;        // half-cycle height the tiles are cut for (every side >= 2h)
+  int P;        // LDS window pitch and rows: widest tile + 2
+  int urow;     // values per row of an upward-frustum panel level: widest tile
+  long long T0;            // level at the start of the half cycle, relative to *tbase
+  const long long* tbase;  // device-resident level base (graph replay), or null
+};
+
+inline RAxis rect_axis(int L, int h) {
+  RAxis a{};
+  a.L = L;
+  a.t = L / (2 * h);
+  a.base = a.t > 0 ? L / a.t : 0;
+  a.rem = a.t > 0 ? L % a.t : 0;
+  return a;
+}
+inline int rect_widest(const RAxis& a) { return a.base + (a.rem ? 1 : 0); }
+// Geometry for an nx x ny grid at half-cycle height h (tiles: 0 if an axis
+// is shorter than 2h).
+inline RGeo rect_geo(int nx, int ny, int h) {
+  RGeo g{};
+  g.h = h;
+  g.ax = rect_axis(nx, h);
+  g.ay = rect_axis(ny, h);
+  g.urow = rect_widest(g.ax) > rect_widest(g.ay) ? rect_widest(g.ax) : rect_widest(g.ay);
+  g.P = g.urow + 2;
+  return g;
+}
+inline int rect_tiles(const RGeo& g) { return g.ax.t * g.ay.t; }
+// Panel values (the same three buffers as the square tiles'): per tile and
+// level, an upward-frustum end holds 2 rows of urow values per value slot,
+// an x-bridge end 2 rows of 2h + 4 (its band and the frustum corners beside
+// it), a y-bridge end 2 rows of 2h; levels 0..h-1.
+inline size_t rect_up_values(const RGeo& g, int nv) { return (size_t)rect_tiles(g) * 4 * g.h * 2 * nv * g.urow; }
+inline size_t rect_xb_values(const RGeo& g, int nv) {
+  return (size_t)rect_tiles(g) * 2 * g.h * 2 * nv * (2 * g.h + 4);
+}
+inline size_t rect_yb_values(const RGeo& g, int nv) { return (size_t)rect_tiles(g) * 2 * g.h * 2 * nv * (2 * g.h); }
+
 // User schemes (swept2d_register_scheme) take scheme ids kNumSchemes + k;
 // their launchers are the registered table's.
 constexpr int kMaxUserSchemes = 32;
@@ -157,6 +235,19 @@ hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, voi
                       const SchemeParams& sp, hipStream_t s);
 hipError_t launch_plain(int scheme, int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
                         const SchemeParams& sp, hipStream_t s);
+// Rectangular tiles (RGeo): one workgroup per tile of tiling upar runs the
+// downward pyramid of height Hd at the corner of tiling 1 - upar inside it
+// (none if Hd == 0), loads the rest of the tile from the state, and
+// continues as the tile's upward frustum of height Hu (Hu == 0: it writes
+// the downward pyramid's square to the state instead); the frustum writes
+// its panels and its level-Hu top. rect_bridge runs the x- and y-bridges of
+// every edge of tiling par (2 t_x t_y workgroups), each writing its panels
+// and its level-H band. Built-in schemes with nw == nv only (hipErrorNotSupported
+// otherwise).
+hipError_t launch_rect_oct(int scheme, const RGeo& g, int upar, int Hd, int Hu, void* state, PanelPtrs p,
+                           const SchemeParams& sp, hipStream_t s);
+hipError_t launch_rect_bridge(int scheme, const RGeo& g, int par, int H, void* state, PanelPtrs p,
+                              const SchemeParams& sp, hipStream_t s);
 // Device-side helpers that are safe inside a captured graph: copy `bytes`
 // (a multiple of 8) and set the level base.
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
@@ -183,6 +274,10 @@ inline size_t oct_stage_bytes(const SchemeInfo& si, int n) {
 }
 inline size_t bridge_stage_bytes(const SchemeInfo& si, int n) {
   return (size_t)2 * 2 * si.nv * (size_t)up_levels_len(n, n / 2) * si.vbytes;
+}
+// LDS of a rectangular-tile stage: a double-buffered P x P window per value.
+inline size_t rect_lds_bytes(const SchemeInfo& si, const RGeo& g) {
+  return (size_t)2 * (size_t)g.P * (size_t)g.P * (size_t)si.nw * (size_t)si.vbytes;
 }
 // Largest panel run per level is n + 2 values; the per-level fetch path holds
 // two per lane.
@@ -318,6 +413,10 @@ struct Stages {
                           const SchemeParams& sp, hipStream_t s);
   static hipError_t lds(size_t bytes);
   static bool fetch_ahead(int n);
+  static hipError_t rect_oct(const RGeo& g, int upar, int Hd, int Hu, void* state, PanelPtrs p,
+                             const SchemeParams& sp, hipStream_t s);
+  static hipError_t rect_bridge(const RGeo& g, int par, int H, void* state, PanelPtrs p, const SchemeParams& sp,
+                                hipStream_t s);
 };
 
 // Kernel of one batch launch class (window pitch WC, NT threads).

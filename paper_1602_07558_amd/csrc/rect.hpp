@@ -1,0 +1,336 @@
+// Swept stages on rectangular tiles of any side of at least 2h (the tiling
+// is described with RGeo in engine.hpp). Included by stages.hpp inside its
+// anonymous namespace; the launchers at the end of stages.hpp instantiate
+// these kernels once per scheme.
+//
+// These stages serve grids that no even square tile side divides (an odd
+// side, a prime) and tiles wider than the square ones: the window pitch and
+// the tile sizes are run-time values, a level is computed one rectangle
+// point per thread with its 3x3 neighbourhood read from LDS, and a
+// workgroup is 256 threads. The component structure is the square tiles':
+// a workgroup keeps its component's window in LDS, double buffered by level
+// parity; panel levels are stored as soon as their level is complete (the
+// band of level l stays untouched in buffer l mod 2 while later levels of
+// that parity are computed strictly inside it).
+//
+// Panel conventions (per tile, end and level l = 0..H-1; row k = 0 nearer
+// the edge the panel faces, value t along that edge; row stride R per value
+// slot and row):
+//  up   ends N, S, W, E (0..3): the two outermost rows or columns of the
+//       frustum's level-l rectangle [l, w-1-l] in tile coordinates,
+//       t = 0 at tile position l; R = urow.
+//  xb   ends N, S (0, 1) of the x-bridge over the east edge E of tile
+//       (a, b): rows l, l+1 (N) or w_y-1-l, w_y-2-l (S) of the tile, for
+//       x in [E-l-2, E+l+2) (the band and the frustum corners); R = 2h + 4.
+//  yb   ends W, E (0, 1) of the y-bridge over the south edge F of tile
+//       (a, b): columns l, l+1 (W) or w_x-1-l, w_x-2-l (E) of the tile, for
+//       y in [F-l, F+l); R = 2h.
+// The downward pyramid at the south-east corner of tile (a, b) reads the S
+// end of xb(a, b), the N end of xb(a, b+1), the E end of yb(a, b) and the W
+// end of yb(a+1, b): the ring two wide around its level-l square, corners
+// included.
+
+constexpr int kRectThreads = 256;
+
+// Cell x + c, with x + c in [-L, 2L), brought into [0, L).
+__device__ __forceinline__ int rect_wrap(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
+
+// One level: every point of the window rectangle [x0, x0+w) x [y0, y0+hg)
+// gets sub-step T from `in` into `out`, one point per thread.
+template <class S>
+__device__ __forceinline__ void rect_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                           int P, int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  if (w <= 0 || hg <= 0) return;
+  const int plane = P * P, npts = w * hg;
+  const float inv = __builtin_amdgcn_rcpf((float)w);
+  for (int k = (int)threadIdx.x; k < npts; k += kRectThreads) {
+    int dy, dx;
+    fdivmod(k, w, inv, dy, dx);
+    const int o = (y0 + dy) * P + x0 + dx;
+    V nb[3][3][NV];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) nb[r][c][v] = in[v * plane + o + (r - 1) * P + (c - 1)];
+    V res[NV];
+    S::step(T, RegNb<V, NV>{&nb[0]}, res, sp);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * plane + o] = res[v];
+  }
+}
+
+// A panel level <-> two window rows of `len` values per value slot: value t
+// of row k of slot v sits at window column c0 + t dc + k kc, row
+// r0 + t dr + k kr, and at pan[(2 v + k) R + t]. TO_PANEL: window -> panel.
+struct RectRun {
+  int c0, r0, dc, dr, kc, kr, len;
+};
+
+template <class S, bool TO_PANEL>
+__device__ __forceinline__ void rect_copy(typename S::V* __restrict__ win, int P, const RectRun& q,
+                                          typename S::V* __restrict__ pan, int R) {
+  constexpr int NV = S::NV;
+  if (q.len <= 0) return;
+  const int plane = P * P, total = 2 * NV * q.len;
+  const float inv = __builtin_amdgcn_rcpf((float)q.len);
+  for (int e = (int)threadIdx.x; e < total; e += kRectThreads) {
+    int vk, t;
+    fdivmod(e, q.len, inv, vk, t);
+    const int k = vk & 1, v = vk >> 1;
+    const int wi = v * plane + (q.r0 + t * q.dr + k * q.kr) * P + q.c0 + t * q.dc + k * q.kc;
+    if (TO_PANEL)
+      pan[vk * R + t] = win[wi];
+    else
+      win[wi] = pan[vk * R + t];
+  }
+}
+
+// Window cells [cx0, cx0+w) x [cy0, cy0+hg) <-> state cells
+// (gx0 + cx, gy0 + cy) modulo the grid (gx0 + cx and gy0 + cy in
+// [-L, 2L)), skipping the window square [qx0, qx0+qs) x [qy0, qy0+qs).
+// LOAD: state -> window.
+template <class S, bool LOAD>
+__device__ __forceinline__ void rect_move(typename S::V* __restrict__ win, int P, typename S::V* __restrict__ state,
+                                          int nx, int ny, int cx0, int cy0, int w, int hg, int gx0, int gy0, int qx0,
+                                          int qy0, int qs) {
+  constexpr int NV = S::NV;
+  if (w <= 0 || hg <= 0) return;
+  const int plane = P * P, npts = w * hg;
+  const size_t splane = (size_t)nx * ny;
+  const float inv = __builtin_amdgcn_rcpf((float)w);
+  for (int k = (int)threadIdx.x; k < npts; k += kRectThreads) {
+    int dy, dx;
+    fdivmod(k, w, inv, dy, dx);
+    const int cx = cx0 + dx, cy = cy0 + dy;
+    if (cx >= qx0 && cx < qx0 + qs && cy >= qy0 && cy < qy0 + qs) continue;
+    const size_t gi = (size_t)rect_wrap(gy0 + cy, ny) * nx + rect_wrap(gx0 + cx, nx);
+    const int wi = cy * P + cx;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (LOAD)
+        win[v * plane + wi] = state[v * splane + gi];
+      else
+        state[v * splane + gi] = win[v * plane + wi];
+    }
+  }
+}
+
+__device__ __forceinline__ size_t rect_up_at(const RGeo& g, int nv, int tile, int end, int l) {
+  return ((size_t)(tile * 4 + end) * g.h + l) * (size_t)(2 * nv * g.urow);
+}
+__device__ __forceinline__ size_t rect_xb_at(const RGeo& g, int nv, int tile, int end, int l) {
+  return ((size_t)(tile * 2 + end) * g.h + l) * (size_t)(2 * nv * (2 * g.h + 4));
+}
+__device__ __forceinline__ size_t rect_yb_at(const RGeo& g, int nv, int tile, int end, int l) {
+  return ((size_t)(tile * 2 + end) * g.h + l) * (size_t)(2 * nv * (2 * g.h));
+}
+
+// Tile `item` of tiling upar: the downward pyramid (height Hd) at the corner
+// of tiling 1 - upar inside it, the rest of the tile from the state, then
+// the upward frustum of the tile (height Hu). Window cell (cx, cy) is tile
+// cell (cx - 1, cy - 1).
+template <class S>
+__device__ void rect_oct_item(const RGeo& g, int upar, int Hd, int Hu, typename S::V* __restrict__ state,
+                              const PanelPtrs& pp, const SchemeParams& sp, int item, typename S::V* smem) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  const int tx = g.ax.t, ty = g.ay.t, P = g.P;
+  const int j = item / tx, i = item - j * tx;
+  int sx, wx, sy, wy;
+  rect_span(g.ax, upar, i, sx, wx);
+  rect_span(g.ay, upar, j, sy, wy);
+  V* buf[2] = {smem, smem + NV * P * P};
+  const long long base = g.T0 + (g.tbase ? *g.tbase : 0LL);
+  const int nx = g.ax.L, ny = g.ay.L;
+  // The corner of the other tiling inside this tile, and the downward
+  // pyramid (tile (di, dj) of that tiling) it belongs to.
+  int ox, oy, di, dj;
+  if (upar == 1) {  // corners of tiling 0: the south-east corner of tile (i, j)
+    ox = rect_width0(g.ax, i) - rect_width0(g.ax, i) / 2;
+    oy = rect_width0(g.ay, j) - rect_width0(g.ay, j) / 2;
+    di = i;
+    dj = j;
+  } else {  // corners of tiling 1: the south-east corner of tile (i-1, j-1)
+    ox = rect_width0(g.ax, i) / 2;
+    oy = rect_width0(g.ay, j) / 2;
+    di = i == 0 ? tx - 1 : i - 1;
+    dj = j == 0 ? ty - 1 : j - 1;
+  }
+  const int cE = 1 + ox, cF = 1 + oy;
+  const V* xb = static_cast<const V*>(pp.xb);
+  const V* yb = static_cast<const V*>(pp.yb);
+  const int tN = di + dj * tx, tS = di + (dj + 1 == ty ? 0 : dj + 1) * tx;
+  const int tE = (di + 1 == tx ? 0 : di + 1) + dj * tx;
+  const int Rx = 2 * g.h + 4, Ry = 2 * g.h;
+  // Ring of the downward pyramid's level l (for its level l + 1).
+  auto place_ring = [&](V* w, int l) {
+    rect_copy<S, false>(w, P, RectRun{cE - l - 2, cF - 1 - l, 1, 0, 0, -1, 2 * l + 4},
+                        const_cast<V*>(xb + rect_xb_at(g, NV, tN, 1, l)), Rx);
+    rect_copy<S, false>(w, P, RectRun{cE - l - 2, cF + l, 1, 0, 0, 1, 2 * l + 4},
+                        const_cast<V*>(xb + rect_xb_at(g, NV, tS, 0, l)), Rx);
+    rect_copy<S, false>(w, P, RectRun{cE - 1 - l, cF - l, 0, 1, -1, 0, 2 * l},
+                        const_cast<V*>(yb + rect_yb_at(g, NV, tN, 1, l)), Ry);
+    rect_copy<S, false>(w, P, RectRun{cE + l, cF - l, 0, 1, 1, 0, 2 * l},
+                        const_cast<V*>(yb + rect_yb_at(g, NV, tE, 0, l)), Ry);
+  };
+  // The tile's cells outside the level-Hd square (all of them if Hd == 0),
+  // at level Hd, from the state; they go to the buffer level Hd ends in,
+  // where no ring or square of an earlier level reaches.
+  if (Hu > 0)
+    rect_move<S, true>(buf[Hd & 1], P, state, nx, ny, 1, 1, wx, wy, sx - 1, sy - 1, cE - Hd, cF - Hd, 2 * Hd);
+  if (Hd > 0) place_ring(buf[0], 0);
+  __syncthreads();
+  for (int l = 1; l <= Hd; ++l) {
+    rect_level<S>(buf[(l - 1) & 1], buf[l & 1], P, cE - l, cF - l, 2 * l, 2 * l, base + l - 1, sp);
+    if (l < Hd) place_ring(buf[l & 1], l);
+    __syncthreads();
+  }
+  if (Hu == 0) {
+    rect_move<S, false>(buf[Hd & 1], P, state, nx, ny, cE - Hd, cF - Hd, 2 * Hd, 2 * Hd, sx - 1, sy - 1, 0, 0, 0);
+    return;
+  }
+  V* up = static_cast<V*>(pp.up);
+  const int tile = item, R = g.urow;
+  for (int m = 1; m <= Hu; ++m) {
+    V* in = buf[(Hd + m - 1) & 1];
+    rect_level<S>(in, buf[(Hd + m) & 1], P, 1 + m, 1 + m, wx - 2 * m, wy - 2 * m, base + Hd + m - 1, sp);
+    // panels of level m - 1: rectangle [m-1, w-m] in tile cells
+    const int l = m - 1, lx = wx - 2 * l, ly = wy - 2 * l;
+    rect_copy<S, true>(in, P, RectRun{m, m, 1, 0, 0, 1, lx}, up + rect_up_at(g, NV, tile, 0, l), R);
+    rect_copy<S, true>(in, P, RectRun{m, wy - l, 1, 0, 0, -1, lx}, up + rect_up_at(g, NV, tile, 1, l), R);
+    rect_copy<S, true>(in, P, RectRun{m, m, 0, 1, 1, 0, ly}, up + rect_up_at(g, NV, tile, 2, l), R);
+    rect_copy<S, true>(in, P, RectRun{wx - l, m, 0, 1, -1, 0, ly}, up + rect_up_at(g, NV, tile, 3, l), R);
+    __syncthreads();
+  }
+  rect_move<S, false>(buf[(Hd + Hu) & 1], P, state, nx, ny, 1 + Hu, 1 + Hu, wx - 2 * Hu, wy - 2 * Hu, sx - 1, sy - 1,
+                      0, 0, 0);
+}
+
+// Bridge `item` of tiling par: items 0 .. t_x t_y - 1 are the x-bridges over
+// the east edge of tile (a, b), the rest the y-bridges over the south edge.
+// The window's columns run across the edge, 2H + 2 of them (cell
+// E - H - 1 + c), its rows along it over the tile's extent; the y-bridge's
+// window is the transpose (row c across the edge).
+template <class S>
+__device__ void rect_bridge_item(const RGeo& g, int par, int H, typename S::V* __restrict__ state,
+                                 const PanelPtrs& pp, const SchemeParams& sp, int item, typename S::V* smem) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  const int tx = g.ax.t, ty = g.ay.t, P = g.P;
+  const bool isx = item < tx * ty;
+  const int e = isx ? item : item - tx * ty;
+  const int b = e / tx, a = e - b * tx;
+  int sx, wx, sy, wy;
+  rect_span(g.ax, par, a, sx, wx);
+  rect_span(g.ay, par, b, sy, wy);
+  V* buf[2] = {smem, smem + NV * P * P};
+  const long long base = g.T0 + (g.tbase ? *g.tbase : 0LL);
+  const int nx = g.ax.L, ny = g.ay.L;
+  const int wal = isx ? wy : wx;  // extent along the edge
+  // Window position of (across, along) as (column, row).
+  auto run = [&](int ac, int al, int dac, int dal, int kac, int kal, int len) {
+    return isx ? RectRun{ac, al, dac, dal, kac, kal, len} : RectRun{al, ac, dal, dac, kal, kac, len};
+  };
+  const V* up = static_cast<const V*>(pp.up);
+  const int tnear = e;
+  const int tfar = isx ? (a + 1 == tx ? 0 : a + 1) + b * tx : a + (b + 1 == ty ? 0 : b + 1) * tx;
+  const int enear = isx ? 3 : 1, efar = isx ? 2 : 0;  // E / S end of the near tile, W / N of the far
+  const int R = g.urow;
+  // Frustum strips of level m: the near tile's at across H - m (k = 0) and
+  // H - m - 1, the far tile's at H + 1 + m and H + 2 + m; along m + t.
+  auto place_strips = [&](V* w, int m) {
+    rect_copy<S, false>(w, P, run(H - m, m, 0, 1, -1, 0, wal - 2 * m), const_cast<V*>(up + rect_up_at(g, NV, tnear, enear, m)),
+                        R);
+    rect_copy<S, false>(w, P, run(H + 1 + m, m, 0, 1, 1, 0, wal - 2 * m),
+                        const_cast<V*>(up + rect_up_at(g, NV, tfar, efar, m)), R);
+  };
+  V* out = static_cast<V*>(isx ? pp.xb : pp.yb);
+  const int Ro = isx ? 2 * g.h + 4 : 2 * g.h;
+  auto at = [&](int end, int l) {
+    return isx ? rect_xb_at(g, NV, e, end, l) : rect_yb_at(g, NV, e, end, l);
+  };
+  place_strips(buf[0], 0);
+  __syncthreads();
+  for (int l = 1; l <= H; ++l) {
+    const V* in = buf[(l - 1) & 1];
+    if (isx)
+      rect_level<S>(in, buf[l & 1], P, H + 1 - l, l, 2 * l, wal - 2 * l, base + l - 1, sp);
+    else
+      rect_level<S>(in, buf[l & 1], P, l, H + 1 - l, wal - 2 * l, 2 * l, base + l - 1, sp);
+    if (l < H) place_strips(buf[l & 1], l);
+    // ends of level m = l - 1: rows (x-bridge) or columns (y-bridge) m, m+1
+    // and wal-1-m, wal-2-m of the tile; across, the x-bridge's run covers
+    // its band and the frustum corners, the y-bridge's its band only
+    const int m = l - 1;
+    const int ac0 = isx ? H - m - 1 : H + 1 - m, len = isx ? 2 * m + 4 : 2 * m;
+    rect_copy<S, true>(const_cast<V*>(in), P, run(ac0, m, 1, 0, 0, 1, len), out + at(0, m), Ro);
+    rect_copy<S, true>(const_cast<V*>(in), P, run(ac0, wal - 1 - m, 1, 0, 0, -1, len), out + at(1, m), Ro);
+    __syncthreads();
+  }
+  // the band at level H: across [1, 2H + 1), along [H, wal - H)
+  if (isx) {
+    const int E = sx + wx >= nx ? sx + wx - nx : sx + wx;
+    rect_move<S, false>(buf[H & 1], P, state, nx, ny, 1, H, 2 * H, wal - 2 * H, E - H - 1, sy, 0, 0, 0);
+  } else {
+    const int F = sy + wy >= ny ? sy + wy - ny : sy + wy;
+    rect_move<S, false>(buf[H & 1], P, state, nx, ny, H, 1, wal - 2 * H, 2 * H, sx, F - H - 1, 0, 0, 0);
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(kRectThreads) void k_rect_oct(RGeo g, int upar, int Hd, int Hu,
+                                                           typename S::V* __restrict__ state, PanelPtrs pp,
+                                                           SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  rect_oct_item<S>(g, upar, Hd, Hu, state, pp, sp, (int)blockIdx.x, reinterpret_cast<typename S::V*>(smem_d));
+}
+
+template <class S>
+__global__ __launch_bounds__(kRectThreads) void k_rect_bridge(RGeo g, int par, int H, typename S::V* __restrict__ state,
+                                                              PanelPtrs pp, SchemeParams sp) {
+  extern __shared__ double smem_d[];
+  rect_bridge_item<S>(g, par, H, state, pp, sp, (int)blockIdx.x, reinterpret_cast<typename S::V*>(smem_d));
+}
+
+template <class S>
+hipError_t rect_oct_t(const RGeo& g, int upar, int Hd, int Hu, void* state, PanelPtrs p, const SchemeParams& sp,
+                      hipStream_t s) {
+  if constexpr (S::NW != S::NV) {
+    return hipErrorNotSupported;
+  } else {
+    const size_t lds = rect_lds_bytes(info_of<S>(), g);
+    hipLaunchKernelGGL(k_rect_oct<S>, dim3(rect_tiles(g)), dim3(kRectThreads), lds, s, g, upar, Hd, Hu,
+                       static_cast<typename S::V*>(state), p, sp);
+    return hipGetLastError();
+  }
+}
+
+template <class S>
+hipError_t rect_bridge_t(const RGeo& g, int par, int H, void* state, PanelPtrs p, const SchemeParams& sp,
+                         hipStream_t s) {
+  if constexpr (S::NW != S::NV) {
+    return hipErrorNotSupported;
+  } else {
+    const size_t lds = rect_lds_bytes(info_of<S>(), g);
+    hipLaunchKernelGGL(k_rect_bridge<S>, dim3(2 * rect_tiles(g)), dim3(kRectThreads), lds, s, g, par, H,
+                       static_cast<typename S::V*>(state), p, sp);
+    return hipGetLastError();
+  }
+}
+
+template <class S>
+hipError_t rect_lds_t(int bytes) {
+  if constexpr (S::NW != S::NV) {
+    return hipSuccess;
+  } else {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_rect_oct<S>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_rect_bridge<S>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  }
+}

@@ -2293,6 +2293,8 @@ hipError_t lds_staged(int b) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, b);
 }
 
+#include "rect.hpp"
+
 template <class S, int WC, int NT>
 hipError_t lds_one(int b) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_up<S, WC, NT>),
@@ -2314,6 +2316,8 @@ hipError_t lds_t(size_t bytes) {
   e = lds_one<S, 34, Lay<S, 34>::NT>(b);
   if (e != hipSuccess) return e;
   e = lds_one<S, 18, Lay<S, 18>::NT>(b);
+  if (e != hipSuccess) return e;
+  e = rect_lds_t<S>(b);
   if (e != hipSuccess) return e;
   return lds_one<S, 66, Lay<S, 66>::NT>(b);
 }
@@ -2620,6 +2624,16 @@ bool Stages<S>::fetch_ahead(int n) {
 template <class S>
 hipError_t Stages<S>::lds(size_t bytes) {
   return lds_t<S>(bytes);
+}
+template <class S>
+hipError_t Stages<S>::rect_oct(const RGeo& g, int upar, int Hd, int Hu, void* state, PanelPtrs p,
+                               const SchemeParams& sp, hipStream_t s) {
+  return rect_oct_t<S>(g, upar, Hd, Hu, state, p, sp, s);
+}
+template <class S>
+hipError_t Stages<S>::rect_bridge(const RGeo& g, int par, int H, void* state, PanelPtrs p, const SchemeParams& sp,
+                                  hipStream_t s) {
+  return rect_bridge_t<S>(g, par, H, state, p, sp, s);
 }
 
 template <int WC, int NT>

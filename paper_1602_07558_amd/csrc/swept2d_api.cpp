@@ -169,6 +169,8 @@ struct swept2d {
   void* xb = nullptr;
   void* yb = nullptr;
   size_t panel_tile = 0;    // tile side the panels are sized for
+  int rect_h = 0;           // half-cycle height of rectangular tiles (0: square tiles of side n)
+  int panel_rect = 0;       // rectangular-tile height the panels are sized for
   long long T = 0;          // global sub-step counter
   long long* d_tbase = nullptr;  // device copy of the level base for graph replay
   int launch_mode = SWEPT2D_LAUNCH_DIRECT;
@@ -226,25 +228,52 @@ void free_panels(swept2d* h) {
   if (h->yb) hipFree(h->yb);
   h->up = h->xb = h->yb = nullptr;
   h->panel_tile = 0;
+  h->panel_rect = 0;
 }
 
 int ensure_panels(swept2d* h) {
-  if (h->panel_tile == (size_t)h->n && h->up) return 0;
+  if (h->up && (h->rect_h ? h->panel_rect == h->rect_h : (h->panel_rect == 0 && h->panel_tile == (size_t)h->n)))
+    return 0;
   free_panels(h);
-  const int ntiles = (h->nx / h->n) * (h->ny / h->n);
   const size_t vb = h->si.vbytes;
-  const size_t ub = std::max<size_t>(8, up_panel_values(ntiles, h->n, h->si.nv) * vb);
-  const size_t xbb = std::max<size_t>(8, xb_panel_values(ntiles, h->n, h->si.nv) * vb);
-  const size_t ybb = std::max<size_t>(8, yb_panel_values(ntiles, h->n, h->si.nv) * vb);
+  size_t ub, xbb, ybb;
+  if (h->rect_h) {
+    const RGeo g = rect_geo(h->nx, h->ny, h->rect_h);
+    ub = rect_up_values(g, h->si.nv) * vb;
+    xbb = rect_xb_values(g, h->si.nv) * vb;
+    ybb = rect_yb_values(g, h->si.nv) * vb;
+  } else {
+    const int ntiles = (h->nx / h->n) * (h->ny / h->n);
+    ub = up_panel_values(ntiles, h->n, h->si.nv) * vb;
+    xbb = xb_panel_values(ntiles, h->n, h->si.nv) * vb;
+    ybb = yb_panel_values(ntiles, h->n, h->si.nv) * vb;
+  }
+  ub = std::max<size_t>(8, ub);
+  xbb = std::max<size_t>(8, xbb);
+  ybb = std::max<size_t>(8, ybb);
   if (hipMalloc(&h->up, ub) != hipSuccess || hipMalloc(&h->xb, xbb) != hipSuccess ||
       hipMalloc(&h->yb, ybb) != hipSuccess) {
     hipGetLastError();
     free_panels(h);
     return fail(SWEPT2D_ENOMEM, "cannot allocate panels (%zu + %zu + %zu bytes)", ub, xbb, ybb);
   }
-  h->panel_tile = (size_t)h->n;
+  if (h->rect_h)
+    h->panel_rect = h->rect_h;
+  else
+    h->panel_tile = (size_t)h->n;
   drop_graphs(h);
   return 0;
+}
+
+// Why rectangular tiles of half-cycle height hh cannot serve the handle, or
+// nullptr.
+const char* rect_problem(const swept2d* h, int hh) {
+  if (hh < 1) return "half-cycle height must be at least 1";
+  if (h->nx < 2 * hh || h->ny < 2 * hh) return "nx and ny must be at least twice the half-cycle height";
+  if (user_scheme(h->scheme - kNumSchemes)) return "registered user schemes run square tiles only";
+  if (h->si.nw != h->si.nv) return "FP32R runs square tiles only";
+  if (rect_lds_bytes(h->si, rect_geo(h->nx, h->ny, hh)) > g_lds_limit) return "tile window exceeds the workgroup LDS";
+  return nullptr;
 }
 
 // Why a tile side is not usable, or nullptr.
@@ -320,6 +349,33 @@ int model_tile(const swept2d* h) {
     if (cost < best_cost * (1.0 - 1e-9)) {
       best_cost = cost;
       best = n;
+    }
+  }
+  return best;
+}
+
+// Half-cycle height of rectangular tiles by the same model: a tile of about
+// (nx / t_x) x (ny / t_y) points, its levels computed one point per thread
+// (weighted 2x against the square tiles' code).
+int model_rect(const swept2d* h) {
+  const double tau = 3.0e-6;
+  const double s_cu = 2.0 * 0.17e-9 * scheme_cost(h->scheme);
+  const double beta = 0.1e-6;
+  int best = 0;
+  double best_cost = 1e300;
+  for (int hh = 1; hh <= std::min(64, std::min(h->nx, h->ny) / 2); ++hh) {
+    if (rect_problem(h, hh)) continue;
+    const RGeo g = rect_geo(h->nx, h->ny, hh);
+    const double tiles = (double)rect_tiles(g);
+    const double per_cu = std::max(1.0, std::floor((double)g_lds_limit / (double)rect_lds_bytes(h->si, g)));
+    const double seq = std::ceil(tiles / h->cu_count);
+    const double resident = std::ceil(tiles / (h->cu_count * std::min(per_cu, 8.0)));
+    const double pts = (double)h->nx * h->ny / tiles;
+    const double half = 2.0 * tau + seq * pts * hh * s_cu + resident * 2 * hh * beta;
+    const double cost = half / hh;
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best = hh;
     }
   }
   return best;
@@ -430,6 +486,56 @@ int enqueue_swept(swept2d* h, long long S, long long T, const long long* tbase, 
   return 0;
 }
 
+// Points computed per half cycle of height H on rectangular tiles, by the
+// frustums, the bridges and the downward pyramids (sums over the tiles of
+// the per-tile volumes).
+double rect_up_points(const RGeo& g, int H) {
+  double s = 0;
+  for (int l = 1; l <= H; ++l) s += (double)(g.ax.L - 2 * l * g.ax.t) * (g.ay.L - 2 * l * g.ay.t);
+  return s;
+}
+double rect_bridge_points(const RGeo& g, int H) {
+  double s = 0;
+  for (int l = 1; l <= H; ++l)
+    s += 2.0 * l * ((double)g.ax.t * (g.ay.L - 2 * l * g.ay.t) + (double)g.ay.t * (g.ax.L - 2 * l * g.ax.t));
+  return s;
+}
+double rect_down_points(const RGeo& g, int H) { return (double)rect_tiles(g) * down_points(H); }
+
+// Enqueue the swept schedule on rectangular tiles for S sub-steps from level
+// T: the first frustums, then per half cycle the bridges and the stage that
+// finishes the downward pyramids and starts the next frustums (the last one
+// writes its squares to the state). Tilings 0 and 1 alternate.
+int enqueue_rect(swept2d* h, long long S, long long T, const long long* tbase, bool timed) {
+  RGeo g = rect_geo(h->nx, h->ny, h->rect_h);
+  g.T0 = T;
+  g.tbase = tbase;
+  const int hh = g.h, sc = h->scheme;
+  PanelPtrs pp{h->up, h->xb, h->yb};
+  Launcher L{h, timed};
+  const long long q = S / hh;
+  const int r = (int)(S % hh);
+  const long long nh = q + (r > 0 ? 1 : 0);
+  auto height = [&](long long c) { return c < q ? hh : r; };
+  int rc = L.run(kKindUp, rect_up_points(g, height(0)), [&] {
+    return launch_rect_oct(sc, g, 0, 0, height(0), h->state, pp, h->sp, h->stream);
+  });
+  if (rc) return rc;
+  int par = 0;
+  for (long long c = 0; c < nh; ++c) {
+    const int Hc = height(c), Hn = c + 1 < nh ? height(c + 1) : 0;
+    rc = L.run(kKindBridge, rect_bridge_points(g, Hc),
+               [&] { return launch_rect_bridge(sc, g, par, Hc, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    rc = L.run(kKindOct, rect_down_points(g, Hc) + rect_up_points(g, Hn),
+               [&] { return launch_rect_oct(sc, g, 1 - par, Hc, Hn, h->state, pp, h->sp, h->stream); });
+    if (rc) return rc;
+    par ^= 1;
+    g.T0 += Hc;
+  }
+  return 0;
+}
+
 // Enqueue S per-step launches starting at level T; the last one writes the
 // state buffer.
 int enqueue_plain(swept2d* h, long long S, long long T, const long long* tbase, bool timed) {
@@ -464,14 +570,23 @@ int run_method(swept2d* h, int method, long long nsteps) {
   const long long S = nsteps * h->substeps;
   int rc;
   if (method == 0) {
-    if (const char* why = tile_problem(h, h->n)) return fail(SWEPT2D_EINVAL, "tile %d: %s", h->n, why);
+    if (h->rect_h) {
+      if (const char* why = rect_problem(h, h->rect_h))
+        return fail(h->si.nw != h->si.nv || user_scheme(h->scheme - kNumSchemes) ? SWEPT2D_EUNSUPPORTED
+                                                                                 : SWEPT2D_EINVAL,
+                    "rectangular tiles %d: %s", h->rect_h, why);
+    } else if (const char* why = tile_problem(h, h->n)) {
+      return fail(SWEPT2D_EINVAL, "tile %d: %s", h->n, why);
+    }
     if ((rc = ensure_panels(h))) return rc;
   } else {
     if ((rc = ensure_scratch(h))) return rc;
   }
   const bool use_graph = (h->launch_mode == SWEPT2D_LAUNCH_GRAPH) && !h->timing;
   if (!use_graph) {
-    rc = method == 0 ? enqueue_swept(h, S, h->T, nullptr, h->timing) : enqueue_plain(h, S, h->T, nullptr, h->timing);
+    rc = method == 0 ? (h->rect_h ? enqueue_rect(h, S, h->T, nullptr, h->timing)
+                                  : enqueue_swept(h, S, h->T, nullptr, h->timing))
+                     : enqueue_plain(h, S, h->T, nullptr, h->timing);
     if (rc) return rc;
     h->T += S;
     return 0;
@@ -496,7 +611,8 @@ int run_method(swept2d* h, int method, long long nsteps) {
     const hipStream_t cap = run_stream ? run_stream : h->own_stream;
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     h->stream = cap;
-    rc = method == 0 ? enqueue_swept(h, S, 0, h->d_tbase, false) : enqueue_plain(h, S, 0, h->d_tbase, false);
+    rc = method == 0 ? (h->rect_h ? enqueue_rect(h, S, 0, h->d_tbase, false) : enqueue_swept(h, S, 0, h->d_tbase, false))
+                     : enqueue_plain(h, S, 0, h->d_tbase, false);
     h->stream = run_stream;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cap, &graph);
@@ -636,6 +752,7 @@ swept2d* swept2d_create(int nx, int ny, int nvars, int pde, int substeps) {
     return nullptr;
   }
   h->n = model_tile(h);
+  if (h->n == 0) h->rect_h = model_rect(h);
   return h;
 }
 
@@ -677,7 +794,8 @@ int swept2d_set_precision(swept2d* h, int prec) {
   free_panels(h);
   int rc = alloc_state(h);
   if (rc) return rc;
-  if (tile_problem(h, h->n)) h->n = model_tile(h);
+  if (!h->rect_h && tile_problem(h, h->n)) h->n = model_tile(h);
+  if (!h->rect_h && h->n == 0) h->rect_h = model_rect(h);
   return 0;
 }
 
@@ -685,19 +803,47 @@ int swept2d_set_tile(swept2d* h, int n) {
   if (!h) return fail(SWEPT2D_EINVAL, "null handle");
   if (n == 0) {
     n = model_tile(h);
-    if (n == 0) return fail(SWEPT2D_EINVAL, "no usable tile side for %d x %d", h->nx, h->ny);
+    if (n == 0) {
+      const int hh = model_rect(h);
+      if (hh == 0) return fail(SWEPT2D_EINVAL, "no usable tile for %d x %d", h->nx, h->ny);
+      return swept2d_set_rect(h, hh);
+    }
   }
   if (const char* why = tile_problem(h, n)) return fail(SWEPT2D_EINVAL, "tile %d: %s", n, why);
-  if (n != h->n) {
+  if (n != h->n || h->rect_h) {
     HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     free_panels(h);
     drop_graphs(h);
   }
   h->n = n;
+  h->rect_h = 0;
   return 0;
 }
 
-int swept2d_get_tile(const swept2d* h) { return h ? h->n : SWEPT2D_EINVAL; }
+int swept2d_get_tile(const swept2d* h) { return h ? (h->rect_h ? 0 : h->n) : SWEPT2D_EINVAL; }
+
+int swept2d_set_rect(swept2d* h, int hh) {
+  if (!h) return fail(SWEPT2D_EINVAL, "null handle");
+  if (hh < 0) return fail(SWEPT2D_EINVAL, "half-cycle height must be >= 0");
+  if (hh == 0) {
+    if (!h->rect_h) return 0;
+    const int n = tile_problem(h, h->n) ? model_tile(h) : h->n;
+    if (n == 0) return fail(SWEPT2D_EINVAL, "no usable square tile side for %d x %d", h->nx, h->ny);
+    return swept2d_set_tile(h, n);
+  }
+  if (const char* why = rect_problem(h, hh))
+    return fail(h->si.nw != h->si.nv || user_scheme(h->scheme - kNumSchemes) ? SWEPT2D_EUNSUPPORTED : SWEPT2D_EINVAL,
+                "rectangular tiles %d: %s", hh, why);
+  if (hh != h->rect_h) {
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    free_panels(h);
+    drop_graphs(h);
+  }
+  h->rect_h = hh;
+  return 0;
+}
+
+int swept2d_get_rect(const swept2d* h) { return h ? h->rect_h : SWEPT2D_EINVAL; }
 
 int swept2d_bind(swept2d* h, void* dev_state, void* hip_stream) {
   if (!h) return fail(SWEPT2D_EINVAL, "null handle");

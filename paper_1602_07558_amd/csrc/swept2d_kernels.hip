@@ -122,6 +122,20 @@ hipError_t launch_oct(int scheme, const Geo& g, int Hd, int Hu, bool staged, voi
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_rect_oct(int scheme, const RGeo& g, int upar, int Hd, int Hu, void* state, PanelPtrs p,
+                           const SchemeParams& sp, hipStream_t s) {
+  if (user_of(scheme)) return hipErrorNotSupported;
+  SWEPT_DISPATCH(rect_oct, g, upar, Hd, Hu, state, p, sp, s)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rect_bridge(int scheme, const RGeo& g, int par, int H, void* state, PanelPtrs p,
+                              const SchemeParams& sp, hipStream_t s) {
+  if (user_of(scheme)) return hipErrorNotSupported;
+  SWEPT_DISPATCH(rect_bridge, g, par, H, state, p, sp, s)
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_plain(int scheme, int nx, int ny, long long T, const long long* tbase, const void* in, void* out,
                         const SchemeParams& sp, hipStream_t s) {
   if (const swept2d_scheme_ops* u = user_of(scheme)) return as_hip(u->plain(nx, ny, T, tbase, in, out, &sp, s));
