@@ -114,8 +114,10 @@ def advance_f32c(pde: int, u: np.ndarray, c: np.ndarray, params, nsub: int, t0: 
 def advance_f32r(pde: int, u: np.ndarray, params, nsub: int, tile: int, t0: int = 0,
                  threads: int | None = None) -> np.ndarray:
     """FP32 state whose compensation lives only within a residency of the
-    swept schedule on tiles of side ``tile`` (0: the per-step method), as one
-    advance of ``nsub`` sub-steps; ``u`` is ``[nvars][ny][nx]`` float32."""
+    swept schedule on tiles of side ``tile`` (0: the per-step method; -1: one
+    residency for the whole advance, the compensation kept everywhere), as
+    one advance of ``nsub`` sub-steps; ``u`` is ``[nvars][ny][nx]`` float32 in
+    the form of ``split_f32r`` (the wave as displacement and velocity)."""
     lib = _load()
     uu = np.ascontiguousarray(u, dtype=np.float32).copy()
     nvars, ny, nx = uu.shape
@@ -138,6 +140,24 @@ def advance_hash25(u: np.ndarray, nsteps: int, k0: int = 0, threads: int | None 
     if rc != 0:
         raise ValueError(f"oracle_advance_hash25 failed with {rc}")
     return uu
+
+
+def split_f32r(pde: int, state64: np.ndarray) -> np.ndarray:
+    """FP32 values of the residency-confined form from an FP64 state: u =
+    fl32(x); the wave keeps (u, v) with v = fl32(u^n - u^(n-1))."""
+    u = state64.astype(np.float32)
+    if pde == 2:  # wave, velocity form
+        u[1] = (state64[0] - state64[1]).astype(np.float32)
+    return u
+
+
+def join_f32r(pde: int, u: np.ndarray) -> np.ndarray:
+    """FP64 state from the residency-confined form (the wave's previous
+    level as u - v)."""
+    x = u.astype(np.float64)
+    if pde == 2:
+        x[1] = x[0] - x[1]
+    return x
 
 
 def residency(x: int, y: int, L: int, tile: int, nx: int, ny: int) -> int:

@@ -526,13 +526,43 @@ using Hash25x2 = PushTwoRing<Hash25>;
 // compensations are window-only values, zero when a point's value arrives
 // from the state or a panel, so a value keeps its compensation while one
 // workgroup computes its successive levels and loses it when it moves on.
-// The updates are those of the FP32C schemes (slots as there, the
-// compensations after the values).
+// The heat update is Heat32C's (slots as there, the compensation after the
+// value); the wave runs in velocity form (below).
 struct Heat32R : Heat32C {
   static constexpr int NV = 1, NW = 2;
 };
-struct Wave32R : Wave32C {
-  static constexpr int NV = 2, NW = 4;
+// The wave in velocity form, v = u^n - u^(n-1): v' = v + C2 lap and
+// u' = u + v', each a compensated sum (the pair tv, c_v' of the new
+// velocity is u's increment, both compensations folded in first); slots u,
+// v and the window-only c_u, c_v; lap as in Wave32C. Equal to leapfrog in
+// exact arithmetic. The stored pair is (u, v): a compensation dropped when a
+// value changes window perturbs u or v by half a unit of its own size,
+// whereas in the (u, u_prev) form the rounding of the displacement would
+// enter the velocity u - u_prev and be integrated.
+struct Wave32R {
+  using V = float;
+  static constexpr int NV = 2, NW = 4, NVAR = 2, SUB = 1;
+  static constexpr bool XY_SYM = true;
+  template <class NB>
+  __device__ __forceinline__ static void step(long long, const NB& nb, V* out, const SchemeParams& sp) {
+    const float c2 = (float)sp.p[0];
+    const float u = nb(0, 0, 0);
+    const float v = nb(0, 0, 1);
+    const float cu = nb(0, 0, 2);
+    const float cv = nb(0, 0, 3);
+    const float lapu = ((nb(-1, 0, 0) - u) + (nb(1, 0, 0) - u)) + ((nb(0, -1, 0) - u) + (nb(0, 1, 0) - u));
+    const float lapc = __builtin_fmaf(-4.0f, cu, (nb(-1, 0, 2) + nb(1, 0, 2)) + (nb(0, -1, 2) + nb(0, 1, 2)));
+    const float lap = lapu - lapc;
+    const float yv = c2 * lap - cv;
+    const float tv = v + yv;
+    const float cv1 = (tv - v) - yv;
+    const float y = tv - (cu + cv1);
+    const float t = u + y;
+    out[2] = (t - u) - y;
+    out[0] = t;
+    out[1] = tv;
+    out[3] = cv1;
+  }
 };
 
 }  // namespace swept

@@ -890,9 +890,14 @@ int swept2d_upload(swept2d* h, const double* host) {
   if (!h || !host) return fail(SWEPT2D_EINVAL, "null argument");
   if (h->prec == SWEPT2D_FP64) return swept2d_upload_raw(h, host);
   const size_t cnt = (size_t)h->nx * h->ny * h->nvars;
-  // FP32C: u then zero compensations; FP32R: u only
+  // FP32C: u then zero compensations; FP32R: u only (the wave as u and
+  // v = fl32(u^n - u^(n-1)))
   std::vector<float> buf(h->prec == SWEPT2D_FP32C ? 2 * cnt : cnt, 0.0f);
   for (size_t i = 0; i < cnt; ++i) buf[i] = (float)host[i];
+  if (h->scheme == kWave32R) {
+    const size_t plane = (size_t)h->nx * h->ny;
+    for (size_t i = 0; i < plane; ++i) buf[plane + i] = (float)(host[i] - host[plane + i]);
+  }
   return swept2d_upload_raw(h, buf.data());
 }
 
@@ -905,6 +910,10 @@ int swept2d_download(swept2d* h, double* host) {
   int rc = swept2d_download_raw(h, buf.data());
   if (rc) return rc;
   for (size_t i = 0; i < cnt; ++i) host[i] = comp ? (double)buf[i] - (double)buf[cnt + i] : (double)buf[i];
+  if (h->scheme == kWave32R) {
+    const size_t plane = (size_t)h->nx * h->ny;
+    for (size_t i = 0; i < plane; ++i) host[plane + i] = (double)buf[i] - (double)buf[plane + i];
+  }
   return 0;
 }
 

@@ -2,10 +2,10 @@
 benchmark runs, in its launch configuration (default tile side, staged
 panels, direct launches), against the oracle on every output point.
 
-FP64: bit for bit (contraction off on both sides). FP32C: the normwise
-relative error against the FP64 oracle, max|x - x_ref| / max|x_ref| per
-variable, must stay within 1e-6; FP32C is also bitwise against the FP32C
-oracle where that oracle run is short enough.
+FP64: bit for bit (contraction off on both sides). FP32C and FP32R: the
+normwise relative error against the FP64 oracle, max|x - x_ref| / max|x_ref|
+per variable, must stay within 1e-6; both are also bitwise against their
+FP32 oracles where those oracle runs are short enough.
 """
 import numpy as np
 import pytest
@@ -110,6 +110,25 @@ def test_wave_2048_10000_steps_fp32c_error():
     err = _normwise(got32, ref)
     print(f"wave 2048^2 FP32C after {WAVE_STEPS} steps: normwise relative error {err:.3e}")
     assert err <= 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_wave_2048_10000_steps_fp32r_error_and_bitwise():
+    """FP32 values only in HBM, the wave in velocity form: within 1e-6 of the
+    FP64 oracle after the full 10000 steps at the benchmark's tile side, and
+    bit for bit the residency oracle over the first 100."""
+    s0 = si.wave_field(2048, 2048, seed=0)
+    p = si.default_params(si.WAVE_LF)
+    got, tile = _swept(si.WAVE_LF, p, s0, WAVE_STEPS, prec=sw.FP32R)
+    assert tile == 64
+    ref = _oracle64("wave2048", si.WAVE_LF, s0, p, WAVE_STEPS)
+    err = _normwise(got, ref)
+    print(f"wave 2048^2 FP32R after {WAVE_STEPS} steps: normwise relative error {err:.3e}")
+    assert err <= 1e-6
+    got2, _ = _swept(si.WAVE_LF, p, s0, 100, prec=sw.FP32R)
+    u = oracle.advance_f32r(si.WAVE_LF, oracle.split_f32r(si.WAVE_LF, s0), p, 100, 64,
+                            threads=oracle.default_threads())
+    assert np.array_equal(got2, oracle.join_f32r(si.WAVE_LF, u))
 
 
 @pytest.mark.timeout(900)

@@ -289,7 +289,7 @@ def test_fp32r_bitwise_against_residency_oracle(pde, nx, ny, steps, tiles):
     and staging mode; the per-step method keeps none."""
     s0 = si.initial_state(pde, nx, ny, seed=4)
     p = si.default_params(pde)
-    u0 = s0.astype(np.float32)
+    u0 = oracle.split_f32r(pde, s0)
     for n in tiles:
         ref = oracle.advance_f32r(pde, u0, p, steps, n)
         for staging in STAGINGS:

@@ -631,18 +631,52 @@ def test_residency_rule_matches_the_decomposition(nx, ny, n, S):
                 assert (keys[q] == key) == (res[q] == res[(x, y, L)]), ((x, y, L), q)
 
 
-@pytest.mark.parametrize("pde,shape", [(si.HEAT5, (48, 32)), (si.WAVE_LF, (32, 48))])
-def test_f32r_per_step_method_is_plain_fp32(pde, shape):
+def test_f32r_per_step_method_is_plain_fp32():
     """Tile side 0 (a launch per sub-step) keeps no compensation across a
-    sub-step: it equals the compensated stepper with c reset every step."""
-    s0 = si.initial_state(pde, *shape, seed=2)
-    p = si.default_params(pde)
+    sub-step: for heat it equals the compensated stepper with c reset every
+    step."""
+    s0 = si.initial_state(si.HEAT5, 48, 32, seed=2)
+    p = si.default_params(si.HEAT5)
     u = s0.astype(np.float32)
-    got = oracle.advance_f32r(pde, u, p, 25, 0)
+    got = oracle.advance_f32r(si.HEAT5, u, p, 25, 0)
     ref = u.copy()
     for _ in range(25):
-        ref, _ = oracle.advance_f32c(pde, ref, np.zeros_like(ref), p, 1)
+        ref, _ = oracle.advance_f32c(si.HEAT5, ref, np.zeros_like(ref), p, 1)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("pde,shape", [(si.HEAT5, (48, 32)), (si.WAVE_LF, (32, 48))])
+def test_f32r_per_step_method_restarts_every_sub_step(pde, shape):
+    """At tile side 0 every sub-step is a residency of its own: one advance
+    of 25 sub-steps equals 25 advances of one (each starting its
+    compensations at zero); at tile side 8 it does not."""
+    s0 = si.initial_state(pde, *shape, seed=2)
+    p = si.default_params(pde)
+    u = oracle.split_f32r(pde, s0)
+    got = oracle.advance_f32r(pde, u, p, 25, 0)
+    ref = u.copy()
+    for k in range(25):
+        ref = oracle.advance_f32r(pde, ref, p, 1, 0, t0=k)
+    assert np.array_equal(got, ref)
+    ref8 = u.copy()
+    for k in range(25):
+        ref8 = oracle.advance_f32r(pde, ref8, p, 1, 8, t0=k)
+    assert not np.array_equal(oracle.advance_f32r(pde, u, p, 25, 8), ref8)
+
+
+def test_f32r_wave_velocity_form_exact_on_dyadic_data():
+    """The wave's velocity form (v = u^n - u^(n-1); v' = v + C2 lap,
+    u' = u + v') is leapfrog in exact arithmetic: on small integers with
+    C2 = 1/4 every value of 4 steps is exact in FP32, and the converted
+    result equals the FP64 leapfrog oracle for every tile side, the
+    conversions to and from (u^n, u^(n-1)) included."""
+    rng = np.random.default_rng(8)
+    u0 = rng.integers(-2, 3, size=(16, 16)).astype(np.float64)
+    s0 = np.stack([u0, u0 + rng.integers(-1, 2, size=(16, 16))])
+    ref = oracle.advance_f64(si.WAVE_LF, s0, [0.25], 4)
+    for n in (4, 8, 16, 0):
+        got = oracle.join_f32r(si.WAVE_LF, oracle.advance_f32r(si.WAVE_LF, oracle.split_f32r(si.WAVE_LF, s0), [0.25], 4, n))
+        assert np.array_equal(got, ref), n
 
 
 def test_f32r_exact_when_fp32_is_exact():
@@ -665,9 +699,38 @@ def test_f32r_error_between_full_compensation_and_plain_fp32(pde, steps):
     u, c = oracle.split_f32c(s0)
     ub, cb = oracle.advance_f32c(pde, u, c, p, steps)
     err_b = _norm_rel(ub.astype(np.float64) - cb.astype(np.float64), ref)
-    errs = {n: _norm_rel(oracle.advance_f32r(pde, u, p, steps, n).astype(np.float64), ref) for n in (0, 16, 64)}
-    assert err_b < errs[64] < errs[16] < errs[0]
-    assert errs[64] < 1e-6
+    u = oracle.split_f32r(pde, s0)
+    errs = {n: _norm_rel(oracle.join_f32r(pde, oracle.advance_f32r(pde, u, p, steps, n)), ref)
+            for n in (-1, 0, 16, 64)}
+    assert errs[-1] < errs[64] < errs[16] < errs[0]
+    assert err_b < errs[64] and errs[64] < 1e-6 and errs[-1] < 2 * err_b
+
+
+def test_f32r_wave_long_run():
+    """Over 10000 steps (256^2), the velocity form with every compensation
+    kept stays within 2e-7 of FP64, which needs the velocity's compensation
+    (without it the error exceeds 4e-7); confined to residencies at tile side
+    64 it is still below the per-step method's plain FP32, which needs the
+    new velocity's compensation in the displacement's increment."""
+    pde, steps = si.WAVE_LF, 10000
+    s0 = si.initial_state(pde, 256, 256, seed=0)
+    p = si.default_params(pde)
+    ref = oracle.advance_f64(pde, s0, p, steps)
+    u = oracle.split_f32r(pde, s0)
+    errs = {n: _norm_rel(oracle.join_f32r(pde, oracle.advance_f32r(pde, u, p, steps, n)), ref) for n in (-1, 0, 64)}
+    assert errs[-1] < 2e-7
+    assert errs[64] < errs[0]
+
+
+def test_f32r_one_residency_is_the_compensated_stepper():
+    """Tile side -1 keeps every compensation for the whole advance: for heat
+    that is the FP32C stepper (compensation carried everywhere), bit for
+    bit."""
+    s0 = si.heat_field(64, 48, seed=6)
+    p = si.default_params(si.HEAT5)
+    u, c = oracle.split_f32c(s0)
+    ref_u, _ = oracle.advance_f32c(si.HEAT5, u, np.zeros_like(c), p, 300)
+    assert np.array_equal(oracle.advance_f32r(si.HEAT5, u, p, 300, -1), ref_u)
 
 
 # ------------------------------------------------- stencils reaching two rings
