@@ -99,8 +99,11 @@ extern "C" {
  *        or a panel. Results therefore depend on the method and tile side:
  *        swept2d_plain_advance keeps no compensation (plain FP32), the swept
  *        advance keeps it within each pyramid, bridge and octahedron.
- *        Available for HEAT5 and WAVE_LF. Device layout: nvars u-planes,
- *        each [ny][nx] float. */
+ *        Available for HEAT5 and WAVE_LF. Device layout: nvars planes,
+ *        each [ny][nx] float; the wave runs in velocity form, its planes
+ *        holding u^n and v = u^n - u^(n-1) (swept2d_upload and
+ *        swept2d_download convert from and to the (u^n, u^(n-1)) slots of
+ *        the other precisions: v = fl32(u^n - u^(n-1)) in, u^n - v out). */
 #define SWEPT2D_FP64 0
 #define SWEPT2D_FP32C 1
 #define SWEPT2D_FP32R 2
@@ -199,11 +202,13 @@ int swept2d_bind(swept2d *h, void *dev_state, void *hip_stream);
 size_t swept2d_state_bytes(const swept2d *h);
 
 /* Copy a host FP64 state [nvars][ny][nx] in (synchronous). FP32C stores
- * u = (float)x and c = 0, FP32R u = (float)x. */
+ * u = (float)x and c = 0, FP32R u = (float)x (the wave's second plane as
+ * v = (float)(x0 - x1), its velocity form). */
 int swept2d_upload(swept2d *h, const double *host);
 
 /* Copy the state out as FP64 [nvars][ny][nx] (synchronous; waits for the
- * stream). FP32C returns (double)u - (double)c, FP32R (double)u. */
+ * stream). FP32C returns (double)u - (double)c, FP32R (double)u (the wave's
+ * second slot as (double)u - (double)v). */
 int swept2d_download(swept2d *h, double *host);
 
 /* Copy the raw device state (swept2d_state_bytes bytes, precision layout)
@@ -381,15 +386,25 @@ void swept2d_batch_destroy(swept2d_batch *b);
 int swept2d_batch_count(const swept2d_batch *b);
 
 /* Tile side of grid idx: n > 0 an even side dividing both grid sides (EINVAL
- * otherwise), 0 the model's choice, negative the per-step method. get
- * returns the side, 0 for the per-step method, or EINVAL. */
+ * otherwise), 0 the model's choice (a square side, rectangular tiles when no
+ * square side is usable, or the per-step method), negative the per-step
+ * method. get returns the side, 0 for rectangular tiles or the per-step
+ * method, or EINVAL. */
 int swept2d_batch_set_tile(swept2d_batch *b, int idx, int n);
 int swept2d_batch_get_tile(const swept2d_batch *b, int idx);
 
-/* Choose every grid's tile side: SWEPT2D_TUNE_MODEL from the cost model,
+/* Rectangular tiles of half-cycle height hh (1..64) for grid idx, as
+ * swept2d_set_rect for a handle; EINVAL if a side is below 2 hh or the
+ * window exceeds the LDS. get returns the height, 0 when the grid runs
+ * square tiles or the per-step method, or EINVAL. */
+int swept2d_batch_set_rect(swept2d_batch *b, int idx, int hh);
+int swept2d_batch_get_rect(const swept2d_batch *b, int idx);
+
+/* Choose every grid's tiling: SWEPT2D_TUNE_MODEL from the cost model,
  * SWEPT2D_TUNE_MEASURE by timing each distinct grid (shape, pde, precision,
- * parameters) alone on a copy of its state at every usable side up to 64
- * and keeping the fastest per sub-step. Grid states are not changed. */
+ * parameters) alone on a copy of its state at every usable square side up
+ * to 64 and rectangular height 8, 12, .., 32, and keeping the fastest per
+ * sub-step. Grid states are not changed. */
 int swept2d_batch_autotune(swept2d_batch *b, int mode);
 
 /* State of grid idx from / to the host, FP64 [nvars][ny][nx] (converted as

@@ -68,7 +68,8 @@ EXPORTS = [
     "swept2d_set_staging",
     "swept2d_set_timing", "swept2d_get_timing", "swept2d_last_error",
     "swept2d_batch_create", "swept2d_batch_destroy", "swept2d_batch_count", "swept2d_batch_set_tile",
-    "swept2d_batch_get_tile", "swept2d_batch_autotune", "swept2d_batch_upload", "swept2d_batch_download",
+    "swept2d_batch_get_tile", "swept2d_batch_set_rect", "swept2d_batch_get_rect", "swept2d_batch_autotune",
+    "swept2d_batch_upload", "swept2d_batch_download",
     "swept2d_batch_advance", "swept2d_batch_synchronize", "swept2d_batch_substep_counter",
     "swept2d_batch_set_wait_limit", "swept2d_batch_set_mode", "swept2d_batch_get_mode",
     "swept2d_batch_launches", "swept2d_advance_noalloc", "swept2d_register_scheme", "swept2d_init_state",
@@ -132,6 +133,8 @@ def load_library():
         "swept2d_batch_count": (i, [vp]),
         "swept2d_batch_set_tile": (i, [vp, i, i]),
         "swept2d_batch_get_tile": (i, [vp, i]),
+        "swept2d_batch_set_rect": (i, [vp, i, i]),
+        "swept2d_batch_get_rect": (i, [vp, i]),
         "swept2d_batch_autotune": (i, [vp, i]),
         "swept2d_batch_upload": (i, [vp, i, vp]),
         "swept2d_batch_download": (i, [vp, i, vp]),
@@ -313,6 +316,14 @@ def swept2d_batch_set_tile(b: int, idx: int, n: int) -> int:
 
 def swept2d_batch_get_tile(b: int, idx: int) -> int:
     return _check(load_library().swept2d_batch_get_tile(b, idx))
+
+
+def swept2d_batch_set_rect(b: int, idx: int, hh: int) -> int:
+    return _check(load_library().swept2d_batch_set_rect(b, idx, hh))
+
+
+def swept2d_batch_get_rect(b: int, idx: int) -> int:
+    return _check(load_library().swept2d_batch_get_rect(b, idx))
 
 
 def swept2d_batch_autotune(b: int, mode: int) -> int:
@@ -566,6 +577,12 @@ class Swept2DBatch:
 
     def set_tile(self, i: int, n: int):
         swept2d_batch_set_tile(self.b, i, n)
+
+    def rect(self, i: int) -> int:
+        return swept2d_batch_get_rect(self.b, i)
+
+    def set_rect(self, i: int, hh: int):
+        swept2d_batch_set_rect(self.b, i, hh)
 
     def autotune(self, mode: int = TUNE_MODEL):
         swept2d_batch_autotune(self.b, mode)

@@ -162,6 +162,8 @@ __host__ __device__ inline void rect_span(const RAxis& a, int par, int i, int& s
   w = s1 - s;
 }
 
+constexpr int kRectThreads = 256;  // workgroup size of the rectangular-tile stages
+
 struct RGeo {
   RAxis ax, ay;
   int h;        // half-cycle height the tiles are cut for (every side >= 2h)
@@ -309,15 +311,18 @@ hipError_t configure_lds(size_t bytes);
 constexpr int kBatchThreads = 1024;
 constexpr int kBatchBlock = 64;  // side of a per-step block
 
-enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1 };
+enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1, kBatchRect = 2 };
 
 // Launch classes of the phased batch: the stage code of tile side 64 on 16
 // waves, of tile side 32 on 4 waves, of tile side 16 on one wave, of any
-// other side on 4 waves, and of other sides up to 22 on one wave; per-step
-// grids run in the 4-wave generic class. One-wave items always stage their
-// panel inputs.
-enum BatchClass : int { kClass66 = 0, kClass34, kClass18, kClassGen256, kClassGen64, kNumBatchClasses };
-inline int batch_class_of(int n) {
+// other side on 4 waves, of other sides up to 22 on one wave, and of
+// rectangular tiles on 4 waves; per-step grids run in the 4-wave generic
+// class. One-wave items always stage their panel inputs.
+enum BatchClass : int { kClass66 = 0, kClass34, kClass18, kClassGen256, kClassGen64, kClassRect, kNumBatchClasses };
+// Window-pitch template argument that marks the rectangular-tile stage code.
+constexpr int kRectWC = 1;
+inline int batch_class_of(int n, int rect_h = 0) {
+  if (rect_h > 0) return kClassRect;
   if (n == 64) return kClass66;
   if (n == 32) return kClass34;
   if (n == 16) return kClass18;
@@ -330,6 +335,7 @@ inline int batch_class_threads(int c) {
 
 struct BatchGrid {
   Geo g0;          // off 0, T0 = the grid's level at the start of an advance
+  RGeo rg;         // rectangular tiles (kind kBatchRect; its T0 unused)
   int scheme;      // Scheme (light schemes only)
   int kind;        // BatchKind
   int wc;          // window pitch of the stage code: 66, 34 or 0
@@ -341,8 +347,9 @@ struct BatchGrid {
   SchemeParams sp;
 };
 
-// Per-grid split of one advance of S sub-steps (h = n/2): q full half
-// cycles and a reduced one of height r, or S per-step phases.
+// Per-grid split of one advance of S sub-steps (h = n/2, or the height of
+// the rectangular tiles): q full half cycles and a reduced one of height r,
+// or S per-step phases.
 struct BatchPlan {
   long long S;
   long long q;

@@ -30,8 +30,6 @@
 // end of yb(a+1, b): the ring two wide around its level-l square, corners
 // included.
 
-constexpr int kRectThreads = 256;
-
 // Cell x + c, with x + c in [-L, 2L), brought into [0, L).
 __device__ __forceinline__ int rect_wrap(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
 

@@ -2400,6 +2400,34 @@ template <class S, int WC, int NT>
 __device__ __forceinline__ void batch_stage(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
   using V = typename S::V;
   V* state = static_cast<V*>(G.state);
+  if constexpr (WC == kRectWC) {
+    // Rectangular tiles: phase 0 the first frustums, odd phases the bridges
+    // of half cycle (p - 1) / 2 on tiling ((p - 1) / 2) mod 2, even phases
+    // the stage that finishes its downward pyramids and starts the next
+    // frustums (the last one of the advance writes its squares).
+    static_assert(NT == kRectThreads, "rectangular tiles run 256 threads");
+    if constexpr (S::NW == S::NV) {
+      RGeo g = G.rg;
+      g.tbase = nullptr;
+      const int h = g.h;
+      V* sm = reinterpret_cast<V*>(smem);
+      if (p == 0) {
+        g.T0 = G.g0.T0;
+        rect_oct_item<S>(g, 0, 0, P.q > 0 ? h : P.r, state, G.pp, G.sp, item, sm);
+        return;
+      }
+      const int hc = (p - 1) / 2;
+      g.T0 = G.g0.T0 + (long long)hc * h;
+      const int H = hc < P.q ? h : P.r;
+      if (p & 1) {
+        rect_bridge_item<S>(g, hc & 1, H, state, G.pp, G.sp, item, sm);
+      } else {
+        const int Hu = (hc + 1 < P.q) ? h : (hc + 1 == P.q ? P.r : 0);
+        rect_oct_item<S>(g, 1 - (hc & 1), H, Hu, state, G.pp, G.sp, item, sm);
+      }
+    }
+    return;
+  } else {
   if constexpr (WC == 0 && NT == 256) {
     if (G.kind == kBatchPlain) {
       V* s2 = static_cast<V*>(G.state2);
@@ -2438,6 +2466,7 @@ __device__ __forceinline__ void batch_stage(const BatchGrid& G, const BatchPlan&
     } else if constexpr (!always_staged) {
       oct_item<S, WC, NT, false>(g, H, Hu, state, G.pp, G.sp, item, smem);
     }
+  }
   }
 }
 

@@ -37,7 +37,8 @@ struct HostGrid {
   int nx = 0, ny = 0, pde = 0, prec = 0, scheme = 0, substeps = 1;
   SchemeInfo si{};
   SchemeParams sp{};
-  int n = 0;  // tile side; 0 = per-step method
+  int n = 0;   // square tile side; 0 = rectangular tiles or the per-step method
+  int rh = 0;  // half-cycle height of rectangular tiles (n == 0); 0 with n == 0: per-step
   void* state = nullptr;
   void* state2 = nullptr;
   void* up = nullptr;
@@ -86,12 +87,23 @@ namespace {
 
 size_t state_bytes(const HostGrid& g) { return (size_t)g.nx * g.ny * g.si.nv * g.si.vbytes; }
 
+// How a grid advances: square tiles of side n, rectangular tiles of
+// half-cycle height rh, or (both 0) the per-step method.
+struct Tiling {
+  int n = 0, rh = 0;
+};
+bool swept(const HostGrid& g) { return g.n > 0 || g.rh > 0; }
+int half_of(const HostGrid& g) { return g.n > 0 ? g.n / 2 : g.rh; }
+int class_of(const HostGrid& g) { return batch_class_of(g.n, g.rh); }
+RGeo rect_of(const HostGrid& g) { return rect_geo(g.nx, g.ny, g.rh); }
+
 // Staging as the single-grid AUTO policy: an octahedron stages its ring runs
 // only when its workgroup has too few waves to keep each wave's runs
 // precomputed for the fetch path (a wave would hold more than two of the
 // 8 NV units); bridges fetch (one-wave classes stage everything).
 size_t stage_lds(const HostGrid& g, bool* staged_oct, bool* staged_bridge) {
   *staged_oct = *staged_bridge = false;
+  if (g.rh > 0) return rect_lds_bytes(g.si, rect_of(g));
   if (g.n == 0) return 0;
   const size_t lim = device_lds_limit();
   const size_t win = window_lds_bytes(g.si, g.n);
@@ -105,6 +117,7 @@ size_t stage_lds(const HostGrid& g, bool* staged_oct, bool* staged_bridge) {
 
 // LDS of one item of phase p of grid g.
 size_t entry_lds(const HostGrid& g, int p) {
+  if (g.rh > 0) return rect_lds_bytes(g.si, rect_of(g));
   if (g.n == 0) return 0;
   bool so = false, sb = false;
   stage_lds(g, &so, &sb);
@@ -129,6 +142,16 @@ const char* batch_tile_problem(const HostGrid& g, int n) {
   return nullptr;
 }
 
+// Why rectangular tiles of half-cycle height rh cannot serve grid g in a
+// batch, or nullptr.
+const char* batch_rect_problem(const HostGrid& g, int rh) {
+  if (rh < 1 || rh > 64) return "half-cycle height must be 1..64";
+  if (g.nx < 2 * rh || g.ny < 2 * rh) return "grid sides must be at least twice the half-cycle height";
+  if (g.si.nw != g.si.nv) return "FP32R runs square tiles only";
+  if (rect_lds_bytes(g.si, rect_geo(g.nx, g.ny, rh)) > device_lds_limit()) return "tile window exceeds the workgroup LDS";
+  return nullptr;
+}
+
 // Model ranking of tile sides for one grid of a batch. Per half cycle
 // (h = n/2 sub-steps) a grid runs one bridge and one octahedron phase, each
 // a fixed cost tau (a launch) plus one workgroup barrier lambda per level
@@ -139,32 +162,43 @@ const char* batch_tile_problem(const HostGrid& g, int n) {
 // [2 tau + 3 h lambda] * rounds / h. The per-step method competes at one
 // launch per sub-step, tau times its rounds of 64 x 64 blocks: a grid whose
 // only usable sides are small (a half cycle of a few levels) runs per step.
-int model_tile(const HostGrid& g, int cus) {
+Tiling model_tiling(const HostGrid& g, int cus) {
   const double tau = 6.0e-6, lambda = 0.75e-6;
   const size_t lim = std::max<size_t>(device_lds_limit(), 1);
   const double blocks = (double)((g.nx + kBatchBlock - 1) / kBatchBlock) * ((g.ny + kBatchBlock - 1) / kBatchBlock);
   const double plain_per_cu = 2048.0 / batch_class_threads(kClassGen256);
-  int best = 0;
+  Tiling best;
   double best_cost = tau * std::ceil(blocks / (plain_per_cu * std::max(cus, 1)));
+  auto consider = [&](Tiling t, int h, double tiles, size_t lds, int threads, double weight) {
+    const double per_cu = std::max(1.0, std::min((double)(lim / std::max<size_t>(lds, 1)), 2048.0 / threads));
+    const double rounds = std::ceil(2.0 * tiles / (per_cu * std::max(cus, 1)));
+    const double cost = weight * (2.0 * tau + 3.0 * h * lambda * threads / 1024.0) * rounds / h;
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best = t;
+    }
+  };
   for (int n = 4; n <= 64; n += 2) {
     if (batch_tile_problem(g, n)) continue;
-    const int h = n / 2;
+    HostGrid t = g;
+    t.n = n;
+    t.rh = 0;
     bool so, sb;
-    const size_t lds = std::max<size_t>(stage_lds(g, &so, &sb), 1);
-    const int threads = batch_class_threads(batch_class_of(n));
-    const double per_cu = std::max(1.0, std::min((double)(lim / lds), 2048.0 / threads));
-    const double tiles = (double)(g.nx / n) * (g.ny / n);
-    const double rounds = std::ceil(2.0 * tiles / (per_cu * std::max(cus, 1)));
-    double cost = (2.0 * tau + 3.0 * h * lambda * threads / 1024.0) * rounds / h;
     // Generic stage code (window pitch known only at run time). In a batch
     // the tile-16 grids set the number of phases, so a larger generic side
     // gains no latency there and costs throughput: measured on the uneven
     // 256-grid workload, side 16 beat the generic sides 34-60 that a factor
     // of 1.25 chose.
-    if (pitch_of(n) == 0) cost *= 2.0;
-    if (cost < best_cost * (1.0 - 1e-9)) {
-      best_cost = cost;
-      best = n;
+    consider(Tiling{n, 0}, n / 2, (double)(g.nx / n) * (g.ny / n), stage_lds(t, &so, &sb),
+             batch_class_threads(batch_class_of(n)), pitch_of(n) == 0 ? 2.0 : 1.0);
+  }
+  // Rectangular tiles (one point per thread, run-time pitch: weighted as the
+  // generic square code), for grids no usable square side divides.
+  if (best.n == 0) {
+    for (int rh = 2; rh <= 32; ++rh) {
+      if (batch_rect_problem(g, rh)) continue;
+      const RGeo r = rect_geo(g.nx, g.ny, rh);
+      consider(Tiling{0, rh}, rh, (double)rect_tiles(r), rect_lds_bytes(g.si, r), kRectThreads, 2.0);
     }
   }
   return best;
@@ -180,6 +214,20 @@ void free_panels(HostGrid& g) {
 
 int alloc_work(HostGrid& g) {
   free_panels(g);
+  if (g.rh > 0) {
+    const RGeo r = rect_of(g);
+    const size_t vb = g.si.vbytes;
+    const size_t ub = std::max<size_t>(8, rect_up_values(r, g.si.nv) * vb);
+    const size_t xbb = std::max<size_t>(8, rect_xb_values(r, g.si.nv) * vb);
+    const size_t ybb = std::max<size_t>(8, rect_yb_values(r, g.si.nv) * vb);
+    if (hipMalloc(&g.up, ub) != hipSuccess || hipMalloc(&g.xb, xbb) != hipSuccess ||
+        hipMalloc(&g.yb, ybb) != hipSuccess) {
+      hipGetLastError();
+      free_panels(g);
+      return set_error(SWEPT2D_ENOMEM, "cannot allocate panels");
+    }
+    return 0;
+  }
   if (g.n == 0) {
     if (hipMalloc(&g.state2, state_bytes(g)) != hipSuccess) {
       hipGetLastError();
@@ -220,6 +268,7 @@ void drop_plans(swept2d_batch* b) {
 }
 
 int units_of(const HostGrid& g) {
+  if (g.rh > 0) return rect_tiles(rect_of(g));
   if (g.n == 0) return ((g.nx + kBatchBlock - 1) / kBatchBlock) * ((g.ny + kBatchBlock - 1) / kBatchBlock);
   return (g.nx / g.n) * (g.ny / g.n);
 }
@@ -228,11 +277,11 @@ BatchPlan plan_of(const HostGrid& g, long long S) {
   BatchPlan p{};
   p.S = S;
   if (S == 0) return p;
-  if (g.n == 0) {
+  if (!swept(g)) {
     p.nphases = (int)(S + (S & 1));
     return p;
   }
-  const int h = g.n / 2;
+  const int h = half_of(g);
   p.q = S / h;
   p.r = (int)(S % h);
   p.nphases = (int)(p.q == 0 ? 3 : 1 + 2 * (p.q + (p.r > 0 ? 1 : 0)));
@@ -255,8 +304,9 @@ int upload_descriptors(swept2d_batch* b, size_t* lds_out) {
     x.g0.W = g.n + 2;
     x.g0.T0 = g.T;
     x.g0.tbase = nullptr;
+    x.rg = g.rh > 0 ? rect_of(g) : RGeo{};
     x.scheme = g.scheme;
-    x.kind = g.n ? kBatchSwept : kBatchPlain;
+    x.kind = g.rh > 0 ? kBatchRect : (g.n ? kBatchSwept : kBatchPlain);
     x.wc = pitch_of(g.n);
     bool so = false, sb = false;
     lds = std::max(lds, stage_lds(g, &so, &sb));
@@ -289,7 +339,7 @@ int upload_array(T** dst, const std::vector<T>& v) {
 // Workgroups of phase p of a grid (the device decode's item count).
 int phase_items(const HostGrid& g, int p) {
   const int u = units_of(g);
-  if (g.n == 0) return u;
+  if (!swept(g)) return u;
   return (p & 1) ? 2 * u : u;
 }
 
@@ -352,7 +402,7 @@ int plan_phased(swept2d_batch* b, const std::vector<BatchPlan>& plans, Plan& pl)
       std::vector<Ent> es;
       for (const auto& e : slot[sidx]) {
         const HostGrid& g = b->grids[e.first];
-        if (batch_class_of(g.n) != cls) continue;
+        if (class_of(g) != cls) continue;
         es.push_back({e.first, e.second, phase_items(g, e.second), entry_lds(g, e.second)});
       }
       if (es.empty()) continue;
@@ -421,7 +471,7 @@ int plan_persistent(swept2d_batch* b, const std::vector<BatchPlan>& plans, Plan&
     const HostGrid& g = b->grids[order[j]];
     const long long u = units_of(g);
     cum1[j + 1] = cum1[j] + u;
-    cum2[j + 1] = cum2[j] + (g.n ? 2 * u : u);
+    cum2[j + 1] = cum2[j] + (swept(g) ? 2 * u : u);
   }
   std::vector<int> active(std::max(P, 1), 0);
   std::vector<long long> base(P + 1, 0);
@@ -526,19 +576,25 @@ int sync_and_check(swept2d_batch* b) {
   return 0;
 }
 
-int set_tile_impl(swept2d_batch* b, int idx, int n) {
+int set_tiling_impl(swept2d_batch* b, int idx, Tiling t) {
   HostGrid& g = b->grids[idx];
-  if (n > 0)
-    if (const char* why = batch_tile_problem(g, n)) return set_error(SWEPT2D_EINVAL, "tile %d: %s", n, why);
-  if (n == g.n && (n ? g.up != nullptr : g.state2 != nullptr)) return 0;
+  if (t.n > 0)
+    if (const char* why = batch_tile_problem(g, t.n)) return set_error(SWEPT2D_EINVAL, "tile %d: %s", t.n, why);
+  if (t.rh > 0)
+    if (const char* why = batch_rect_problem(g, t.rh))
+      return set_error(g.si.nw != g.si.nv ? SWEPT2D_EUNSUPPORTED : SWEPT2D_EINVAL, "rectangular tiles %d: %s", t.rh, why);
+  if (t.n == g.n && t.rh == g.rh && ((t.n || t.rh) ? g.up != nullptr : g.state2 != nullptr)) return 0;
   BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  g.n = n;
+  g.n = t.n;
+  g.rh = t.n > 0 ? 0 : t.rh;
   int rc = alloc_work(g);
   if (rc) return rc;
   drop_plans(b);
   b->dirty = true;
   return 0;
 }
+
+int set_tile_impl(swept2d_batch* b, int idx, int n) { return set_tiling_impl(b, idx, Tiling{n, 0}); }
 
 }  // namespace
 
@@ -625,9 +681,9 @@ swept2d_batch* swept2d_batch_create(int count, const int* nx, const int* ny, con
     set_error(SWEPT2D_EHIP, "hipMemset failed");
     return bail(0, "");
   }
-  // Initial tile sides from the model.
+  // Initial tilings from the model.
   for (int i = 0; i < count; ++i) {
-    if (set_tile_impl(b, i, model_tile(b->grids[i], b->cu_count))) return bail(0, "");
+    if (set_tiling_impl(b, i, model_tiling(b->grids[i], b->cu_count))) return bail(0, "");
   }
   return b;
 }
@@ -654,13 +710,25 @@ int swept2d_batch_set_tile(swept2d_batch* b, int idx, int n) {
   int rc = check_idx(b, idx);
   if (rc) return rc;
   if (n < 0) return set_tile_impl(b, idx, 0);
-  if (n == 0) n = model_tile(b->grids[idx], b->cu_count);
+  if (n == 0) return set_tiling_impl(b, idx, model_tiling(b->grids[idx], b->cu_count));
   return set_tile_impl(b, idx, n);
 }
 
 int swept2d_batch_get_tile(const swept2d_batch* b, int idx) {
   if (!b || idx < 0 || idx >= b->count) return SWEPT2D_EINVAL;
   return b->grids[idx].n;
+}
+
+int swept2d_batch_set_rect(swept2d_batch* b, int idx, int hh) {
+  int rc = check_idx(b, idx);
+  if (rc) return rc;
+  if (hh < 1) return set_error(SWEPT2D_EINVAL, "half-cycle height must be at least 1");
+  return set_tiling_impl(b, idx, Tiling{0, hh});
+}
+
+int swept2d_batch_get_rect(const swept2d_batch* b, int idx) {
+  if (!b || idx < 0 || idx >= b->count) return SWEPT2D_EINVAL;
+  return b->grids[idx].rh;
 }
 
 int swept2d_batch_upload(swept2d_batch* b, int idx, const double* host) {
@@ -785,14 +853,15 @@ int swept2d_batch_autotune(swept2d_batch* b, int mode) {
   int rc;
   if (mode == SWEPT2D_TUNE_MODEL) {
     for (int i = 0; i < b->count; ++i)
-      if ((rc = set_tile_impl(b, i, model_tile(b->grids[i], b->cu_count)))) return rc;
+      if ((rc = set_tiling_impl(b, i, model_tiling(b->grids[i], b->cu_count)))) return rc;
     return 0;
   }
   // Measured: run each grid alone, on a copy of its state, for a few
-  // half cycles at every usable side (up to 64) and keep the fastest per
-  // sub-step. Grids of one shape, scheme and parameters share a result.
+  // half cycles at every usable square side (up to 64) and rectangular
+  // height (8 to 32 in steps of 4), and keep the fastest per sub-step.
+  // Grids of one shape, scheme and parameters share a result.
   BHIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  std::map<std::vector<double>, int> seen;
+  std::map<std::vector<double>, Tiling> seen;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   BHIP(hipEventCreate(&e0), "hipEventCreate");
   BHIP(hipEventCreate(&e1), "hipEventCreate");
@@ -803,7 +872,7 @@ int swept2d_batch_autotune(swept2d_batch* b, int mode) {
                                g.sp.p[0], g.sp.p[1], g.sp.p[2], g.sp.p[3]};
     auto it = seen.find(key);
     if (it != seen.end()) {
-      rc = set_tile_impl(b, i, it->second);
+      rc = set_tiling_impl(b, i, it->second);
       continue;
     }
     const double par[4] = {g.sp.p[0], g.sp.p[1], g.sp.p[2], g.sp.p[3]};
@@ -818,12 +887,17 @@ int swept2d_batch_autotune(swept2d_batch* b, int mode) {
       rc = set_error(SWEPT2D_EHIP, "hipMemcpy");
       break;
     }
-    int best = g.n;
+    Tiling best{g.n, g.rh};
     double best_t = 1e300;
-    for (int n = 64; n >= 4 && rc == 0; n -= 2) {
-      if (batch_tile_problem(g, n)) continue;
-      if ((rc = set_tile_impl(t, 0, n))) break;
-      const long long steps = std::max(2LL * (n / 2), 64LL);
+    std::vector<Tiling> cands;
+    for (int n = 64; n >= 4; n -= 2)
+      if (!batch_tile_problem(g, n)) cands.push_back(Tiling{n, 0});
+    for (int rh = 32; rh >= 8; rh -= 4)
+      if (!batch_rect_problem(g, rh)) cands.push_back(Tiling{0, rh});
+    for (const Tiling& c : cands) {
+      if ((rc = set_tiling_impl(t, 0, c))) break;
+      const int hh = c.n > 0 ? c.n / 2 : c.rh;
+      const long long steps = std::max(2LL * hh, 64LL);
       if ((rc = swept2d_batch_advance(t, steps)) || (rc = swept2d_batch_synchronize(t))) break;
       if (hipEventRecord(e0, t->stream) != hipSuccess) { rc = set_error(SWEPT2D_EHIP, "hipEventRecord"); break; }
       if ((rc = swept2d_batch_advance(t, steps))) break;
@@ -834,13 +908,13 @@ int swept2d_batch_autotune(swept2d_batch* b, int mode) {
       const double per = ms / (double)steps;
       if (per < best_t) {
         best_t = per;
-        best = n;
+        best = c;
       }
     }
     swept2d_batch_destroy(t);
     if (rc) break;
     seen[key] = best;
-    rc = set_tile_impl(b, i, best);
+    rc = set_tiling_impl(b, i, best);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

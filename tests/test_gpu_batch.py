@@ -3,7 +3,7 @@
 Each grid of a batch must give exactly what the oracle gives for that grid
 alone (bitwise: hash, heat, wave in FP64; FP32C against the FP32C oracle),
 whatever tile side (and hence launch class) each grid runs with, per-step
-grids included, across split advances, graph replays and advances longer
+and rectangular-tile grids included, across split advances, graph replays and advances longer
 than one graph. Every case runs in the phased mode (slots of launches, no
 workgroup waits for another); the same cases in the persistent mode are
 kept, skipped (see PERSISTENT_OFF).
@@ -64,7 +64,7 @@ def _inits(specs):
 MIXED = [
     dict(nx=64, ny=64, pde=si.TEST_HASH),
     dict(nx=96, ny=48, pde=si.TEST_HASH),
-    dict(nx=67, ny=45, pde=si.TEST_HASH),          # no even side divides: per-step
+    dict(nx=67, ny=45, pde=si.TEST_HASH),          # no even side divides: rectangular tiles
     dict(nx=100, ny=36, pde=si.HEAT5),
     dict(nx=128, ny=64, pde=si.HEAT5),
     dict(nx=80, ny=48, pde=si.WAVE_LF),
@@ -80,7 +80,7 @@ def test_mixed_batch_matches_oracle_per_grid(mode):
     inits = _inits(specs)
     _say("mixed batch", len(specs), "grids, 70 steps, mode", mode)
     with _make(specs, mode) as b:
-        assert b.tile(2) == 0  # 67 x 45: per-step
+        assert b.tile(2) == 0 and b.rect(2) > 0  # 67 x 45: no even side divides, rectangular tiles
         for i, s0 in enumerate(inits):
             b.upload(i, s0)
         steps = 70
@@ -195,8 +195,9 @@ def test_uneven_batch_sampled_against_oracle(mode):
 def test_literal_batch_50000_steps_sampled_against_oracle():
     """The 256-grid workload with sides drawn from every integer in 64..512
     (heat or wave, FP64 or FP32C) advanced its full 50000 steps in phased
-    launches; the three smallest grids that run swept and the three smallest
-    that fall back to the per-step method equal the oracle bit for bit."""
+    launches: every grid runs swept (square tiles where an even side divides
+    both sides, rectangular tiles elsewhere); the three smallest grids of
+    each kind equal the oracle bit for bit."""
     specs = si.batch_specs(256, seed=0, quantum=1)
     inits = _inits(specs)
     steps = 50000
@@ -207,19 +208,70 @@ def test_literal_batch_50000_steps_sampled_against_oracle():
         b.advance(steps)
         b.synchronize()
         by_size = sorted(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])
-        swept = [i for i in by_size if b.tile(i) > 0][:3]
-        plain = [i for i in by_size if b.tile(i) == 0][:3]
-        assert len(swept) == 3 and len(plain) == 3
-        for i in swept + plain:
-            _say("grid", i, specs[i], "tile", b.tile(i))
+        assert all(b.tile(i) > 0 or b.rect(i) > 0 for i in by_size)
+        square = [i for i in by_size if b.tile(i) > 0][:3]
+        rect = [i for i in by_size if b.rect(i) > 0][:3]
+        assert len(square) == 3 and len(rect) == 3
+        for i in square + rect:
+            _say("grid", i, specs[i], "tile", b.tile(i), "rect", b.rect(i))
             ref = _oracle(specs[i], inits[i], steps)
-            assert np.array_equal(b.download(i), ref), (i, specs[i], b.tile(i))
+            assert np.array_equal(b.download(i), ref), (i, specs[i], b.tile(i), b.rect(i))
+
+
+RECT_MIXED = [
+    dict(nx=67, ny=45, pde=si.TEST_HASH),
+    dict(nx=101, ny=77, pde=si.HEAT5),
+    dict(nx=97, ny=131, pde=si.WAVE_LF),
+    dict(nx=83, ny=64, pde=si.HEAT5, prec=sw.FP32C),
+    dict(nx=71, ny=59, pde=si.WAVE_LF, prec=sw.FP32C),
+    dict(nx=64, ny=64, pde=si.TEST_HASH),
+    dict(nx=96, ny=48, pde=si.HEAT5),
+]
+
+
+@pytest.mark.parametrize("heights", [[5, 8, 16, 12, 9, 7, 0], [2, 3, 24, 4, 6, 16, 11], [0, 0, 0, 0, 0, 0, 0]])
+def test_rect_grids_in_batch(heights):
+    """Rectangular tiles inside a batch (0: the model's choice), next to
+    square tiles, through split advances and an advance longer than one
+    graph: every grid bit for bit the oracle."""
+    specs = RECT_MIXED
+    inits = _inits(specs)
+    _say("rect batch heights", heights)
+    with _make(specs) as b:
+        for i, hh in enumerate(heights):
+            if hh:
+                b.set_rect(i, hh)
+                assert b.rect(i) == hh and b.tile(i) == 0
+        for i, s0 in enumerate(inits):
+            b.upload(i, s0)
+        for k in (29, 29, 3, 1100):
+            b.advance(k)
+        total = 29 + 29 + 3 + 1100
+        for i, (spec, s0) in enumerate(zip(specs, inits)):
+            assert np.array_equal(b.download(i), _oracle(spec, s0, total)), (i, spec, b.tile(i), b.rect(i))
+
+
+def test_rect_batch_equals_single_handles():
+    specs = [dict(nx=101, ny=77, pde=si.HEAT5), dict(nx=97, ny=61, pde=si.WAVE_LF, prec=sw.FP32C)]
+    inits = _inits(specs)
+    with _make(specs) as b:
+        for i, s0 in enumerate(inits):
+            b.set_rect(i, 8 + 4 * i)
+            b.upload(i, s0)
+        b.advance(100)
+        for i, (spec, s0) in enumerate(zip(specs, inits)):
+            g = sw.Swept2D(spec["nx"], spec["ny"], spec["pde"], _params(spec["pde"]), prec=spec.get("prec", sw.FP64))
+            g.rect = b.rect(i)
+            g.upload(s0)
+            g.advance(100)
+            assert np.array_equal(b.download(i), g.download()), i
+            g.close()
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_any_sides_batch(mode):
-    """Sides drawn from every integer: most grids fall back to the per-step
-    method, the rest run swept; all exact."""
+    """Sides drawn from every integer: grids no even side divides run
+    rectangular tiles, the rest square tiles; all exact."""
     specs = si.batch_specs(12, seed=3, lo=20, hi=90, quantum=1)
     inits = _inits(specs)
     _say("any-sides batch, mode", mode)
