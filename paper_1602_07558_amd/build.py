@@ -34,7 +34,8 @@ PLUGIN_LIB = os.path.join(ROOT, "tests", "plugin", "libpaper_eq1_scheme.so")
 SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C", "Wave32C", "Euler32C",
            "Heat32R", "Wave32R", "Hash25x2"]
 # Batch launch classes: (window pitch, workgroup size).
-BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64), (1, 256)]  # pitch 1: rectangular tiles
+# negative pitches: rectangular tiles at window pitch 66, 34 and run-time
+BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64), (-66, 1024), (-34, 256), (-1, 256)]
 
 SOURCES = [os.path.join(CSRC, f) for f in ("stages_scheme.hip", "stages_batch.hip", "swept2d_kernels.hip",
                                            "swept2d_api.cpp", "swept2d_batch.cpp",

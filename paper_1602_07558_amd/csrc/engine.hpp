@@ -173,6 +173,10 @@ struct RGeo {
   const long long* tbase;  // device-resident level base (graph replay), or null
 };
 
+// Light schemes (at most 16 bytes per point in the window) run the column
+// layout at the fixed pitches.
+inline bool light_scheme(int nw, int vbytes) { return nw * vbytes <= 16; }
+
 inline RAxis rect_axis(int L, int h) {
   RAxis a{};
   a.L = L;
@@ -183,14 +187,15 @@ inline RAxis rect_axis(int L, int h) {
 }
 inline int rect_widest(const RAxis& a) { return a.base + (a.rem ? 1 : 0); }
 // Geometry for an nx x ny grid at half-cycle height h (tiles: 0 if an axis
-// is shorter than 2h).
-inline RGeo rect_geo(int nx, int ny, int h) {
+// is shorter than 2h). A light scheme's window takes pitch 34 or 66 when
+// every tile is at most 32 or 64 wide (the fixed-pitch level code).
+inline RGeo rect_geo(int nx, int ny, int h, bool light) {
   RGeo g{};
   g.h = h;
   g.ax = rect_axis(nx, h);
   g.ay = rect_axis(ny, h);
   g.urow = rect_widest(g.ax) > rect_widest(g.ay) ? rect_widest(g.ax) : rect_widest(g.ay);
-  g.P = g.urow + 2;
+  g.P = light && g.urow <= 32 ? 34 : (light && g.urow <= 64 ? 66 : g.urow + 2);
   return g;
 }
 inline int rect_tiles(const RGeo& g) { return g.ax.t * g.ay.t; }
@@ -316,13 +321,25 @@ enum BatchKind : int { kBatchSwept = 0, kBatchPlain = 1, kBatchRect = 2 };
 // Launch classes of the phased batch: the stage code of tile side 64 on 16
 // waves, of tile side 32 on 4 waves, of tile side 16 on one wave, of any
 // other side on 4 waves, of other sides up to 22 on one wave, and of
-// rectangular tiles on 4 waves; per-step grids run in the 4-wave generic
-// class. One-wave items always stage their panel inputs.
-enum BatchClass : int { kClass66 = 0, kClass34, kClass18, kClassGen256, kClassGen64, kClassRect, kNumBatchClasses };
-// Window-pitch template argument that marks the rectangular-tile stage code.
-constexpr int kRectWC = 1;
-inline int batch_class_of(int n, int rect_h = 0) {
-  if (rect_h > 0) return kClassRect;
+// rectangular tiles at window pitch 66 (16 waves), 34 (4 waves) or a
+// run-time pitch (4 waves); per-step grids run in the 4-wave generic class.
+// One-wave items always stage their panel inputs.
+enum BatchClass : int {
+  kClass66 = 0,
+  kClass34,
+  kClass18,
+  kClassGen256,
+  kClassGen64,
+  kClassRect66,
+  kClassRect34,
+  kClassRect0,
+  kNumBatchClasses
+};
+// Window-pitch template argument of a batch launch class that marks the
+// rectangular-tile stage code: -66, -34, or -1 for the run-time pitch.
+constexpr int rect_marker(int pitch) { return pitch == 66 || pitch == 34 ? -pitch : -1; }
+inline int batch_class_of(int n, int rect_h = 0, int rect_pitch = 0) {
+  if (rect_h > 0) return rect_pitch == 66 ? kClassRect66 : (rect_pitch == 34 ? kClassRect34 : kClassRect0);
   if (n == 64) return kClass66;
   if (n == 32) return kClass34;
   if (n == 16) return kClass18;
@@ -330,7 +347,7 @@ inline int batch_class_of(int n, int rect_h = 0) {
   return kClassGen256;
 }
 inline int batch_class_threads(int c) {
-  return c == kClass66 ? 1024 : ((c == kClassGen64 || c == kClass18) ? 64 : 256);
+  return (c == kClass66 || c == kClassRect66) ? 1024 : ((c == kClassGen64 || c == kClass18) ? 64 : 256);
 }
 
 struct BatchGrid {

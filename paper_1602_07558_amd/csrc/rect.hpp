@@ -4,10 +4,13 @@
 // these kernels once per scheme.
 //
 // These stages serve grids that no even square tile side divides (an odd
-// side, a prime) and tiles wider than the square ones: the window pitch and
-// the tile sizes are run-time values, a level is computed one rectangle
-// point per thread with its 3x3 neighbourhood read from LDS, and a
-// workgroup is 256 threads. The component structure is the square tiles':
+// side, a prime) and tiles wider than the square ones. The tile sizes are
+// run-time values; the window pitch WC is 66 when every tile is at most 64
+// wide and the scheme is light (levels in the column layout with lane
+// shifts of the square tiles' code, 16 waves), 34 when at most 32 wide
+// (one point per thread at a fixed pitch, 4 waves), and otherwise the
+// run-time widest tile + 2 (WC = 0: one rectangle point per thread with its
+// 3x3 neighbourhood read from LDS, 4 waves). The component structure is the square tiles':
 // a workgroup keeps its component's window in LDS, double buffered by level
 // parity; panel levels are stored as soon as their level is complete (the
 // band of level l stays untouched in buffer l mod 2 while later levels of
@@ -34,16 +37,29 @@
 __device__ __forceinline__ int rect_wrap(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
 
 // One level: every point of the window rectangle [x0, x0+w) x [y0, y0+hg)
-// gets sub-step T from `in` into `out`, one point per thread.
-template <class S>
+// gets sub-step T from `in` into `out`. At pitch 66 the column layout takes
+// its side neighbours by lane shifts where the rectangle lies within window
+// columns 2..63, and from LDS otherwise; at pitch 34 one point per thread;
+// at a run-time pitch one point per thread as well.
+template <class S, int WC, int NT>
 __device__ __forceinline__ void rect_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                            int P, int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
   using V = typename S::V;
   constexpr int NV = S::NV;
   if (w <= 0 || hg <= 0) return;
+  if constexpr (WC == 66) {
+    if (x0 >= 2 && x0 + w <= 64)
+      compute_level<S, 66, NT, false, false>(in, out, 66, x0, y0, w, hg, T, sp);
+    else
+      compute_level<S, 66, NT, false, true>(in, out, 66, x0, y0, w, hg, T, sp);
+    return;
+  } else if constexpr (WC == 34) {
+    compute_level<S, 34, NT, false>(in, out, 34, x0, y0, w, hg, T, sp);
+    return;
+  }
   const int plane = P * P, npts = w * hg;
   const float inv = __builtin_amdgcn_rcpf((float)w);
-  for (int k = (int)threadIdx.x; k < npts; k += kRectThreads) {
+  for (int k = (int)threadIdx.x; k < npts; k += NT) {
     int dy, dx;
     fdivmod(k, w, inv, dy, dx);
     const int o = (y0 + dy) * P + x0 + dx;
@@ -68,14 +84,14 @@ struct RectRun {
   int c0, r0, dc, dr, kc, kr, len;
 };
 
-template <class S, bool TO_PANEL>
+template <class S, int NT, bool TO_PANEL>
 __device__ __forceinline__ void rect_copy(typename S::V* __restrict__ win, int P, const RectRun& q,
                                           typename S::V* __restrict__ pan, int R) {
   constexpr int NV = S::NV;
   if (q.len <= 0) return;
   const int plane = P * P, total = 2 * NV * q.len;
   const float inv = __builtin_amdgcn_rcpf((float)q.len);
-  for (int e = (int)threadIdx.x; e < total; e += kRectThreads) {
+  for (int e = (int)threadIdx.x; e < total; e += NT) {
     int vk, t;
     fdivmod(e, q.len, inv, vk, t);
     const int k = vk & 1, v = vk >> 1;
@@ -87,11 +103,84 @@ __device__ __forceinline__ void rect_copy(typename S::V* __restrict__ win, int P
   }
 }
 
+// Panel runs placed in the window, fetched into registers a level ahead
+// (the fixed-pitch instantiations): up to four runs of one level, each
+// thread holding elements threadIdx.x + j NT (j < KR) of every run with
+// their window positions (-1: none). KR covers the longest run those
+// instantiations meet (a ring run of 2h + 4 values, h <= 32 at pitch 66 and
+// <= 16 at pitch 34).
+template <class S, int WC, int NT>
+constexpr int rect_kr() {
+  return WC == 66 ? (136 * S::NV + NT - 1) / NT : (WC == 34 ? (72 * S::NV + NT - 1) / NT : 1);
+}
+
+template <class V, int KR>
+struct RectFetch {
+  V val[4][KR];
+  int wi[4][KR];
+};
+
+struct RectRuns {
+  int n;
+  RectRun q[4];
+  const void* src[4];
+  int R[4];
+};
+
+template <class S, int NT, int KR>
+__device__ __forceinline__ bool rect_runs_fit(const RectRuns& rs) {
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r < rs.n) ok = ok && 2 * S::NV * rs.q[r].len <= KR * NT;
+  return ok;
+}
+
+template <class S, int NT, int KR>
+__device__ __forceinline__ void rect_fetch(RectFetch<typename S::V, KR>& f, const RectRuns& rs, int P) {
+  using V = typename S::V;
+  constexpr int NV = S::NV;
+  const int plane = P * P;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const RectRun& q = rs.q[r];
+    const float inv = __builtin_amdgcn_rcpf((float)(q.len > 0 ? q.len : 1));
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      f.wi[r][j] = -1;
+      const int e = (int)threadIdx.x + j * NT;
+      if (r < rs.n && e < 2 * NV * q.len) {
+        int vk, t;
+        fdivmod(e, q.len, inv, vk, t);
+        const int k = vk & 1, v = vk >> 1;
+        f.wi[r][j] = v * plane + (q.r0 + t * q.dr + k * q.kr) * P + q.c0 + t * q.dc + k * q.kc;
+        f.val[r][j] = static_cast<const V*>(rs.src[r])[vk * rs.R[r] + t];
+      }
+    }
+  }
+}
+
+template <class S, int KR>
+__device__ __forceinline__ void rect_place(const RectFetch<typename S::V, KR>& f, typename S::V* __restrict__ win) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int j = 0; j < KR; ++j)
+      if (f.wi[r][j] >= 0) win[f.wi[r][j]] = f.val[r][j];
+}
+
+template <class S, int NT>
+__device__ __forceinline__ void rect_copy_runs(typename S::V* __restrict__ win, int P, const RectRuns& rs) {
+  for (int r = 0; r < rs.n; ++r)
+    rect_copy<S, NT, false>(win, P, rs.q[r], const_cast<typename S::V*>(static_cast<const typename S::V*>(rs.src[r])),
+                            rs.R[r]);
+}
+
 // Window cells [cx0, cx0+w) x [cy0, cy0+hg) <-> state cells
 // (gx0 + cx, gy0 + cy) modulo the grid (gx0 + cx and gy0 + cy in
 // [-L, 2L)), skipping the window square [qx0, qx0+qs) x [qy0, qy0+qs).
 // LOAD: state -> window.
-template <class S, bool LOAD>
+template <class S, int NT, bool LOAD>
 __device__ __forceinline__ void rect_move(typename S::V* __restrict__ win, int P, typename S::V* __restrict__ state,
                                           int nx, int ny, int cx0, int cy0, int w, int hg, int gx0, int gy0, int qx0,
                                           int qy0, int qs) {
@@ -100,7 +189,7 @@ __device__ __forceinline__ void rect_move(typename S::V* __restrict__ win, int P
   const int plane = P * P, npts = w * hg;
   const size_t splane = (size_t)nx * ny;
   const float inv = __builtin_amdgcn_rcpf((float)w);
-  for (int k = (int)threadIdx.x; k < npts; k += kRectThreads) {
+  for (int k = (int)threadIdx.x; k < npts; k += NT) {
     int dy, dx;
     fdivmod(k, w, inv, dy, dx);
     const int cx = cx0 + dx, cy = cy0 + dy;
@@ -131,8 +220,8 @@ __device__ __forceinline__ size_t rect_yb_at(const RGeo& g, int nv, int tile, in
 // of tiling 1 - upar inside it, the rest of the tile from the state, then
 // the upward frustum of the tile (height Hu). Window cell (cx, cy) is tile
 // cell (cx - 1, cy - 1).
-template <class S>
-__device__ void rect_oct_item(const RGeo& g, int upar, int Hd, int Hu, typename S::V* __restrict__ state,
+template <class S, int WC, int NT>
+__device__ __forceinline__ void rect_oct_item(const RGeo& g, int upar, int Hd, int Hu, typename S::V* __restrict__ state,
                               const PanelPtrs& pp, const SchemeParams& sp, int item, typename S::V* smem) {
   using V = typename S::V;
   constexpr int NV = S::NV;
@@ -141,7 +230,11 @@ __device__ void rect_oct_item(const RGeo& g, int upar, int Hd, int Hu, typename 
   int sx, wx, sy, wy;
   rect_span(g.ax, upar, i, sx, wx);
   rect_span(g.ay, upar, j, sy, wy);
-  V* buf[2] = {smem, smem + NV * P * P};
+  // The two level buffers, chosen by parity with a select (an array of
+  // pointers would hide from the compiler that they point into LDS).
+  V* const buf0 = smem;
+  V* const buf1 = smem + NV * P * P;
+  auto buf = [&](int k) { return (k & 1) ? buf1 : buf0; };
   const long long base = g.T0 + (g.tbase ? *g.tbase : 0LL);
   const int nx = g.ax.L, ny = g.ay.L;
   // The corner of the other tiling inside this tile, and the downward
@@ -165,46 +258,67 @@ __device__ void rect_oct_item(const RGeo& g, int upar, int Hd, int Hu, typename 
   const int tE = (di + 1 == tx ? 0 : di + 1) + dj * tx;
   const int Rx = 2 * g.h + 4, Ry = 2 * g.h;
   // Ring of the downward pyramid's level l (for its level l + 1).
-  auto place_ring = [&](V* w, int l) {
-    rect_copy<S, false>(w, P, RectRun{cE - l - 2, cF - 1 - l, 1, 0, 0, -1, 2 * l + 4},
-                        const_cast<V*>(xb + rect_xb_at(g, NV, tN, 1, l)), Rx);
-    rect_copy<S, false>(w, P, RectRun{cE - l - 2, cF + l, 1, 0, 0, 1, 2 * l + 4},
-                        const_cast<V*>(xb + rect_xb_at(g, NV, tS, 0, l)), Rx);
-    rect_copy<S, false>(w, P, RectRun{cE - 1 - l, cF - l, 0, 1, -1, 0, 2 * l},
-                        const_cast<V*>(yb + rect_yb_at(g, NV, tN, 1, l)), Ry);
-    rect_copy<S, false>(w, P, RectRun{cE + l, cF - l, 0, 1, 1, 0, 2 * l},
-                        const_cast<V*>(yb + rect_yb_at(g, NV, tE, 0, l)), Ry);
+  auto ring = [&](int l) {
+    return RectRuns{4,
+                    {RectRun{cE - l - 2, cF - 1 - l, 1, 0, 0, -1, 2 * l + 4},
+                     RectRun{cE - l - 2, cF + l, 1, 0, 0, 1, 2 * l + 4}, RectRun{cE - 1 - l, cF - l, 0, 1, -1, 0, 2 * l},
+                     RectRun{cE + l, cF - l, 0, 1, 1, 0, 2 * l}},
+                    {xb + rect_xb_at(g, NV, tN, 1, l), xb + rect_xb_at(g, NV, tS, 0, l),
+                     yb + rect_yb_at(g, NV, tN, 1, l), yb + rect_yb_at(g, NV, tE, 0, l)},
+                    {Rx, Rx, Ry, Ry}};
   };
   // The tile's cells outside the level-Hd square (all of them if Hd == 0),
   // at level Hd, from the state; they go to the buffer level Hd ends in,
   // where no ring or square of an earlier level reaches.
   if (Hu > 0)
-    rect_move<S, true>(buf[Hd & 1], P, state, nx, ny, 1, 1, wx, wy, sx - 1, sy - 1, cE - Hd, cF - Hd, 2 * Hd);
-  if (Hd > 0) place_ring(buf[0], 0);
-  __syncthreads();
-  for (int l = 1; l <= Hd; ++l) {
-    rect_level<S>(buf[(l - 1) & 1], buf[l & 1], P, cE - l, cF - l, 2 * l, 2 * l, base + l - 1, sp);
-    if (l < Hd) place_ring(buf[l & 1], l);
+    rect_move<S, NT, true>(buf(Hd), P, state, nx, ny, 1, 1, wx, wy, sx - 1, sy - 1, cE - Hd, cF - Hd, 2 * Hd);
+  if (Hd > 0) rect_copy_runs<S, NT>(buf(0), P, ring(0));
+  if constexpr (WC != 0) {
+    // Each level's ring is fetched during the level before and placed at
+    // the start of its own (beside the square it surrounds).
+    constexpr int KR = rect_kr<S, WC, NT>();
+    RectFetch<V, KR> f;
+    bool ahead = Hd > 1 && rect_runs_fit<S, NT, KR>(ring(Hd - 1));
+    if (ahead) rect_fetch<S, NT, KR>(f, ring(1), P);
     __syncthreads();
+    for (int l = 1; l <= Hd; ++l) {
+      if (l < Hd) {
+        if (ahead) {
+          rect_place<S, KR>(f, buf(l));
+          if (l + 1 < Hd) rect_fetch<S, NT, KR>(f, ring(l + 1), P);
+        } else {
+          rect_copy_runs<S, NT>(buf(l), P, ring(l));
+        }
+      }
+      rect_level<S, WC, NT>(buf(l - 1), buf(l), P, cE - l, cF - l, 2 * l, 2 * l, base + l - 1, sp);
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();
+    for (int l = 1; l <= Hd; ++l) {
+      rect_level<S, WC, NT>(buf(l - 1), buf(l), P, cE - l, cF - l, 2 * l, 2 * l, base + l - 1, sp);
+      if (l < Hd) rect_copy_runs<S, NT>(buf(l), P, ring(l));
+      __syncthreads();
+    }
   }
   if (Hu == 0) {
-    rect_move<S, false>(buf[Hd & 1], P, state, nx, ny, cE - Hd, cF - Hd, 2 * Hd, 2 * Hd, sx - 1, sy - 1, 0, 0, 0);
+    rect_move<S, NT, false>(buf(Hd), P, state, nx, ny, cE - Hd, cF - Hd, 2 * Hd, 2 * Hd, sx - 1, sy - 1, 0, 0, 0);
     return;
   }
   V* up = static_cast<V*>(pp.up);
   const int tile = item, R = g.urow;
   for (int m = 1; m <= Hu; ++m) {
-    V* in = buf[(Hd + m - 1) & 1];
-    rect_level<S>(in, buf[(Hd + m) & 1], P, 1 + m, 1 + m, wx - 2 * m, wy - 2 * m, base + Hd + m - 1, sp);
+    V* in = buf(Hd + m - 1);
+    rect_level<S, WC, NT>(in, buf(Hd + m), P, 1 + m, 1 + m, wx - 2 * m, wy - 2 * m, base + Hd + m - 1, sp);
     // panels of level m - 1: rectangle [m-1, w-m] in tile cells
     const int l = m - 1, lx = wx - 2 * l, ly = wy - 2 * l;
-    rect_copy<S, true>(in, P, RectRun{m, m, 1, 0, 0, 1, lx}, up + rect_up_at(g, NV, tile, 0, l), R);
-    rect_copy<S, true>(in, P, RectRun{m, wy - l, 1, 0, 0, -1, lx}, up + rect_up_at(g, NV, tile, 1, l), R);
-    rect_copy<S, true>(in, P, RectRun{m, m, 0, 1, 1, 0, ly}, up + rect_up_at(g, NV, tile, 2, l), R);
-    rect_copy<S, true>(in, P, RectRun{wx - l, m, 0, 1, -1, 0, ly}, up + rect_up_at(g, NV, tile, 3, l), R);
+    rect_copy<S, NT, true>(in, P, RectRun{m, m, 1, 0, 0, 1, lx}, up + rect_up_at(g, NV, tile, 0, l), R);
+    rect_copy<S, NT, true>(in, P, RectRun{m, wy - l, 1, 0, 0, -1, lx}, up + rect_up_at(g, NV, tile, 1, l), R);
+    rect_copy<S, NT, true>(in, P, RectRun{m, m, 0, 1, 1, 0, ly}, up + rect_up_at(g, NV, tile, 2, l), R);
+    rect_copy<S, NT, true>(in, P, RectRun{wx - l, m, 0, 1, -1, 0, ly}, up + rect_up_at(g, NV, tile, 3, l), R);
     __syncthreads();
   }
-  rect_move<S, false>(buf[(Hd + Hu) & 1], P, state, nx, ny, 1 + Hu, 1 + Hu, wx - 2 * Hu, wy - 2 * Hu, sx - 1, sy - 1,
+  rect_move<S, NT, false>(buf(Hd + Hu), P, state, nx, ny, 1 + Hu, 1 + Hu, wx - 2 * Hu, wy - 2 * Hu, sx - 1, sy - 1,
                       0, 0, 0);
 }
 
@@ -213,8 +327,8 @@ __device__ void rect_oct_item(const RGeo& g, int upar, int Hd, int Hu, typename 
 // The window's columns run across the edge, 2H + 2 of them (cell
 // E - H - 1 + c), its rows along it over the tile's extent; the y-bridge's
 // window is the transpose (row c across the edge).
-template <class S>
-__device__ void rect_bridge_item(const RGeo& g, int par, int H, typename S::V* __restrict__ state,
+template <class S, int WC, int NT>
+__device__ __forceinline__ void rect_bridge_item(const RGeo& g, int par, int H, typename S::V* __restrict__ state,
                                  const PanelPtrs& pp, const SchemeParams& sp, int item, typename S::V* smem) {
   using V = typename S::V;
   constexpr int NV = S::NV;
@@ -225,7 +339,11 @@ __device__ void rect_bridge_item(const RGeo& g, int par, int H, typename S::V* _
   int sx, wx, sy, wy;
   rect_span(g.ax, par, a, sx, wx);
   rect_span(g.ay, par, b, sy, wy);
-  V* buf[2] = {smem, smem + NV * P * P};
+  // The two level buffers, chosen by parity with a select (an array of
+  // pointers would hide from the compiler that they point into LDS).
+  V* const buf0 = smem;
+  V* const buf1 = smem + NV * P * P;
+  auto buf = [&](int k) { return (k & 1) ? buf1 : buf0; };
   const long long base = g.T0 + (g.tbase ? *g.tbase : 0LL);
   const int nx = g.ax.L, ny = g.ay.L;
   const int wal = isx ? wy : wx;  // extent along the edge
@@ -240,58 +358,87 @@ __device__ void rect_bridge_item(const RGeo& g, int par, int H, typename S::V* _
   const int R = g.urow;
   // Frustum strips of level m: the near tile's at across H - m (k = 0) and
   // H - m - 1, the far tile's at H + 1 + m and H + 2 + m; along m + t.
-  auto place_strips = [&](V* w, int m) {
-    rect_copy<S, false>(w, P, run(H - m, m, 0, 1, -1, 0, wal - 2 * m), const_cast<V*>(up + rect_up_at(g, NV, tnear, enear, m)),
-                        R);
-    rect_copy<S, false>(w, P, run(H + 1 + m, m, 0, 1, 1, 0, wal - 2 * m),
-                        const_cast<V*>(up + rect_up_at(g, NV, tfar, efar, m)), R);
+  auto strips = [&](int m) {
+    return RectRuns{2,
+                    {run(H - m, m, 0, 1, -1, 0, wal - 2 * m), run(H + 1 + m, m, 0, 1, 1, 0, wal - 2 * m), RectRun{},
+                     RectRun{}},
+                    {up + rect_up_at(g, NV, tnear, enear, m), up + rect_up_at(g, NV, tfar, efar, m), nullptr, nullptr},
+                    {R, R, 0, 0}};
   };
   V* out = static_cast<V*>(isx ? pp.xb : pp.yb);
   const int Ro = isx ? 2 * g.h + 4 : 2 * g.h;
   auto at = [&](int end, int l) {
     return isx ? rect_xb_at(g, NV, e, end, l) : rect_yb_at(g, NV, e, end, l);
   };
-  place_strips(buf[0], 0);
+  rect_copy_runs<S, NT>(buf(0), P, strips(0));
+  // At the fixed pitches each level's strips are fetched during the level
+  // before and placed at the start of their own.
+  constexpr int KR = rect_kr<S, WC, NT>();
+  RectFetch<V, KR> f;
+  const bool ahead = WC != 0 && H > 1 && rect_runs_fit<S, NT, KR>(strips(0));
+  if (ahead) rect_fetch<S, NT, KR>(f, strips(1), P);
   __syncthreads();
   for (int l = 1; l <= H; ++l) {
-    const V* in = buf[(l - 1) & 1];
+    const V* in = buf(l - 1);
+    if (l < H) {
+      if (ahead) {
+        rect_place<S, KR>(f, buf(l));
+        if (l + 1 < H) rect_fetch<S, NT, KR>(f, strips(l + 1), P);
+      } else {
+        rect_copy_runs<S, NT>(buf(l), P, strips(l));
+      }
+    }
     if (isx)
-      rect_level<S>(in, buf[l & 1], P, H + 1 - l, l, 2 * l, wal - 2 * l, base + l - 1, sp);
+      rect_level<S, WC, NT>(in, buf(l), P, H + 1 - l, l, 2 * l, wal - 2 * l, base + l - 1, sp);
     else
-      rect_level<S>(in, buf[l & 1], P, l, H + 1 - l, wal - 2 * l, 2 * l, base + l - 1, sp);
-    if (l < H) place_strips(buf[l & 1], l);
-    // ends of level m = l - 1: rows (x-bridge) or columns (y-bridge) m, m+1
-    // and wal-1-m, wal-2-m of the tile; across, the x-bridge's run covers
-    // its band and the frustum corners, the y-bridge's its band only
-    const int m = l - 1;
-    const int ac0 = isx ? H - m - 1 : H + 1 - m, len = isx ? 2 * m + 4 : 2 * m;
-    rect_copy<S, true>(const_cast<V*>(in), P, run(ac0, m, 1, 0, 0, 1, len), out + at(0, m), Ro);
-    rect_copy<S, true>(const_cast<V*>(in), P, run(ac0, wal - 1 - m, 1, 0, 0, -1, len), out + at(1, m), Ro);
+      rect_level<S, WC, NT>(in, buf(l), P, l, H + 1 - l, wal - 2 * l, 2 * l, base + l - 1, sp);
     __syncthreads();
+  }
+  // The ends of every level m, stored once all levels are done (their cells
+  // stay untouched in buffer m mod 2: later levels of that parity write
+  // only inside them), so that no level waits for panel stores before it
+  // places its prefetched strips: rows (x-bridge) or columns (y-bridge) m,
+  // m+1 and wal-1-m, wal-2-m of the tile; across, the x-bridge's run covers
+  // its band and the frustum corners, the y-bridge's its band only.
+  for (int m = 0; m < H; ++m) {
+    V* in = buf(m);
+    const int ac0 = isx ? H - m - 1 : H + 1 - m, len = isx ? 2 * m + 4 : 2 * m;
+    rect_copy<S, NT, true>(in, P, run(ac0, m, 1, 0, 0, 1, len), out + at(0, m), Ro);
+    rect_copy<S, NT, true>(in, P, run(ac0, wal - 1 - m, 1, 0, 0, -1, len), out + at(1, m), Ro);
   }
   // the band at level H: across [1, 2H + 1), along [H, wal - H)
   if (isx) {
     const int E = sx + wx >= nx ? sx + wx - nx : sx + wx;
-    rect_move<S, false>(buf[H & 1], P, state, nx, ny, 1, H, 2 * H, wal - 2 * H, E - H - 1, sy, 0, 0, 0);
+    rect_move<S, NT, false>(buf(H), P, state, nx, ny, 1, H, 2 * H, wal - 2 * H, E - H - 1, sy, 0, 0, 0);
   } else {
     const int F = sy + wy >= ny ? sy + wy - ny : sy + wy;
-    rect_move<S, false>(buf[H & 1], P, state, nx, ny, H, 1, wal - 2 * H, 2 * H, sx, F - H - 1, 0, 0, 0);
+    rect_move<S, NT, false>(buf(H), P, state, nx, ny, H, 1, wal - 2 * H, 2 * H, sx, F - H - 1, 0, 0, 0);
   }
 }
 
-template <class S>
-__global__ __launch_bounds__(kRectThreads) void k_rect_oct(RGeo g, int upar, int Hd, int Hu,
-                                                           typename S::V* __restrict__ state, PanelPtrs pp,
-                                                           SchemeParams sp) {
+template <class S, int WC, int NT>
+__global__ __launch_bounds__(NT) void k_rect_oct(RGeo g, int upar, int Hd, int Hu, typename S::V* __restrict__ state,
+                                                 PanelPtrs pp, SchemeParams sp) {
   extern __shared__ double smem_d[];
-  rect_oct_item<S>(g, upar, Hd, Hu, state, pp, sp, (int)blockIdx.x, reinterpret_cast<typename S::V*>(smem_d));
+  rect_oct_item<S, WC, NT>(g, upar, Hd, Hu, state, pp, sp, (int)blockIdx.x, reinterpret_cast<typename S::V*>(smem_d));
 }
 
-template <class S>
-__global__ __launch_bounds__(kRectThreads) void k_rect_bridge(RGeo g, int par, int H, typename S::V* __restrict__ state,
-                                                              PanelPtrs pp, SchemeParams sp) {
+template <class S, int WC, int NT>
+__global__ __launch_bounds__(NT) void k_rect_bridge(RGeo g, int par, int H, typename S::V* __restrict__ state,
+                                                    PanelPtrs pp, SchemeParams sp) {
   extern __shared__ double smem_d[];
-  rect_bridge_item<S>(g, par, H, state, pp, sp, (int)blockIdx.x, reinterpret_cast<typename S::V*>(smem_d));
+  rect_bridge_item<S, WC, NT>(g, par, H, state, pp, sp, (int)blockIdx.x, reinterpret_cast<typename S::V*>(smem_d));
+}
+
+// The instantiation that runs window pitch P: 66 and 34 for light schemes
+// (rect_geo picks those pitches only for them), the run-time pitch otherwise.
+template <class S, class F>
+hipError_t rect_by_pitch(int P, F&& f) {
+  if constexpr (Lay<S, 66>::light) {
+    if (P == 66) return f(std::integral_constant<int, 66>{}, std::integral_constant<int, 1024>{});
+    if (P == 34) return f(std::integral_constant<int, 34>{}, std::integral_constant<int, 256>{});
+  }
+  return f(std::integral_constant<int, 0>{}, std::integral_constant<int, kRectThreads>{});
 }
 
 template <class S>
@@ -301,9 +448,11 @@ hipError_t rect_oct_t(const RGeo& g, int upar, int Hd, int Hu, void* state, Pane
     return hipErrorNotSupported;
   } else {
     const size_t lds = rect_lds_bytes(info_of<S>(), g);
-    hipLaunchKernelGGL(k_rect_oct<S>, dim3(rect_tiles(g)), dim3(kRectThreads), lds, s, g, upar, Hd, Hu,
-                       static_cast<typename S::V*>(state), p, sp);
-    return hipGetLastError();
+    return rect_by_pitch<S>(g.P, [&](auto wc, auto nt) {
+      hipLaunchKernelGGL((k_rect_oct<S, decltype(wc)::value, decltype(nt)::value>), dim3(rect_tiles(g)),
+                         dim3(decltype(nt)::value), lds, s, g, upar, Hd, Hu, static_cast<typename S::V*>(state), p, sp);
+      return hipGetLastError();
+    });
   }
 }
 
@@ -314,10 +463,21 @@ hipError_t rect_bridge_t(const RGeo& g, int par, int H, void* state, PanelPtrs p
     return hipErrorNotSupported;
   } else {
     const size_t lds = rect_lds_bytes(info_of<S>(), g);
-    hipLaunchKernelGGL(k_rect_bridge<S>, dim3(2 * rect_tiles(g)), dim3(kRectThreads), lds, s, g, par, H,
-                       static_cast<typename S::V*>(state), p, sp);
-    return hipGetLastError();
+    return rect_by_pitch<S>(g.P, [&](auto wc, auto nt) {
+      hipLaunchKernelGGL((k_rect_bridge<S, decltype(wc)::value, decltype(nt)::value>), dim3(2 * rect_tiles(g)),
+                         dim3(decltype(nt)::value), lds, s, g, par, H, static_cast<typename S::V*>(state), p, sp);
+      return hipGetLastError();
+    });
   }
+}
+
+template <class S, int WC, int NT>
+hipError_t rect_lds_one(int bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_rect_oct<S, WC, NT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_rect_bridge<S, WC, NT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <class S>
@@ -325,10 +485,11 @@ hipError_t rect_lds_t(int bytes) {
   if constexpr (S::NW != S::NV) {
     return hipSuccess;
   } else {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_rect_oct<S>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_rect_bridge<S>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = rect_lds_one<S, 0, kRectThreads>(bytes);
+    if constexpr (Lay<S, 66>::light) {
+      if (e == hipSuccess) e = rect_lds_one<S, 66, 1024>(bytes);
+      if (e == hipSuccess) e = rect_lds_one<S, 34, 256>(bytes);
+    }
+    return e;
   }
 }

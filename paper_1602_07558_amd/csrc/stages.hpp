@@ -2400,30 +2400,31 @@ template <class S, int WC, int NT>
 __device__ __forceinline__ void batch_stage(const BatchGrid& G, const BatchPlan& P, int p, int item, double* smem) {
   using V = typename S::V;
   V* state = static_cast<V*>(G.state);
-  if constexpr (WC == kRectWC) {
-    // Rectangular tiles: phase 0 the first frustums, odd phases the bridges
-    // of half cycle (p - 1) / 2 on tiling ((p - 1) / 2) mod 2, even phases
-    // the stage that finishes its downward pyramids and starts the next
-    // frustums (the last one of the advance writes its squares).
-    static_assert(NT == kRectThreads, "rectangular tiles run 256 threads");
-    if constexpr (S::NW == S::NV) {
+  if constexpr (WC < 0) {
+    // Rectangular tiles (WC = rect_marker(pitch)): phase 0 the first
+    // frustums, odd phases the bridges of half cycle (p - 1) / 2 on tiling
+    // ((p - 1) / 2) mod 2, even phases the stage that finishes its downward
+    // pyramids and starts the next frustums (the last one of the advance
+    // writes its squares).
+    constexpr int RW = WC == -1 ? 0 : -WC;
+    if constexpr (S::NW == S::NV && (RW == 0 || Lay<S, 66>::light)) {
       RGeo g = G.rg;
       g.tbase = nullptr;
       const int h = g.h;
       V* sm = reinterpret_cast<V*>(smem);
       if (p == 0) {
         g.T0 = G.g0.T0;
-        rect_oct_item<S>(g, 0, 0, P.q > 0 ? h : P.r, state, G.pp, G.sp, item, sm);
+        rect_oct_item<S, RW, NT>(g, 0, 0, P.q > 0 ? h : P.r, state, G.pp, G.sp, item, sm);
         return;
       }
       const int hc = (p - 1) / 2;
       g.T0 = G.g0.T0 + (long long)hc * h;
       const int H = hc < P.q ? h : P.r;
       if (p & 1) {
-        rect_bridge_item<S>(g, hc & 1, H, state, G.pp, G.sp, item, sm);
+        rect_bridge_item<S, RW, NT>(g, hc & 1, H, state, G.pp, G.sp, item, sm);
       } else {
         const int Hu = (hc + 1 < P.q) ? h : (hc + 1 == P.q ? P.r : 0);
-        rect_oct_item<S>(g, 1 - (hc & 1), H, Hu, state, G.pp, G.sp, item, sm);
+        rect_oct_item<S, RW, NT>(g, 1 - (hc & 1), H, Hu, state, G.pp, G.sp, item, sm);
       }
     }
     return;

@@ -238,7 +238,7 @@ int ensure_panels(swept2d* h) {
   const size_t vb = h->si.vbytes;
   size_t ub, xbb, ybb;
   if (h->rect_h) {
-    const RGeo g = rect_geo(h->nx, h->ny, h->rect_h);
+    const RGeo g = rect_geo(h->nx, h->ny, h->rect_h, light_scheme(h->si.nw, h->si.vbytes));
     ub = rect_up_values(g, h->si.nv) * vb;
     xbb = rect_xb_values(g, h->si.nv) * vb;
     ybb = rect_yb_values(g, h->si.nv) * vb;
@@ -272,7 +272,7 @@ const char* rect_problem(const swept2d* h, int hh) {
   if (h->nx < 2 * hh || h->ny < 2 * hh) return "nx and ny must be at least twice the half-cycle height";
   if (user_scheme(h->scheme - kNumSchemes)) return "registered user schemes run square tiles only";
   if (h->si.nw != h->si.nv) return "FP32R runs square tiles only";
-  if (rect_lds_bytes(h->si, rect_geo(h->nx, h->ny, hh)) > g_lds_limit) return "tile window exceeds the workgroup LDS";
+  if (rect_lds_bytes(h->si, rect_geo(h->nx, h->ny, hh, light_scheme(h->si.nw, h->si.vbytes))) > g_lds_limit) return "tile window exceeds the workgroup LDS";
   return nullptr;
 }
 
@@ -365,7 +365,7 @@ int model_rect(const swept2d* h) {
   double best_cost = 1e300;
   for (int hh = 1; hh <= std::min(64, std::min(h->nx, h->ny) / 2); ++hh) {
     if (rect_problem(h, hh)) continue;
-    const RGeo g = rect_geo(h->nx, h->ny, hh);
+    const RGeo g = rect_geo(h->nx, h->ny, hh, light_scheme(h->si.nw, h->si.vbytes));
     const double tiles = (double)rect_tiles(g);
     const double per_cu = std::max(1.0, std::floor((double)g_lds_limit / (double)rect_lds_bytes(h->si, g)));
     const double seq = std::ceil(tiles / h->cu_count);
@@ -507,7 +507,7 @@ double rect_down_points(const RGeo& g, int H) { return (double)rect_tiles(g) * d
 // finishes the downward pyramids and starts the next frustums (the last one
 // writes its squares to the state). Tilings 0 and 1 alternate.
 int enqueue_rect(swept2d* h, long long S, long long T, const long long* tbase, bool timed) {
-  RGeo g = rect_geo(h->nx, h->ny, h->rect_h);
+  RGeo g = rect_geo(h->nx, h->ny, h->rect_h, light_scheme(h->si.nw, h->si.vbytes));
   g.T0 = T;
   g.tbase = tbase;
   const int hh = g.h, sc = h->scheme;

@@ -94,8 +94,8 @@ struct Tiling {
 };
 bool swept(const HostGrid& g) { return g.n > 0 || g.rh > 0; }
 int half_of(const HostGrid& g) { return g.n > 0 ? g.n / 2 : g.rh; }
-int class_of(const HostGrid& g) { return batch_class_of(g.n, g.rh); }
-RGeo rect_of(const HostGrid& g) { return rect_geo(g.nx, g.ny, g.rh); }
+RGeo rect_of(const HostGrid& g) { return rect_geo(g.nx, g.ny, g.rh, light_scheme(g.si.nw, g.si.vbytes)); }
+int class_of(const HostGrid& g) { return batch_class_of(g.n, g.rh, g.rh > 0 ? rect_of(g).P : 0); }
 
 // Staging as the single-grid AUTO policy: an octahedron stages its ring runs
 // only when its workgroup has too few waves to keep each wave's runs
@@ -148,7 +148,7 @@ const char* batch_rect_problem(const HostGrid& g, int rh) {
   if (rh < 1 || rh > 64) return "half-cycle height must be 1..64";
   if (g.nx < 2 * rh || g.ny < 2 * rh) return "grid sides must be at least twice the half-cycle height";
   if (g.si.nw != g.si.nv) return "FP32R runs square tiles only";
-  if (rect_lds_bytes(g.si, rect_geo(g.nx, g.ny, rh)) > device_lds_limit()) return "tile window exceeds the workgroup LDS";
+  if (rect_lds_bytes(g.si, rect_geo(g.nx, g.ny, rh, light_scheme(g.si.nw, g.si.vbytes))) > device_lds_limit()) return "tile window exceeds the workgroup LDS";
   return nullptr;
 }
 
@@ -197,8 +197,10 @@ Tiling model_tiling(const HostGrid& g, int cus) {
   if (best.n == 0) {
     for (int rh = 2; rh <= 32; ++rh) {
       if (batch_rect_problem(g, rh)) continue;
-      const RGeo r = rect_geo(g.nx, g.ny, rh);
-      consider(Tiling{0, rh}, rh, (double)rect_tiles(r), rect_lds_bytes(g.si, r), kRectThreads, 2.0);
+      const RGeo r = rect_geo(g.nx, g.ny, rh, light_scheme(g.si.nw, g.si.vbytes));
+      const int cls = batch_class_of(0, rh, r.P);
+      consider(Tiling{0, rh}, rh, (double)rect_tiles(r), rect_lds_bytes(g.si, r), batch_class_threads(cls),
+               cls == kClassRect0 ? 2.0 : 1.0);
     }
   }
   return best;

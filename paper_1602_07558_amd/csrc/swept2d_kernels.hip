@@ -27,7 +27,9 @@ extern template struct BatchPhase<34, 256>;
 extern template struct BatchPhase<18, 64>;
 extern template struct BatchPhase<0, 256>;
 extern template struct BatchPhase<0, 64>;
-extern template struct BatchPhase<kRectWC, 256>;
+extern template struct BatchPhase<-66, 1024>;
+extern template struct BatchPhase<-34, 256>;
+extern template struct BatchPhase<-1, 256>;
 
 namespace {
 
@@ -172,7 +174,9 @@ hipError_t configure_lds(size_t bytes) {
   if (e == hipSuccess) e = BatchPhase<18, 64>::lds(b);
   if (e == hipSuccess) e = BatchPhase<0, 256>::lds(b);
   if (e == hipSuccess) e = BatchPhase<0, 64>::lds(b);
-  if (e == hipSuccess) e = BatchPhase<kRectWC, 256>::lds(b);
+  if (e == hipSuccess) e = BatchPhase<-66, 1024>::lds(b);
+  if (e == hipSuccess) e = BatchPhase<-34, 256>::lds(b);
+  if (e == hipSuccess) e = BatchPhase<-1, 256>::lds(b);
   return e;
 }
 
@@ -183,7 +187,9 @@ hipError_t launch_batch_phase(int cls, const PhaseLaunch& L, int blocks, size_t 
     case kClass18: return BatchPhase<18, 64>::launch(L, blocks, lds, st);
     case kClassGen256: return BatchPhase<0, 256>::launch(L, blocks, lds, st);
     case kClassGen64: return BatchPhase<0, 64>::launch(L, blocks, lds, st);
-    case kClassRect: return BatchPhase<kRectWC, 256>::launch(L, blocks, lds, st);
+    case kClassRect66: return BatchPhase<-66, 1024>::launch(L, blocks, lds, st);
+    case kClassRect34: return BatchPhase<-34, 256>::launch(L, blocks, lds, st);
+    case kClassRect0: return BatchPhase<-1, 256>::launch(L, blocks, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -195,7 +201,9 @@ hipError_t batch_phase_resident(int cls, size_t lds, int* out) {
     case kClass18: return BatchPhase<18, 64>::resident(lds, out);
     case kClassGen256: return BatchPhase<0, 256>::resident(lds, out);
     case kClassGen64: return BatchPhase<0, 64>::resident(lds, out);
-    case kClassRect: return BatchPhase<kRectWC, 256>::resident(lds, out);
+    case kClassRect66: return BatchPhase<-66, 1024>::resident(lds, out);
+    case kClassRect34: return BatchPhase<-34, 256>::resident(lds, out);
+    case kClassRect0: return BatchPhase<-1, 256>::resident(lds, out);
     default: return hipErrorInvalidValue;
   }
 }
