@@ -2,6 +2,9 @@
 
   python -m paper_1602_07558_amd.profiling stats DIR
       per-kernel calls / average / total duration from *_kernel_stats.csv
+  python -m paper_1602_07558_amd.profiling counters DIR COUNTER [COUNTER ...]
+      per-launch averages of --pmc counters for the swept2d stage and
+      per-step kernels in DIR
   python -m paper_1602_07558_amd.profiling traffic FETCH_DIR WRITE_DIR OUT [--copy-bytes B]
       HBM bytes per launch of the heat benchmark's kernels (octahedron, bridge
       pair, first upward pyramid, per-step kernel) from two --pmc runs
@@ -111,6 +114,20 @@ def main(argv):
         for k in sorted(kernel_stats(argv[1]), key=lambda r: -r["total_ns"]):
             print(f"{short_name(k['name']):40s} calls={k['calls']:7d} avg_us={k['avg_ns'] / 1e3:10.2f} "
                   f"total_ms={k['total_ns'] / 1e6:10.3f} pct={k['pct']:6.2f}")
+        return 0
+    if argv and argv[0] == "counters":
+        directory, names = argv[1], argv[2:]
+        rows = defaultdict(dict)
+        for c in names:
+            for k, vals in counter_values(directory, c).items():
+                n = short_name(k)
+                if n.startswith("k_"):
+                    rows[n][c] = (sum(vals) / len(vals), len(vals))
+        print(f"{'kernel':42s} {'launches':>8s} " + " ".join(f"{c:>16s}" for c in names))
+        for n in sorted(rows):
+            launches = max(v[1] for v in rows[n].values())
+            print(f"{n:42s} {launches:8d} " +
+                  " ".join(f"{rows[n][c][0]:16.1f}" if c in rows[n] else f"{'-':>16s}" for c in names))
         return 0
     if argv and argv[0] == "traffic":
         fetch_dir, write_dir, out = argv[1], argv[2], argv[3]
