@@ -120,45 +120,81 @@ struct RectFetch {
   int wi[4][KR];
 };
 
+// The fixed-pitch instantiations describe each kind of run once for all
+// levels: level l of the run starts at window cell (c0 + l dc0, r0 + l dr0)
+// with len0 + l dlen values per row, value t of row k of slot v lying at
+// (+ t dc + k kc, + t dr + k kr) and at src[l sstride + (2 v + k) R + t].
+// A thread keeps its elements of a run for every level (element
+// threadIdx.x + j NT is row e / S, value e mod S, S the run's longest
+// level), so a level costs it one test and two additions per element.
+struct RunLin {
+  int c0, r0, dc0, dr0, dc, dr, kc, kr, len0, dlen, R, sstride;
+};
+
+template <int KR>
+struct RunLanes {
+  int wi[KR];  // window index at level 0 (buffer-relative)
+  int pi[KR];  // panel index at level 0
+  int t[KR];   // value index along the run
+  bool ok[KR];
+};
+
+template <class S, int NT, int KR>
+__device__ __forceinline__ RunLanes<KR> run_lanes(const RunLin& q, int S_len, int P) {
+  constexpr int NV = S::NV;
+  RunLanes<KR> L;
+  const float inv = __builtin_amdgcn_rcpf((float)(S_len > 0 ? S_len : 1));
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const int e = (int)threadIdx.x + j * NT;
+    int vk, t;
+    fdivmod(e, S_len > 0 ? S_len : 1, inv, vk, t);
+    const int k = vk & 1, v = vk >> 1;
+    L.ok[j] = S_len > 0 && vk < 2 * NV;
+    L.t[j] = t;
+    L.wi[j] = v * P * P + (q.r0 + t * q.dr + k * q.kr) * P + q.c0 + t * q.dc + k * q.kc;
+    L.pi[j] = vk * q.R + t;
+  }
+  return L;
+}
+
+// Level l of up to four runs into registers (window positions -1: none).
+template <class S, int KR>
+__device__ __forceinline__ void lin_fetch(RectFetch<typename S::V, KR>& f, const RunLanes<KR> (&L)[4],
+                                          const RunLin (&q)[4], const typename S::V* const (&src)[4], int n, int l,
+                                          int P) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int len = q[r].len0 + l * q[r].dlen, dw = l * (q[r].dr0 * P + q[r].dc0);
+    const typename S::V* sp = src[r] + (long long)l * q[r].sstride;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      f.wi[r][j] = -1;
+      if (r < n && L[r].ok[j] && L[r].t[j] < len) {
+        f.wi[r][j] = L[r].wi[j] + dw;
+        f.val[r][j] = sp[L[r].pi[j]];
+      }
+    }
+  }
+}
+
+// Level l of one run, window -> panel.
+template <class S, int KR>
+__device__ __forceinline__ void lin_emit(const typename S::V* __restrict__ win, const RunLanes<KR>& L, const RunLin& q,
+                                         typename S::V* __restrict__ dst, int l, int P) {
+  const int len = q.len0 + l * q.dlen, dw = l * (q.dr0 * P + q.dc0);
+  typename S::V* dp = dst + (long long)l * q.sstride;
+#pragma unroll
+  for (int j = 0; j < KR; ++j)
+    if (L.ok[j] && L.t[j] < len) dp[L.pi[j]] = win[L.wi[j] + dw];
+}
+
 struct RectRuns {
   int n;
   RectRun q[4];
   const void* src[4];
   int R[4];
 };
-
-template <class S, int NT, int KR>
-__device__ __forceinline__ bool rect_runs_fit(const RectRuns& rs) {
-  bool ok = true;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (r < rs.n) ok = ok && 2 * S::NV * rs.q[r].len <= KR * NT;
-  return ok;
-}
-
-template <class S, int NT, int KR>
-__device__ __forceinline__ void rect_fetch(RectFetch<typename S::V, KR>& f, const RectRuns& rs, int P) {
-  using V = typename S::V;
-  constexpr int NV = S::NV;
-  const int plane = P * P;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const RectRun& q = rs.q[r];
-    const float inv = __builtin_amdgcn_rcpf((float)(q.len > 0 ? q.len : 1));
-#pragma unroll
-    for (int j = 0; j < KR; ++j) {
-      f.wi[r][j] = -1;
-      const int e = (int)threadIdx.x + j * NT;
-      if (r < rs.n && e < 2 * NV * q.len) {
-        int vk, t;
-        fdivmod(e, q.len, inv, vk, t);
-        const int k = vk & 1, v = vk >> 1;
-        f.wi[r][j] = v * plane + (q.r0 + t * q.dr + k * q.kr) * P + q.c0 + t * q.dc + k * q.kc;
-        f.val[r][j] = static_cast<const V*>(rs.src[r])[vk * rs.R[r] + t];
-      }
-    }
-  }
-}
 
 template <class S, int KR>
 __device__ __forceinline__ void rect_place(const RectFetch<typename S::V, KR>& f, typename S::V* __restrict__ win) {
@@ -277,18 +313,22 @@ __device__ __forceinline__ void rect_oct_item(const RGeo& g, int upar, int Hd, i
     // Each level's ring is fetched during the level before and placed at
     // the start of its own (beside the square it surrounds).
     constexpr int KR = rect_kr<S, WC, NT>();
+    const RunLin rq[4] = {{cE - 2, cF - 1, -1, -1, 1, 0, 0, -1, 4, 2, Rx, 2 * NV * Rx},
+                          {cE - 2, cF, -1, 1, 1, 0, 0, 1, 4, 2, Rx, 2 * NV * Rx},
+                          {cE - 1, cF, -1, -1, 0, 1, -1, 0, 0, 2, Ry, 2 * NV * Ry},
+                          {cE, cF, 1, -1, 0, 1, 1, 0, 0, 2, Ry, 2 * NV * Ry}};
+    const V* const rsrc[4] = {xb + rect_xb_at(g, NV, tN, 1, 0), xb + rect_xb_at(g, NV, tS, 0, 0),
+                              yb + rect_yb_at(g, NV, tN, 1, 0), yb + rect_yb_at(g, NV, tE, 0, 0)};
+    const int Smax = 2 * Hd + 2;
+    const RunLanes<KR> rl[4] = {run_lanes<S, NT, KR>(rq[0], Smax, P), run_lanes<S, NT, KR>(rq[1], Smax, P),
+                                run_lanes<S, NT, KR>(rq[2], Smax, P), run_lanes<S, NT, KR>(rq[3], Smax, P)};
     RectFetch<V, KR> f;
-    bool ahead = Hd > 1 && rect_runs_fit<S, NT, KR>(ring(Hd - 1));
-    if (ahead) rect_fetch<S, NT, KR>(f, ring(1), P);
+    if (Hd > 1) lin_fetch<S, KR>(f, rl, rq, rsrc, 4, 1, P);
     __syncthreads();
     for (int l = 1; l <= Hd; ++l) {
       if (l < Hd) {
-        if (ahead) {
-          rect_place<S, KR>(f, buf(l));
-          if (l + 1 < Hd) rect_fetch<S, NT, KR>(f, ring(l + 1), P);
-        } else {
-          rect_copy_runs<S, NT>(buf(l), P, ring(l));
-        }
+        rect_place<S, KR>(f, buf(l));
+        if (l + 1 < Hd) lin_fetch<S, KR>(f, rl, rq, rsrc, 4, l + 1, P);
       }
       rect_level<S, WC, NT>(buf(l - 1), buf(l), P, cE - l, cF - l, 2 * l, 2 * l, base + l - 1, sp);
       __syncthreads();
@@ -307,16 +347,36 @@ __device__ __forceinline__ void rect_oct_item(const RGeo& g, int upar, int Hd, i
   }
   V* up = static_cast<V*>(pp.up);
   const int tile = item, R = g.urow;
-  for (int m = 1; m <= Hu; ++m) {
-    V* in = buf(Hd + m - 1);
-    rect_level<S, WC, NT>(in, buf(Hd + m), P, 1 + m, 1 + m, wx - 2 * m, wy - 2 * m, base + Hd + m - 1, sp);
-    // panels of level m - 1: rectangle [m-1, w-m] in tile cells
-    const int l = m - 1, lx = wx - 2 * l, ly = wy - 2 * l;
-    rect_copy<S, NT, true>(in, P, RectRun{m, m, 1, 0, 0, 1, lx}, up + rect_up_at(g, NV, tile, 0, l), R);
-    rect_copy<S, NT, true>(in, P, RectRun{m, wy - l, 1, 0, 0, -1, lx}, up + rect_up_at(g, NV, tile, 1, l), R);
-    rect_copy<S, NT, true>(in, P, RectRun{m, m, 0, 1, 1, 0, ly}, up + rect_up_at(g, NV, tile, 2, l), R);
-    rect_copy<S, NT, true>(in, P, RectRun{wx - l, m, 0, 1, -1, 0, ly}, up + rect_up_at(g, NV, tile, 3, l), R);
-    __syncthreads();
+  if constexpr (WC != 0) {
+    // the frustum's strips of level l (rectangle [l, w-1-l] in tile cells)
+    constexpr int KR = rect_kr<S, WC, NT>();
+    const int us = 2 * NV * R;
+    const RunLin uq[4] = {{1, 1, 1, 1, 1, 0, 0, 1, wx, -2, R, us}, {1, wy, 1, -1, 1, 0, 0, -1, wx, -2, R, us},
+                          {1, 1, 1, 1, 0, 1, 1, 0, wy, -2, R, us}, {wx, 1, -1, 1, 0, 1, -1, 0, wy, -2, R, us}};
+    const int Smax = wx > wy ? wx : wy;
+    const RunLanes<KR> ul[4] = {run_lanes<S, NT, KR>(uq[0], Smax, P), run_lanes<S, NT, KR>(uq[1], Smax, P),
+                                run_lanes<S, NT, KR>(uq[2], Smax, P), run_lanes<S, NT, KR>(uq[3], Smax, P)};
+    V* const ub[4] = {up + rect_up_at(g, NV, tile, 0, 0), up + rect_up_at(g, NV, tile, 1, 0),
+                      up + rect_up_at(g, NV, tile, 2, 0), up + rect_up_at(g, NV, tile, 3, 0)};
+    for (int m = 1; m <= Hu; ++m) {
+      V* in = buf(Hd + m - 1);
+      rect_level<S, WC, NT>(in, buf(Hd + m), P, 1 + m, 1 + m, wx - 2 * m, wy - 2 * m, base + Hd + m - 1, sp);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lin_emit<S, KR>(in, ul[r], uq[r], ub[r], m - 1, P);
+      __syncthreads();
+    }
+  } else {
+    for (int m = 1; m <= Hu; ++m) {
+      V* in = buf(Hd + m - 1);
+      rect_level<S, WC, NT>(in, buf(Hd + m), P, 1 + m, 1 + m, wx - 2 * m, wy - 2 * m, base + Hd + m - 1, sp);
+      // panels of level m - 1: rectangle [m-1, w-m] in tile cells
+      const int l = m - 1, lx = wx - 2 * l, ly = wy - 2 * l;
+      rect_copy<S, NT, true>(in, P, RectRun{m, m, 1, 0, 0, 1, lx}, up + rect_up_at(g, NV, tile, 0, l), R);
+      rect_copy<S, NT, true>(in, P, RectRun{m, wy - l, 1, 0, 0, -1, lx}, up + rect_up_at(g, NV, tile, 1, l), R);
+      rect_copy<S, NT, true>(in, P, RectRun{m, m, 0, 1, 1, 0, ly}, up + rect_up_at(g, NV, tile, 2, l), R);
+      rect_copy<S, NT, true>(in, P, RectRun{wx - l, m, 0, 1, -1, 0, ly}, up + rect_up_at(g, NV, tile, 3, l), R);
+      __syncthreads();
+    }
   }
   rect_move<S, NT, false>(buf(Hd + Hu), P, state, nx, ny, 1 + Hu, 1 + Hu, wx - 2 * Hu, wy - 2 * Hu, sx - 1, sy - 1,
                       0, 0, 0);
@@ -371,40 +431,70 @@ __device__ __forceinline__ void rect_bridge_item(const RGeo& g, int par, int H, 
     return isx ? rect_xb_at(g, NV, e, end, l) : rect_yb_at(g, NV, e, end, l);
   };
   rect_copy_runs<S, NT>(buf(0), P, strips(0));
-  // At the fixed pitches each level's strips are fetched during the level
-  // before and placed at the start of their own.
-  constexpr int KR = rect_kr<S, WC, NT>();
-  RectFetch<V, KR> f;
-  const bool ahead = WC != 0 && H > 1 && rect_runs_fit<S, NT, KR>(strips(0));
-  if (ahead) rect_fetch<S, NT, KR>(f, strips(1), P);
-  __syncthreads();
-  for (int l = 1; l <= H; ++l) {
-    const V* in = buf(l - 1);
-    if (l < H) {
-      if (ahead) {
-        rect_place<S, KR>(f, buf(l));
-        if (l + 1 < H) rect_fetch<S, NT, KR>(f, strips(l + 1), P);
-      } else {
-        rect_copy_runs<S, NT>(buf(l), P, strips(l));
-      }
-    }
-    if (isx)
-      rect_level<S, WC, NT>(in, buf(l), P, H + 1 - l, l, 2 * l, wal - 2 * l, base + l - 1, sp);
-    else
-      rect_level<S, WC, NT>(in, buf(l), P, l, H + 1 - l, wal - 2 * l, 2 * l, base + l - 1, sp);
+  if constexpr (WC != 0) {
+    // Each level's strips are fetched during the level before and placed at
+    // the start of their own; the runs are described once for all levels.
+    constexpr int KR = rect_kr<S, WC, NT>();
+    const int ss = 2 * NV * R;
+    const RunLin sq[4] = {isx ? RunLin{H, 0, -1, 1, 0, 1, -1, 0, wal, -2, R, ss} : RunLin{0, H, 1, -1, 1, 0, 0, -1, wal, -2, R, ss},
+                          isx ? RunLin{H + 1, 0, 1, 1, 0, 1, 1, 0, wal, -2, R, ss}
+                              : RunLin{0, H + 1, 1, 1, 1, 0, 0, 1, wal, -2, R, ss},
+                          RunLin{}, RunLin{}};
+    const V* const ssrc[4] = {up + rect_up_at(g, NV, tnear, enear, 0), up + rect_up_at(g, NV, tfar, efar, 0), nullptr,
+                              nullptr};
+    const RunLanes<KR> sl[4] = {run_lanes<S, NT, KR>(sq[0], wal, P), run_lanes<S, NT, KR>(sq[1], wal, P),
+                                RunLanes<KR>{}, RunLanes<KR>{}};
+    RectFetch<V, KR> f;
+    if (H > 1) lin_fetch<S, KR>(f, sl, sq, ssrc, 2, 1, P);
     __syncthreads();
-  }
-  // The ends of every level m, stored once all levels are done (their cells
-  // stay untouched in buffer m mod 2: later levels of that parity write
-  // only inside them), so that no level waits for panel stores before it
-  // places its prefetched strips: rows (x-bridge) or columns (y-bridge) m,
-  // m+1 and wal-1-m, wal-2-m of the tile; across, the x-bridge's run covers
-  // its band and the frustum corners, the y-bridge's its band only.
-  for (int m = 0; m < H; ++m) {
-    V* in = buf(m);
-    const int ac0 = isx ? H - m - 1 : H + 1 - m, len = isx ? 2 * m + 4 : 2 * m;
-    rect_copy<S, NT, true>(in, P, run(ac0, m, 1, 0, 0, 1, len), out + at(0, m), Ro);
-    rect_copy<S, NT, true>(in, P, run(ac0, wal - 1 - m, 1, 0, 0, -1, len), out + at(1, m), Ro);
+    for (int l = 1; l <= H; ++l) {
+      const V* in = buf(l - 1);
+      if (l < H) {
+        rect_place<S, KR>(f, buf(l));
+        if (l + 1 < H) lin_fetch<S, KR>(f, sl, sq, ssrc, 2, l + 1, P);
+      }
+      if (isx)
+        rect_level<S, WC, NT>(in, buf(l), P, H + 1 - l, l, 2 * l, wal - 2 * l, base + l - 1, sp);
+      else
+        rect_level<S, WC, NT>(in, buf(l), P, l, H + 1 - l, wal - 2 * l, 2 * l, base + l - 1, sp);
+      __syncthreads();
+    }
+    // The ends of every level m, stored once all levels are done (their
+    // cells stay untouched in buffer m mod 2: later levels of that parity
+    // write only inside them), so that no level waits for panel stores
+    // before it places its prefetched strips: rows (x-bridge) or columns
+    // (y-bridge) m, m+1 and wal-1-m, wal-2-m of the tile; across, the
+    // x-bridge's run covers its band and the frustum corners, the y-bridge's
+    // its band only.
+    const int os = 2 * NV * Ro;
+    const RunLin eq[2] = {isx ? RunLin{H - 1, 0, -1, 1, 1, 0, 0, 1, 4, 2, Ro, os}
+                              : RunLin{0, H + 1, 1, -1, 0, 1, 1, 0, 0, 2, Ro, os},
+                          isx ? RunLin{H - 1, wal - 1, -1, -1, 1, 0, 0, -1, 4, 2, Ro, os}
+                              : RunLin{wal - 1, H + 1, -1, -1, 0, 1, -1, 0, 0, 2, Ro, os}};
+    const RunLanes<KR> el[2] = {run_lanes<S, NT, KR>(eq[0], 2 * H + 2, P), run_lanes<S, NT, KR>(eq[1], 2 * H + 2, P)};
+    V* const eb[2] = {out + at(0, 0), out + at(1, 0)};
+    for (int m = 0; m < H; ++m) {
+      lin_emit<S, KR>(buf(m), el[0], eq[0], eb[0], m, P);
+      lin_emit<S, KR>(buf(m), el[1], eq[1], eb[1], m, P);
+    }
+  } else {
+    __syncthreads();
+    for (int l = 1; l <= H; ++l) {
+      const V* in = buf(l - 1);
+      if (l < H) rect_copy_runs<S, NT>(buf(l), P, strips(l));
+      if (isx)
+        rect_level<S, WC, NT>(in, buf(l), P, H + 1 - l, l, 2 * l, wal - 2 * l, base + l - 1, sp);
+      else
+        rect_level<S, WC, NT>(in, buf(l), P, l, H + 1 - l, wal - 2 * l, 2 * l, base + l - 1, sp);
+      __syncthreads();
+    }
+    // The ends of every level m, stored once all levels are done (as above).
+    for (int m = 0; m < H; ++m) {
+      V* in = buf(m);
+      const int ac0 = isx ? H - m - 1 : H + 1 - m, len = isx ? 2 * m + 4 : 2 * m;
+      rect_copy<S, NT, true>(in, P, run(ac0, m, 1, 0, 0, 1, len), out + at(0, m), Ro);
+      rect_copy<S, NT, true>(in, P, run(ac0, wal - 1 - m, 1, 0, 0, -1, len), out + at(1, m), Ro);
+    }
   }
   // the band at level H: across [1, 2H + 1), along [H, wal - H)
   if (isx) {
