@@ -179,7 +179,8 @@ def other_workloads(sw, si, np):
     """Throughput of the other workloads at their full sizes over a bounded
     number of steps (the step counts of their parity tests are longer), with
     the FP32 forms' normwise error against the FP64 result of the same run:
-    the wave 2048^2 and Euler 512^2 grids (swept) and the uneven 256-grid
+    the wave 2048^2 and Euler 512^2 grids (swept), heat on 8192^2 (state
+    beyond the Infinity Cache: swept and per-step) and the uneven 256-grid
     batches (phased launches, model tile sides)."""
     out = {}
 
@@ -230,13 +231,36 @@ def other_workloads(sw, si, np):
             g.upload(s_e)
             return g
         v, tile, _ = rate(mk, 500, 512 * 512)
-        rec = {"value": v, "unit": "point-updates/s (full RK2 steps)", "steps": 500, "tile": tile}
+        rec = {"value": v, "unit": "point-updates/s (full RK2 steps)", "substep_value": 2 * v,
+               "steps": 500, "tile": tile}
         res = final_state(mk, EULER_STEPS)
         if ref is None:
             ref = res
         else:
             rec[f"error_vs_fp64_after_{EULER_STEPS}_steps"] = normwise(res[:4], ref[:4])
         out[f"euler512_{name}"] = rec
+    # Heat 8192^2 FP64 (512 MB of state, beyond the 256 MB Infinity Cache):
+    # the per-step kernel's traffic goes to HBM, with the swept rule beside it.
+    s_h = si.heat_field(8192, 8192, seed=0)
+    p_h = si.default_params(si.HEAT5)
+    big = {}
+    for method in ("swept", "plain"):
+        g = sw.Swept2D(8192, 8192, si.HEAT5, p_h)
+        g.upload(s_h)
+        run = g.advance if method == "swept" else g.plain_advance
+        run(64)
+        g.synchronize()
+        t0 = time.perf_counter()
+        run(256)
+        g.synchronize()
+        dt = time.perf_counter() - t0
+        big[method] = 8192 * 8192 * 256 / dt
+        big["tile"] = g.tile
+        g.close()
+    out["heat8192_fp64"] = {"swept_value": big["swept"], "plain_value": big["plain"], "unit": "point-updates/s",
+                            "steps": 256, "tile": big["tile"], "swept_over_plain": big["swept"] / big["plain"],
+                            "plain_algorithmic_hbm_GBs": big["plain"] * 16 / 1e9,
+                            "note": "512 MB state: the per-step kernel's 16 B per point-update go to HBM"}
     for quantum, steps, key in ((16, BATCH_STEPS, "batch256"), (1, BATCH_LITERAL_STEPS, "batch256_literal")):
         specs = si.batch_specs(256, seed=0, quantum=quantum)
         grids = [dict(nx=b["nx"], ny=b["ny"], pde=b["pde"], prec=b["prec"], params=list(si.default_params(b["pde"])))
