@@ -49,7 +49,7 @@ extern "C" {
 #define SWEPT2D_EINVAL (-1)       /* bad argument: sizes, ids, tile, null handle */
 #define SWEPT2D_EHIP (-2)         /* HIP runtime error; message carries hipGetErrorString */
 #define SWEPT2D_ENOMEM (-3)       /* device allocation failed */
-#define SWEPT2D_EUNSUPPORTED (-4) /* valid request this build does not provide */
+#define SWEPT2D_EUNSUPPORTED (-4) /* valid request the library does not provide */
 #define SWEPT2D_EABORTED (-5)     /* a persistent batch kernel stopped: a dependency wait hit its limit */
 
 /* ------------------------------------------------------------- scheme ids

@@ -141,13 +141,14 @@ def main(argv):
             fo.write("# HBM traffic per launch of the heat 1024x1024 FP64 kernels (tile 64): k_oct<Heat64,66,1024,false>\n"
                      "# (downward pyramid + next upward pyramid), k_bridge_pair<Heat64,66,512,false>, k_up<Heat64,66,1024>\n"
                      "# and the per-step kernel k_plain_cols<Heat64,2>, from bench.py --profile-pass\n"
-                     "# Commands (from the repository root, one MI355X; each counter in a run of its own):\n"
-                     "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/pmc_fetch -o fetch -- "
+                     "# Commands (from the repository root, one MI355X; each counter in a run of its own; OUTDIR is any\n"
+                     "# scratch directory):\n"
+                     "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUTDIR/pmc_fetch -o fetch -- "
                      "python3 bench.py --profile-pass\n"
-                     "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/pmc_write -o write -- "
+                     "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUTDIR/pmc_write -o write -- "
                      "python3 bench.py --profile-pass\n"
-                     "#   python3 -m paper_1602_07558_amd.profiling traffic gpurun_out/prof/pmc_fetch "
-                     "gpurun_out/prof/pmc_write OUT\n"
+                     "#   python3 -m paper_1602_07558_amd.profiling traffic OUTDIR/pmc_fetch "
+                     "OUTDIR/pmc_write OUT\n"
                      "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the ratio of the known bytes "
                      "(64 MiB) of the\n# torch copy that --profile-pass runs to what the same counter reads for that "
                      "copy (fetch_scale, write_scale).\n")
