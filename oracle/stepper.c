@@ -43,11 +43,12 @@
 #define PDE_HEAT5 1
 #define PDE_WAVE_LF 2
 #define PDE_EULER_RUS_RK2 3
+#define PDE_EULER_FD_RK4 4
 #define PDE_TEST_HASH 100
 #define PDE_TEST_INCR 101
 #define PDE_TEST_PUSH5 102
 
-#define MAXV 8
+#define MAXV 12
 
 /* ---------------------------------------------------------------- FP64 */
 
@@ -201,12 +202,93 @@ static void st_euler(long long T, const double nb[9][MAXV], double *out, const d
     }
 }
 
+/* Euler in the paper's own discretisation (Sec. 8): conservative,
+ * skew-symmetric central finite differences and a four-stage Runge-Kutta
+ * step. The split (skew-symmetric) form of a convective derivative
+ * d(m phi)/dx, with m the mass flux component and phi in {1, u, v, H},
+ * H = (E + p) / rho, is half the sum of d(m phi), m d(phi) and phi d(m).
+ * With central differences it is conservative: it equals the difference of
+ * the face fluxes (m_L + m_R)(phi_L + phi_R) / 4; the pressure term takes
+ * (p_L + p_R) / 2 on the face. Points are (rho, mx, my, E). */
+static void eulerfd_prim(const double *U, double gamma, double *u, double *v, double *p, double *H)
+{
+    double rho = U[0], mx = U[1], my = U[2], en = U[3];
+    *u = mx / rho;
+    *v = my / rho;
+    *p = (gamma - 1.0) * (en - 0.5 * ((mx * mx + my * my) / rho));
+    *H = (en + *p) / rho;
+}
+
+/* Face flux between the left / lower point L and the right / upper point R
+ * along d (0 = x, 1 = y), arguments always in (left, right) order. */
+static void eulerfd_face(const double *L, const double *R, int d, double gamma, double *F)
+{
+    double uL, vL, pL, HL, uR, vR, pR, HR;
+    eulerfd_prim(L, gamma, &uL, &vL, &pL, &HL);
+    eulerfd_prim(R, gamma, &uR, &vR, &pR, &HR);
+    double a = 0.25 * (L[1 + d] + R[1 + d]);
+    double pf = 0.5 * (pL + pR);
+    F[0] = 2.0 * a;
+    if (d == 0) {
+        F[1] = a * (uL + uR) + pf;
+        F[2] = a * (vL + vR);
+    } else {
+        F[1] = a * (uL + uR);
+        F[2] = a * (vL + vR) + pf;
+    }
+    F[3] = a * (HL + HR);
+}
+
+/* The classical four-stage Runge-Kutta step as four sub-steps on the stage
+ * values Y (slots 4..7): sub-step s forms r = h div F(Y) at the point (so
+ * that dt L(Y) = -(dt/h) r) and, with U^n in slots 0..3 and the sum of the
+ * stage derivatives K (slots 8..11, in units of -r):
+ *   s = 0: K = -r;        Y = U - (dt/2h) r
+ *   s = 1: K = K - 2 r;   Y = U - (dt/2h) r
+ *   s = 2: K = K - 2 r;   Y = U - (dt/h) r
+ *   s = 3: U = U + (dt/6h) (K - r);  Y = U;  K = 0
+ * A state enters with Y = U and K = 0. Parameters: gamma, dt/h. */
+static void st_eulerfd(long long T, const double nb[9][MAXV], double *out, const double *prm)
+{
+    double gamma = prm[0], dth = prm[1];
+    const double *C = nb[4];
+    double Fw[4], Fe[4], Gn[4], Gs[4];
+    eulerfd_face(nb[3] + 4, C + 4, 0, gamma, Fw);
+    eulerfd_face(C + 4, nb[5] + 4, 0, gamma, Fe);
+    eulerfd_face(nb[1] + 4, C + 4, 1, gamma, Gn);
+    eulerfd_face(C + 4, nb[7] + 4, 1, gamma, Gs);
+    int s = (int)(T & 3);
+    for (int k = 0; k < 4; ++k) {
+        double r = (Fe[k] - Fw[k]) + (Gs[k] - Gn[k]);
+        double U = C[k], K = C[8 + k];
+        if (s == 0) {
+            out[k] = U;
+            out[8 + k] = -r;
+            out[4 + k] = U - (0.5 * dth) * r;
+        } else if (s == 1) {
+            out[k] = U;
+            out[8 + k] = K - 2.0 * r;
+            out[4 + k] = U - (0.5 * dth) * r;
+        } else if (s == 2) {
+            out[k] = U;
+            out[8 + k] = K - 2.0 * r;
+            out[4 + k] = U - dth * r;
+        } else {
+            double v = U + (dth / 6.0) * (K - r);
+            out[k] = v;
+            out[4 + k] = v;
+            out[8 + k] = 0.0;
+        }
+    }
+}
+
 static int pde_shape_ok(int pde, int nvars)
 {
     switch (pde) {
     case PDE_HEAT5: return nvars == 1;
     case PDE_WAVE_LF: return nvars == 2;
     case PDE_EULER_RUS_RK2: return nvars == 8;
+    case PDE_EULER_FD_RK4: return nvars == 12;
     case PDE_TEST_HASH: return nvars == 1;
     case PDE_TEST_INCR: return nvars == 1;
     case PDE_TEST_PUSH5: return nvars == 5;
@@ -220,6 +302,7 @@ static int nparams_needed(int pde)
     case PDE_HEAT5: return 1;
     case PDE_WAVE_LF: return 1;
     case PDE_EULER_RUS_RK2: return 2;
+    case PDE_EULER_FD_RK4: return 2;
     default: return 0;
     }
 }
@@ -259,6 +342,7 @@ int oracle_advance_f64(int pde, int nx, int ny, int nvars, const double *params,
                 case PDE_HEAT5: st_heat(nb, out, params); break;
                 case PDE_WAVE_LF: st_wave(nb, out, params); break;
                 case PDE_EULER_RUS_RK2: st_euler(T, nb, out, params); break;
+                case PDE_EULER_FD_RK4: st_eulerfd(T, nb, out, params); break;
                 case PDE_TEST_HASH: st_hash(T, nb, out); break;
                 case PDE_TEST_INCR: st_incr(nb, out); break;
                 case PDE_TEST_PUSH5: st_push5(T, nb, out); break;

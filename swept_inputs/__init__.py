@@ -21,6 +21,11 @@ with the shapes of those workloads):
 * euler: 4 isentropic vortices (strength beta = 5) on a uniform flow
   rho = 1, p = 1, (u, v) = (1, 1), on a periodic square of side 20, vortex
   centres drawn with minimum-image separation of at least a quarter side.
+* euler_fd: the paper's wind-tunnel free stream (rho = 1.084, Mach 0.2 along
+  x, v = 0, p = 101325, cells of 50/1024 on both axes) with a seeded
+  isentropic pressure pulse of 1 % (Gaussian, width 16 cells) in place of
+  the obstacle; slots 4..7 (the Runge-Kutta stage) start as a copy of the
+  conserved variables, slots 8..11 at zero.
 * hash: uniform random integers in [0, 2^52) stored exactly as doubles.
 * incr: constant field (the paper's worked example starts at value 1).
 * push5: random small integers in slot 0, zeros in slots 1..4.
@@ -35,6 +40,7 @@ import numpy as np
 HEAT5 = 1
 WAVE_LF = 2
 EULER_RUS_RK2 = 3
+EULER_FD_RK4 = 4
 TEST_HASH = 100
 TEST_INCR = 101
 TEST_PUSH5 = 102
@@ -44,6 +50,7 @@ PDE_NAMES = {
     HEAT5: "heat5",
     WAVE_LF: "wave_lf",
     EULER_RUS_RK2: "euler_rus_rk2",
+    EULER_FD_RK4: "euler_fd_rk4",
     TEST_HASH: "test_hash",
     TEST_INCR: "test_incr",
     TEST_PUSH5: "test_push5",
@@ -55,6 +62,7 @@ PDE_SHAPE = {
     HEAT5: (1, 1),
     WAVE_LF: (2, 1),
     EULER_RUS_RK2: (8, 2),
+    EULER_FD_RK4: (12, 4),
     TEST_HASH: (1, 1),
     TEST_INCR: (1, 1),
     TEST_PUSH5: (5, 2),
@@ -67,6 +75,13 @@ EULER_GAMMA = 1.4
 EULER_CFL = 0.4
 EULER_SIDE = 20.0
 EULER_BETA = 5.0
+# The paper's Euler experiment (Sec. 8): a 50 x 25 tunnel on 1024 x 512
+# cells, dt = 1e-6, free stream rho = 1.084, Mach 0.2, v = 0, p = 101325.
+EULERFD_H = 50.0 / 1024.0
+EULERFD_DT = 1e-6
+EULERFD_RHO = 1.084
+EULERFD_MACH = 0.2
+EULERFD_P = 101325.0
 
 
 def default_params(pde: int, state: np.ndarray | None = None) -> np.ndarray:
@@ -79,6 +94,8 @@ def default_params(pde: int, state: np.ndarray | None = None) -> np.ndarray:
         if state is None:
             raise ValueError("euler parameters need the initial state for dt")
         return np.array([EULER_GAMMA, euler_dt_over_h(state)], dtype=np.float64)
+    if pde == EULER_FD_RK4:
+        return np.array([EULER_GAMMA, EULERFD_DT / EULERFD_H], dtype=np.float64)
     return np.zeros(0, dtype=np.float64)
 
 
@@ -165,6 +182,33 @@ def euler_field(nx: int, ny: int, seed: int = 0, vortices: int = 4) -> np.ndarra
     return np.concatenate([cons, cons.copy()]).copy()
 
 
+def eulerfd_conserved(rho, u, v, p, gamma: float = EULER_GAMMA) -> np.ndarray:
+    """(rho, rho u, rho v, E) from primitive fields."""
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def eulerfd_state(cons: np.ndarray) -> np.ndarray:
+    """The 12-slot state of the four-stage scheme from (rho, mx, my, E):
+    the stage slots a copy, the derivative sum zero."""
+    return np.concatenate([cons, cons.copy(), np.zeros_like(cons)]).copy()
+
+
+def eulerfd_field(nx: int, ny: int, seed: int = 0, amp: float = 0.01, width: float = 16.0) -> np.ndarray:
+    gamma = EULER_GAMMA
+    rng = np.random.default_rng(seed)
+    cx, cy = rng.uniform(0.0, nx), rng.uniform(0.0, ny)
+    i = np.arange(nx, dtype=np.float64)[None, :]
+    j = np.arange(ny, dtype=np.float64)[:, None]
+    dx = _min_image(i - cx, nx)
+    dy = _min_image(j - cy, ny)
+    c0 = math.sqrt(gamma * EULERFD_P / EULERFD_RHO)
+    p = EULERFD_P * (1.0 + amp * np.exp(-(dx * dx + dy * dy) / (2.0 * width * width)))
+    rho = EULERFD_RHO * (p / EULERFD_P) ** (1.0 / gamma)
+    u = np.full((ny, nx), EULERFD_MACH * c0)
+    v = np.zeros((ny, nx))
+    return eulerfd_state(eulerfd_conserved(rho, u, v, p, gamma))
+
+
 def euler_dt_over_h(state: np.ndarray, cfl: float = EULER_CFL, gamma: float = EULER_GAMMA) -> float:
     """Fixed time step from the initial field: dt = cfl / max((|u|+c)/h + (|v|+c)/h)
     on a square grid; returned as dt/h (the only combination the scheme uses)."""
@@ -209,6 +253,8 @@ def initial_state(pde: int, nx: int, ny: int, seed: int = 0) -> np.ndarray:
         return wave_field(nx, ny, seed)
     if pde == EULER_RUS_RK2:
         return euler_field(nx, ny, seed)
+    if pde == EULER_FD_RK4:
+        return eulerfd_field(nx, ny, seed)
     if pde == TEST_HASH:
         return hash_field(nx, ny, seed)
     if pde == TEST_INCR:

@@ -323,6 +323,140 @@ def test_euler_vortex_advects_with_the_flow():
 
 # ----------------------------------------------------------- test stencils
 
+# ------------------------------------------------- euler, central / rk4
+
+EFD = si.EULER_FD_RK4
+
+
+def _efd_state(rho, u, v, p, gamma=1.4):
+    return si.eulerfd_state(si.eulerfd_conserved(rho, u, v, p, gamma))
+
+
+def _efd_prim(s, gamma=1.4):
+    rho = s[0]
+    u, v = s[1] / rho, s[2] / rho
+    p = (gamma - 1.0) * (s[3] - 0.5 * (s[1] ** 2 + s[2] ** 2) / rho)
+    return np.stack([rho, u, v, p])
+
+
+def test_eulerfd_uniform_free_stream_preserved_bitwise():
+    """The paper's tunnel free stream: every face flux is the same, so no
+    sub-step changes a bit and the stage slots return to their entry values."""
+    s = si.eulerfd_state(si.eulerfd_conserved(*(np.full((10, 14), x) for x in (
+        si.EULERFD_RHO, si.EULERFD_MACH * math.sqrt(1.4 * si.EULERFD_P / si.EULERFD_RHO), 0.0, si.EULERFD_P))))
+    out = oracle.advance_f64(EFD, s, si.default_params(EFD), 4 * 5)
+    assert np.array_equal(out, s)
+
+
+def test_eulerfd_rest_with_uniform_pressure_is_steady_bitwise():
+    """At rest with uniform pressure every mass flux is zero and the pressure
+    terms cancel exactly, however the density varies (a stationary contact)."""
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.5, 2.0, (12, 16))
+    z = np.zeros_like(rho)
+    s = _efd_state(rho, z, z, np.full_like(rho, 0.8))
+    out = oracle.advance_f64(EFD, s, [1.4, 0.3], 4 * 7)
+    assert np.array_equal(out, s)
+
+
+def test_eulerfd_first_substep_is_the_split_form():
+    """Sub-step 0 leaves -r in the derivative slots, r = h div F. Written out
+    independently as the skew-symmetric split form of the convective terms,
+    per direction d with mass flux m = rho u_d and phi in (1, u, v, H):
+    r = sum_d 1/4 [D(m phi) + m D(phi) + phi D(m)] + 1/2 D(p) e_d,
+    D f = f(+1) - f(-1), a central difference (Sec. 8; the face-flux form
+    in the oracle is algebraically the same and conservative)."""
+    gamma = 1.4
+    rng = np.random.default_rng(11)
+    ny, nx = 9, 13
+    rho = rng.uniform(0.8, 1.3, (ny, nx))
+    u, v = rng.uniform(-0.4, 0.4, (2, ny, nx))
+    p = rng.uniform(0.6, 1.1, (ny, nx))
+    s = _efd_state(rho, u, v, p, gamma)
+    out = oracle.advance_f64(EFD, s, [gamma, 0.1], 1)
+    got = -out[8:12]
+    H = (s[3] + p) / rho
+
+    def D(f, ax):
+        return np.roll(f, -1, axis=ax) - np.roll(f, 1, axis=ax)
+
+    want = np.zeros((4, ny, nx))
+    scale = np.zeros((4, ny, nx))
+    for ax, m in ((1, s[1]), (0, s[2])):
+        for k, phi in enumerate((np.ones_like(rho), u, v, H)):
+            want[k] += 0.25 * (D(m * phi, ax) + m * D(phi, ax) + phi * D(m, ax))
+            scale[k] += np.abs(m * phi) + np.abs(m) + np.abs(phi)
+        want[2 if ax == 0 else 1] += 0.5 * D(p, ax)
+        scale[2 if ax == 0 else 1] += np.abs(p)
+    assert np.all(np.abs(got - want) <= 1e-14 * scale)
+    # the plain average flux (f_L + f_R) / 2 differs from the split form
+    plain = 0.5 * (D(s[1], 1) + D(s[2], 0))
+    assert np.allclose(got[0], plain, rtol=0, atol=1e-13)
+    plain_mx = 0.5 * (D(s[1] * u + p, 1) + D(s[2] * u, 0))
+    assert np.max(np.abs(got[1] - plain_mx)) > 1e-3
+
+
+def test_eulerfd_conservation_and_stage_slots():
+    s = si.eulerfd_field(48, 32, seed=2, amp=0.2, width=4.0)
+    out = oracle.advance_f64(EFD, s, [1.4, 2e-4], 4 * 30)
+    for k in range(4):
+        t0, t1 = float(np.sum(s[k])), float(np.sum(out[k]))
+        scale = float(np.sum(np.abs(s[1 if k == 2 else k])))  # my starts at zero: use mx's scale
+        assert abs(t1 - t0) <= 1e-14 * scale
+    assert not np.array_equal(out[:4], s[:4]) and np.max(np.abs(out[2])) > 1e-3 * np.max(np.abs(s[1]))
+    assert np.array_equal(out[4:8], out[:4]) and not np.any(out[8:])
+
+
+def test_eulerfd_transpose_symmetry_bitwise():
+    s = si.eulerfd_field(24, 24, seed=4, amp=0.1, width=3.0)
+    s[2] += 0.3 * s[0] * np.sin(np.arange(24) / 3.0)[:, None]
+    s[6] = s[2]
+    t = s.transpose(0, 2, 1).copy()
+    for a, b in ((1, 2), (5, 6), (9, 10)):
+        t[[a, b]] = t[[b, a]]
+    prm = [1.4, 1e-4]
+    a = oracle.advance_f64(EFD, s, prm, 4 * 3 + 2)
+    b = oracle.advance_f64(EFD, t, prm, 4 * 3 + 2)
+    b = b.transpose(0, 2, 1).copy()
+    for x, y in ((1, 2), (5, 6), (9, 10)):
+        b[[x, y]] = b[[y, x]]
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("family", ["acoustic+", "acoustic-", "entropy", "shear"])
+def test_eulerfd_linear_modes_rk4_amplification(family):
+    """Small modes on a uniform stream (rho = 1, u0 = 0.3, p = 1/gamma, so
+    c = 1). The face flux is a symmetric two-point flux, so linearised it is
+    A (U_L + U_R) / 2 and the semi-discrete operator on exp(i theta i) is
+    -(i sin(theta) / h) A: each characteristic family (eigenvalue u0 - c, u0,
+    u0, u0 + c of A) is multiplied per step by the four-stage Runge-Kutta
+    polynomial 1 + z + z^2/2 + z^3/6 + z^4/24, z = -i lambda sin(theta) dt/h.
+    The difference of the runs from +eps and -eps removes the even orders of
+    the nonlinearity."""
+    gamma, nx, ny, eps, dth, steps = 1.4, 32, 3, 1e-5, 0.8, 16
+    rho0, u0, p0 = 1.0, 0.3, 1.0 / gamma
+    c = 1.0
+    r, lam = {"acoustic+": ((1.0, 1.0, 0.0, 1.0), u0 + c), "acoustic-": ((1.0, -1.0, 0.0, 1.0), u0 - c),
+              "entropy": ((1.0, 0.0, 0.0, 0.0), u0), "shear": ((0.0, 0.0, 1.0, 0.0), u0)}[family]
+    theta = 2.0 * math.pi * 7 / nx
+    wave = np.cos(theta * np.arange(nx))[None, :] * np.ones((ny, 1))
+    base = [np.full((ny, nx), x) for x in (rho0, u0, 0.0, p0)]
+
+    def run(e):
+        w = [base[k] + e * r[k] * wave for k in range(4)]
+        return _efd_prim(oracle.advance_f64(EFD, _efd_state(*w, gamma), [gamma, dth], 4 * steps), gamma)
+
+    got = (run(eps) - run(-eps)) / (2.0 * eps)
+    z = complex(0.0, -lam * math.sin(theta) * dth)
+    g = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    want = np.real(g ** steps * np.exp(1j * theta * np.arange(nx)))
+    for k in range(4):
+        assert np.max(np.abs(got[k] - r[k] * want[None, :])) < 1e-8
+    # the bound separates the polynomial from its third-order truncation
+    g3 = 1 + z + z ** 2 / 2 + z ** 3 / 6
+    assert abs(g ** steps - g3 ** steps) > 1e-5
+
+
 def test_push5_two_substeps_equal_wide_stencil():
     """Eq. (2)-(3) reproduce Eq. (1) bit for bit (same values, same order)."""
     s = si.push5_field(24, 20, seed=7)
