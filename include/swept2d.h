@@ -62,6 +62,15 @@ extern "C" {
  *                         the Rusanov flux, two-stage SSP Runge-Kutta; slots
  *                         0..3 conserved (rho, rho u, rho v, E), 4..7 the
  *                         stage; params {gamma, dt/h}
+ *   EULER_FD_RK4  12 / 4 compressible Euler in the discretisation of Sec. 8:
+ *                         conservative skew-symmetric central differences
+ *                         (face flux (m_L + m_R)(phi_L + phi_R) / 4 for phi
+ *                         in {1, u, v, H}, pressure (p_L + p_R) / 2) and
+ *                         the classical four-stage Runge-Kutta method, one
+ *                         stage per sub-step; slots 0..3 conserved, 4..7
+ *                         the stage value (equal to 0..3 at full steps),
+ *                         8..11 the stage-derivative sum (zero at full
+ *                         steps); params {gamma, dt/h}. FP64 only.
  *   TEST_HASH      1 / 1  order-sensitive 64-bit mix of the 9 neighbours and
  *                         the sub-step index (values: integers < 2^52)
  *   TEST_INCR      1 / 1  u' = u + 1 if all 9 neighbours equal u, else NaN
@@ -79,6 +88,7 @@ extern "C" {
 #define SWEPT2D_HEAT5 1
 #define SWEPT2D_WAVE_LF 2
 #define SWEPT2D_EULER_RUS_RK2 3
+#define SWEPT2D_EULER_FD_RK4 4
 #define SWEPT2D_TEST_HASH 100
 #define SWEPT2D_TEST_INCR 101
 #define SWEPT2D_TEST_PUSH5 102

@@ -31,6 +31,7 @@ EABORTED = -5
 HEAT5 = 1
 WAVE_LF = 2
 EULER_RUS_RK2 = 3
+EULER_FD_RK4 = 4
 TEST_HASH = 100
 TEST_INCR = 101
 TEST_PUSH5 = 102
@@ -368,7 +369,7 @@ def swept2d_batch_launches(b: int, nsteps: int) -> int:
     return _check(load_library().swept2d_batch_launches(b, nsteps))
 
 
-PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), TEST_HASH: (1, 1),
+PDE_SHAPE = {HEAT5: (1, 1), WAVE_LF: (2, 1), EULER_RUS_RK2: (8, 2), EULER_FD_RK4: (12, 4), TEST_HASH: (1, 1),
              TEST_INCR: (1, 1), TEST_PUSH5: (5, 2), TEST_HASH25: (9, 2)}
 
 

@@ -121,6 +121,7 @@ enum Scheme : int {
   kHeat32R,
   kWave32R,
   kHash25x2,
+  kEulerFD64,
   kNumSchemes
 };
 

@@ -207,6 +207,22 @@ __device__ __forceinline__ void increment(const double* W, const double* E, cons
   }
 }
 
+// Column-walk hooks of the Rusanov schemes: a cell's face data along an
+// axis is its state, its physical flux and its signal speed (9 doubles).
+constexpr int kCellN = 9;
+__device__ __forceinline__ void cells(const double* C, double gamma, double* cx, double* cy) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    cx[k] = C[k];
+    cy[k] = C[k];
+  }
+  phys(C, 0, gamma, cx + 4, cx[8]);
+  phys(C, 1, gamma, cy + 4, cy[8]);
+}
+__device__ __forceinline__ void cell_face(const double* cL, const double* cR, double* F) {
+  face(cL + 4, cL[8], cL, cR + 4, cR[8], cR, F);
+}
+
 }  // namespace euler
 
 // Two-stage SSP Runge-Kutta as two sub-steps; slots 0..3 = U^n, 4..7 = U*.
@@ -217,14 +233,24 @@ struct Euler64 {
   static constexpr int NV = 8, NW = 8, NVAR = 8, SUB = 2;
   static constexpr bool XY_SYM = false;
   // Levels run by the column walk of the stage kernels, which computes each
-  // cell's physical fluxes once and each face flux once, through wload (the
-  // value of slot v at p) and finish (the cell's new slots from its own old
-  // slots at `own`, its stage values C and dt L(U) = du); the same
+  // cell's physical fluxes once and each face flux once; the same
   // expressions as step.
   static constexpr bool WALK = true;
+  static constexpr int CN = euler::kCellN;
+  __device__ __forceinline__ static int wstage(long long T) { return (T & 1) ? 4 : 0; }
   __device__ __forceinline__ static double wload(const V* p, int plane, int v) { return p[v * plane]; }
+  __device__ __forceinline__ static void wcells(const double* C, const SchemeParams& sp, double* cx, double* cy) {
+    euler::cells(C, sp.p[0], cx, cy);
+  }
+  __device__ __forceinline__ static void wface(const double* cL, const double* cR, int, const SchemeParams&,
+                                               double* F) {
+    euler::cell_face(cL, cR, F);
+  }
   __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double* C,
-                                                const double* du, V* dst) {
+                                                const double* div, const SchemeParams& sp, V* dst) {
+    double du[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) du[k] = -(sp.p[1] * div[k]);
     if ((T & 1) == 0) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -268,6 +294,137 @@ struct Euler64 {
         out[4 + k] = v;
       }
     }
+  }
+};
+
+// Compressible Euler in the paper's discretisation (Sec. 8): conservative,
+// skew-symmetric central differences and the classical four-stage
+// Runge-Kutta method. The split form of a convective derivative d(m phi)
+// (m the mass flux along the axis, phi in {1, u, v, H}, H = (E + p) / rho)
+// is half of d(m phi) + m d(phi) + phi d(m); with central differences it
+// equals the difference of the face fluxes (m_L + m_R)(phi_L + phi_R) / 4,
+// and the pressure enters as (p_L + p_R) / 2 on the face. Faces are taken
+// with (left/north, right/south) arguments.
+namespace eulerfd {
+
+struct Prim {
+  double u, v, p, H;
+};
+
+__device__ __forceinline__ Prim prim(const double* U, double gamma) {
+  const double rho = U[0], mx = U[1], my = U[2], en = U[3];
+  Prim q;
+  q.u = mx / rho;
+  q.v = my / rho;
+  q.p = (gamma - 1.0) * (en - 0.5 * ((mx * mx + my * my) / rho));
+  q.H = (en + q.p) / rho;
+  return q;
+}
+
+// Face flux along d between L and R from their mass fluxes mL, mR along d
+// and their primitives.
+__device__ __forceinline__ void face(double mL, const Prim& L, double mR, const Prim& R, int d, double* F) {
+  const double a = 0.25 * (mL + mR);
+  const double pf = 0.5 * (L.p + R.p);
+  F[0] = 2.0 * a;
+  if (d == 0) {
+    F[1] = a * (L.u + R.u) + pf;
+    F[2] = a * (L.v + R.v);
+  } else {
+    F[1] = a * (L.u + R.u);
+    F[2] = a * (L.v + R.v) + pf;
+  }
+  F[3] = a * (L.H + R.H);
+}
+
+}  // namespace eulerfd
+
+// The four-stage Runge-Kutta step as four sub-steps. Slots 0..3 = U^n,
+// 4..7 = the stage value Y the fluxes are taken from, 8..11 = the sum K of
+// the stage derivatives so far, in units of -r with r = h div F(Y). Sub-step
+// s: s = 0: K = -r, Y = U - (dt/2h) r; s = 1: K = K - 2r, Y = U - (dt/2h) r;
+// s = 2: K = K - 2r, Y = U - (dt/h) r; s = 3: U = Y = U + (dt/6h)(K - r),
+// K = 0. A state enters a step with Y = U and K = 0. Params {gamma, dt/h}.
+struct EulerFD64 {
+  using V = double;
+  static constexpr int NV = 12, NW = 12, NVAR = 12, SUB = 4;
+  static constexpr bool XY_SYM = false;
+  // Column walk (as Euler64): a cell's face data along an axis is its mass
+  // flux along that axis and its primitives (u, v, p, H), one set of
+  // divisions per cell.
+  static constexpr bool WALK = true;
+  static constexpr int CN = 5;
+  __device__ __forceinline__ static int wstage(long long) { return 4; }
+  __device__ __forceinline__ static double wload(const V* p, int plane, int v) { return p[v * plane]; }
+  __device__ __forceinline__ static void wcells(const double* C, const SchemeParams& sp, double* cx, double* cy) {
+    const eulerfd::Prim q = eulerfd::prim(C, sp.p[0]);
+    cx[0] = C[1];
+    cy[0] = C[2];
+    cx[1] = cy[1] = q.u;
+    cx[2] = cy[2] = q.v;
+    cx[3] = cy[3] = q.p;
+    cx[4] = cy[4] = q.H;
+  }
+  __device__ __forceinline__ static void wface(const double* cL, const double* cR, int d, const SchemeParams&,
+                                               double* F) {
+    eulerfd::face(cL[0], eulerfd::Prim{cL[1], cL[2], cL[3], cL[4]}, cR[0], eulerfd::Prim{cR[1], cR[2], cR[3], cR[4]},
+                  d, F);
+  }
+  __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double*,
+                                                const double* div, const SchemeParams& sp, V* dst) {
+    update(T, [&](int v) { return own[v * plane]; }, div, sp.p[1], dst, plane);
+  }
+  // The point's new slots from its old ones and r.
+  template <class OLD>
+  __device__ __forceinline__ static void update(long long T, const OLD& old, const double* r, double dth, V* out,
+                                                int stride) {
+    const int s = (int)(T & 3);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double U = old(k), K = old(8 + k);
+      if (s == 0) {
+        out[k * stride] = U;
+        out[(8 + k) * stride] = -r[k];
+        out[(4 + k) * stride] = U - (0.5 * dth) * r[k];
+      } else if (s == 1) {
+        out[k * stride] = U;
+        out[(8 + k) * stride] = K - 2.0 * r[k];
+        out[(4 + k) * stride] = U - (0.5 * dth) * r[k];
+      } else if (s == 2) {
+        out[k * stride] = U;
+        out[(8 + k) * stride] = K - 2.0 * r[k];
+        out[(4 + k) * stride] = U - dth * r[k];
+      } else {
+        const double v = U + (dth / 6.0) * (K - r[k]);
+        out[k * stride] = v;
+        out[(4 + k) * stride] = v;
+        out[(8 + k) * stride] = 0.0;
+      }
+    }
+  }
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
+    const double gamma = sp.p[0], dth = sp.p[1];
+    double W[4], E[4], N[4], S[4], C[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      W[k] = nb(-1, 0, 4 + k);
+      E[k] = nb(1, 0, 4 + k);
+      N[k] = nb(0, -1, 4 + k);
+      S[k] = nb(0, 1, 4 + k);
+      C[k] = nb(0, 0, 4 + k);
+    }
+    const eulerfd::Prim pw = eulerfd::prim(W, gamma), pe = eulerfd::prim(E, gamma);
+    const eulerfd::Prim pn = eulerfd::prim(N, gamma), ps = eulerfd::prim(S, gamma);
+    const eulerfd::Prim pc = eulerfd::prim(C, gamma);
+    double Fw[4], Fe[4], Gn[4], Gs[4], r[4];
+    eulerfd::face(W[1], pw, C[1], pc, 0, Fw);
+    eulerfd::face(C[1], pc, E[1], pe, 0, Fe);
+    eulerfd::face(N[2], pn, C[2], pc, 1, Gn);
+    eulerfd::face(C[2], pc, S[2], ps, 1, Gs);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = (Fe[k] - Fw[k]) + (Gs[k] - Gn[k]);
+    update(T, [&](int v) { return nb(0, 0, v); }, r, dth, out, 1);
   }
 };
 
@@ -333,11 +490,23 @@ struct Euler32C {
   static constexpr int NV = 16, NW = 16, NVAR = 8, SUB = 2;
   static constexpr bool XY_SYM = false;
   static constexpr bool WALK = true;  // as Euler64
+  static constexpr int CN = euler::kCellN;
+  __device__ __forceinline__ static int wstage(long long T) { return (T & 1) ? 4 : 0; }
   __device__ __forceinline__ static double wload(const V* p, int plane, int v) {
     return (double)p[v * plane] - (double)p[(8 + v) * plane];
   }
+  __device__ __forceinline__ static void wcells(const double* C, const SchemeParams& sp, double* cx, double* cy) {
+    euler::cells(C, sp.p[0], cx, cy);
+  }
+  __device__ __forceinline__ static void wface(const double* cL, const double* cR, int, const SchemeParams&,
+                                               double* F) {
+    euler::cell_face(cL, cR, F);
+  }
   __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double* C,
-                                                const double* du, V* dst) {
+                                                const double* div, const SchemeParams& sp, V* dst) {
+    double du[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) du[k] = -(sp.p[1] * div[k]);
     if ((T & 1) == 0) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {

@@ -480,37 +480,48 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
   }
 }
 
-// One Euler level over the rectangle [x0, x0+w) x [y0, y0+hg) as a column
-// walk. The rectangle is cut into segments of at most 30 columns (one or two
-// chunks across) by kWalkRows rows; a segment runs on cw + 2 consecutive
-// lanes of one wave (lane i on window column xa - 1 + i: the chunk's columns
-// and one on each side; lanes past them repeat the last one), as many
-// segments per wave as fit. Each lane walks its segment's rows with one row
-// above and below it. Per row a lane computes its cell's physical fluxes
-// along both axes once (the pressure, velocity and sound speed: four
-// divisions and a square root), takes the east lane's state and flux by a
-// DPP lane shift, forms the face flux between them, and passes it west by
-// another shift (the shifts cross segments only at their side lanes, which
-// store nothing); the face between consecutive rows is formed once as the
-// walk reaches the lower row. Every face flux is the same expression on the
-// same operands as in the per-point step (left/lower state first), so the
+// One level of a flux scheme (S::WALK: the Euler schemes) over the rectangle
+// [x0, x0+w) x [y0, y0+hg) as a column walk. The rectangle is cut into
+// segments of at most 30 columns (one or two chunks across) by kWalkRows
+// rows; a segment runs on cw + 2 consecutive lanes of one wave (lane i on
+// window column xa - 1 + i: the chunk's columns and one on each side; lanes
+// past them repeat the last one), as many segments per wave as fit. Each
+// lane walks its segment's rows with one row above and below it. Per row a
+// lane computes its cell's face data along both axes once (S::wcells: what
+// a face flux needs of one side, e.g. the pressure, velocities and sound
+// speed, with their divisions and square root), takes the east lane's by a
+// DPP lane shift, forms the face flux between them (S::wface), and passes it
+// west by another shift (the shifts cross segments only at their side
+// lanes, which store nothing); the face between consecutive rows is formed
+// once as the walk reaches the lower row. Every face flux is the same
+// expression on the same operands as in the per-point step (left/lower side
+// first), and the flux difference is summed in the step's order, so the
 // results are bit for bit the same. TR (transposed window, the x-bridge):
 // window rows run along x, so the walk is the x axis and the lanes the y
 // axis.
-// Rows per segment: one (measured on 512^2 Euler at tile side 32 in full RK2
-// steps per second: 1 row 1.27e10, 2 rows 1.23e10, 4 rows 9.6e9, 6 rows
-// 7.6e9). The levels are latency-bound at one 8-wave workgroup per CU (the
-// window fills the LDS), so independent lanes pay more than the flux work a
-// lane repeats for the rows above and below it.
+//
+// A WALK scheme provides: CN (doubles of face data per cell and axis),
+// wstage(T) (first slot of the four values the fluxes are taken from),
+// wload(p, plane, v) (slot v at p as a double), wcells(C, sp, cx, cy) (the
+// face data along x and y from those four values), wface(cL, cR, d, sp, F)
+// (the flux through the face along d between cells L and R), and
+// finish(T, own, plane, C, div, sp, dst) (the cell's new slots from its own
+// old slots at `own`, its four flux values C and div = h times the
+// divergence of the face fluxes, x terms first).
+//
+// Rows per segment: one (measured on 512^2 Rusanov Euler at tile side 32 in
+// full RK2 steps per second: 1 row 1.27e10, 2 rows 1.23e10, 4 rows 9.6e9,
+// 6 rows 7.6e9). The levels are latency-bound at one 8-wave workgroup per
+// CU (the window fills the LDS), so independent lanes pay more than the
+// flux work a lane repeats for the rows above and below it.
 constexpr int kWalkRows = 1;
 template <class S, int WC, int NT, bool TR>
-__device__ __forceinline__ void euler_walk(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
-                                           int Wrt, int x0, int y0, int w, int hg, long long T,
-                                           const SchemeParams& sp) {
-  constexpr int R = kWalkRows, NWv = NT / 64;
+__device__ __forceinline__ void flux_walk(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
+                                          int Wrt, int x0, int y0, int w, int hg, long long T,
+                                          const SchemeParams& sp) {
+  constexpr int R = kWalkRows, NWv = NT / 64, CN = S::CN;
   const int W = WC ? WC : Wrt, plane = W * W;
-  const double gamma = sp.p[0], dtoh = sp.p[1];
-  const int o = (T & 1) ? 4 : 0;
+  const int o = S::wstage(T);
   constexpr int dl = TR ? 1 : 0;  // axis along the lanes (window columns)
   constexpr int dw = TR ? 0 : 1;  // axis along the walk (window rows)
   if (w <= 0 || hg <= 0) return;
@@ -535,46 +546,40 @@ __device__ __forceinline__ void euler_walk(const typename S::V* __restrict__ in,
     const int ys = y0 + rs * R;
     const int ye = min(ys + R, y0 + hg);         // rows ys .. ye-1 are computed
     // Rows ys-1 .. ys+R (rows past ye repeat row ye and store nothing): all
-    // rows' physical fluxes first, independent of one another, then the
-    // faces, then the updates.
-    double C[R + 2][4], Fl[R + 2][4], al[R + 2], Fw_[R + 2][4], aw[R + 2];
+    // rows' face data first, independent of one another, then the faces,
+    // then the updates.
+    double C[R + 2][4], cx[R + 2][CN], cy[R + 2][CN];
 #pragma unroll
     for (int i = 0; i < R + 2; ++i) {
       const int r = min(ys - 1 + i, ye);
       const typename S::V* src = in + r * W + col;
 #pragma unroll
       for (int k = 0; k < 4; ++k) C[i][k] = S::wload(src, plane, o + k);
-      euler::phys(C[i], dl, gamma, Fl[i], al[i]);
-      euler::phys(C[i], dw, gamma, Fw_[i], aw[i]);
+      S::wcells(C[i], sp, cx[i], cy[i]);
     }
+    auto& cl = TR ? cy : cx;  // face data along the lanes
+    auto& cwk = TR ? cx : cy;  // face data along the walk
     double G[R + 1][4];  // G[i]: face between rows i and i+1 (walk axis)
 #pragma unroll
-    for (int i = 0; i < R + 1; ++i) euler::face(Fw_[i], aw[i], C[i], Fw_[i + 1], aw[i + 1], C[i + 1], G[i]);
+    for (int i = 0; i < R + 1; ++i) S::wface(cwk[i], cwk[i + 1], dw, sp, G[i]);
 #pragma unroll
     for (int i = 1; i <= R; ++i) {
       // faces along the lanes: with the east lane, then the west one's
       // passed over
-      double Ce[4], Fe_[4], FeL[4], FwL[4];
+      double ce[CN], FeL[4], FwL[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        Ce[k] = dpp_shift<false>(C[i][k]);
-        Fe_[k] = dpp_shift<false>(Fl[i][k]);
-      }
-      const double ae = dpp_shift<false>(al[i]);
-      euler::face(Fl[i], al[i], C[i], Fe_, ae, Ce, FeL);
+      for (int k = 0; k < CN; ++k) ce[k] = dpp_shift<false>(cl[i][k]);
+      S::wface(cl[i], ce, dl, sp, FeL);
 #pragma unroll
       for (int k = 0; k < 4; ++k) FwL[k] = dpp_shift<true>(FeL[k]);
-      double du[4];
+      double div[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double div = TR ? (G[i][k] - G[i - 1][k]) + (FeL[k] - FwL[k])
-                              : (FeL[k] - FwL[k]) + (G[i][k] - G[i - 1][k]);
-        du[k] = -(dtoh * div);
-      }
+      for (int k = 0; k < 4; ++k)
+        div[k] = TR ? (G[i][k] - G[i - 1][k]) + (FeL[k] - FwL[k]) : (FeL[k] - FwL[k]) + (G[i][k] - G[i - 1][k]);
       const int r = ys - 1 + i;
       if (store && r < ye) {
         const int q = r * W + col;
-        S::finish(T, in + q, plane, C[i], du, out + q);
+        S::finish(T, in + q, plane, C[i], div, sp, out + q);
       }
     }
   }
@@ -587,7 +592,7 @@ __device__ __forceinline__ void compute_level(const typename S::V* __restrict__ 
                                               int Wrt, int x0, int y0, int w, int hg, long long T,
                                               const SchemeParams& sp) {
   if constexpr (walks<S>::value) {
-    euler_walk<S, WC, NT, TR>(in, out, Wrt, x0, y0, w, hg, T, sp);
+    flux_walk<S, WC, NT, TR>(in, out, Wrt, x0, y0, w, hg, T, sp);
   } else if constexpr (Lay<S, WC, NT>::cols) {
     compute_cols<S, WC, NT, TR, !EDGE>(in, out, x0, y0, w, hg, T, sp);
   } else {

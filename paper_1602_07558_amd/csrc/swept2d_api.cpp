@@ -60,6 +60,7 @@ int pde_nvars(int pde) {
     case SWEPT2D_HEAT5: return 1;
     case SWEPT2D_WAVE_LF: return 2;
     case SWEPT2D_EULER_RUS_RK2: return 8;
+    case SWEPT2D_EULER_FD_RK4: return 12;
     case SWEPT2D_TEST_HASH: return 1;
     case SWEPT2D_TEST_INCR: return 1;
     case SWEPT2D_TEST_PUSH5: return 5;
@@ -74,6 +75,7 @@ int pde_substeps(int pde) {
     case SWEPT2D_EULER_RUS_RK2:
     case SWEPT2D_TEST_PUSH5:
     case SWEPT2D_TEST_HASH25: return 2;
+    case SWEPT2D_EULER_FD_RK4: return 4;
     default: return pde_nvars(pde) > 0 ? 1 : -1;
   }
 }
@@ -84,6 +86,7 @@ int pde_nparams(int pde) {
     case SWEPT2D_HEAT5: return 1;
     case SWEPT2D_WAVE_LF: return 1;
     case SWEPT2D_EULER_RUS_RK2: return 2;
+    case SWEPT2D_EULER_FD_RK4: return 2;
     default: return 0;
   }
 }
@@ -94,6 +97,7 @@ int scheme_of(int pde, int prec) {
       case SWEPT2D_HEAT5: return kHeat64;
       case SWEPT2D_WAVE_LF: return kWave64;
       case SWEPT2D_EULER_RUS_RK2: return kEuler64;
+      case SWEPT2D_EULER_FD_RK4: return kEulerFD64;
       case SWEPT2D_TEST_HASH: return kHash64;
       case SWEPT2D_TEST_INCR: return kIncr64;
       case SWEPT2D_TEST_PUSH5: return kPush5;
@@ -314,6 +318,7 @@ double scheme_cost(int scheme) {
   switch (scheme) {
     case kWave64: return 1.4;
     case kEuler64: return 30.0;
+    case kEulerFD64: return 60.0;
     case kHash64: return 3.0;
     case kPush5: return 2.5;
     case kHeat32C: return 1.5;
