@@ -179,9 +179,10 @@ def other_workloads(sw, si, np):
     """Throughput of the other workloads at their full sizes over a bounded
     number of steps (the step counts of their parity tests are longer), with
     the FP32 forms' normwise error against the FP64 result of the same run:
-    the wave 2048^2 and Euler 512^2 grids (swept), heat on 8192^2 (state
-    beyond the Infinity Cache: swept and per-step) and the uneven 256-grid
-    batches (phased launches, model tile sides)."""
+    the wave 2048^2 and Euler 512^2 grids (swept), the paper's Euler
+    discretisation on its 1024 x 512 tunnel (swept and per-step), heat on
+    8192^2 (state beyond the Infinity Cache: swept and per-step) and the
+    uneven 256-grid batches (phased launches, model tile sides)."""
     out = {}
 
     def rate(make, steps, pts):
@@ -239,6 +240,28 @@ def other_workloads(sw, si, np):
         else:
             rec[f"error_vs_fp64_after_{EULER_STEPS}_steps"] = normwise(res[:4], ref[:4])
         out[f"euler512_{name}"] = rec
+    # The paper's own Euler discretisation (skew-symmetric central
+    # differences, four-stage Runge-Kutta) on its 1024 x 512 tunnel grid.
+    s_f = si.initial_state(si.EULER_FD_RK4, 1024, 512, seed=0)
+    p_f = si.default_params(si.EULER_FD_RK4)
+    fd = {}
+    for method in ("swept", "plain"):
+        g = sw.Swept2D(1024, 512, si.EULER_FD_RK4, p_f)
+        g.upload(s_f)
+        run = g.advance if method == "swept" else g.plain_advance
+        run(20)
+        g.synchronize()
+        t0 = time.perf_counter()
+        run(200)
+        g.synchronize()
+        fd[method] = 1024 * 512 * 200 / (time.perf_counter() - t0)
+        fd["tile"] = g.tile
+        g.close()
+    out["euler_fd_tunnel1024x512_fp64"] = {
+        "swept_value": fd["swept"], "plain_value": fd["plain"], "unit": "point-updates/s (full RK4 steps)",
+        "swept_substep_value": 4 * fd["swept"], "steps": 200, "tile": fd["tile"],
+        "swept_over_plain": fd["swept"] / fd["plain"],
+        "note": "50 MB state (12 FP64 values per point) stays in the Infinity Cache; both paths latency-bound"}
     # Heat 8192^2 FP64 (512 MB of state, beyond the 256 MB Infinity Cache):
     # the per-step kernel's traffic goes to HBM, with the swept rule beside it.
     s_h = si.heat_field(8192, 8192, seed=0)

@@ -210,13 +210,16 @@ static void st_euler(long long T, const double nb[9][MAXV], double *out, const d
  * With central differences it is conservative: it equals the difference of
  * the face fluxes (m_L + m_R)(phi_L + phi_R) / 4; the pressure term takes
  * (p_L + p_R) / 2 on the face. Points are (rho, mx, my, E). */
+/* Primitives from (rho, mx, my, E) through one reciprocal of the density
+ * (the paper fixes no evaluation order; this is the order used here). */
 static void eulerfd_prim(const double *U, double gamma, double *u, double *v, double *p, double *H)
 {
     double rho = U[0], mx = U[1], my = U[2], en = U[3];
-    *u = mx / rho;
-    *v = my / rho;
-    *p = (gamma - 1.0) * (en - 0.5 * ((mx * mx + my * my) / rho));
-    *H = (en + *p) / rho;
+    double ri = 1.0 / rho;
+    *u = mx * ri;
+    *v = my * ri;
+    *p = (gamma - 1.0) * (en - 0.5 * ((mx * mx + my * my) * ri));
+    *H = (en + *p) * ri;
 }
 
 /* Face flux between the left / lower point L and the right / upper point R

@@ -311,13 +311,15 @@ struct Prim {
   double u, v, p, H;
 };
 
+// Primitives through one reciprocal of the density.
 __device__ __forceinline__ Prim prim(const double* U, double gamma) {
   const double rho = U[0], mx = U[1], my = U[2], en = U[3];
+  const double ri = 1.0 / rho;
   Prim q;
-  q.u = mx / rho;
-  q.v = my / rho;
-  q.p = (gamma - 1.0) * (en - 0.5 * ((mx * mx + my * my) / rho));
-  q.H = (en + q.p) / rho;
+  q.u = mx * ri;
+  q.v = my * ri;
+  q.p = (gamma - 1.0) * (en - 0.5 * ((mx * mx + my * my) * ri));
+  q.H = (en + q.p) * ri;
   return q;
 }
 

@@ -509,11 +509,12 @@ __device__ __forceinline__ void compute_cols(const typename S::V* __restrict__ i
 // old slots at `own`, its four flux values C and div = h times the
 // divergence of the face fluxes, x terms first).
 //
-// Rows per segment: one (measured on 512^2 Rusanov Euler at tile side 32 in
-// full RK2 steps per second: 1 row 1.27e10, 2 rows 1.23e10, 4 rows 9.6e9,
-// 6 rows 7.6e9). The levels are latency-bound at one 8-wave workgroup per
-// CU (the window fills the LDS), so independent lanes pay more than the
-// flux work a lane repeats for the rows above and below it.
+// Rows per segment: one. The levels are latency-bound, so independent lanes
+// pay more than the flux work a lane repeats for the rows above and below
+// it. Measured with 1, 2 and 4 rows: Rusanov Euler on 512^2 at tile side 32
+// (one 8-wave workgroup per CU), full RK2 steps per second 1.27e10, 1.23e10,
+// 9.6e9 (6 rows 7.6e9); the 12-value Euler on 1024 x 512 at tile side 16,
+// full RK4 steps 3.32e9, 2.83e9, 1.20e9.
 constexpr int kWalkRows = 1;
 template <class S, int WC, int NT, bool TR>
 __device__ __forceinline__ void flux_walk(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
