@@ -40,7 +40,8 @@ __device__ __forceinline__ int rect_wrap(int x, int L) { return x < 0 ? x + L : 
 // gets sub-step T from `in` into `out`. At pitch 66 the column layout takes
 // its side neighbours by lane shifts where the rectangle lies within window
 // columns 2..63, and from LDS otherwise; at pitch 34 one point per thread;
-// at a run-time pitch one point per thread as well.
+// at a run-time pitch the flux schemes walk columns and the others take one
+// point per thread.
 template <class S, int WC, int NT>
 __device__ __forceinline__ void rect_level(const typename S::V* __restrict__ in, typename S::V* __restrict__ out,
                                            int P, int x0, int y0, int w, int hg, long long T, const SchemeParams& sp) {
@@ -55,6 +56,11 @@ __device__ __forceinline__ void rect_level(const typename S::V* __restrict__ in,
     return;
   } else if constexpr (WC == 34) {
     compute_level<S, 34, NT, false>(in, out, 34, x0, y0, w, hg, T, sp);
+    return;
+  } else if constexpr (walks<S>::value) {
+    // the flux schemes' column walk at the run-time pitch (their tiles are
+    // at most 33 wide: the window of two buffers fills the LDS)
+    compute_level<S, 0, NT, false>(in, out, P, x0, y0, w, hg, T, sp);
     return;
   }
   const int plane = P * P, npts = w * hg;

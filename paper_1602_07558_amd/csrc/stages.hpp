@@ -529,6 +529,10 @@ __device__ __forceinline__ void flux_walk(const typename S::V* __restrict__ in, 
   const int nch = w + 2 <= 32 ? 1 : 2;          // chunks across
   const int cw = (w + nch - 1) / nch;            // columns per chunk (the last may have fewer)
   const int lps = cw + 2;                        // lanes per segment
+  // A segment fits one wave for w <= 124. The walk schemes' windows (at
+  // least 64 bytes per point, two buffers) bound their tiles to 33 columns
+  // in the 160 KB of LDS, so this never returns.
+  if (lps > 64) return;
   const int spw = 64 / lps;                      // segments per wave
   const int nseg = nch * ((hg + R - 1) / R);
   const int nunit = (nseg + spw - 1) / spw;
