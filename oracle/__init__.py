@@ -69,6 +69,10 @@ def _load():
         lib.oracle_advance_hash25.restype = ctypes.c_int
         lib.oracle_advance_hash25.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
                                               ctypes.c_longlong, ctypes.c_int]
+        lib.oracle_advance3d_f64.restype = ctypes.c_int
+        lib.oracle_advance3d_f64.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong,
+                                             ctypes.c_int]
         lib.oracle_residency.restype = ctypes.c_longlong
         lib.oracle_residency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
@@ -92,6 +96,22 @@ def advance_f64(pde: int, state: np.ndarray, params, nsub: int, t0: int = 0, thr
                                 s.ctypes.data, int(t0), int(nsub), int(threads or default_threads()))
     if rc != 0:
         raise ValueError(f"oracle_advance_f64 failed with {rc}")
+    return s
+
+
+def advance3d_f64(pde: int, state: np.ndarray, params, nsub: int, t0: int = 0,
+                  threads: int | None = None) -> np.ndarray:
+    """3D: the state ``[nz][ny][nx]`` float64 after ``nsub`` sub-steps from
+    global sub-step t0 (pde 1: 7-point heat, params {r}; 100: 27-point
+    hash). ``state`` is not modified."""
+    lib = _load()
+    s = np.ascontiguousarray(state, dtype=np.float64).copy()
+    nz, ny, nx = s.shape
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    rc = lib.oracle_advance3d_f64(int(pde), nx, ny, nz, p.ctypes.data if p.size else None, int(p.size),
+                                  s.ctypes.data, int(t0), int(nsub), int(threads or default_threads()))
+    if rc != 0:
+        raise ValueError(f"oracle_advance3d_f64 failed with {rc}")
     return s
 
 

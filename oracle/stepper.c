@@ -748,3 +748,77 @@ int oracle_advance_hash25(int nx, int ny, double *u, long long k0, long long nst
     free(tmp);
     return 0;
 }
+
+/* ------------------------------------------------------------------- 3D
+ *
+ * The swept rule in three dimensions (Sec. 1 motivates it with 3D grids):
+ * the same plain definition on a triply periodic grid, state[z][y][x] with
+ * x fastest, one value per point. Neighbour k = 9 (dz + 1) + 3 (dy + 1) +
+ * (dx + 1) of the 3x3x3 neighbourhood.
+ *   heat, 7 points: t = ((u_W + u_E) + (u_N + u_S)) + (u_B + u_F),
+ *     lap = t - 6u, u' = u + r lap (B / F: z - 1 / z + 1); params {r}
+ *   test hash, 27 points: an order-sensitive 64-bit mix of the 27 values
+ *     (k = 0..26) seeded with the sub-step index; integers below 2^52. */
+#define PDE3_HEAT7 1
+#define PDE3_TEST_HASH27 100
+
+static double st3_heat(const double nb[27], const double *prm)
+{
+    double u = nb[13];
+    double t = ((nb[12] + nb[14]) + (nb[10] + nb[16])) + (nb[4] + nb[22]);
+    double lap = t - 6.0 * u;
+    return u + prm[0] * lap;
+}
+
+static double st3_hash(long long T, const double nb[27])
+{
+    uint64_t h = 0x94D049BB133111EBull ^ (uint64_t)T;
+    for (int k = 0; k < 27; ++k) {
+        h ^= (uint64_t)nb[k];
+        h *= 0xFF51AFD7ED558CCDull;
+        h ^= h >> 32;
+    }
+    return (double)(h >> 12);
+}
+
+int oracle_advance3d_f64(int pde, int nx, int ny, int nz, const double *params, int nparams, double *state,
+                         long long t0, long long nsub, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nsub < 0 || t0 < 0 || !state)
+        return -1;
+    if (pde != PDE3_HEAT7 && pde != PDE3_TEST_HASH27)
+        return -1;
+    if (pde == PDE3_HEAT7 && (nparams < 1 || !params))
+        return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t tot = (size_t)nx * ny * nz;
+    double *tmp = (double *)malloc(tot * sizeof(double));
+    if (!tmp) return -3;
+    double *cur = state, *nxt = tmp;
+    for (long long s = 0; s < nsub; ++s) {
+        long long T = t0 + s;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int k = 0; k < nz; ++k) {
+            double nb[27];
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    for (int dk = -1; dk <= 1; ++dk)
+                        for (int dj = -1; dj <= 1; ++dj)
+                            for (int di = -1; di <= 1; ++di) {
+                                int kk = (k + dk + nz) % nz, jj = (j + dj + ny) % ny, ii = (i + di + nx) % nx;
+                                nb[9 * (dk + 1) + 3 * (dj + 1) + (di + 1)] =
+                                    cur[((size_t)kk * ny + jj) * nx + ii];
+                            }
+                    nxt[((size_t)k * ny + j) * nx + i] =
+                        pde == PDE3_HEAT7 ? st3_heat(nb, params) : st3_hash(T, nb);
+                }
+        }
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != state)
+        memcpy(state, cur, tot * sizeof(double));
+    free(tmp);
+    return 0;
+}

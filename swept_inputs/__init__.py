@@ -246,6 +246,32 @@ def hash25_field(nx: int, ny: int, seed: int = 0) -> np.ndarray:
     return s
 
 
+# ------------------------------------------------------------------- 3D
+# 3D schemes (their own ids): 7-point heat and the 27-point test hash.
+HEAT7_3D = 1
+TEST_HASH27_3D = 100
+HEAT3D_R = 0.125
+
+
+def heat3d_field(nx: int, ny: int, nz: int, seed: int = 0, modes: int = 8) -> np.ndarray:
+    """Sum of seeded Fourier modes, k in U{1..4} per axis, on [nz][ny][nx]."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx)[None, None, :] / nx
+    y = np.arange(ny)[None, :, None] / ny
+    z = np.arange(nz)[:, None, None] / nz
+    u = np.zeros((nz, ny, nx))
+    for _ in range(modes):
+        kx, ky, kz = rng.integers(1, 5, 3)
+        a, ph = rng.uniform(-1.0, 1.0), rng.uniform(0.0, 2.0 * math.pi)
+        u += a * np.cos(2.0 * math.pi * (kx * x + ky * y + kz * z) + ph)
+    return u
+
+
+def hash3d_field(nx: int, ny: int, nz: int, seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << 52, size=(nz, ny, nx), dtype=np.int64).astype(np.float64)
+
+
 def initial_state(pde: int, nx: int, ny: int, seed: int = 0) -> np.ndarray:
     if pde == HEAT5:
         return heat_field(nx, ny, seed)
