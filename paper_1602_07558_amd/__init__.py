@@ -74,6 +74,9 @@ EXPORTS = [
     "swept2d_batch_advance", "swept2d_batch_synchronize", "swept2d_batch_substep_counter",
     "swept2d_batch_set_wait_limit", "swept2d_batch_set_mode", "swept2d_batch_get_mode",
     "swept2d_batch_launches", "swept2d_advance_noalloc", "swept2d_register_scheme", "swept2d_init_state",
+    "swept3d_create", "swept3d_destroy", "swept3d_set_params", "swept3d_set_tile", "swept3d_get_tile",
+    "swept3d_upload", "swept3d_download", "swept3d_advance", "swept3d_plain_advance", "swept3d_synchronize",
+    "swept3d_get_step", "swept3d_set_step",
 ]
 
 _lib = None
@@ -149,6 +152,18 @@ def load_library():
         "swept2d_advance_noalloc": (i, [i, i, i, i, i, i, ctypes.POINTER(d), i, i, vp, ll, ll, vp]),
         "swept2d_register_scheme": (i, [vp]),
         "swept2d_init_state": (i, [vp]),
+        "swept3d_create": (vp, [i, i, i, i]),
+        "swept3d_destroy": (None, [vp]),
+        "swept3d_set_params": (i, [vp, ctypes.POINTER(d), i]),
+        "swept3d_set_tile": (i, [vp, i]),
+        "swept3d_get_tile": (i, [vp]),
+        "swept3d_upload": (i, [vp, vp]),
+        "swept3d_download": (i, [vp, vp]),
+        "swept3d_advance": (i, [vp, ll]),
+        "swept3d_plain_advance": (i, [vp, ll]),
+        "swept3d_synchronize": (i, [vp]),
+        "swept3d_get_step": (ll, [vp]),
+        "swept3d_set_step": (i, [vp, ll]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -403,6 +418,134 @@ def swept2d_advance_noalloc(nx: int, ny: int, pde: int, prec: int, params, tile:
     pp = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
     return _check(load_library().swept2d_advance_noalloc(nx, ny, nvars, pde, sub, prec, pp, int(p.size), tile,
                                                          dev_ptr, T, nsteps, stream or NULL_STREAM))
+
+
+# --------------------------------------------------------------------- 3D
+HEAT7_3D = 1
+TEST_HASH27_3D = 100
+
+
+def swept3d_create(nx: int, ny: int, nz: int, pde: int):
+    h = load_library().swept3d_create(nx, ny, nz, pde)
+    if not h:
+        raise Swept2DError(EINVAL, swept2d_last_error())
+    return h
+
+
+def swept3d_destroy(h) -> None:
+    load_library().swept3d_destroy(h)
+
+
+def swept3d_set_params(h, params) -> int:
+    arr = (ctypes.c_double * len(params))(*[float(x) for x in params])
+    return _check(load_library().swept3d_set_params(h, arr, len(params)))
+
+
+def swept3d_set_tile(h, n: int) -> int:
+    return _check(load_library().swept3d_set_tile(h, n))
+
+
+def swept3d_get_tile(h) -> int:
+    return _check(load_library().swept3d_get_tile(h))
+
+
+def swept3d_upload(h, host_ptr: int) -> int:
+    return _check(load_library().swept3d_upload(h, host_ptr))
+
+
+def swept3d_download(h, host_ptr: int) -> int:
+    return _check(load_library().swept3d_download(h, host_ptr))
+
+
+def swept3d_advance(h, nsteps: int) -> int:
+    return _check(load_library().swept3d_advance(h, nsteps))
+
+
+def swept3d_plain_advance(h, nsteps: int) -> int:
+    return _check(load_library().swept3d_plain_advance(h, nsteps))
+
+
+def swept3d_synchronize(h) -> int:
+    return _check(load_library().swept3d_synchronize(h))
+
+
+def swept3d_get_step(h) -> int:
+    return _check(load_library().swept3d_get_step(h))
+
+
+def swept3d_set_step(h, T: int) -> int:
+    return _check(load_library().swept3d_set_step(h, T))
+
+
+class Swept3D:
+    """Owner of one swept3d handle (state [nz][ny][nx] float64)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, pde: int, params=None, tile: int = 0):
+        self.nx, self.ny, self.nz, self.pde = nx, ny, nz, pde
+        self.h = swept3d_create(nx, ny, nz, pde)
+        try:
+            if params is not None and len(params):
+                swept3d_set_params(self.h, params)
+            if tile:
+                swept3d_set_tile(self.h, tile)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "h", None):
+            swept3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def tile(self) -> int:
+        return swept3d_get_tile(self.h)
+
+    @tile.setter
+    def tile(self, n: int):
+        swept3d_set_tile(self.h, n)
+
+    @property
+    def T(self) -> int:
+        return swept3d_get_step(self.h)
+
+    @T.setter
+    def T(self, value: int):
+        swept3d_set_step(self.h, value)
+
+    def upload(self, state):
+        import numpy as np
+        a = np.ascontiguousarray(state, dtype=np.float64)
+        if a.shape != (self.nz, self.ny, self.nx):
+            raise ValueError(f"state must be ({self.nz}, {self.ny}, {self.nx})")
+        swept3d_upload(self.h, a.ctypes.data)
+
+    def download(self):
+        import numpy as np
+        a = np.empty((self.nz, self.ny, self.nx), dtype=np.float64)
+        swept3d_download(self.h, a.ctypes.data)
+        return a
+
+    def advance(self, nsteps: int):
+        swept3d_advance(self.h, nsteps)
+
+    def plain_advance(self, nsteps: int):
+        swept3d_plain_advance(self.h, nsteps)
+
+    def synchronize(self):
+        swept3d_synchronize(self.h)
 
 
 class Swept2D:

@@ -39,9 +39,9 @@ BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64), (-66, 1024)
 
 SOURCES = [os.path.join(CSRC, f) for f in ("stages_scheme.hip", "stages_batch.hip", "swept2d_kernels.hip",
                                            "swept2d_api.cpp", "swept2d_batch.cpp",
-                                           "swept2d_noalloc.hip")]
+                                           "swept2d_noalloc.hip", "swept3d.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("engine.hpp", "schemes.hpp", "stages.hpp")] + \
-    [os.path.join(ROOT, "include", "swept2d.h")]
+    [os.path.join(ROOT, "include", "swept2d.h"), os.path.join(ROOT, "include", "swept3d.h")]
 
 FLAGS = [
     "--offload-arch=gfx950",

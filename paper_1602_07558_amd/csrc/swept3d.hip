@@ -1,0 +1,477 @@
+// The swept rule in 3D on cube tiles (the level function of the 2D rule,
+// Sec. 3-4, carried to three axes): stage kernels, the per-step kernel and
+// the C ABI of include/swept3d.h.
+//
+// Geometry. Tiles of side n = 2h start at off + i n on every axis (off = 0
+// or h, alternating between half cycles, Sec. 4). A point at distance d to
+// the nearest tile face along an axis (d = min(t, n - 1 - t), t its
+// position in the tile) is, at level l of a half cycle, on a growing axis of
+// its component if d < l and on a shrinking axis otherwise; its component
+// class is the set of growing axes: none (upward pyramid), one (face
+// bridge), two (edge bridge) or three (downward pyramid). A component's
+// region at level l is, along a shrinking axis of its tile [T, T + n),
+// [T + l, T + n - l), and along a growing axis around its face F,
+// [F - l, F + l). The half cycle runs the classes in four launches (no
+// growing axis, one, two, three): every value a component reads from
+// another one at level l - 1 was computed by an earlier launch, and lies in
+// the two cells at either end of the producer's region along one of the
+// producer's shrinking axes, which is what each component publishes per
+// level (the 3D form of the two-wide panels of Sec. 3).
+//
+// Exchange. The published bands of level l (1 <= l < H) go to a band buffer
+// indexed by level and global point; level 0 is the state the half cycle
+// starts from and level H is written to the other state buffer. The band
+// buffer is dense (one slot per point and level) but only band points are
+// written and read, so the traffic is that of the bands.
+//
+// A component runs in one workgroup with a double-buffered window of
+// (n + 2)^3 values in LDS: per axis the tile and one cell each side
+// (shrinking) or the face's 2h cells and one each side (growing). Per level
+// it loads its ring (the points of its next region's neighbourhood it did
+// not compute itself) from the level below, publishes the previous level's
+// bands, computes its region from the window (one point per thread) and
+// moves on; the two buffers alternate by level parity.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "engine.hpp"
+#include "swept2d.h"
+#include "swept3d.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr int kThreads3 = 256;
+
+struct G3 {
+  int nx, ny, nz;
+  int n, h, off;
+  int tx, ty, tz;
+  int H;
+  long long T0;  // level l applies sub-step T0 + l - 1
+  double r;
+};
+
+struct Box {
+  int x0, x1, y0, y1, z0, z1;  // window coordinates, half-open
+  __device__ int vol() const {
+    const int a = x1 - x0, b = y1 - y0, c = z1 - z0;
+    return (a > 0 && b > 0 && c > 0) ? a * b * c : 0;
+  }
+  __device__ bool has(int x, int y, int z) const {
+    return x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1;
+  }
+};
+
+__device__ __forceinline__ void axis_range(bool grow, int l, int n, int h, int& a, int& b) {
+  if (grow) {
+    a = h + 1 - l;
+    b = h + 1 + l;
+  } else {
+    a = l + 1;
+    b = n + 1 - l;
+  }
+}
+
+__device__ __forceinline__ Box region(int cls, int l, int n, int h) {
+  Box b;
+  axis_range(cls & 1, l, n, h, b.x0, b.x1);
+  axis_range(cls & 2, l, n, h, b.y0, b.y1);
+  axis_range(cls & 4, l, n, h, b.z0, b.z1);
+  return b;
+}
+
+__device__ __forceinline__ int wrap3(int v, int L) {
+  v %= L;
+  return v < 0 ? v + L : v;
+}
+
+// k -> (x, y, z) within a box of widths (a, b).
+__device__ __forceinline__ void unflat(int k, int a, int b, int& x, int& y, int& z) {
+  const int ab = a * b;
+  z = k / ab;
+  const int r = k - z * ab;
+  y = r / a;
+  x = r - y * a;
+}
+
+// 7-point heat and the 27-point hash; nb(q) is neighbour q =
+// 9 (dz + 1) + 3 (dy + 1) + (dx + 1).
+template <class NB>
+__device__ __forceinline__ double heat7(const NB& nb, double r) {
+  const double u = nb(13);
+  const double t = ((nb(12) + nb(14)) + (nb(10) + nb(16))) + (nb(4) + nb(22));
+  const double lap = t - 6.0 * u;
+  return u + r * lap;
+}
+
+template <class NB>
+__device__ __forceinline__ double hash27(long long T, const NB& nb) {
+  uint64_t m = 0x94D049BB133111EBull ^ (uint64_t)T;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    m ^= (uint64_t)nb(q);
+    m *= 0xFF51AFD7ED558CCDull;
+    m ^= m >> 32;
+  }
+  return (double)(m >> 12);
+}
+
+template <int PDE, class NB>
+__device__ __forceinline__ double apply(long long T, const NB& nb, double r) {
+  if constexpr (PDE == SWEPT3D_HEAT7)
+    return heat7(nb, r);
+  else
+    return hash27(T, nb);
+}
+
+// One component of launch `group` (0: upward pyramids, 1: face bridges,
+// 2: edge bridges, 3: downward pyramids) per workgroup.
+template <int PDE>
+__global__ __launch_bounds__(kThreads3) void k3_stage(G3 g, int group, const double* __restrict__ in,
+                                                      double* __restrict__ out, double* __restrict__ bands) {
+  extern __shared__ double win[];
+  const int n = g.n, h = g.h, W = n + 2, W3 = W * W * W;
+  double* const w0 = win;
+  double* const w1 = win + W3;
+  auto buf = [&](int l) { return (l & 1) ? w1 : w0; };
+  const int tiles = g.tx * g.ty * g.tz;
+  int j = (int)blockIdx.x, cls;
+  if (group == 0) {
+    cls = 0;
+  } else if (group == 3) {
+    cls = 7;
+  } else {
+    const int b = j / tiles;
+    j -= b * tiles;
+    cls = group == 1 ? (1 << b) : (7 ^ (1 << b));
+  }
+  const int ix = j % g.tx, iy = (j / g.tx) % g.ty, iz = j / (g.tx * g.ty);
+  // global coordinate of window cell 0 per axis
+  const int bx = g.off + ix * n + ((cls & 1) ? -h - 1 : -1);
+  const int by = g.off + iy * n + ((cls & 2) ? -h - 1 : -1);
+  const int bz = g.off + iz * n + ((cls & 4) ? -h - 1 : -1);
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  auto gidx = [&](int x, int y, int z) {
+    return ((size_t)wrap3(bz + z, g.nz) * g.ny + wrap3(by + y, g.ny)) * g.nx + wrap3(bx + x, g.nx);
+  };
+  const int tid = (int)threadIdx.x;
+
+  // publish level l: its bands to the band buffer (l < H) or its whole
+  // region to the output state (l == H)
+  auto publish = [&](int l) {
+    const Box b = region(cls, l, n, h);
+    const int vol = b.vol();
+    const double* src = buf(l);
+    const bool last = l == g.H;
+    double* dst = last ? out : bands + (size_t)(l - 1) * N;
+    for (int k = tid; k < vol; k += kThreads3) {
+      int x, y, z;
+      unflat(k, b.x1 - b.x0, b.y1 - b.y0, x, y, z);
+      x += b.x0;
+      y += b.y0;
+      z += b.z0;
+      bool keep = last;
+      if (!(cls & 1)) keep = keep || x - b.x0 < 2 || b.x1 - 1 - x < 2;
+      if (!(cls & 2)) keep = keep || y - b.y0 < 2 || b.y1 - 1 - y < 2;
+      if (!(cls & 4)) keep = keep || z - b.z0 < 2 || b.z1 - 1 - z < 2;
+      if (keep) dst[gidx(x, y, z)] = src[(z * W + y) * W + x];
+    }
+  };
+
+  for (int l = 1; l <= g.H; ++l) {
+    // inputs of level l at level l - 1 that this component did not compute
+    Box e = region(cls, l, n, h);
+    e.x0 -= 1;
+    e.x1 += 1;
+    e.y0 -= 1;
+    e.y1 += 1;
+    e.z0 -= 1;
+    e.z1 += 1;
+    const Box own = region(cls, l - 1, n, h);
+    const bool first = l == 1;
+    const double* src = first ? in : bands + (size_t)(l - 2) * N;
+    double* dst = buf(l - 1);
+    const int ev = e.vol();
+    for (int k = tid; k < ev; k += kThreads3) {
+      int x, y, z;
+      unflat(k, e.x1 - e.x0, e.y1 - e.y0, x, y, z);
+      x += e.x0;
+      y += e.y0;
+      z += e.z0;
+      if (!first && own.has(x, y, z)) continue;
+      dst[(z * W + y) * W + x] = src[gidx(x, y, z)];
+    }
+    if (l >= 2) publish(l - 1);
+    __syncthreads();
+    const Box b = region(cls, l, n, h);
+    const int vol = b.vol();
+    const double* I = buf(l - 1);
+    double* O = buf(l);
+    const long long T = g.T0 + l - 1;
+    for (int k = tid; k < vol; k += kThreads3) {
+      int x, y, z;
+      unflat(k, b.x1 - b.x0, b.y1 - b.y0, x, y, z);
+      const int c = ((z + b.z0) * W + (y + b.y0)) * W + (x + b.x0);
+      auto nb = [&](int q) { return I[c + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)]; };
+      O[c] = apply<PDE>(T, nb, g.r);
+    }
+    __syncthreads();
+  }
+  publish(g.H);
+}
+
+// One step of every point, reading its neighbourhood with periodic wrap.
+template <int PDE>
+__global__ __launch_bounds__(256) void k3_plain(const double* __restrict__ in, double* __restrict__ out, int nx,
+                                                int ny, int nz, long long T, double r) {
+  const size_t N = (size_t)nx * ny * nz;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((size_t)nx * ny));
+  int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+  auto nb = [&](int q) { return in[((size_t)zs[q / 9] * ny + ys[(q / 3) % 3]) * nx + xs[q % 3]]; };
+  out[p] = apply<PDE>(T, nb, r);
+}
+
+size_t window_bytes3(int n) { return (size_t)2 * (n + 2) * (n + 2) * (n + 2) * sizeof(double); }
+
+template <int PDE>
+hipError_t stage_lds(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k3_stage<PDE>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace
+
+struct swept3d {
+  int nx = 0, ny = 0, nz = 0, pde = 0, n = 0;
+  double r = 0.0;
+  size_t N = 0;
+  double* state[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* bands = nullptr;
+  int band_levels = 0;
+  hipStream_t stream = nullptr;
+  long long T = 0, half = 0;
+  size_t lds_limit = 0;
+};
+
+namespace {
+
+using swept::set_error;
+
+int hip3(hipError_t e, const char* what) {
+  return set_error(SWEPT2D_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+#define HIP3(call, what)                   \
+  do {                                     \
+    hipError_t e_ = (call);                \
+    if (e_ != hipSuccess) return hip3(e_, what); \
+  } while (0)
+
+const char* tile_problem3(const swept3d* h, int n) {
+  if (n < 2 || (n & 1)) return "tile side must be even and at least 2";
+  if (h->nx % n || h->ny % n || h->nz % n) return "tile side must divide nx, ny and nz";
+  if (window_bytes3(n) > h->lds_limit) return "tile window exceeds the workgroup LDS";
+  return nullptr;
+}
+
+int ensure_bands(swept3d* h, int levels) {
+  if (levels <= h->band_levels) return 0;
+  if (h->bands) hipFree(h->bands);
+  h->bands = nullptr;
+  h->band_levels = 0;
+  if (hipMalloc(&h->bands, (size_t)levels * h->N * sizeof(double)) != hipSuccess)
+    return set_error(SWEPT2D_ENOMEM, "cannot allocate %d band levels", levels);
+  h->band_levels = levels;
+  return 0;
+}
+
+std::once_flag g_lds3_once;
+hipError_t g_lds3_err = hipSuccess;
+
+}  // namespace
+
+extern "C" {
+
+swept3d* swept3d_create(int nx, int ny, int nz, int pde) {
+  if (nx < 2 || ny < 2 || nz < 2) {
+    set_error(SWEPT2D_EINVAL, "grid sides must be at least 2");
+    return nullptr;
+  }
+  if (pde != SWEPT3D_HEAT7 && pde != SWEPT3D_TEST_HASH27) {
+    set_error(SWEPT2D_EINVAL, "unknown 3D scheme %d", pde);
+    return nullptr;
+  }
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    set_error(SWEPT2D_EHIP, "no device");
+    return nullptr;
+  }
+  std::call_once(g_lds3_once, [&] {
+    g_lds3_err = stage_lds<SWEPT3D_HEAT7>((size_t)lds);
+    if (g_lds3_err == hipSuccess) g_lds3_err = stage_lds<SWEPT3D_TEST_HASH27>((size_t)lds);
+  });
+  if (g_lds3_err != hipSuccess) {
+    hip3(g_lds3_err, "hipFuncSetAttribute");
+    return nullptr;
+  }
+  swept3d* h = new swept3d();
+  h->nx = nx;
+  h->ny = ny;
+  h->nz = nz;
+  h->pde = pde;
+  h->N = (size_t)nx * ny * nz;
+  h->lds_limit = (size_t)lds;
+  for (int n = 16; n >= 2; n -= 2)
+    if (!tile_problem3(h, n)) {
+      h->n = n;
+      break;
+    }
+  const size_t bytes = h->N * sizeof(double);
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&h->state[0], bytes) != hipSuccess || hipMalloc(&h->state[1], bytes) != hipSuccess) {
+    set_error(SWEPT2D_ENOMEM, "cannot allocate %zu bytes of state", 2 * bytes);
+    swept3d_destroy(h);
+    return nullptr;
+  }
+  if (hipMemsetAsync(h->state[0], 0, bytes, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    set_error(SWEPT2D_EHIP, "cannot clear the state");
+    swept3d_destroy(h);
+    return nullptr;
+  }
+  return h;
+}
+
+void swept3d_destroy(swept3d* h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  if (h->state[0]) hipFree(h->state[0]);
+  if (h->state[1]) hipFree(h->state[1]);
+  if (h->bands) hipFree(h->bands);
+  if (h->stream) hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int swept3d_set_params(swept3d* h, const double* params, int nparams) {
+  if (!h) return set_error(SWEPT2D_EINVAL, "null handle");
+  const int need = h->pde == SWEPT3D_HEAT7 ? 1 : 0;
+  if (nparams < need || (need && !params)) return set_error(SWEPT2D_EINVAL, "scheme needs %d parameters", need);
+  if (need) h->r = params[0];
+  return 0;
+}
+
+int swept3d_set_tile(swept3d* h, int n) {
+  if (!h) return set_error(SWEPT2D_EINVAL, "null handle");
+  if (const char* why = tile_problem3(h, n)) return set_error(SWEPT2D_EINVAL, "tile side %d: %s", n, why);
+  h->n = n;
+  return 0;
+}
+
+int swept3d_get_tile(const swept3d* h) { return h ? h->n : set_error(SWEPT2D_EINVAL, "null handle"); }
+
+int swept3d_upload(swept3d* h, const double* host) {
+  if (!h || !host) return set_error(SWEPT2D_EINVAL, "null argument");
+  HIP3(hipMemcpyAsync(h->state[h->cur], host, h->N * sizeof(double), hipMemcpyHostToDevice, h->stream),
+       "hipMemcpyAsync");
+  HIP3(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return 0;
+}
+
+int swept3d_download(swept3d* h, double* host) {
+  if (!h || !host) return set_error(SWEPT2D_EINVAL, "null argument");
+  HIP3(hipMemcpyAsync(host, h->state[h->cur], h->N * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+       "hipMemcpyAsync");
+  HIP3(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return 0;
+}
+
+int swept3d_advance(swept3d* h, long long nsteps) {
+  if (!h) return set_error(SWEPT2D_EINVAL, "null handle");
+  if (nsteps < 0) return set_error(SWEPT2D_EINVAL, "negative step count");
+  if (nsteps == 0) return 0;
+  if (!h->n) return set_error(SWEPT2D_EINVAL, "no even tile side up to 16 divides %d x %d x %d", h->nx, h->ny, h->nz);
+  const int hh = h->n / 2;
+  if (hh > 1) {
+    if (int rc = ensure_bands(h, hh - 1)) return rc;
+  }
+  const size_t lds = window_bytes3(h->n);
+  const int tiles = (h->nx / h->n) * (h->ny / h->n) * (h->nz / h->n);
+  for (long long done = 0; done < nsteps;) {
+    G3 g;
+    g.nx = h->nx;
+    g.ny = h->ny;
+    g.nz = h->nz;
+    g.n = h->n;
+    g.h = hh;
+    g.off = (h->half & 1) ? hh : 0;
+    g.tx = h->nx / h->n;
+    g.ty = h->ny / h->n;
+    g.tz = h->nz / h->n;
+    g.H = (int)std::min<long long>(hh, nsteps - done);
+    g.T0 = h->T;
+    g.r = h->r;
+    const double* in = h->state[h->cur];
+    double* out = h->state[h->cur ^ 1];
+    for (int group = 0; group < 4; ++group) {
+      const int blocks = (group == 1 || group == 2) ? 3 * tiles : tiles;
+      if (h->pde == SWEPT3D_HEAT7)
+        hipLaunchKernelGGL(k3_stage<SWEPT3D_HEAT7>, dim3(blocks), dim3(kThreads3), lds, h->stream, g, group, in, out,
+                           h->bands);
+      else
+        hipLaunchKernelGGL(k3_stage<SWEPT3D_TEST_HASH27>, dim3(blocks), dim3(kThreads3), lds, h->stream, g, group, in,
+                           out, h->bands);
+      HIP3(hipGetLastError(), "stage launch");
+    }
+    h->cur ^= 1;
+    h->half += 1;
+    h->T += g.H;
+    done += g.H;
+  }
+  return 0;
+}
+
+int swept3d_plain_advance(swept3d* h, long long nsteps) {
+  if (!h) return set_error(SWEPT2D_EINVAL, "null handle");
+  if (nsteps < 0) return set_error(SWEPT2D_EINVAL, "negative step count");
+  const unsigned blocks = (unsigned)((h->N + 255) / 256);
+  for (long long s = 0; s < nsteps; ++s) {
+    const double* in = h->state[h->cur];
+    double* out = h->state[h->cur ^ 1];
+    if (h->pde == SWEPT3D_HEAT7)
+      hipLaunchKernelGGL(k3_plain<SWEPT3D_HEAT7>, dim3(blocks), dim3(256), 0, h->stream, in, out, h->nx, h->ny, h->nz,
+                         h->T, h->r);
+    else
+      hipLaunchKernelGGL(k3_plain<SWEPT3D_TEST_HASH27>, dim3(blocks), dim3(256), 0, h->stream, in, out, h->nx, h->ny,
+                         h->nz, h->T, h->r);
+    HIP3(hipGetLastError(), "per-step launch");
+    h->cur ^= 1;
+    h->T += 1;
+  }
+  return 0;
+}
+
+int swept3d_synchronize(swept3d* h) {
+  if (!h) return set_error(SWEPT2D_EINVAL, "null handle");
+  HIP3(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return 0;
+}
+
+long long swept3d_get_step(const swept3d* h) { return h ? h->T : set_error(SWEPT2D_EINVAL, "null handle"); }
+
+int swept3d_set_step(swept3d* h, long long T) {
+  if (!h || T < 0) return set_error(SWEPT2D_EINVAL, "null handle or negative step");
+  h->T = T;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (CPU only: no kernel is launched).
 
-The library must load and export every function include/swept2d.h declares;
+The library must load and export every function include/swept2d.h and
+include/swept3d.h declare;
 the Python binding must carry the same names; without a GPU, creating a handle
 fails with an error message instead of falling back to anything.
 """
@@ -13,13 +14,15 @@ import pytest
 import paper_1602_07558_amd as sw
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "swept2d.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in ("swept2d.h", "swept3d.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(swept2d_[a-z_]+)\s*\(", text)))
+    names = set()
+    for path in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"\b(swept[23]d_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +40,7 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol(lib):
     out = subprocess.run(["nm", "-D", "--defined-only", sw.LIB_PATH], capture_output=True, text=True, check=True).stdout
-    exported = set(re.findall(r"\bT (swept2d_[a-z_]+)\b", out))
+    exported = set(re.findall(r"\bT (swept[23]d_[a-z_]+)\b", out))
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     for n in declared_functions():
