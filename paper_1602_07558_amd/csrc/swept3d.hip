@@ -45,8 +45,6 @@
 
 namespace {
 
-constexpr int kThreads3 = 256;
-
 struct G3 {
   int nx, ny, nz;
   int n, h, off;
@@ -54,17 +52,6 @@ struct G3 {
   int H;
   long long T0;  // level l applies sub-step T0 + l - 1
   double r;
-};
-
-struct Box {
-  int x0, x1, y0, y1, z0, z1;  // window coordinates, half-open
-  __device__ int vol() const {
-    const int a = x1 - x0, b = y1 - y0, c = z1 - z0;
-    return (a > 0 && b > 0 && c > 0) ? a * b * c : 0;
-  }
-  __device__ bool has(int x, int y, int z) const {
-    return x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1;
-  }
 };
 
 __device__ __forceinline__ void axis_range(bool grow, int l, int n, int h, int& a, int& b) {
@@ -77,26 +64,54 @@ __device__ __forceinline__ void axis_range(bool grow, int l, int n, int h, int& 
   }
 }
 
-__device__ __forceinline__ Box region(int cls, int l, int n, int h) {
-  Box b;
-  axis_range(cls & 1, l, n, h, b.x0, b.x1);
-  axis_range(cls & 2, l, n, h, b.y0, b.y1);
-  axis_range(cls & 4, l, n, h, b.z0, b.z1);
-  return b;
+// A window coordinate's global position lies in [-L, 2L) (the window starts
+// at most h + 1 before the grid and ends at most h + 1 past it, n = 2h <= L).
+__device__ __forceinline__ int wrap3(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// q = a d + b, 0 <= b < d, for q < 2^24: the float reciprocal gives a within
+// one, which the correction fixes.
+__device__ __forceinline__ void divmod3(int q, int d, float inv, int& a, int& b) {
+  a = (int)((float)q * inv);
+  b = q - a * d;
+  if (b < 0) {
+    a -= 1;
+    b += d;
+  } else if (b >= d) {
+    a += 1;
+    b -= d;
+  }
 }
 
-__device__ __forceinline__ int wrap3(int v, int L) {
-  v %= L;
-  return v < 0 ? v + L : v;
+// The points of a product of per-axis position sets: along each axis either
+// the range [p0, p0 + cnt) or four positions p0, p0 + 1, p2, p2 + 1.
+struct AxisSet {
+  int cnt;
+  bool range;
+  int p0, p2;
+  __device__ int at(int i) const { return (range || i < 2) ? p0 + i : p2 + (i - 2); }
+};
+__device__ __forceinline__ AxisSet aset_range(int a, int b) { return AxisSet{b > a ? b - a : 0, true, a, 0}; }
+// The two cells at either end of [a, b) (all of it when it is at most four
+// wide): a shrinking axis's band positions.
+__device__ __forceinline__ AxisSet aset_ends(int a, int b) {
+  return b - a <= 4 ? aset_range(a, b) : AxisSet{4, false, a, b - 2};
 }
+// Ring positions of a growing axis at level l: the expanded range [a - 1,
+// b + 1) without the previous level's [a + 1, b - 1).
+__device__ __forceinline__ AxisSet aset_ring(int a, int b) { return AxisSet{4, false, a - 1, b - 1}; }
 
-// k -> (x, y, z) within a box of widths (a, b).
-__device__ __forceinline__ void unflat(int k, int a, int b, int& x, int& y, int& z) {
-  const int ab = a * b;
-  z = k / ab;
-  const int r = k - z * ab;
-  y = r / a;
-  x = r - y * a;
+// Calls f(x, y, z) for every point of sx * sy * sz, NT threads in turn.
+template <int NT, class F>
+__device__ __forceinline__ void for_points(const AxisSet& sx, const AxisSet& sy, const AxisSet& sz, F&& f) {
+  const int nxy = sx.cnt * sy.cnt, tot = nxy * sz.cnt;
+  if (tot <= 0) return;
+  const float ixy = 1.0f / (float)nxy, ix = 1.0f / (float)sx.cnt;
+  for (int k = (int)threadIdx.x; k < tot; k += NT) {
+    int z, r, y, x;
+    divmod3(k, nxy, ixy, z, r);
+    divmod3(r, sx.cnt, ix, y, x);
+    f(sx.at(x), sy.at(y), sz.at(z));
+  }
 }
 
 // 7-point heat and the 27-point hash; nb(q) is neighbour q =
@@ -130,10 +145,10 @@ __device__ __forceinline__ double apply(long long T, const NB& nb, double r) {
 }
 
 // One component of launch `group` (0: upward pyramids, 1: face bridges,
-// 2: edge bridges, 3: downward pyramids) per workgroup.
-template <int PDE>
-__global__ __launch_bounds__(kThreads3) void k3_stage(G3 g, int group, const double* __restrict__ in,
-                                                      double* __restrict__ out, double* __restrict__ bands) {
+// 2: edge bridges, 3: downward pyramids) per workgroup of NT threads.
+template <int PDE, int NT>
+__global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __restrict__ in,
+                                               double* __restrict__ out, double* __restrict__ bands) {
   extern __shared__ double win[];
   const int n = g.n, h = g.h, W = n + 2, W3 = W * W * W;
   double* const w0 = win;
@@ -159,67 +174,82 @@ __global__ __launch_bounds__(kThreads3) void k3_stage(G3 g, int group, const dou
   auto gidx = [&](int x, int y, int z) {
     return ((size_t)wrap3(bz + z, g.nz) * g.ny + wrap3(by + y, g.ny)) * g.nx + wrap3(bx + x, g.nx);
   };
-  const int tid = (int)threadIdx.x;
+  auto widx = [&](int x, int y, int z) { return (z * W + y) * W + x; };
+  auto grows = [&](int a) { return ((cls >> a) & 1) != 0; };
 
-  // publish level l: its bands to the band buffer (l < H) or its whole
-  // region to the output state (l == H)
+  // publish level l: the bands of its shrinking axes to the band buffer
+  // (l < H; each band point once: along the first shrinking axis where it
+  // is in a band), or its whole region to the output state (l == H)
   auto publish = [&](int l) {
-    const Box b = region(cls, l, n, h);
-    const int vol = b.vol();
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
     const double* src = buf(l);
-    const bool last = l == g.H;
-    double* dst = last ? out : bands + (size_t)(l - 1) * N;
-    for (int k = tid; k < vol; k += kThreads3) {
-      int x, y, z;
-      unflat(k, b.x1 - b.x0, b.y1 - b.y0, x, y, z);
-      x += b.x0;
-      y += b.y0;
-      z += b.z0;
-      bool keep = last;
-      if (!(cls & 1)) keep = keep || x - b.x0 < 2 || b.x1 - 1 - x < 2;
-      if (!(cls & 2)) keep = keep || y - b.y0 < 2 || b.y1 - 1 - y < 2;
-      if (!(cls & 4)) keep = keep || z - b.z0 < 2 || b.z1 - 1 - z < 2;
-      if (keep) dst[gidx(x, y, z)] = src[(z * W + y) * W + x];
+    if (l == g.H) {
+      for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
+                     [&](int x, int y, int z) { out[gidx(x, y, z)] = src[widx(x, y, z)]; });
+      return;
+    }
+    double* dst = bands + (size_t)(l - 1) * N;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (grows(a)) continue;
+      AxisSet s[3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (b == a)
+          s[b] = aset_ends(lo[b], hi[b]);
+        else if (b < a && !grows(b))
+          s[b] = aset_range(lo[b] + 2, hi[b] - 2);
+        else
+          s[b] = aset_range(lo[b], hi[b]);
+      }
+      for_points<NT>(s[0], s[1], s[2], [&](int x, int y, int z) { dst[gidx(x, y, z)] = src[widx(x, y, z)]; });
     }
   };
 
   for (int l = 1; l <= g.H; ++l) {
-    // inputs of level l at level l - 1 that this component did not compute
-    Box e = region(cls, l, n, h);
-    e.x0 -= 1;
-    e.x1 += 1;
-    e.y0 -= 1;
-    e.y1 += 1;
-    e.z0 -= 1;
-    e.z1 += 1;
-    const Box own = region(cls, l - 1, n, h);
-    const bool first = l == 1;
-    const double* src = first ? in : bands + (size_t)(l - 2) * N;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
+    // the inputs at level l - 1 this component did not compute: at l = 1 the
+    // whole neighbourhood of its region, from the state; later only the ring
+    // along its growing axes (each ring point once: along the first growing
+    // axis where it is outside the previous level's region)
     double* dst = buf(l - 1);
-    const int ev = e.vol();
-    for (int k = tid; k < ev; k += kThreads3) {
-      int x, y, z;
-      unflat(k, e.x1 - e.x0, e.y1 - e.y0, x, y, z);
-      x += e.x0;
-      y += e.y0;
-      z += e.z0;
-      if (!first && own.has(x, y, z)) continue;
-      dst[(z * W + y) * W + x] = src[gidx(x, y, z)];
+    if (l == 1) {
+      for_points<NT>(aset_range(lo[0] - 1, hi[0] + 1), aset_range(lo[1] - 1, hi[1] + 1),
+                     aset_range(lo[2] - 1, hi[2] + 1),
+                     [&](int x, int y, int z) { dst[widx(x, y, z)] = in[gidx(x, y, z)]; });
+    } else {
+      const double* src = bands + (size_t)(l - 2) * N;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (!grows(a)) continue;
+        AxisSet s[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          if (b == a)
+            s[b] = aset_ring(lo[b], hi[b]);
+          else if (b < a && grows(b))
+            s[b] = aset_range(lo[b] + 1, hi[b] - 1);
+          else
+            s[b] = aset_range(lo[b] - 1, hi[b] + 1);
+        }
+        for_points<NT>(s[0], s[1], s[2], [&](int x, int y, int z) { dst[widx(x, y, z)] = src[gidx(x, y, z)]; });
+      }
     }
     if (l >= 2) publish(l - 1);
     __syncthreads();
-    const Box b = region(cls, l, n, h);
-    const int vol = b.vol();
     const double* I = buf(l - 1);
     double* O = buf(l);
     const long long T = g.T0 + l - 1;
-    for (int k = tid; k < vol; k += kThreads3) {
-      int x, y, z;
-      unflat(k, b.x1 - b.x0, b.y1 - b.y0, x, y, z);
-      const int c = ((z + b.z0) * W + (y + b.y0)) * W + (x + b.x0);
-      auto nb = [&](int q) { return I[c + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)]; };
-      O[c] = apply<PDE>(T, nb, g.r);
-    }
+    for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
+                   [&](int x, int y, int z) {
+                     const int c = widx(x, y, z);
+                     auto nb = [&](int q) { return I[c + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)]; };
+                     O[c] = apply<PDE>(T, nb, g.r);
+                   });
     __syncthreads();
   }
   publish(g.H);
@@ -242,10 +272,28 @@ __global__ __launch_bounds__(256) void k3_plain(const double* __restrict__ in, d
 
 size_t window_bytes3(int n) { return (size_t)2 * (n + 2) * (n + 2) * (n + 2) * sizeof(double); }
 
+// Workgroup size by tile side: 512 threads from side 12 on (a window that
+// holds one workgroup per CU), 256 below.
+constexpr int stage_threads(int n) { return n >= 12 ? 512 : 256; }
+
+template <int PDE, int NT>
+hipError_t stage_lds_one(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k3_stage<PDE, NT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 template <int PDE>
 hipError_t stage_lds(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k3_stage<PDE>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  hipError_t e = stage_lds_one<PDE, 256>(bytes);
+  return e != hipSuccess ? e : stage_lds_one<PDE, 512>(bytes);
+}
+
+template <int PDE>
+void launch_stage(int n, int blocks, size_t lds, hipStream_t st, const G3& g, int group, const double* in,
+                  double* out, double* bands) {
+  if (stage_threads(n) == 512)
+    hipLaunchKernelGGL((k3_stage<PDE, 512>), dim3(blocks), dim3(512), lds, st, g, group, in, out, bands);
+  else
+    hipLaunchKernelGGL((k3_stage<PDE, 256>), dim3(blocks), dim3(256), lds, st, g, group, in, out, bands);
 }
 
 }  // namespace
@@ -425,11 +473,9 @@ int swept3d_advance(swept3d* h, long long nsteps) {
     for (int group = 0; group < 4; ++group) {
       const int blocks = (group == 1 || group == 2) ? 3 * tiles : tiles;
       if (h->pde == SWEPT3D_HEAT7)
-        hipLaunchKernelGGL(k3_stage<SWEPT3D_HEAT7>, dim3(blocks), dim3(kThreads3), lds, h->stream, g, group, in, out,
-                           h->bands);
+        launch_stage<SWEPT3D_HEAT7>(h->n, blocks, lds, h->stream, g, group, in, out, h->bands);
       else
-        hipLaunchKernelGGL(k3_stage<SWEPT3D_TEST_HASH27>, dim3(blocks), dim3(kThreads3), lds, h->stream, g, group, in,
-                           out, h->bands);
+        launch_stage<SWEPT3D_TEST_HASH27>(h->n, blocks, lds, h->stream, g, group, in, out, h->bands);
       HIP3(hipGetLastError(), "stage launch");
     }
     h->cur ^= 1;
