@@ -180,8 +180,9 @@ def other_workloads(sw, si, np):
     number of steps (the step counts of their parity tests are longer), with
     the FP32 forms' normwise error against the FP64 result of the same run:
     the wave 2048^2 and Euler 512^2 grids (swept), the paper's Euler
-    discretisation on its 1024 x 512 tunnel (swept and per-step), heat on
-    8192^2 (state beyond the Infinity Cache: swept and per-step) and the
+    discretisation on its 1024 x 512 tunnel (swept and per-step), 3D heat on
+    128^3 and 256^3 (swept and per-step), heat on 8192^2 (state beyond the
+    Infinity Cache: swept and per-step) and the
     uneven 256-grid batches (phased launches, model tile sides)."""
     out = {}
 
@@ -262,6 +263,26 @@ def other_workloads(sw, si, np):
         "swept_substep_value": 4 * fd["swept"], "steps": 200, "tile": fd["tile"],
         "swept_over_plain": fd["swept"] / fd["plain"],
         "note": "50 MB state (12 FP64 values per point) stays in the Infinity Cache; both paths latency-bound"}
+    # The swept rule in 3D: 7-point heat on 128^3 and 256^3, cube tiles of
+    # side 16, swept and per-step.
+    for L in (128, 256):
+        s3 = si.heat3d_field(L, L, L, seed=0)
+        r3 = {}
+        for method in ("swept", "plain"):
+            g = sw.Swept3D(L, L, L, si.HEAT7_3D, [si.HEAT3D_R])
+            g.upload(s3)
+            run = g.advance if method == "swept" else g.plain_advance
+            run(16)
+            g.synchronize()
+            t0 = time.perf_counter()
+            run(64)
+            g.synchronize()
+            r3[method] = L ** 3 * 64 / (time.perf_counter() - t0)
+            r3["tile"] = g.tile
+            g.close()
+        out[f"heat3d_{L}_fp64"] = {"swept_value": r3["swept"], "plain_value": r3["plain"],
+                                   "unit": "point-updates/s", "steps": 64, "tile": r3["tile"],
+                                   "swept_over_plain": r3["swept"] / r3["plain"]}
     # Heat 8192^2 FP64 (512 MB of state, beyond the 256 MB Infinity Cache):
     # the per-step kernel's traffic goes to HBM, with the swept rule beside it.
     s_h = si.heat_field(8192, 8192, seed=0)

@@ -151,9 +151,10 @@ __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __
                                                double* __restrict__ out, double* __restrict__ bands) {
   extern __shared__ double win[];
   const int n = g.n, h = g.h, W = n + 2, W3 = W * W * W;
-  double* const w0 = win;
-  double* const w1 = win + W3;
-  auto buf = [&](int l) { return (l & 1) ? w1 : w0; };
+  // buffer l & 1 of the window starts at win + off(l): kept as an offset
+  // from the LDS array (a selected pointer would be a generic one, and every
+  // window access a flat access)
+  auto off = [&](int l) { return (l & 1) * W3; };
   const int tiles = g.tx * g.ty * g.tz;
   int j = (int)blockIdx.x, cls;
   if (group == 0) {
@@ -184,10 +185,10 @@ __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __
     int lo[3], hi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
-    const double* src = buf(l);
+    const int src = off(l);
     if (l == g.H) {
       for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
-                     [&](int x, int y, int z) { out[gidx(x, y, z)] = src[widx(x, y, z)]; });
+                     [&](int x, int y, int z) { out[gidx(x, y, z)] = win[src + widx(x, y, z)]; });
       return;
     }
     double* dst = bands + (size_t)(l - 1) * N;
@@ -204,7 +205,8 @@ __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __
         else
           s[b] = aset_range(lo[b], hi[b]);
       }
-      for_points<NT>(s[0], s[1], s[2], [&](int x, int y, int z) { dst[gidx(x, y, z)] = src[widx(x, y, z)]; });
+      for_points<NT>(s[0], s[1], s[2],
+                     [&](int x, int y, int z) { dst[gidx(x, y, z)] = win[src + widx(x, y, z)]; });
     }
   };
 
@@ -216,11 +218,11 @@ __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __
     // whole neighbourhood of its region, from the state; later only the ring
     // along its growing axes (each ring point once: along the first growing
     // axis where it is outside the previous level's region)
-    double* dst = buf(l - 1);
+    const int dst = off(l - 1);
     if (l == 1) {
       for_points<NT>(aset_range(lo[0] - 1, hi[0] + 1), aset_range(lo[1] - 1, hi[1] + 1),
                      aset_range(lo[2] - 1, hi[2] + 1),
-                     [&](int x, int y, int z) { dst[widx(x, y, z)] = in[gidx(x, y, z)]; });
+                     [&](int x, int y, int z) { win[dst + widx(x, y, z)] = in[gidx(x, y, z)]; });
     } else {
       const double* src = bands + (size_t)(l - 2) * N;
 #pragma unroll
@@ -236,19 +238,21 @@ __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __
           else
             s[b] = aset_range(lo[b] - 1, hi[b] + 1);
         }
-        for_points<NT>(s[0], s[1], s[2], [&](int x, int y, int z) { dst[widx(x, y, z)] = src[gidx(x, y, z)]; });
+        for_points<NT>(s[0], s[1], s[2],
+                       [&](int x, int y, int z) { win[dst + widx(x, y, z)] = src[gidx(x, y, z)]; });
       }
     }
     if (l >= 2) publish(l - 1);
     __syncthreads();
-    const double* I = buf(l - 1);
-    double* O = buf(l);
+    const int I = off(l - 1), O = off(l);
     const long long T = g.T0 + l - 1;
     for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
                    [&](int x, int y, int z) {
                      const int c = widx(x, y, z);
-                     auto nb = [&](int q) { return I[c + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)]; };
-                     O[c] = apply<PDE>(T, nb, g.r);
+                     auto nb = [&](int q) {
+                       return win[I + c + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)];
+                     };
+                     win[O + c] = apply<PDE>(T, nb, g.r);
                    });
     __syncthreads();
   }
