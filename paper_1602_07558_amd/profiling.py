@@ -2,6 +2,10 @@
 
   python -m paper_1602_07558_amd.profiling stats DIR
       per-kernel calls / average / total duration from *_kernel_stats.csv
+  python -m paper_1602_07558_amd.profiling grids DIR
+      per kernel and grid size, calls and average duration from
+      *_kernel_trace.csv (one kernel runs several workloads: their launches
+      differ in grid size)
   python -m paper_1602_07558_amd.profiling counters DIR COUNTER [COUNTER ...]
       per-launch averages of --pmc counters for the swept2d stage and
       per-step kernels in DIR
@@ -37,7 +41,7 @@ def kernel_stats(directory: str):
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"(k_[a-z0-9_]+)<([^()]*)>", name)
+    m = re.search(r"(k[0-9]?_[a-z0-9_]+)<([^()]*)>", name)
     if m:
         args = m.group(2).replace("swept::", "").replace(" ", "")
         return f"{m.group(1)}<{args}>"
@@ -109,7 +113,26 @@ def traffic_summary(fetch_dir: str, write_dir: str, copy_bytes: int):
     return out
 
 
+def grid_stats(directory: str):
+    """(short kernel name, grid size in workitems) -> [calls, total ns]."""
+    out = defaultdict(lambda: [0, 0.0])
+    for r in _rows(directory, "kernel_trace.csv"):
+        name = r.get("Kernel_Name", "")
+        grid = r.get("Grid_Size_X") or r.get("Grid_Size") or "0"
+        dur = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        e = out[(short_name(name), int(float(grid)))]
+        e[0] += 1
+        e[1] += dur
+    return out
+
+
 def main(argv):
+    if argv and argv[0] == "grids":
+        rows = grid_stats(argv[1])
+        for (name, grid), (calls, tot) in sorted(rows.items(), key=lambda kv: -kv[1][1]):
+            print(f"{name:40s} grid={grid:9d} calls={calls:7d} avg_us={tot / calls / 1e3:10.2f} "
+                  f"total_ms={tot / 1e6:10.3f}")
+        return 0
     if argv and argv[0] == "stats":
         for k in sorted(kernel_stats(argv[1]), key=lambda r: -r["total_ns"]):
             print(f"{short_name(k['name']):40s} calls={k['calls']:7d} avg_us={k['avg_ns'] / 1e3:10.2f} "
