@@ -54,8 +54,8 @@ void swept3d_destroy(swept3d *h);
 int swept3d_set_params(swept3d *h, const double *params, int nparams);
 
 /* Cube tile side n: even, at least 2, dividing nx, ny and nz, with
- * 2 (n + 2)^3 doubles of window within the workgroup LDS (n <= 16 on
- * gfx950). EINVAL otherwise, leaving the side unchanged. */
+ * 2 (n + 2)^3 doubles of window within the workgroup LDS (n <= 18 in the
+ * 160 KB of gfx950). EINVAL otherwise, leaving the side unchanged. */
 int swept3d_set_tile(swept3d *h, int n);
 int swept3d_get_tile(const swept3d *h);
 

@@ -35,12 +35,13 @@ def run3(pde, state, params, steps, tile=0, method="swept", splits=None, T=0):
         return g.download(), g.tile
 
 
-@pytest.mark.parametrize("shape,steps", [((16, 16, 16), 13), ((8, 12, 16), 7), ((24, 24, 24), 9), ((6, 6, 6), 5)])
+@pytest.mark.parametrize("shape,steps", [((16, 16, 16), 13), ((8, 12, 16), 7), ((24, 24, 24), 9), ((6, 6, 6), 5),
+                                         ((18, 18, 36), 11)])
 def test_hash27_every_tile_side(shape, steps):
     nz, ny, nx = shape
     s0 = si.hash3d_field(nx, ny, nz, seed=1)
     ref = oracle.advance3d_f64(HASH, s0, [], steps)
-    sides = [n for n in range(2, 17, 2) if nx % n == 0 and ny % n == 0 and nz % n == 0]
+    sides = [n for n in range(2, 19, 2) if nx % n == 0 and ny % n == 0 and nz % n == 0]
     for n in sides:
         got, tile = run3(HASH, s0, [], steps, tile=n)
         assert tile == n and np.array_equal(got, ref), n
@@ -78,7 +79,7 @@ def test_heat7_128_cubed_full_size():
 def test_errors():
     with sw.Swept3D(12, 12, 12, HEAT, [si.HEAT3D_R]) as g:
         assert g.tile == 12
-        for bad in (5, 8, 18, 0):
+        for bad in (5, 8, 18, 20, 0):
             with pytest.raises(sw.Swept2DError):
                 g.tile = bad
         assert g.tile == 12
