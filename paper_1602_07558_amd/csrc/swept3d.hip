@@ -346,8 +346,11 @@ int ensure_bands(swept3d* h, int levels) {
   return 0;
 }
 
-std::once_flag g_lds3_once;
-hipError_t g_lds3_err = hipSuccess;
+// The stage kernels' dynamic LDS limit is raised once per device (the
+// attribute is per device).
+constexpr int kMaxDevices3 = 64;
+std::mutex g_lds3_mu;
+bool g_lds3_done[kMaxDevices3] = {};
 
 }  // namespace
 
@@ -368,13 +371,21 @@ swept3d* swept3d_create(int nx, int ny, int nz, int pde) {
     set_error(SWEPT2D_EHIP, "no device");
     return nullptr;
   }
-  std::call_once(g_lds3_once, [&] {
-    g_lds3_err = stage_lds<SWEPT3D_HEAT7>((size_t)lds);
-    if (g_lds3_err == hipSuccess) g_lds3_err = stage_lds<SWEPT3D_TEST_HASH27>((size_t)lds);
-  });
-  if (g_lds3_err != hipSuccess) {
-    hip3(g_lds3_err, "hipFuncSetAttribute");
+  if (dev < 0 || dev >= kMaxDevices3) {
+    set_error(SWEPT2D_EUNSUPPORTED, "device index %d", dev);
     return nullptr;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_lds3_mu);
+    if (!g_lds3_done[dev]) {
+      hipError_t e = stage_lds<SWEPT3D_HEAT7>((size_t)lds);
+      if (e == hipSuccess) e = stage_lds<SWEPT3D_TEST_HASH27>((size_t)lds);
+      if (e != hipSuccess) {
+        hip3(e, "hipFuncSetAttribute");
+        return nullptr;
+      }
+      g_lds3_done[dev] = true;
+    }
   }
   swept3d* h = new swept3d();
   h->nx = nx;
