@@ -9,7 +9,9 @@
  * upward pyramid of its tile, to a face bridge, to an edge bridge or to a
  * downward pyramid, by which of its three distances to the nearest tile
  * faces are below l. Each half cycle runs four stages in that order, each
- * one launch over all its components; a component computes its levels in
+ * one launch over all its components (the downward pyramids go on as the
+ * next half cycle's upward pyramids, octahedra as in 2D, when another full
+ * half cycle follows); a component computes its levels in
  * the LDS of one workgroup and exchanges only the two-wide bands at the ends
  * of its shrinking axes, level by level, through device memory. Tilings
  * alternate between offset 0 and h on every axis (Sec. 4). Every space-time
@@ -45,8 +47,9 @@ typedef struct swept3d swept3d;
 /* Create a grid of nx * ny * nz points (each at least 2) for scheme `pde`
  * on the current device, with the state at zero, sub-step counter 0 and the
  * default tile side (the largest even side up to 16 dividing nx, ny and nz
- * whose two-buffer window fits the workgroup LDS). Allocates the two state
- * buffers and the band buffer. NULL on error. */
+ * whose two-buffer window fits the workgroup LDS). Allocates three state
+ * buffers (the advance rotates over them) and, at the first advance, two
+ * band buffers of (n/2 - 1) levels each. NULL on error. */
 swept3d *swept3d_create(int nx, int ny, int nz, int pde);
 void swept3d_destroy(swept3d *h);
 

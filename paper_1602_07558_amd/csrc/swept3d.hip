@@ -52,6 +52,7 @@ struct G3 {
   int H;
   long long T0;  // level l applies sub-step T0 + l - 1
   double r;
+  int Hn;        // downward pyramids: height of the next half cycle's upward pyramid to continue with (0: none)
 };
 
 __device__ __forceinline__ void axis_range(bool grow, int l, int n, int h, int& a, int& b) {
@@ -145,16 +146,18 @@ __device__ __forceinline__ double apply(long long T, const NB& nb, double r) {
 }
 
 // One component of launch `group` (0: upward pyramids, 1: face bridges,
-// 2: edge bridges, 3: downward pyramids) per workgroup of NT threads.
+// 2: edge bridges, 3: downward pyramids) per workgroup of NT threads. A
+// downward pyramid that reaches the half cycle's last level h holds the whole
+// tile centred on its corner: that is a tile of the next half cycle's tiling
+// (shifted by h), whose window starts at the same cell, so with g.Hn > 0 the
+// workgroup goes on as that tile's upward pyramid (an octahedron, as in
+// 2D), publishing into the next half cycle's band buffer and output state.
 template <int PDE, int NT>
 __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __restrict__ in,
-                                               double* __restrict__ out, double* __restrict__ bands) {
+                                               double* __restrict__ out, double* __restrict__ bands,
+                                               double* __restrict__ out_next, double* __restrict__ bands_next) {
   extern __shared__ double win[];
   const int n = g.n, h = g.h, W = n + 2, W3 = W * W * W;
-  // buffer l & 1 of the window starts at win + off(l): kept as an offset
-  // from the LDS array (a selected pointer would be a generic one, and every
-  // window access a flat access)
-  auto off = [&](int l) { return (l & 1) * W3; };
   const int tiles = g.tx * g.ty * g.tz;
   int j = (int)blockIdx.x, cls;
   if (group == 0) {
@@ -176,87 +179,99 @@ __global__ __launch_bounds__(NT) void k3_stage(G3 g, int group, const double* __
     return ((size_t)wrap3(bz + z, g.nz) * g.ny + wrap3(by + y, g.ny)) * g.nx + wrap3(bx + x, g.nx);
   };
   auto widx = [&](int x, int y, int z) { return (z * W + y) * W + x; };
-  auto grows = [&](int a) { return ((cls >> a) & 1) != 0; };
 
-  // publish level l: the bands of its shrinking axes to the band buffer
-  // (l < H; each band point once: along the first shrinking axis where it
-  // is in a band), or its whole region to the output state (l == H)
-  auto publish = [&](int l) {
-    int lo[3], hi[3];
+  // Levels 1..H of a component of class c whose level l lives in window
+  // buffer (l + pb) & 1 (kept as an offset from the LDS array: a selected
+  // pointer would be a generic one, and every window access a flat access).
+  // With from_state, level 0 of the region's neighbourhood is loaded from
+  // `src0`; otherwise the window already holds it.
+  auto run = [&](int c, int H, long long T0, const double* src0, bool from_state, double* dst_out, double* bnd,
+                 int pb) {
+    auto grows = [&](int a) { return ((c >> a) & 1) != 0; };
+    auto off = [&](int l) { return ((l + pb) & 1) * W3; };
+    // publish level l: the bands of its shrinking axes to the band buffer
+    // (l < H; each band point once: along the first shrinking axis where it
+    // is in a band), or its whole region to the output state (l == H)
+    auto publish = [&](int l) {
+      int lo[3], hi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
-    const int src = off(l);
-    if (l == g.H) {
-      for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
-                     [&](int x, int y, int z) { out[gidx(x, y, z)] = win[src + widx(x, y, z)]; });
-      return;
-    }
-    double* dst = bands + (size_t)(l - 1) * N;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (grows(a)) continue;
-      AxisSet s[3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        if (b == a)
-          s[b] = aset_ends(lo[b], hi[b]);
-        else if (b < a && !grows(b))
-          s[b] = aset_range(lo[b] + 2, hi[b] - 2);
-        else
-          s[b] = aset_range(lo[b], hi[b]);
+      for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
+      const int src = off(l);
+      if (l == H) {
+        for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
+                       [&](int x, int y, int z) { dst_out[gidx(x, y, z)] = win[src + widx(x, y, z)]; });
+        return;
       }
-      for_points<NT>(s[0], s[1], s[2],
-                     [&](int x, int y, int z) { dst[gidx(x, y, z)] = win[src + widx(x, y, z)]; });
-    }
-  };
-
-  for (int l = 1; l <= g.H; ++l) {
-    int lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
-    // the inputs at level l - 1 this component did not compute: at l = 1 the
-    // whole neighbourhood of its region, from the state; later only the ring
-    // along its growing axes (each ring point once: along the first growing
-    // axis where it is outside the previous level's region)
-    const int dst = off(l - 1);
-    if (l == 1) {
-      for_points<NT>(aset_range(lo[0] - 1, hi[0] + 1), aset_range(lo[1] - 1, hi[1] + 1),
-                     aset_range(lo[2] - 1, hi[2] + 1),
-                     [&](int x, int y, int z) { win[dst + widx(x, y, z)] = in[gidx(x, y, z)]; });
-    } else {
-      const double* src = bands + (size_t)(l - 2) * N;
+      double* dst = bnd + (size_t)(l - 1) * N;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        if (!grows(a)) continue;
+        if (grows(a)) continue;
         AxisSet s[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
           if (b == a)
-            s[b] = aset_ring(lo[b], hi[b]);
-          else if (b < a && grows(b))
-            s[b] = aset_range(lo[b] + 1, hi[b] - 1);
+            s[b] = aset_ends(lo[b], hi[b]);
+          else if (b < a && !grows(b))
+            s[b] = aset_range(lo[b] + 2, hi[b] - 2);
           else
-            s[b] = aset_range(lo[b] - 1, hi[b] + 1);
+            s[b] = aset_range(lo[b], hi[b]);
         }
         for_points<NT>(s[0], s[1], s[2],
-                       [&](int x, int y, int z) { win[dst + widx(x, y, z)] = src[gidx(x, y, z)]; });
+                       [&](int x, int y, int z) { dst[gidx(x, y, z)] = win[src + widx(x, y, z)]; });
       }
+    };
+    for (int l = 1; l <= H; ++l) {
+      int lo[3], hi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) axis_range(grows(a), l, n, h, lo[a], hi[a]);
+      // the inputs at level l - 1 this component did not compute: at l = 1
+      // the whole neighbourhood of its region, from the state; later only the
+      // ring along its growing axes (each ring point once: along the first
+      // growing axis where it is outside the previous level's region)
+      const int dst = off(l - 1);
+      if (l == 1) {
+        if (from_state)
+          for_points<NT>(aset_range(lo[0] - 1, hi[0] + 1), aset_range(lo[1] - 1, hi[1] + 1),
+                         aset_range(lo[2] - 1, hi[2] + 1),
+                         [&](int x, int y, int z) { win[dst + widx(x, y, z)] = src0[gidx(x, y, z)]; });
+      } else {
+        const double* src = bnd + (size_t)(l - 2) * N;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (!grows(a)) continue;
+          AxisSet s[3];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            if (b == a)
+              s[b] = aset_ring(lo[b], hi[b]);
+            else if (b < a && grows(b))
+              s[b] = aset_range(lo[b] + 1, hi[b] - 1);
+            else
+              s[b] = aset_range(lo[b] - 1, hi[b] + 1);
+          }
+          for_points<NT>(s[0], s[1], s[2],
+                         [&](int x, int y, int z) { win[dst + widx(x, y, z)] = src[gidx(x, y, z)]; });
+        }
+      }
+      if (l >= 2) publish(l - 1);
+      __syncthreads();
+      const int I = off(l - 1), O = off(l);
+      const long long T = T0 + l - 1;
+      for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
+                     [&](int x, int y, int z) {
+                       const int cc = widx(x, y, z);
+                       auto nb = [&](int q) {
+                         return win[I + cc + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)];
+                       };
+                       win[O + cc] = apply<PDE>(T, nb, g.r);
+                     });
+      __syncthreads();
     }
-    if (l >= 2) publish(l - 1);
-    __syncthreads();
-    const int I = off(l - 1), O = off(l);
-    const long long T = g.T0 + l - 1;
-    for_points<NT>(aset_range(lo[0], hi[0]), aset_range(lo[1], hi[1]), aset_range(lo[2], hi[2]),
-                   [&](int x, int y, int z) {
-                     const int c = widx(x, y, z);
-                     auto nb = [&](int q) {
-                       return win[I + c + ((q / 9 - 1) * W + ((q / 3) % 3 - 1)) * W + (q % 3 - 1)];
-                     };
-                     win[O + c] = apply<PDE>(T, nb, g.r);
-                   });
-    __syncthreads();
-  }
-  publish(g.H);
+    publish(H);
+  };
+
+  run(cls, g.H, g.T0, in, true, out, bands, 0);
+  if (group == 3 && g.Hn > 0) run(0, g.Hn, g.T0 + g.H, nullptr, false, out_next, bands_next, g.H);
 }
 
 // One step of every point, reading its neighbourhood with periodic wrap.
@@ -293,11 +308,13 @@ hipError_t stage_lds(size_t bytes) {
 
 template <int PDE>
 void launch_stage(int n, int blocks, size_t lds, hipStream_t st, const G3& g, int group, const double* in,
-                  double* out, double* bands) {
+                  double* out, double* bands, double* out_next, double* bands_next) {
   if (stage_threads(n) == 512)
-    hipLaunchKernelGGL((k3_stage<PDE, 512>), dim3(blocks), dim3(512), lds, st, g, group, in, out, bands);
+    hipLaunchKernelGGL((k3_stage<PDE, 512>), dim3(blocks), dim3(512), lds, st, g, group, in, out, bands, out_next,
+                       bands_next);
   else
-    hipLaunchKernelGGL((k3_stage<PDE, 256>), dim3(blocks), dim3(256), lds, st, g, group, in, out, bands);
+    hipLaunchKernelGGL((k3_stage<PDE, 256>), dim3(blocks), dim3(256), lds, st, g, group, in, out, bands, out_next,
+                       bands_next);
 }
 
 }  // namespace
@@ -306,9 +323,12 @@ struct swept3d {
   int nx = 0, ny = 0, nz = 0, pde = 0, n = 0;
   double r = 0.0;
   size_t N = 0;
-  double* state[2] = {nullptr, nullptr};
+  // three state buffers: a half cycle reads level 0 from one and writes its
+  // last level to the next; the octahedra of its downward pyramids write the
+  // next half cycle's upward pyramids' last level to the third
+  double* state[3] = {nullptr, nullptr, nullptr};
   int cur = 0;
-  double* bands = nullptr;
+  double* bands[2] = {nullptr, nullptr};  // by half-cycle parity
   int band_levels = 0;
   hipStream_t stream = nullptr;
   long long T = 0, half = 0;
@@ -337,11 +357,14 @@ const char* tile_problem3(const swept3d* h, int n) {
 
 int ensure_bands(swept3d* h, int levels) {
   if (levels <= h->band_levels) return 0;
-  if (h->bands) hipFree(h->bands);
-  h->bands = nullptr;
+  for (double*& b : h->bands) {
+    if (b) hipFree(b);
+    b = nullptr;
+  }
   h->band_levels = 0;
-  if (hipMalloc(&h->bands, (size_t)levels * h->N * sizeof(double)) != hipSuccess)
-    return set_error(SWEPT2D_ENOMEM, "cannot allocate %d band levels", levels);
+  for (double*& b : h->bands)
+    if (hipMalloc(&b, (size_t)levels * h->N * sizeof(double)) != hipSuccess)
+      return set_error(SWEPT2D_ENOMEM, "cannot allocate %d band levels", levels);
   h->band_levels = levels;
   return 0;
 }
@@ -401,8 +424,9 @@ swept3d* swept3d_create(int nx, int ny, int nz, int pde) {
     }
   const size_t bytes = h->N * sizeof(double);
   if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipMalloc(&h->state[0], bytes) != hipSuccess || hipMalloc(&h->state[1], bytes) != hipSuccess) {
-    set_error(SWEPT2D_ENOMEM, "cannot allocate %zu bytes of state", 2 * bytes);
+      hipMalloc(&h->state[0], bytes) != hipSuccess || hipMalloc(&h->state[1], bytes) != hipSuccess ||
+      hipMalloc(&h->state[2], bytes) != hipSuccess) {
+    set_error(SWEPT2D_ENOMEM, "cannot allocate %zu bytes of state", 3 * bytes);
     swept3d_destroy(h);
     return nullptr;
   }
@@ -418,9 +442,10 @@ swept3d* swept3d_create(int nx, int ny, int nz, int pde) {
 void swept3d_destroy(swept3d* h) {
   if (!h) return;
   if (h->stream) hipStreamSynchronize(h->stream);
-  if (h->state[0]) hipFree(h->state[0]);
-  if (h->state[1]) hipFree(h->state[1]);
-  if (h->bands) hipFree(h->bands);
+  for (double* p : h->state)
+    if (p) hipFree(p);
+  for (double* p : h->bands)
+    if (p) hipFree(p);
   if (h->stream) hipStreamDestroy(h->stream);
   delete h;
 }
@@ -469,6 +494,11 @@ int swept3d_advance(swept3d* h, long long nsteps) {
   }
   const size_t lds = window_bytes3(h->n);
   const int tiles = (h->nx / h->n) * (h->ny / h->n) * (h->nz / h->n);
+  // Half cycles: upward pyramids (only where the previous half cycle's
+  // octahedra did not already compute them), face bridges, edge bridges,
+  // downward pyramids, the last fused with the next half cycle's upward
+  // pyramids when this half cycle is full and another follows.
+  bool ups_done = false;
   for (long long done = 0; done < nsteps;) {
     G3 g;
     g.nx = h->nx;
@@ -483,17 +513,24 @@ int swept3d_advance(swept3d* h, long long nsteps) {
     g.H = (int)std::min<long long>(hh, nsteps - done);
     g.T0 = h->T;
     g.r = h->r;
+    const long long rest = nsteps - done - g.H;
+    g.Hn = (g.H == hh && rest > 0) ? (int)std::min<long long>(hh, rest) : 0;
     const double* in = h->state[h->cur];
-    double* out = h->state[h->cur ^ 1];
-    for (int group = 0; group < 4; ++group) {
+    double* out = h->state[(h->cur + 1) % 3];
+    double* out_next = h->state[(h->cur + 2) % 3];
+    double* bands = h->bands[h->half & 1];
+    double* bands_next = h->bands[(h->half + 1) & 1];
+    for (int group = ups_done ? 1 : 0; group < 4; ++group) {
       const int blocks = (group == 1 || group == 2) ? 3 * tiles : tiles;
       if (h->pde == SWEPT3D_HEAT7)
-        launch_stage<SWEPT3D_HEAT7>(h->n, blocks, lds, h->stream, g, group, in, out, h->bands);
+        launch_stage<SWEPT3D_HEAT7>(h->n, blocks, lds, h->stream, g, group, in, out, bands, out_next, bands_next);
       else
-        launch_stage<SWEPT3D_TEST_HASH27>(h->n, blocks, lds, h->stream, g, group, in, out, h->bands);
+        launch_stage<SWEPT3D_TEST_HASH27>(h->n, blocks, lds, h->stream, g, group, in, out, bands, out_next,
+                                          bands_next);
       HIP3(hipGetLastError(), "stage launch");
     }
-    h->cur ^= 1;
+    ups_done = g.Hn > 0;
+    h->cur = (h->cur + 1) % 3;
     h->half += 1;
     h->T += g.H;
     done += g.H;
@@ -507,7 +544,7 @@ int swept3d_plain_advance(swept3d* h, long long nsteps) {
   const unsigned blocks = (unsigned)((h->N + 255) / 256);
   for (long long s = 0; s < nsteps; ++s) {
     const double* in = h->state[h->cur];
-    double* out = h->state[h->cur ^ 1];
+    double* out = h->state[(h->cur + 1) % 3];
     if (h->pde == SWEPT3D_HEAT7)
       hipLaunchKernelGGL(k3_plain<SWEPT3D_HEAT7>, dim3(blocks), dim3(256), 0, h->stream, in, out, h->nx, h->ny, h->nz,
                          h->T, h->r);
@@ -515,7 +552,7 @@ int swept3d_plain_advance(swept3d* h, long long nsteps) {
       hipLaunchKernelGGL(k3_plain<SWEPT3D_TEST_HASH27>, dim3(blocks), dim3(256), 0, h->stream, in, out, h->nx, h->ny,
                          h->nz, h->T, h->r);
     HIP3(hipGetLastError(), "per-step launch");
-    h->cur ^= 1;
+    h->cur = (h->cur + 1) % 3;
     h->T += 1;
   }
   return 0;
