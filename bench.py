@@ -181,7 +181,7 @@ def other_workloads(sw, si, np):
     the FP32 forms' normwise error against the FP64 result of the same run:
     the wave 2048^2 and Euler 512^2 grids (swept), the paper's Euler
     discretisation on its 1024 x 512 tunnel (swept and per-step), 3D heat on
-    128^3 and 256^3 (swept and per-step), heat on 8192^2 (state beyond the
+    128^3 and 192^3 (swept and per-step), heat on 8192^2 (state beyond the
     Infinity Cache: swept and per-step) and the
     uneven 256-grid batches (phased launches, model tile sides)."""
     out = {}
@@ -263,9 +263,9 @@ def other_workloads(sw, si, np):
         "swept_substep_value": 4 * fd["swept"], "steps": 200, "tile": fd["tile"],
         "swept_over_plain": fd["swept"] / fd["plain"],
         "note": "50 MB state (12 FP64 values per point) stays in the Infinity Cache; both paths latency-bound"}
-    # The swept rule in 3D: 7-point heat on 128^3 and 256^3, cube tiles of
-    # side 16, swept and per-step.
-    for L in (128, 256):
+    # The swept rule in 3D: 7-point heat on 128^3 (cube tile 16) and 192^3
+    # (tile 12), swept and per-step.
+    for L in (128, 192):
         s3 = si.heat3d_field(L, L, L, seed=0)
         r3 = {}
         for method in ("swept", "plain"):

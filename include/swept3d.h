@@ -46,8 +46,9 @@ typedef struct swept3d swept3d;
 
 /* Create a grid of nx * ny * nz points (each at least 2) for scheme `pde`
  * on the current device, with the state at zero, sub-step counter 0 and the
- * default tile side (the largest even side up to 16 dividing nx, ny and nz
- * whose two-buffer window fits the workgroup LDS). Allocates three state
+ * default tile side (the first of 12, 14, 16, 10, 18, 8, 6, 4, 2 that
+ * divides nx, ny and nz and whose two-buffer window fits the workgroup LDS;
+ * 0 if none, and then only swept3d_plain_advance runs). Allocates three state
  * buffers (the advance rotates over them) and, at the first advance, two
  * band buffers of (n/2 - 1) levels each. NULL on error. */
 swept3d *swept3d_create(int nx, int ny, int nz, int pde);
