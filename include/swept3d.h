@@ -52,30 +52,45 @@ typedef struct swept3d swept3d;
  * buffers (the advance rotates over them) and, at the first advance, two
  * band buffers of (n/2 - 1) levels each. NULL on error. */
 swept3d *swept3d_create(int nx, int ny, int nz, int pde);
+
+/* Wait for the handle's work, free its device memory and stream, and the
+ * handle. NULL is ignored. */
 void swept3d_destroy(swept3d *h);
 
-/* Parameters of the scheme (HEAT7: 1 value). Copied. */
+/* Parameters of the scheme (HEAT7: {r}, 1 value; TEST_HASH27: none), copied
+ * from the caller's array. EINVAL for a null handle or fewer values than
+ * the scheme needs. */
 int swept3d_set_params(swept3d *h, const double *params, int nparams);
 
 /* Cube tile side n: even, at least 2, dividing nx, ny and nz, with
  * 2 (n + 2)^3 doubles of window within the workgroup LDS (n <= 18 in the
  * 160 KB of gfx950). EINVAL otherwise, leaving the side unchanged. */
 int swept3d_set_tile(swept3d *h, int n);
+
+/* The current tile side (0: no side divides the grid), or EINVAL for a null
+ * handle. */
 int swept3d_get_tile(const swept3d *h);
 
-/* Host <-> device copies of the state (nz * ny * nx doubles, host memory
- * owned by the caller). Synchronous. */
+/* Host <-> device copies of the state (nz * ny * nx doubles, [z][y][x],
+ * host memory owned by the caller). Synchronous: they wait for the handle's
+ * earlier work. EINVAL for null arguments, EHIP on a copy failure. */
 int swept3d_upload(swept3d *h, const double *host);
 int swept3d_download(swept3d *h, double *host);
 
-/* Advance nsteps steps (nsteps >= 0) with the swept rule: half cycles of h
- * levels, the last one reduced to the remaining count. Asynchronous on the
- * handle's stream. */
+/* Advance nsteps steps (nsteps >= 0) with the swept rule (Sec. 3-4, the
+ * level function on cube tiles): half cycles of h = n/2 levels, the last one
+ * reduced to the remaining count, tilings alternating between offsets 0 and
+ * h. Asynchronous on the handle's stream; the first call allocates the band
+ * buffers (ENOMEM if they do not fit). EINVAL for a negative count or when
+ * no tile side divides the grid. The results equal swept3d_plain_advance's
+ * bit for bit. */
 int swept3d_advance(swept3d *h, long long nsteps);
 
-/* Advance nsteps steps with one launch per step (the comparison method). */
+/* Advance nsteps steps with one launch per step (the comparison method;
+ * Sec. 2's plain stepping). Asynchronous; EINVAL for a negative count. */
 int swept3d_plain_advance(swept3d *h, long long nsteps);
 
+/* Wait for the handle's work; EHIP reports a failure of earlier kernels. */
 int swept3d_synchronize(swept3d *h);
 
 /* Global sub-step counter (the stencil's sub-step index). set_step fixes it
