@@ -2,7 +2,8 @@
 bit for bit: the 27-point test hash (any misplaced neighbour or level changes
 the result) at every even tile side that divides the grid, step counts that
 end inside a half cycle, split advances and a nonzero starting sub-step; the
-per-step method; 7-point heat at full size; error codes.
+per-step method; 7-point heat at full size (128^3 at tile 16, 192^3 at tile
+12); error codes.
 """
 import sys
 
@@ -74,6 +75,17 @@ def test_heat7_128_cubed_full_size():
     got, tile = run3(HEAT, s0, [si.HEAT3D_R], 200)
     ref = oracle.advance3d_f64(HEAT, s0, [si.HEAT3D_R], 200, threads=oracle.default_threads())
     assert tile == 16 and np.array_equal(got, ref)
+
+
+@pytest.mark.timeout(600)
+def test_heat7_192_cubed_default_tile_12():
+    """192^3 at its default tile side (12, as the benchmark runs it), 64
+    steps (eight half cycles, every downward pyramid but the last fused with
+    the next upward pyramid), every point."""
+    s0 = si.heat3d_field(192, 192, 192, seed=0)
+    got, tile = run3(HEAT, s0, [si.HEAT3D_R], 64)
+    ref = oracle.advance3d_f64(HEAT, s0, [si.HEAT3D_R], 64, threads=oracle.default_threads())
+    assert tile == 12 and np.array_equal(got, ref)
 
 
 def test_errors():
