@@ -527,12 +527,19 @@ __global__ __launch_bounds__(NT) void k_rect_bridge(RGeo g, int par, int H, type
 }
 
 // The instantiation that runs window pitch P: 66 and 34 for light schemes
-// (rect_geo picks those pitches only for them), the run-time pitch otherwise.
+// (rect_geo picks those pitches only for them), the run-time pitch otherwise,
+// on 4 waves, or on 8 for the flux schemes' column walk from pitch 22 (tiles
+// of 20 and more: Rusanov Euler on 511 x 509, full RK2 steps/s, height 12
+// 5.6e9 on 4 waves, 6.4e9 on 8; height 6 6.3e9 and 3.7e9).
+constexpr int kRectWalkWidePitch = 22;
 template <class S, class F>
 hipError_t rect_by_pitch(int P, F&& f) {
   if constexpr (Lay<S, 66>::light) {
     if (P == 66) return f(std::integral_constant<int, 66>{}, std::integral_constant<int, 1024>{});
     if (P == 34) return f(std::integral_constant<int, 34>{}, std::integral_constant<int, 256>{});
+  }
+  if constexpr (walks<S>::value) {
+    if (P >= kRectWalkWidePitch) return f(std::integral_constant<int, 0>{}, std::integral_constant<int, 512>{});
   }
   return f(std::integral_constant<int, 0>{}, std::integral_constant<int, kRectThreads>{});
 }
@@ -582,6 +589,9 @@ hipError_t rect_lds_t(int bytes) {
     return hipSuccess;
   } else {
     hipError_t e = rect_lds_one<S, 0, kRectThreads>(bytes);
+    if constexpr (walks<S>::value) {
+      if (e == hipSuccess) e = rect_lds_one<S, 0, 512>(bytes);
+    }
     if constexpr (Lay<S, 66>::light) {
       if (e == hipSuccess) e = rect_lds_one<S, 66, 1024>(bytes);
       if (e == hipSuccess) e = rect_lds_one<S, 34, 256>(bytes);

@@ -74,7 +74,7 @@ def test_eulerfd_split_advances_and_graph_replay():
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("nx,ny,hh,steps", [(45, 39, 3, 10), (37, 64, 4, 9), (21, 21, 2, 6)])
+@pytest.mark.parametrize("nx,ny,hh,steps", [(45, 39, 3, 10), (37, 64, 4, 9), (21, 21, 2, 6), (45, 41, 10, 12)])
 def test_eulerfd_rect_tiles_bitwise(nx, ny, hh, steps):
     s0 = _field(nx, ny, 3)
     ref = oracle.advance_f64(EFD, s0, PRM, 4 * steps)

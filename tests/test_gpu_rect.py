@@ -78,10 +78,21 @@ def test_rect_euler_and_push5_fp64():
     assert np.array_equal(got, ref)
 
 
+def test_rect_euler_wide_tiles_fp64():
+    """Tiles 20 and more wide (window pitch 22 and up): the Euler column walk
+    on its 8-wave workgroups."""
+    s0 = si.euler_field(61, 43, seed=4)
+    prm = si.default_params(si.EULER_RUS_RK2, s0)
+    ref = oracle.advance_f64(si.EULER_RUS_RK2, s0, prm, 2 * 25)
+    got = rect_run(si.EULER_RUS_RK2, s0, prm, 25, 10)
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("pde,nx,ny,steps,hh", [
     (si.HEAT5, 61, 47, 400, 5),
     (si.WAVE_LF, 53, 71, 300, 7),
     (si.EULER_RUS_RK2, 33, 35, 20, 4),
+    (si.EULER_RUS_RK2, 49, 45, 12, 11),
 ])
 def test_rect_fp32c_bitwise_against_compensated_oracle(pde, nx, ny, steps, hh):
     s0 = si.initial_state(pde, nx, ny, seed=5)
