@@ -17,7 +17,8 @@ library's stream; the LDS and FP64 rooflines of the same kernel sit beside
 it, the LDS peak measured on the device.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu]
-  python bench.py --profile-pass     (short run used under rocprofv3 --pmc)
+  python bench.py --profile-pass [--profile-workload heat|euler_fd|heat3d]
+                                     (short run used under rocprofv3 --pmc)
 """
 from __future__ import annotations
 
@@ -339,6 +340,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--profile-workload", choices=("heat", "euler_fd", "heat3d"), default="heat")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (the swept decomposition would "
@@ -357,13 +359,26 @@ def main():
     p = si.default_params(si.HEAT5)
 
     if args.profile_pass:
-        # Short run for counter collection: the swept FP64 path (20 half
-        # cycles), 64 per-step launches, and a plain copy of known size that
-        # calibrates the byte counters.
-        g = sw.Swept2D(NX, NY, si.HEAT5, p)
-        g.upload(s0)
-        g.advance(640)
-        g.plain_advance(64)
+        # Short run for counter collection: the swept FP64 path, per-step
+        # launches, and a plain copy of known size that calibrates the byte
+        # counters. heat: 1024^2, 20 half cycles and 64 steps; euler_fd: the
+        # 1024 x 512 tunnel, 5 half cycles (40 steps) and 8 steps; heat3d:
+        # 128^3, 4 half cycles (32 steps) and 8 steps.
+        if args.profile_workload == "euler_fd":
+            g = sw.Swept2D(1024, 512, si.EULER_FD_RK4, si.default_params(si.EULER_FD_RK4))
+            g.upload(si.initial_state(si.EULER_FD_RK4, 1024, 512, seed=0))
+            g.advance(40)
+            g.plain_advance(8)
+        elif args.profile_workload == "heat3d":
+            g = sw.Swept3D(128, 128, 128, si.HEAT7_3D, [si.HEAT3D_R])
+            g.upload(si.heat3d_field(128, 128, 128, seed=0))
+            g.advance(32)
+            g.plain_advance(8)
+        else:
+            g = sw.Swept2D(NX, NY, si.HEAT5, p)
+            g.upload(s0)
+            g.advance(640)
+            g.plain_advance(64)
         g.synchronize()
         a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)

@@ -144,7 +144,7 @@ def main(argv):
         for c in names:
             for k, vals in counter_values(directory, c).items():
                 n = short_name(k)
-                if n.startswith("k_"):
+                if re.match(r"k[0-9]?_", n):
                     rows[n][c] = (sum(vals) / len(vals), len(vals))
         print(f"{'kernel':42s} {'launches':>8s} " + " ".join(f"{c:>16s}" for c in names))
         for n in sorted(rows):
