@@ -90,6 +90,13 @@ def test_eulerfd_uniform_free_stream_unchanged():
     assert np.array_equal(got, s0)
 
 
+def test_eulerfd_has_no_fp32_forms():
+    for prec in (sw.FP32C, sw.FP32R):
+        with pytest.raises(sw.Swept2DError) as e:
+            sw.Swept2D(64, 32, EFD, PRM, prec=prec)
+        assert e.value.code == sw.EUNSUPPORTED
+
+
 @pytest.mark.timeout(600)
 def test_eulerfd_tunnel_1024x512_full_size_bitwise():
     """The paper's tunnel grid and time step in the benchmark's configuration
