@@ -1,8 +1,9 @@
 """Pins of the 3D oracle and of the 3D swept decomposition model (CPU).
 
 The plain 3D stepper is pinned by closed forms (the discrete von Neumann
-factor of the 7-point heat stencil, conservation) and by the locality of the
-27-point hash. The decomposition model (``oracle/swept_model3d.py``) must
+factor of the 7-point heat stencil, conservation, exact dyadic steps) and by
+the locality and level seeding of the 27-point hash; planted mistakes in
+either stencil fail these pins. The decomposition model (``oracle/swept_model3d.py``) must
 reach plain stepping bit for bit on cube tilings of every even side that
 divides the grid, for full and reduced half cycles and both tiling offsets,
 and it must fail when the class groups run in another order or when a
@@ -53,6 +54,15 @@ def test_hash27_is_local_to_the_neighbourhood():
     diff = np.argwhere(out != base)
     assert diff.min(axis=0).tolist() == [1, 2, 3] and diff.max(axis=0).tolist() == [5, 6, 7]
     assert len(diff) == 125
+
+
+def test_hash27_is_seeded_with_the_sub_step_index():
+    """A value computed at the wrong level must differ: the same
+    neighbourhood hashed at sub-steps 0 and 1 gives different values."""
+    u0 = si.hash3d_field(6, 5, 4, seed=8)
+    a = oracle.advance3d_f64(HASH27, u0, [], 1, t0=0)
+    b = oracle.advance3d_f64(HASH27, u0, [], 1, t0=1)
+    assert np.all(a != b)
 
 
 @pytest.mark.parametrize("shape,n,steps", [((8, 8, 8), 4, 5), ((8, 12, 16), 4, 7), ((8, 8, 8), 8, 9),
