@@ -63,6 +63,11 @@ def test_hash27_is_seeded_with_the_sub_step_index():
     a = oracle.advance3d_f64(HASH27, u0, [], 1, t0=0)
     b = oracle.advance3d_f64(HASH27, u0, [], 1, t0=1)
     assert np.all(a != b)
+    # order-sensitive: exchanging two neighbours of a point changes its value
+    w = u0.copy()
+    w[2, 2, 2], w[2, 2, 3] = u0[2, 2, 3], u0[2, 2, 2]
+    c = oracle.advance3d_f64(HASH27, w, [], 1, t0=0)
+    assert c[2, 2, 2] != a[2, 2, 2] and c[2, 3, 3] != a[2, 3, 3]
 
 
 @pytest.mark.parametrize("shape,n,steps", [((8, 8, 8), 4, 5), ((8, 12, 16), 4, 7), ((8, 8, 8), 8, 9),
