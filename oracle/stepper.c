@@ -455,14 +455,41 @@ static void st_euler_f32c(long long T, const float nu[9][MAXV], const float nc[9
     }
 }
 
+/* The paper's Euler discretisation (st_eulerfd) on FP32-compensated slots:
+ * every input widened to the FP64 value u - c, the FP64 sub-step applied,
+ * each slot the sub-step changes split back; slots it carries unchanged (the
+ * conserved values U before the last stage) keep their pair as it is, and
+ * the zeroed derivative sum is the pair (0, 0). */
+static void st_eulerfd_f32c(long long T, const float nu[9][MAXV], const float nc[9][MAXV], float *ou,
+                            float *oc, const double *prm)
+{
+    double nb[9][MAXV], out[MAXV];
+    for (int k = 0; k < 9; ++k)
+        for (int v = 0; v < 12; ++v)
+            nb[k][v] = (double)nu[k][v] - (double)nc[k][v];
+    st_eulerfd(T, nb, out, prm);
+    const int last = (int)(T & 3) == 3;
+    for (int v = 0; v < 12; ++v) {
+        if (v < 4 && !last) {
+            ou[v] = nu[4][v];
+            oc[v] = nc[4][v];
+        } else if (v >= 8 && last) {
+            ou[v] = 0.0f;
+            oc[v] = 0.0f;
+        } else {
+            split_f64(out[v], &ou[v], &oc[v]);
+        }
+    }
+}
+
 /* Advance an FP32-compensated state (u and c planes, each [nvars][ny][nx]).
- * Only heat, wave and Euler have a compensated form. */
+ * Heat, wave and both Euler schemes have a compensated form. */
 int oracle_advance_f32c(int pde, int nx, int ny, int nvars, const double *params, int nparams,
                         float *u, float *c, long long t0, long long nsub, int nthreads)
 {
     if (nx < 1 || ny < 1 || nsub < 0 || t0 < 0 || !u || !c || !pde_shape_ok(pde, nvars))
         return -1;
-    if (pde != PDE_HEAT5 && pde != PDE_WAVE_LF && pde != PDE_EULER_RUS_RK2)
+    if (pde != PDE_HEAT5 && pde != PDE_WAVE_LF && pde != PDE_EULER_RUS_RK2 && pde != PDE_EULER_FD_RK4)
         return -1;
     if (nparams < nparams_needed(pde) || !params)
         return -1;
@@ -499,6 +526,7 @@ int oracle_advance_f32c(int pde, int nx, int ny, int nvars, const double *params
                 case PDE_HEAT5: st_heat_f32c(nu, ncp[4], ou, oc, params); break;
                 case PDE_WAVE_LF: st_wave_f32c(nu, ncp, ou, oc, params); break;
                 case PDE_EULER_RUS_RK2: st_euler_f32c(T, nu, ncp, ou, oc, params); break;
+                case PDE_EULER_FD_RK4: st_eulerfd_f32c(T, nu, ncp, ou, oc, params); break;
                 }
                 for (int v = 0; v < nvars; ++v) {
                     xu[(size_t)v * plane + (size_t)j * nx + i] = ou[v];
