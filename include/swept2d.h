@@ -70,7 +70,7 @@ extern "C" {
  *                         stage per sub-step; slots 0..3 conserved, 4..7
  *                         the stage value (equal to 0..3 at full steps),
  *                         8..11 the stage-derivative sum (zero at full
- *                         steps); params {gamma, dt/h}. FP64 only.
+ *                         steps); params {gamma, dt/h}. FP64 and FP32C.
  *   TEST_HASH      1 / 1  order-sensitive 64-bit mix of the 9 neighbours and
  *                         the sub-step index (values: integers < 2^52)
  *   TEST_INCR      1 / 1  u' = u + 1 if all 9 neighbours equal u, else NaN
@@ -98,9 +98,11 @@ extern "C" {
 /* ------------------------------------------------------------- precisions
  * FP64:  one double per value.
  * FP32C: FP32 value u plus an FP32 compensation c per value (the pair stands
- *        for u - c); the time update is compensated (Kahan), Euler fluxes and
- *        pressure are evaluated in FP64. Available for HEAT5, WAVE_LF and
- *        EULER_RUS_RK2. Device layout: nvars u-planes then nvars c-planes,
+ *        for u - c). Heat and wave compensate the time update (Kahan); the
+ *        Euler schemes widen every value to the FP64 u - c, apply the FP64
+ *        sub-step and split each result t into u = fl32(t), c = fl32(u - t).
+ *        Available for HEAT5, WAVE_LF, EULER_RUS_RK2 and EULER_FD_RK4.
+ *        Device layout: nvars u-planes then nvars c-planes,
  *        each [ny][nx] float. Swept and per-step results are identical.
  * FP32R: FP32 values u only in the state and the panels (half the bytes of
  *        FP32C); the compensations of the same updates live only in a

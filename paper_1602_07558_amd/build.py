@@ -32,7 +32,7 @@ PLUGIN_SRC = os.path.join(ROOT, "tests", "plugin", "paper_eq1_scheme.hip")
 PLUGIN_LIB = os.path.join(ROOT, "tests", "plugin", "libpaper_eq1_scheme.so")
 
 SCHEMES = ["Heat64", "Wave64", "Euler64", "Hash64", "Incr64", "Push5", "Heat32C", "Wave32C", "Euler32C",
-           "Heat32R", "Wave32R", "Hash25x2", "EulerFD64"]
+           "Heat32R", "Wave32R", "Hash25x2", "EulerFD64", "EulerFD32C"]
 # Batch launch classes: (window pitch, workgroup size).
 # negative pitches: rectangular tiles at window pitch 66, 34 and run-time
 BATCH_CLASSES = [(66, 1024), (34, 256), (18, 64), (0, 256), (0, 64), (-66, 1024), (-34, 256), (-1, 256)]

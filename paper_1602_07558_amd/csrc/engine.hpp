@@ -122,6 +122,7 @@ enum Scheme : int {
   kWave32R,
   kHash25x2,
   kEulerFD64,
+  kEulerFD32C,
   kNumSchemes
 };
 

@@ -574,6 +574,67 @@ struct Euler32C {
   }
 };
 
+// The central-difference Euler scheme with FP32 state, as Euler32C: every
+// slot widened to the FP64 value u - c, EulerFD64's sub-step applied, and
+// each slot the sub-step changes split into u = fl32(t), c = fl32(u - t);
+// the U slots that sub-steps 0..2 carry keep both halves as they are, and
+// the last sub-step clears K in both. Slots 0..11 values, 12..23
+// compensations.
+struct EulerFD32C {
+  using V = float;
+  static constexpr int NV = 24, NW = 24, NVAR = 12, SUB = 4;
+  static constexpr bool XY_SYM = false;
+  static constexpr bool WALK = true;  // as EulerFD64, on the widened values
+  static constexpr int CN = EulerFD64::CN;
+  __device__ __forceinline__ static int wstage(long long T) { return EulerFD64::wstage(T); }
+  __device__ __forceinline__ static double wload(const V* p, int plane, int v) {
+    return (double)p[v * plane] - (double)p[(12 + v) * plane];
+  }
+  __device__ __forceinline__ static void wcells(const double* C, const SchemeParams& sp, double* cx, double* cy) {
+    EulerFD64::wcells(C, sp, cx, cy);
+  }
+  __device__ __forceinline__ static void wface(const double* cL, const double* cR, int d, const SchemeParams& sp,
+                                               double* F) {
+    EulerFD64::wface(cL, cR, d, sp, F);
+  }
+  __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double*,
+                                                const double* div, const SchemeParams& sp, V* dst) {
+    double t[12];
+    EulerFD64::update(T, [&](int v) { return wload(own, plane, v); }, div, sp.p[1], t, 1);
+    store(T, [&](int v) { return own[v * plane]; }, t, dst, plane);
+  }
+  // Slots of the new point from the FP64 results t and the old halves.
+  template <class OLD>
+  __device__ __forceinline__ static void store(long long T, const OLD& old, const double* t, V* out, int stride) {
+    const bool last = (T & 3) == 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (last) {
+        split(t[k], out[k * stride], out[(12 + k) * stride]);
+        out[(8 + k) * stride] = 0.0f;
+        out[(20 + k) * stride] = 0.0f;
+      } else {
+        out[k * stride] = old(k);
+        out[(12 + k) * stride] = old(12 + k);
+        split(t[8 + k], out[(8 + k) * stride], out[(20 + k) * stride]);
+      }
+      split(t[4 + k], out[(4 + k) * stride], out[(16 + k) * stride]);
+    }
+  }
+  __device__ __forceinline__ static void split(double t, float& u, float& c) {
+    const float hi = (float)t;
+    u = hi;
+    c = (float)((double)hi - t);
+  }
+  template <class NB>
+  __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
+    double t[12];
+    EulerFD64::step(T, [&](int di, int dj, int v) { return (double)nb(di, dj, v) - (double)nb(di, dj, 12 + v); },
+                    t, sp);
+    store(T, [&](int v) { return nb(0, 0, v); }, t, out, 1);
+  }
+};
+
 // ------------------------------------------- stencils reaching two rings
 //
 // Sec. 2 asks a stencil that reads beyond its nearest neighbours to be split

@@ -109,6 +109,7 @@ int scheme_of(int pde, int prec) {
       case SWEPT2D_HEAT5: return kHeat32C;
       case SWEPT2D_WAVE_LF: return kWave32C;
       case SWEPT2D_EULER_RUS_RK2: return kEuler32C;
+      case SWEPT2D_EULER_FD_RK4: return kEulerFD32C;
     }
   } else if (prec == SWEPT2D_FP32R) {
     switch (pde) {
@@ -333,6 +334,7 @@ double scheme_cost(int scheme) {
     case kHeat32R: return 1.5;
     case kWave32R: return 2.2;
     case kEuler32C: return 36.0;
+    case kEulerFD32C: return 66.0;
     default: return 1.0;
   }
 }

@@ -23,6 +23,7 @@ extern template struct Stages<Heat32R>;
 extern template struct Stages<Wave32R>;
 extern template struct Stages<Hash25x2>;
 extern template struct Stages<EulerFD64>;
+extern template struct Stages<EulerFD32C>;
 extern template struct BatchPhase<66, 1024>;
 extern template struct BatchPhase<34, 256>;
 extern template struct BatchPhase<18, 64>;
@@ -63,6 +64,7 @@ __global__ void k_batch_bump(BatchGrid* grids, const BatchPlan* plans, int ngrid
     case kWave32R: return Stages<Wave32R>::FN(__VA_ARGS__);   \
     case kHash25x2: return Stages<Hash25x2>::FN(__VA_ARGS__); \
     case kEulerFD64: return Stages<EulerFD64>::FN(__VA_ARGS__); \
+    case kEulerFD32C: return Stages<EulerFD32C>::FN(__VA_ARGS__); \
     default: break;                                          \
   }
 

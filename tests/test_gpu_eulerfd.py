@@ -1,6 +1,6 @@
 """GPU parity of the paper's Euler discretisation (EULER_FD_RK4: skew-symmetric
-central differences, four-stage Runge-Kutta as four sub-steps, 12 FP64 values
-per point) against the oracle, bit for bit.
+central differences, four-stage Runge-Kutta as four sub-steps, 12 values per
+point) against the oracle, bit for bit, in FP64 and in compensated FP32.
 
 Square tiles of every side whose window fits the LDS, staged and unstaged
 panels, step counts that end inside a half cycle, split advances that start
@@ -26,16 +26,21 @@ def _say(*a):
 
 
 def run(state, params, nsteps, tile=0, rect=0, method="swept", mode=sw.LAUNCH_DIRECT, staging=sw.STAGING_AUTO,
-        splits=None):
-    nvars, ny, nx = state.shape
-    _say("euler_fd_rk4", f"{nx}x{ny}", "tile", tile, "rect", rect, "steps", nsteps, method, "mode", mode,
-         "staging", staging, "splits", splits)
-    with sw.Swept2D(nx, ny, EFD, params, tile=tile) as g:
+        splits=None, prec=sw.FP64):
+    """Advance `state` (FP64 slots, or for FP32C the raw u planes then c
+    planes) and return the raw device state."""
+    _, ny, nx = state.shape
+    _say("euler_fd_rk4", f"{nx}x{ny}", "prec", prec, "tile", tile, "rect", rect, "steps", nsteps, method,
+         "mode", mode, "staging", staging, "splits", splits)
+    with sw.Swept2D(nx, ny, EFD, params, prec=prec, tile=tile) as g:
         if rect:
             g.rect = rect
         g.set_launch_mode(mode)
         g.set_staging(staging)
-        g.upload(state)
+        if prec == sw.FP64:
+            g.upload(state)
+        else:
+            g.upload_raw(state)
         for part in (splits or [nsteps]):
             (g.advance if method == "swept" else g.plain_advance)(part)
         g.synchronize()
@@ -90,11 +95,45 @@ def test_eulerfd_uniform_free_stream_unchanged():
     assert np.array_equal(got, s0)
 
 
-def test_eulerfd_has_no_fp32_forms():
-    for prec in (sw.FP32C, sw.FP32R):
-        with pytest.raises(sw.Swept2DError) as e:
-            sw.Swept2D(64, 32, EFD, PRM, prec=prec)
-        assert e.value.code == sw.EUNSUPPORTED
+def test_eulerfd_has_no_fp32r_form():
+    with pytest.raises(sw.Swept2DError) as e:
+        sw.Swept2D(64, 32, EFD, PRM, prec=sw.FP32R)
+    assert e.value.code == sw.EUNSUPPORTED
+
+
+# ------------------------------------------------------ FP32 compensated
+
+def _f32c(state64, params, nsub):
+    """Raw FP32C start (u = fl32(x), c = 0) and the oracle's raw result."""
+    u, c = oracle.split_f32c(state64)
+    ru, rc = oracle.advance_f32c(EFD, u, c, params, nsub, threads=oracle.default_threads())
+    return np.concatenate([u, c]), np.concatenate([ru, rc])
+
+
+def test_eulerfd_fp32c_square_tiles_bitwise():
+    s0 = _field(64, 32, 5)
+    raw0, ref = _f32c(s0, PRM, 4 * 13)
+    for n in (2, 4, 8, 16):
+        got, tile, _ = run(raw0, PRM, 13, tile=n, prec=sw.FP32C)
+        assert tile == n and np.array_equal(got, ref), n
+    got, _, _ = run(raw0, PRM, 13, tile=8, staging=sw.STAGING_OFF, prec=sw.FP32C)
+    assert np.array_equal(got, ref)
+    got, _, _ = run(raw0, PRM, 13, method="plain", prec=sw.FP32C)
+    assert np.array_equal(got, ref)
+    assert np.any(got[12:16])  # the compensations carry information
+
+
+def test_eulerfd_fp32c_split_advances_graph_and_rect_tiles():
+    s0 = _field(32, 32, 6)
+    raw0, ref = _f32c(s0, PRM, 4 * 11)
+    got, _, _ = run(raw0, PRM, 11, tile=8, splits=[3, 1, 5, 2], prec=sw.FP32C)
+    assert np.array_equal(got, ref)
+    got, _, _ = run(raw0, PRM, 11, tile=8, mode=sw.LAUNCH_GRAPH, splits=[4, 4, 3], prec=sw.FP32C)
+    assert np.array_equal(got, ref)
+    for nx, ny, hh, steps in ((45, 39, 3, 10), (45, 41, 10, 12)):
+        raw0, ref = _f32c(_field(nx, ny, 7), PRM, 4 * steps)
+        got, tile, rect = run(raw0, PRM, steps, rect=hh, prec=sw.FP32C)
+        assert tile == 0 and rect == hh and np.array_equal(got, ref), (nx, ny, hh)
 
 
 @pytest.mark.timeout(600)
@@ -107,3 +146,22 @@ def test_eulerfd_tunnel_1024x512_full_size_bitwise():
     ref = oracle.advance_f64(EFD, s0, p, 4 * 500, threads=oracle.default_threads())
     assert np.array_equal(got, ref), (tile, rect)
     assert np.max(np.abs(got[0] - s0[0])) > 1e-6  # the pulse has moved
+
+
+@pytest.mark.timeout(600)
+def test_eulerfd_tunnel_1024x512_fp32c_full_size():
+    """The tunnel in compensated FP32 with the default tiling, 100 steps:
+    bit for bit the oracle at every point, and within 1e-12 (normwise, both
+    momenta against the momentum scale since v starts at zero) of the FP64
+    stepper run from the same start; the oracle measures about 3e-14 there,
+    plain FP32 about 5e-8."""
+    s0 = si.initial_state(EFD, 1024, 512, seed=0)
+    p = si.default_params(EFD)
+    raw0, ref = _f32c(s0, p, 4 * 100)
+    got, tile, rect = run(raw0, p, 100, prec=sw.FP32C)
+    assert np.array_equal(got, ref), (tile, rect)
+    r64, _, _ = run(raw0[:12].astype(np.float64), p, 100)
+    wide = got[:12].astype(np.float64) - got[12:].astype(np.float64)
+    mom = max(np.max(np.abs(r64[1])), np.max(np.abs(r64[2])))
+    for k, scale in ((0, np.max(np.abs(r64[0]))), (1, mom), (2, mom), (3, np.max(np.abs(r64[3])))):
+        assert np.max(np.abs(wide[k] - r64[k])) <= 1e-12 * scale, k
