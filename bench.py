@@ -246,24 +246,40 @@ def other_workloads(sw, si, np):
     # differences, four-stage Runge-Kutta) on its 1024 x 512 tunnel grid.
     s_f = si.initial_state(si.EULER_FD_RK4, 1024, 512, seed=0)
     p_f = si.default_params(si.EULER_FD_RK4)
-    fd = {}
-    for method in ("swept", "plain"):
-        g = sw.Swept2D(1024, 512, si.EULER_FD_RK4, p_f)
-        g.upload(s_f)
-        run = g.advance if method == "swept" else g.plain_advance
-        run(20)
-        g.synchronize()
-        t0 = time.perf_counter()
-        run(200)
-        g.synchronize()
-        fd[method] = 1024 * 512 * 200 / (time.perf_counter() - t0)
-        fd["tile"] = g.tile
-        g.close()
-    out["euler_fd_tunnel1024x512_fp64"] = {
-        "swept_value": fd["swept"], "plain_value": fd["plain"], "unit": "point-updates/s (full RK4 steps)",
-        "swept_substep_value": 4 * fd["swept"], "steps": 200, "tile": fd["tile"],
-        "swept_over_plain": fd["swept"] / fd["plain"],
-        "note": "50 MB state (12 FP64 values per point) stays in the Infinity Cache; both paths latency-bound"}
+    ref = None
+    for prec, name in ((sw.FP64, "fp64"), (sw.FP32C, "fp32c")):
+        fd = {}
+        for method in ("swept", "plain"):
+            g = sw.Swept2D(1024, 512, si.EULER_FD_RK4, p_f, prec=prec)
+            if prec == sw.FP64:
+                g.upload(s_f)
+            else:
+                # the start as the exact pair u - c of the FP64 state, so the
+                # error below is that of the compensated arithmetic, not the
+                # FP32 rounding of the free stream (upload keeps c = 0)
+                hi = s_f.astype(np.float32)
+                g.upload_raw(np.concatenate([hi, (hi.astype(np.float64) - s_f).astype(np.float32)]))
+            run = g.advance if method == "swept" else g.plain_advance
+            run(20)
+            g.synchronize()
+            t0 = time.perf_counter()
+            run(200)
+            g.synchronize()
+            fd[method] = 1024 * 512 * 200 / (time.perf_counter() - t0)
+            fd["tile"] = g.tile
+            if method == "swept":
+                res = g.download()  # after 220 steps
+            g.close()
+        rec = {"swept_value": fd["swept"], "plain_value": fd["plain"], "unit": "point-updates/s (full RK4 steps)",
+               "swept_substep_value": 4 * fd["swept"], "steps": 200, "tile": fd["tile"],
+               "swept_over_plain": fd["swept"] / fd["plain"],
+               "note": "50 MB state (12 values per point, 8 bytes each) stays in the Infinity Cache; "
+                       "both paths latency-bound"}
+        if ref is None:
+            ref = res
+        else:
+            rec["error_vs_fp64_after_220_steps"] = normwise(res[:4], ref[:4])
+        out[f"euler_fd_tunnel1024x512_{name}"] = rec
     # The swept rule in 3D: 7-point heat on 128^3 (cube tile 16) and 192^3
     # (tile 12), swept and per-step.
     for L in (128, 192):

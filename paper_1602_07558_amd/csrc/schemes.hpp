@@ -269,15 +269,17 @@ struct Euler64 {
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
     const double gamma = sp.p[0], dtoh = sp.p[1];
-    const int o = (T & 1) ? 4 : 0;
+    // The stage's slots are picked by value: a slot index known only at run
+    // time would put a caller's register neighbourhood on the stack.
+    const bool odd = (T & 1) != 0;
     double W[4], E[4], N[4], S[4], C[4], du[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      W[k] = nb(-1, 0, o + k);
-      E[k] = nb(1, 0, o + k);
-      N[k] = nb(0, -1, o + k);
-      S[k] = nb(0, 1, o + k);
-      C[k] = nb(0, 0, o + k);
+      W[k] = odd ? nb(-1, 0, 4 + k) : nb(-1, 0, k);
+      E[k] = odd ? nb(1, 0, 4 + k) : nb(1, 0, k);
+      N[k] = odd ? nb(0, -1, 4 + k) : nb(0, -1, k);
+      S[k] = odd ? nb(0, 1, 4 + k) : nb(0, 1, k);
+      C[k] = odd ? nb(0, 0, 4 + k) : nb(0, 0, k);
     }
     euler::increment(W, E, N, S, C, gamma, dtoh, du);
     if ((T & 1) == 0) {
@@ -376,32 +378,35 @@ struct EulerFD64 {
                                                 const double* div, const SchemeParams& sp, V* dst) {
     update(T, [&](int v) { return own[v * plane]; }, div, sp.p[1], dst, plane);
   }
-  // The point's new slots from its old ones and r.
+  // Sub-step s of variable k: its new U, Y and K from its old U and K and r.
+  __device__ __forceinline__ static void slot(int s, double U, double K, double r, double dth, double& nu,
+                                              double& ny, double& nk) {
+    if (s == 3) {
+      const double v = U + (dth / 6.0) * (K - r);
+      nu = v;
+      ny = v;
+      nk = 0.0;
+    } else {
+      nu = U;
+      nk = s == 0 ? -r : K - 2.0 * r;
+      ny = U - (s == 2 ? dth : 0.5 * dth) * r;
+    }
+  }
+  // The point's new slots from its old ones and r. Each slot is stored once
+  // at a fixed index (stores to different slots at the ends of per-sub-step
+  // branches would be merged into one store at a computed index, which puts
+  // a register array on the stack).
   template <class OLD>
   __device__ __forceinline__ static void update(long long T, const OLD& old, const double* r, double dth, V* out,
                                                 int stride) {
     const int s = (int)(T & 3);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double U = old(k), K = old(8 + k);
-      if (s == 0) {
-        out[k * stride] = U;
-        out[(8 + k) * stride] = -r[k];
-        out[(4 + k) * stride] = U - (0.5 * dth) * r[k];
-      } else if (s == 1) {
-        out[k * stride] = U;
-        out[(8 + k) * stride] = K - 2.0 * r[k];
-        out[(4 + k) * stride] = U - (0.5 * dth) * r[k];
-      } else if (s == 2) {
-        out[k * stride] = U;
-        out[(8 + k) * stride] = K - 2.0 * r[k];
-        out[(4 + k) * stride] = U - dth * r[k];
-      } else {
-        const double v = U + (dth / 6.0) * (K - r[k]);
-        out[k * stride] = v;
-        out[(4 + k) * stride] = v;
-        out[(8 + k) * stride] = 0.0;
-      }
+      double nu, ny, nk;
+      slot(s, old(k), old(8 + k), r[k], dth, nu, ny, nk);
+      out[k * stride] = nu;
+      out[(4 + k) * stride] = ny;
+      out[(8 + k) * stride] = nk;
     }
   }
   template <class NB>
@@ -416,17 +421,24 @@ struct EulerFD64 {
       S[k] = nb(0, 1, 4 + k);
       C[k] = nb(0, 0, 4 + k);
     }
+    double r[4];
+    divergence(W, E, N, S, C, gamma, r);
+    update(T, [&](int v) { return nb(0, 0, v); }, r, dth, out, 1);
+  }
+  // r = h div F from the stage values of the point (C) and its four
+  // neighbours, x terms first.
+  __device__ __forceinline__ static void divergence(const double* W, const double* E, const double* N,
+                                                    const double* S, const double* C, double gamma, double* r) {
     const eulerfd::Prim pw = eulerfd::prim(W, gamma), pe = eulerfd::prim(E, gamma);
     const eulerfd::Prim pn = eulerfd::prim(N, gamma), ps = eulerfd::prim(S, gamma);
     const eulerfd::Prim pc = eulerfd::prim(C, gamma);
-    double Fw[4], Fe[4], Gn[4], Gs[4], r[4];
+    double Fw[4], Fe[4], Gn[4], Gs[4];
     eulerfd::face(W[1], pw, C[1], pc, 0, Fw);
     eulerfd::face(C[1], pc, E[1], pe, 0, Fe);
     eulerfd::face(N[2], pn, C[2], pc, 1, Gn);
     eulerfd::face(C[2], pc, S[2], ps, 1, Gs);
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[k] = (Fe[k] - Fw[k]) + (Gs[k] - Gn[k]);
-    update(T, [&](int v) { return nb(0, 0, v); }, r, dth, out, 1);
   }
 };
 
@@ -544,15 +556,15 @@ struct Euler32C {
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
     const double gamma = sp.p[0], dtoh = sp.p[1];
-    const int o = (T & 1) ? 4 : 0;
+    const bool odd = (T & 1) != 0;  // slots picked by value, as Euler64
     double W[4], E[4], N[4], S[4], C[4], du[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      W[k] = wide(nb, -1, 0, o + k);
-      E[k] = wide(nb, 1, 0, o + k);
-      N[k] = wide(nb, 0, -1, o + k);
-      S[k] = wide(nb, 0, 1, o + k);
-      C[k] = wide(nb, 0, 0, o + k);
+      W[k] = odd ? wide(nb, -1, 0, 4 + k) : wide(nb, -1, 0, k);
+      E[k] = odd ? wide(nb, 1, 0, 4 + k) : wide(nb, 1, 0, k);
+      N[k] = odd ? wide(nb, 0, -1, 4 + k) : wide(nb, 0, -1, k);
+      S[k] = odd ? wide(nb, 0, 1, 4 + k) : wide(nb, 0, 1, k);
+      C[k] = odd ? wide(nb, 0, 0, 4 + k) : wide(nb, 0, 0, k);
     }
     euler::increment(W, E, N, S, C, gamma, dtoh, du);
     if ((T & 1) == 0) {
@@ -599,26 +611,30 @@ struct EulerFD32C {
   }
   __device__ __forceinline__ static void finish(long long T, const V* own, int plane, const double*,
                                                 const double* div, const SchemeParams& sp, V* dst) {
-    double t[12];
-    EulerFD64::update(T, [&](int v) { return wload(own, plane, v); }, div, sp.p[1], t, 1);
-    store(T, [&](int v) { return own[v * plane]; }, t, dst, plane);
+    update(T, [&](int v) { return own[v * plane]; }, div, sp.p[1], dst, plane);
   }
-  // Slots of the new point from the FP64 results t and the old halves.
+  // The point's new slots from its old halves (old(v), v < 24) and r: per
+  // variable, the FP64 sub-step on the widened U and K, then the changed
+  // slots split. One split serves U on the last sub-step and K before it.
   template <class OLD>
-  __device__ __forceinline__ static void store(long long T, const OLD& old, const double* t, V* out, int stride) {
-    const bool last = (T & 3) == 3;
+  __device__ __forceinline__ static void update(long long T, const OLD& old, const double* r, double dth, V* out,
+                                                int stride) {
+    const int s = (int)(T & 3);
+    const bool last = s == 3;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (last) {
-        split(t[k], out[k * stride], out[(12 + k) * stride]);
-        out[(8 + k) * stride] = 0.0f;
-        out[(20 + k) * stride] = 0.0f;
-      } else {
-        out[k * stride] = old(k);
-        out[(12 + k) * stride] = old(12 + k);
-        split(t[8 + k], out[(8 + k) * stride], out[(20 + k) * stride]);
-      }
-      split(t[4 + k], out[(4 + k) * stride], out[(16 + k) * stride]);
+      const float uu = old(k), uc = old(12 + k);
+      double nu, ny, nk;
+      EulerFD64::slot(s, (double)uu - (double)uc, (double)old(8 + k) - (double)old(20 + k), r[k], dth, nu, ny, nk);
+      float a, b, yu, yc;
+      split(last ? nu : nk, a, b);
+      split(ny, yu, yc);
+      out[k * stride] = last ? a : uu;
+      out[(12 + k) * stride] = last ? b : uc;
+      out[(8 + k) * stride] = last ? 0.0f : a;
+      out[(20 + k) * stride] = last ? 0.0f : b;
+      out[(4 + k) * stride] = yu;
+      out[(16 + k) * stride] = yc;
     }
   }
   __device__ __forceinline__ static void split(double t, float& u, float& c) {
@@ -628,10 +644,23 @@ struct EulerFD32C {
   }
   template <class NB>
   __device__ __forceinline__ static void step(long long T, const NB& nb, V* out, const SchemeParams& sp) {
-    double t[12];
-    EulerFD64::step(T, [&](int di, int dj, int v) { return (double)nb(di, dj, v) - (double)nb(di, dj, 12 + v); },
-                    t, sp);
-    store(T, [&](int v) { return nb(0, 0, v); }, t, out, 1);
+    const double gamma = sp.p[0];
+    double W[4], E[4], N[4], S[4], C[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      W[k] = wide(nb, -1, 0, 4 + k);
+      E[k] = wide(nb, 1, 0, 4 + k);
+      N[k] = wide(nb, 0, -1, 4 + k);
+      S[k] = wide(nb, 0, 1, 4 + k);
+      C[k] = wide(nb, 0, 0, 4 + k);
+    }
+    double r[4];
+    EulerFD64::divergence(W, E, N, S, C, gamma, r);
+    update(T, [&](int v) { return nb(0, 0, v); }, r, sp.p[1], out, 1);
+  }
+  template <class NB>
+  __device__ __forceinline__ static double wide(const NB& nb, int di, int dj, int v) {
+    return (double)nb(di, dj, v) - (double)nb(di, dj, 12 + v);
   }
 };
 

@@ -60,6 +60,46 @@ def test_library_built_for_gfx950_without_contraction():
     assert "-packed-fp32-ops" in flags
 
 
+LLVM = "/opt/rocm/llvm/bin"
+
+
+def kernel_scratch_sizes(lib_path, workdir):
+    """(kernel name, private segment bytes per lane) of every gfx950 kernel in
+    a library built here: its device-code section holds one offload bundle
+    per object, each unbundled and its kernel metadata read."""
+    sec = os.path.join(workdir, "fatbin.bin")
+    subprocess.run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section", ".hip_fatbin=" + sec, lib_path,
+                    os.path.join(workdir, "stripped.so")], check=True)
+    data = open(sec, "rb").read()
+    starts = [m.start() for m in re.finditer(b"__CLANG_OFFLOAD_BUNDLE__", data)] + [len(data)]
+    out = []
+    for i in range(len(starts) - 1):
+        b, co = os.path.join(workdir, f"b{i}.bin"), os.path.join(workdir, f"c{i}.elf")
+        open(b, "wb").write(data[starts[i]:starts[i + 1]])
+        subprocess.run([os.path.join(LLVM, "clang-offload-bundler"), "--unbundle", "--type=o",
+                        "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + b, "--output=" + co], check=True)
+        notes = subprocess.run([os.path.join(LLVM, "llvm-readelf"), "--notes", co], capture_output=True, text=True,
+                               check=True).stdout
+        name = None
+        for line in notes.splitlines():
+            line = line.strip()
+            if line.startswith(".name:"):
+                name = line.split(":", 1)[1].strip()
+            elif line.startswith(".private_segment_fixed_size:"):
+                out.append((name, int(line.split(":", 1)[1])))
+    return out
+
+
+def test_no_kernel_uses_scratch_memory(lib, tmp_path):
+    """Every kernel keeps its per-thread arrays in registers: a register
+    array indexed by a value known only at run time, or stores to different
+    slots merged at a computed index, would put it in scratch memory, which
+    costs the latency-bound level loops far more than its bytes."""
+    sizes = kernel_scratch_sizes(sw._build.LIB, str(tmp_path))
+    assert len(sizes) > 300  # the stage kernels of every scheme and launch class
+    assert [k for k in sizes if k[1]] == []
+
+
 def _gpu_present():
     try:
         import torch
