@@ -1,4 +1,6 @@
-"""Host-side checks of integer facts the stage kernels rely on (no GPU).
+"""Host-side checks of integer facts the stage kernels rely on (no GPU): the
+float row index of the point-per-thread pass, and the rectangular tilings the
+library cuts (a host-only build of its tiling code against the oracle model).
 
 The point-per-thread level pass (tile sides 16 and 32) maps thread index k
 to row k // w and column k % w of a w-wide rectangle through one binary32
@@ -35,3 +37,52 @@ def test_float_row_index_margin():
         margin = np.min(np.abs(q - np.rint(q)))
         assert margin >= 0.5 / w - 1e-12
         assert margin > 10 * worst_err
+
+
+# ------------------------------------------------ rectangular tilings (host)
+#
+# The library cuts an axis of length L into floor(L / 2h) tiles for a half
+# cycle of height h and alternates that tiling with the one whose edges are
+# its midpoints. A host-only build of its tiling functions prints every span
+# for L <= 160; the spans must be the oracle model's tilings exactly.
+
+import os
+import subprocess
+
+import pytest
+
+from oracle import swept_model as sm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def library_spans(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("host") / "rect_axis_dump")
+    subprocess.run(["/opt/rocm/bin/hipcc", "--cuda-host-only", "-x", "hip", "-O1", "-std=c++17",
+                    "-I" + os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "host", "rect_axis_dump.cpp"),
+                    "-o", exe], check=True, capture_output=True)
+    out = subprocess.run([exe, "160"], check=True, capture_output=True, text=True).stdout
+    spans = {}
+    for line in out.splitlines():
+        L, h, par, t, *sw = map(int, line.split())
+        assert len(sw) == 2 * t
+        spans[(L, h, par)] = [(sw[2 * i], sw[2 * i + 1]) for i in range(t)]
+    return spans
+
+
+def test_library_rect_tilings_equal_the_model(library_spans):
+    n = 0
+    for (L, h, par), spans in library_spans.items():
+        ax = sm.rect_axis(L, h)
+        if par:
+            ax = sm.mid_axis(ax)
+        want = sorted(zip(ax.edges, ax.widths()))
+        got = sorted((s % L, w) for s, w in spans)
+        assert got == want, (L, h, par)
+        # tiles in order, each starting where the one before ends
+        for (s, w), (s2, _) in zip(spans, spans[1:]):
+            assert s + w == s2, (L, h, par)
+        assert min(w for _, w in spans) >= 2 * h and max(w for _, w in spans) - min(w for _, w in spans) <= 1
+        n += 1
+    assert n == sum(2 * (L // 2) for L in range(2, 161))
