@@ -51,6 +51,30 @@ def test_heat_1024_20000_steps_fp64_bitwise():
 
 
 @pytest.mark.timeout(900)
+def test_heat_8192_fp64_bitwise():
+    """The benchmark's grid beyond the Infinity Cache (512 MB of state; two
+    64-tile workgroups per compute unit): 64 steps (two half cycles: the
+    first pyramids, bridges, octahedra, bridges and the last downward
+    pyramids) swept against the oracle at every point, and the benchmark's
+    64 + 256 steps swept against the per-step kernel."""
+    s0 = si.heat_field(8192, 8192, seed=0)
+    p = si.default_params(si.HEAT5)
+    got, tile = _swept(si.HEAT5, p, s0, 64)
+    assert tile == 64
+    ref = oracle.advance_f64(si.HEAT5, s0, p, 64, threads=oracle.default_threads())
+    assert np.array_equal(got, ref)
+    del got, ref
+    res = {}
+    for method in ("swept", "plain"):
+        with sw.Swept2D(8192, 8192, si.HEAT5, p) as g:
+            g.upload(s0)
+            (g.advance if method == "swept" else g.plain_advance)(64)
+            (g.advance if method == "swept" else g.plain_advance)(256)
+            res[method] = g.download()
+    assert np.array_equal(res["swept"], res["plain"])
+
+
+@pytest.mark.timeout(900)
 def test_heat_1024_20000_steps_fp32c_error():
     s0 = si.heat_field(1024, 1024, seed=0)
     p = si.default_params(si.HEAT5)
