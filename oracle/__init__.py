@@ -76,8 +76,23 @@ def _load():
         lib.oracle_residency.restype = ctypes.c_longlong
         lib.oracle_residency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
+        lib.oracle_point_wave_f32v.restype = None
+        lib.oracle_point_wave_f32v.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_double]
         _lib = lib
     return _lib
+
+
+def point_wave_f32v(nu, nc, c2: float):
+    """One point of the FP32 wave's velocity form: nu, nc are [3][3][2]
+    float32 neighbourhoods (rows north to south, slots u, v) of values and
+    compensations; returns the new (u, v) and their compensations."""
+    lib = _load()
+    a = np.ascontiguousarray(nu, dtype=np.float32).reshape(18)
+    b = np.ascontiguousarray(nc, dtype=np.float32).reshape(18)
+    ou, oc = np.zeros(2, np.float32), np.zeros(2, np.float32)
+    lib.oracle_point_wave_f32v(a.ctypes.data, b.ctypes.data, ou.ctypes.data, oc.ctypes.data, float(c2))
+    return ou, oc
 
 
 def default_threads() -> int:

@@ -29,11 +29,10 @@
  * whose code is not part of the text); the expressions are this project's
  * definitions and are restated, not shared, on the GPU side.
  *
- * Parity unpinned (one term): in the wave's velocity form for FP32 with the
- * compensation confined to residencies (st_wave_f32v), the sign with which
- * the new velocity's compensation enters the displacement's increment
- * changes no property the tests can observe (its effect is far below the
- * unit of the displacement); every other term of that form is pinned.
+ * In the wave's velocity form for FP32 with the compensation confined to
+ * residencies (st_wave_f32v), the sign with which the new velocity's
+ * compensation enters the displacement's increment is pinned on one point
+ * with dyadic values, where the compensated form must give exact leapfrog.
  */
 #include <math.h>
 #include <stdint.h>
@@ -633,6 +632,22 @@ static void st_wave_f32v(const float nu[9][MAXV], const float nc[9][MAXV], float
 long long oracle_residency(int x, int y, long long L, int n, int nx, int ny)
 {
     return residency(x, y, L, n, nx, ny);
+}
+
+/* One point of the wave's velocity form (st_wave_f32v) on a given 3x3
+ * neighbourhood (exported for the pins): nu, nc are [9][2] (row-major
+ * neighbours, north-west first; slots u, v), ou, oc [2]. */
+void oracle_point_wave_f32v(const float *nu, const float *nc, float *ou, float *oc, double c2)
+{
+    float u9[9][MAXV], c9[9][MAXV];
+    memset(u9, 0, sizeof u9);
+    memset(c9, 0, sizeof c9);
+    for (int k = 0; k < 9; ++k)
+        for (int v = 0; v < 2; ++v) {
+            u9[k][v] = nu[2 * k + v];
+            c9[k][v] = nc[2 * k + v];
+        }
+    st_wave_f32v(u9, c9, ou, oc, &c2);
 }
 
 /* Advance u ([nvars][ny][nx] FP32) by nsub sub-steps from global sub-step t0

@@ -851,6 +851,27 @@ def test_f32r_wave_velocity_form_exact_on_dyadic_data():
         assert np.array_equal(got, ref), n
 
 
+def test_f32r_wave_velocity_compensations_give_exact_leapfrog_on_one_point():
+    """The pairs stand for u - c_u and v - c_v, so one point of the velocity
+    form must be leapfrog on those values, which dyadic data makes exact.
+    Neighbours 0 (no compensation), the point's u = 0 with c_u = 2^-25 and
+    v = 1 with c_v = 0, C2 = 1/4: U = -2^-25, V = 1, lap U = 4 * 2^-25, so
+    V' = V + C2 lap U = 1 + 2^-25 and U' = U + V' = 1 exactly. The new
+    velocity rounds to tv = 1 with compensation -2^-25, and the displacement
+    takes the increment V' - c_u = tv - (c_u + c_v'): taking that
+    compensation with the other sign gives U' = 1 - 2^-24."""
+    nu = np.zeros((3, 3, 2), np.float32)
+    nc = np.zeros((3, 3, 2), np.float32)
+    nu[1, 1] = (0.0, 1.0)
+    nc[1, 1] = (2.0 ** -25, 0.0)
+    ou, oc = oracle.point_wave_f32v(nu, nc, 0.25)
+    U1 = Fraction(float(ou[0])) - Fraction(float(oc[0]))
+    V1 = Fraction(float(ou[1])) - Fraction(float(oc[1]))
+    assert V1 == 1 + Fraction(1, 2 ** 25)
+    assert U1 == 1
+    assert (float(ou[1]), float(oc[1])) == (1.0, -(2.0 ** -25))
+
+
 def test_f32r_exact_when_fp32_is_exact():
     rng = np.random.default_rng(5)
     u0 = rng.integers(-8, 9, size=(1, 16, 16)).astype(np.float64)
