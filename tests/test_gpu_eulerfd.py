@@ -70,6 +70,20 @@ def test_eulerfd_square_tiles_bitwise(nx, ny, steps):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("staging", [sw.STAGING_ON, sw.STAGING_SINGLE_BRIDGES, sw.STAGING_OFF])
+def test_eulerfd_every_staging_mode_bitwise(staging):
+    """AUTO never stages this scheme at tile side 16 (a staged workgroup
+    would be alone on its compute unit); the staged octahedra and bridges
+    that STAGING_ON selects give the same bits, in FP64 and FP32C."""
+    s0 = _field(64, 32, 8)
+    ref = oracle.advance_f64(EFD, s0, PRM, 4 * 11)
+    got, tile, _ = run(s0, PRM, 11, tile=16, staging=staging)
+    assert tile == 16 and np.array_equal(got, ref)
+    raw0, ref32 = _f32c(s0, PRM, 4 * 11)
+    got, _, _ = run(raw0, PRM, 11, tile=16, staging=staging, prec=sw.FP32C)
+    assert np.array_equal(got, ref32)
+
+
 def test_eulerfd_split_advances_and_graph_replay():
     s0 = _field(32, 32, 2)
     ref = oracle.advance_f64(EFD, s0, PRM, 4 * 11)
