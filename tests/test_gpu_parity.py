@@ -247,6 +247,21 @@ def test_euler_bitwise():
     assert np.array_equal(gpu_run(si.EULER_RUS_RK2, s0, p, 50, method="plain"), ref)
 
 
+@pytest.mark.parametrize("staging", [sw.STAGING_ON, sw.STAGING_SINGLE_BRIDGES])
+def test_euler_staged_paths_bitwise(staging):
+    """The staged octahedra and bridges of the column walk (STAGING_ON
+    stages whatever fits beside the window) in FP64 and FP32C."""
+    s0 = si.euler_field(64, 64, seed=2)
+    p = si.default_params(si.EULER_RUS_RK2, s0)
+    ref = oracle.advance_f64(si.EULER_RUS_RK2, s0, p, 2 * 20)
+    u, c = oracle.split_f32c(s0)
+    ru, rc = oracle.advance_f32c(si.EULER_RUS_RK2, u, c, p, 2 * 20)
+    for n in (8, 16, 32):
+        assert np.array_equal(gpu_run(si.EULER_RUS_RK2, s0, p, 20, tile=n, staging=staging), ref), n
+        got = gpu_run(si.EULER_RUS_RK2, np.concatenate([u, c]), p, 20, tile=n, prec=sw.FP32C, staging=staging)
+        assert np.array_equal(got, np.concatenate([ru, rc])), n
+
+
 # ------------------------------------------------------ FP32 compensated
 
 @pytest.mark.parametrize("pde,nx,ny,steps,tiles", [
