@@ -30,6 +30,9 @@
  *     the next call that checks the stream.
  *   - No C++ exception crosses this interface.
  *   - A handle is not thread safe: one thread at a time per handle.
+ *     Different handles may be created and used from different threads at
+ *     once; the first handle on each device sets that device's kernel
+ *     limits once, under a lock.
  *
  * State layout (device and host): structure of arrays [nvars][ny][nx], x
  * fastest, row j = 0 is the north edge. The paper's point (i, j) is

@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -120,21 +122,57 @@ int scheme_of(int pde, int prec) {
   return -1;
 }
 
-bool g_lds_configured = false;
-size_t g_lds_limit = 0;
+// Each device's kernels get their dynamic-LDS limit once, the first time a
+// handle is made on it; handles may be created from several threads at
+// once. g_lds_limit is the smallest per-workgroup LDS of the devices set up
+// (one value on a node of one GPU model).
+constexpr int kMaxSetupDevices = 64;
+std::mutex g_setup_mu;
+bool g_setup_done[kMaxSetupDevices] = {};
+std::atomic<size_t> g_lds_limit{0};
 
 int ensure_device_setup(int* device_out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-  if (!g_lds_configured) {
+  if (dev < 0 || dev >= kMaxSetupDevices)
+    return swept::set_error(SWEPT2D_EUNSUPPORTED, "device %d beyond the %d the library sets up", dev,
+                            kMaxSetupDevices);
+  std::lock_guard<std::mutex> lock(g_setup_mu);
+  if (!g_setup_done[dev]) {
     int lds = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
-    g_lds_limit = (size_t)lds;
-    HIP_TRY(configure_lds(g_lds_limit), "hipFuncSetAttribute");
-    g_lds_configured = true;
+    HIP_TRY(configure_lds((size_t)lds), "hipFuncSetAttribute");  // on the current device
+    for (int k = 0; const swept2d_scheme_ops* u = user_scheme(k); ++k)
+      HIP_TRY(static_cast<hipError_t>(u->lds((size_t)lds)), "scheme LDS limit");
+    const size_t cur = g_lds_limit.load();
+    if (cur == 0 || (size_t)lds < cur) g_lds_limit.store((size_t)lds);
+    g_setup_done[dev] = true;
   }
   *device_out = dev;
   return 0;
+}
+
+// Registers a user scheme: its kernels' LDS limit is set on every device
+// set up so far (devices set up later take it from the table), and it joins
+// the table under the same lock, so no device misses it. Returns its index,
+// or a negative error code.
+int register_user_scheme(const swept2d_scheme_ops& ops) {
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_setup_mu);
+  int rc = 0;
+  for (int d = 0; d < kMaxSetupDevices && rc == 0; ++d) {
+    if (!g_setup_done[d]) continue;
+    hipError_t e = hipSetDevice(d);
+    if (e == hipSuccess) e = static_cast<hipError_t>(ops.lds(g_lds_limit));
+    if (e != hipSuccess) rc = hipfail(e, "scheme LDS limit");
+  }
+  const hipError_t back = hipSetDevice(cur);
+  if (rc) return rc;
+  if (back != hipSuccess) return hipfail(back, "hipSetDevice");
+  const int k = add_user_scheme(ops);
+  if (k < 0) return swept::set_error(SWEPT2D_EUNSUPPORTED, "%d user schemes are registered already", kMaxUserSchemes);
+  return k;
 }
 
 }  // namespace
@@ -943,9 +981,8 @@ int swept2d_register_scheme(const swept2d_scheme_ops* ops) {
     return fail(SWEPT2D_EINVAL, "scheme table lacks a launcher");
   int dev = 0;
   if (int rc = ensure_device_setup(&dev)) return rc;
-  HIP_TRY(static_cast<hipError_t>(ops->lds(g_lds_limit)), "scheme LDS limit");
-  const int k = add_user_scheme(*ops);
-  if (k < 0) return fail(SWEPT2D_EUNSUPPORTED, "%d user schemes are registered already", kMaxUserSchemes);
+  const int k = register_user_scheme(*ops);
+  if (k < 0) return k;
   return SWEPT2D_USER_PDE_BASE + k;
 }
 

@@ -247,6 +247,63 @@ def test_euler_bitwise():
     assert np.array_equal(gpu_run(si.EULER_RUS_RK2, s0, p, 50, method="plain"), ref)
 
 
+def test_handles_on_concurrent_threads():
+    """Handles are independent: eight host threads, each creating, advancing
+    and reading back its own handle (heat, wave and both Euler schemes, FP64
+    and FP32C, square and rectangular tiles) at the same time, each get the
+    oracle's bits. The binding releases the interpreter lock in every
+    library call, so the calls overlap."""
+    import threading
+    cases = [(si.HEAT5, 64, 64, 40, sw.FP64, 0), (si.WAVE_LF, 64, 32, 30, sw.FP64, 0),
+             (si.EULER_RUS_RK2, 32, 32, 10, sw.FP64, 0), (si.EULER_FD_RK4, 32, 32, 6, sw.FP64, 0),
+             (si.HEAT5, 45, 39, 25, sw.FP64, 3), (si.HEAT5, 64, 64, 40, sw.FP32C, 0),
+             (si.EULER_FD_RK4, 48, 32, 5, sw.FP32C, 0), (si.WAVE_LF, 64, 64, 30, sw.FP32C, 0)]
+    refs, inputs, params = [], [], []
+    for pde, nx, ny, steps, prec, _ in cases:
+        s0 = si.initial_state(pde, nx, ny, seed=11)
+        p = si.default_params(pde, s0)
+        params.append(p)
+        m = si.PDE_SHAPE[pde][1]
+        if prec == sw.FP64:
+            inputs.append(s0)
+            refs.append(oracle.advance_f64(pde, s0, p, m * steps))
+        else:
+            u, c = oracle.split_f32c(s0)
+            inputs.append(np.concatenate([u, c]))
+            refs.append(np.concatenate(oracle.advance_f32c(pde, u, c, p, m * steps)))
+    results, errors = [None] * len(cases), []
+    start = threading.Barrier(len(cases))
+
+    def work(i):
+        pde, nx, ny, steps, prec, rect = cases[i]
+        try:
+            start.wait()
+            with sw.Swept2D(nx, ny, pde, params[i], prec=prec) as g:
+                if rect:
+                    g.rect = rect
+                if prec == sw.FP64:
+                    g.upload(inputs[i])
+                else:
+                    g.upload_raw(inputs[i])
+                for part in (steps // 2, steps - steps // 2):
+                    g.advance(part)
+                g.synchronize()
+                results[i] = g.download_raw()
+        except Exception as e:  # reported below, with the case
+            errors.append((i, repr(e)))
+
+    _say("threads", len(cases))
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+    for i, (got, ref) in enumerate(zip(results, refs)):
+        assert np.array_equal(got, ref), cases[i]
+
+
 @pytest.mark.parametrize("staging", [sw.STAGING_ON, sw.STAGING_SINGLE_BRIDGES])
 def test_euler_staged_paths_bitwise(staging):
     """The staged octahedra and bridges of the column walk (STAGING_ON
