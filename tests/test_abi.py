@@ -115,6 +115,37 @@ def test_create_without_device_fails_loudly(lib):
     assert sw.swept2d_last_error()
 
 
+def test_error_message_is_per_thread(lib):
+    """Each thread sees the message of its own last failure: threads whose
+    creates fail for different reasons at the same moment each read back
+    their own, and a thread that made no failing call reads none."""
+    import threading
+    start = threading.Barrier(8)
+    seen = {}
+
+    def work(i):
+        start.wait()
+        if i % 2:
+            assert not lib.swept2d_create(64, 64, 2, sw.HEAT5, 1)  # wrong nvars for heat
+        else:
+            assert not lib.swept2d_create(64, 64, 1, 12345, 1)  # unknown pde
+        seen[i] = sw.swept2d_last_error()
+
+    def quiet():
+        start.wait()
+        seen["quiet"] = sw.swept2d_last_error()
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(7)] + [threading.Thread(target=quiet)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=60)
+    assert seen["quiet"] == ""
+    for i in range(7):
+        assert seen[i], i
+        assert ("nvars" in seen[i]) == bool(i % 2), (i, seen[i])
+
+
 def test_invalid_pde_shapes_rejected_before_device(lib):
     assert not lib.swept2d_create(64, 64, 2, sw.HEAT5, 1)
     assert "nvars" in sw.swept2d_last_error()
