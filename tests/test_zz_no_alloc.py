@@ -79,6 +79,28 @@ def test_noalloc_fp32c_and_model_tile():
     assert np.array_equal(a[0], oracle.advance_f64(si.HEAT5, s1, p1, 45)[0])
 
 
+def test_noalloc_euler_schemes_two_calls():
+    """The column-walk schemes: the central-difference Euler scheme in FP64
+    (12 values per point, four sub-steps), then a smaller Rusanov grid in
+    FP32C on the same static array."""
+    efd = si.EULER_FD_RK4
+    s1 = si.eulerfd_field(256, 128, seed=6, amp=0.2, width=4.0)
+    p1 = si.default_params(efd)
+    _say("noalloc euler_fd 256x128 fp64 tile 16 steps 21")
+    a = _noalloc_advance(efd, sw.FP64, p1, s1, 16, 0, 21)
+    b = _handle_advance(efd, sw.FP64, p1, s1, 16, 0, 21)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, oracle.advance_f64(efd, s1, p1, 4 * 21))
+    s2 = si.euler_field(64, 64, seed=7)
+    p2 = si.default_params(si.EULER_RUS_RK2, s2)
+    _say("noalloc euler_rus 64x64 fp32c tile 16 steps 13")
+    a = _noalloc_advance(si.EULER_RUS_RK2, sw.FP32C, p2, s2, 16, 0, 13)
+    b = _handle_advance(si.EULER_RUS_RK2, sw.FP32C, p2, s2, 16, 0, 13)
+    assert np.array_equal(a, b)
+    u, c = oracle.split_f32c(s2)
+    assert np.array_equal(a, np.concatenate(oracle.advance_f32c(si.EULER_RUS_RK2, u, c, p2, 2 * 13)))
+
+
 def test_noalloc_rejects_grids_beyond_the_static_array():
     import torch
     s0 = si.wave_field(2048, 2048, seed=0)
