@@ -378,13 +378,17 @@ def main():
         # Short run for counter collection: the swept FP64 path, per-step
         # launches, and a plain copy of known size that calibrates the byte
         # counters. heat: 1024^2, 20 half cycles and 64 steps; euler_fd: the
-        # 1024 x 512 tunnel, 5 half cycles (40 steps) and 8 steps; heat3d:
-        # 128^3, 4 half cycles (32 steps) and 8 steps.
+        # 1024 x 512 tunnel, 5 half cycles (40 steps) and 8 steps, in FP64 and
+        # then in FP32C; heat3d: 128^3, 4 half cycles (32 steps) and 8 steps.
         if args.profile_workload == "euler_fd":
-            g = sw.Swept2D(1024, 512, si.EULER_FD_RK4, si.default_params(si.EULER_FD_RK4))
-            g.upload(si.initial_state(si.EULER_FD_RK4, 1024, 512, seed=0))
-            g.advance(40)
-            g.plain_advance(8)
+            for prec in (sw.FP32C, sw.FP64):  # the FP64 handle stays open below
+                g = sw.Swept2D(1024, 512, si.EULER_FD_RK4, si.default_params(si.EULER_FD_RK4), prec=prec)
+                g.upload(si.initial_state(si.EULER_FD_RK4, 1024, 512, seed=0))
+                g.advance(40)
+                g.plain_advance(8)
+                if prec == sw.FP32C:
+                    g.synchronize()
+                    g.close()
         elif args.profile_workload == "heat3d":
             g = sw.Swept3D(128, 128, 128, si.HEAT7_3D, [si.HEAT3D_R])
             g.upload(si.heat3d_field(128, 128, 128, seed=0))
